@@ -1,0 +1,211 @@
+"""FP64 CPU oracle for the neBEM hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product library (HIP kernels + C-ABI) never calls
+it, links it or falls back to it, and it shares no code with that library.
+
+The C part (nebem_oracle.c) holds the panel integrals, evaluation, assembly
+and point-charge sums; this module wraps it with ctypes and adds the pieces
+that are plain library steps: the dense solve (LAPACK LU with partial
+pivoting through scipy, paper Eq. Matrix and Algorithm 1's factorisation)
+and the explicit-Euler space-charge step (paper Algorithm 4 with the fixed
+drift model described at `spacecharge_step`).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nebem_oracle.c")
+_LIB = os.path.join(_HERE, "libnebem_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA
+    contraction, OpenMP over the independent outer loops)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Images(ctypes.Structure):
+    _fields_ = [("a1", ctypes.c_double * 3), ("a2", ctypes.c_double * 3),
+                ("n1", ctypes.c_int32), ("n2", ctypes.c_int32),
+                ("mirror_mask", ctypes.c_int32),
+                ("mirror_pos", ctypes.c_double * 3),
+                ("mirror_parity", ctypes.c_int32 * 3)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    lib.oracle_panel.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_int, P]
+    lib.oracle_panel_exact.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_int, P]
+    lib.oracle_panel_gauss.argtypes = [ctypes.c_int, P, P, P, P, P]
+    lib.oracle_eval.argtypes = [i64, P, P, P, P, P, ctypes.POINTER(_Images), i64, P, P, ctypes.c_int]
+    lib.oracle_assemble.argtypes = [i64, P, P, P, P, P, P, P, ctypes.POINTER(_Images), P, P, ctypes.c_int]
+    lib.oracle_coulomb.argtypes = [i64, P, P, i64, P, P, P, ctypes.c_int]
+    lib.oracle_ke.restype = ctypes.c_double
+    lib.oracle_eps0.restype = ctypes.c_double
+    lib.oracle_max_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def ke() -> float:
+    return _load().oracle_ke()
+
+
+def eps0() -> float:
+    return _load().oracle_eps0()
+
+
+def max_threads() -> int:
+    return _load().oracle_max_threads()
+
+
+def _images(img) -> _Images:
+    s = _Images()
+    if img is None:
+        return s
+    for k in range(3):
+        s.a1[k] = float(img.a1[k])
+        s.a2[k] = float(img.a2[k])
+        s.mirror_pos[k] = float(img.mirror_pos[k])
+        s.mirror_parity[k] = int(img.mirror_parity[k])
+    s.n1, s.n2, s.mirror_mask = int(img.n1), int(img.n2), int(img.mirror_mask)
+    return s
+
+
+def panel(kind, o, u, w, p, on_plane=False, method="auto") -> np.ndarray:
+    """(Phi', E'x, E'y, E'z) of one unit-density panel at point p."""
+    lib = _load()
+    out = np.zeros(4)
+    o, u, w, p = (_f64(x, 3) for x in (o, u, w, p))
+    if method == "auto":
+        lib.oracle_panel(int(kind), _p(o), _p(u), _p(w), _p(p), int(on_plane), _p(out))
+    elif method == "exact":
+        lib.oracle_panel_exact(int(kind), _p(o), _p(u), _p(w), _p(p), int(on_plane), _p(out))
+    elif method == "gauss":
+        lib.oracle_panel_gauss(int(kind), _p(o), _p(u), _p(w), _p(p), _p(out))
+    else:
+        raise ValueError(method)
+    return out
+
+
+def eval_points(geom, sigma, pts, nthreads: int = 0) -> np.ndarray:
+    """(phi, Ex, Ey, Ez) [m, 4] at points from all panels and their copies."""
+    lib = _load()
+    pts = _f64(pts, (-1, 3))
+    out = np.zeros((pts.shape[0], 4))
+    kind = np.ascontiguousarray(geom.kind, dtype=np.int32)
+    o, u, w = _f64(geom.o), _f64(geom.u), _f64(geom.w)
+    sig = _f64(sigma)
+    im = _images(geom.images)
+    lib.oracle_eval(geom.n, _p(kind), _p(o), _p(u), _p(w), _p(sig), ctypes.byref(im),
+                    pts.shape[0], _p(pts), _p(out), int(nthreads))
+    return out
+
+
+def assemble(geom, colloc=None, nthreads: int = 0) -> np.ndarray:
+    """Influence matrix, column-major storage returned as a Fortran-ordered
+    [n, n] array A with A[i, j] = influence of panel j at collocation i."""
+    lib = _load()
+    n = geom.n
+    A = np.zeros(n * n)
+    kind = np.ascontiguousarray(geom.kind, dtype=np.int32)
+    bc = np.ascontiguousarray(geom.bc, dtype=np.int32)
+    o, u, w = _f64(geom.o), _f64(geom.u), _f64(geom.w)
+    ep, en = _f64(geom.eps_pos), _f64(geom.eps_neg)
+    c = None if colloc is None else _f64(colloc, (-1, 3))
+    im = _images(geom.images)
+    lib.oracle_assemble(n, _p(kind), _p(o), _p(u), _p(w), _p(bc), _p(ep), _p(en), ctypes.byref(im),
+                        _p(c), _p(A), int(nthreads))
+    return A.reshape((n, n), order="F")
+
+
+def coulomb(targets, sources, q, self_index=None, nthreads: int = 0) -> np.ndarray:
+    """(phi, E) [nt, 4] of point charges at targets, skipping self pairs."""
+    lib = _load()
+    t = _f64(targets, (-1, 3))
+    s = _f64(sources, (-1, 3))
+    qq = _f64(q)
+    si = None if self_index is None else np.ascontiguousarray(self_index, dtype=np.int64)
+    out = np.zeros((t.shape[0], 4))
+    lib.oracle_coulomb(t.shape[0], _p(t), _p(si), s.shape[0], _p(s), _p(qq), _p(out), int(nthreads))
+    return out
+
+
+def solve(A, b):
+    """sigma solving A sigma = b by LU with partial pivoting (LAPACK getrf /
+    getrs via scipy).  The paper forms K^-1 (Algorithm 1) and multiplies;
+    the solution is the same vector."""
+    import scipy.linalg as sla
+    lu, piv = sla.lu_factor(A)
+    return sla.lu_solve((lu, piv), b)
+
+
+def rhs_with_charges(geom, b0, qxyz, q, nthreads: int = 0) -> np.ndarray:
+    """Boundary values with the known charges moved to the right-hand side
+    (paper Sec. 4.1, RHVector with the known-charge contribution):
+    conductor rows V_i - phi_q(c_i), dielectric rows -n_i . E_q(c_i)."""
+    c = geom.centroids()
+    f = coulomb(c, qxyz, q, None, nthreads)
+    n = geom.normals()
+    en = np.einsum("ij,ij->i", f[:, 1:], n)
+    return np.where(geom.bc == 0, b0 - f[:, 0], -en)
+
+
+@dataclass
+class SpaceChargeParams:
+    dt: float = 1e-12          # s
+    mobility: float = 1e-4     # m^2 / (V s), same for both signs
+    resolve_every: int = 10
+
+
+def spacecharge_step(geom, A, b0, sigma, qxyz, q, step_index, params: SpaceChargeParams,
+                     nthreads: int = 0):
+    """One step of the dynamic space-charge loop (paper Algorithm 4 with a
+    fixed drift model in place of the avalanche transport):
+      1. if step_index % resolve_every == 0: re-solve sigma with the charges
+         on the right-hand side;
+      2. E at every charge = panel part (all copies) + point-charge part
+         (all other charges, no copies);
+      3. every charge moves by sign(q) * mobility * E * dt (all fields from
+         the start-of-step positions).
+    Returns (new positions, sigma, E at the charges)."""
+    if step_index % params.resolve_every == 0:
+        b = rhs_with_charges(geom, b0, qxyz, q, nthreads)
+        sigma = solve(A, b)
+    ep = eval_points(geom, sigma, qxyz, nthreads)[:, 1:]
+    ec = coulomb(qxyz, qxyz, q, np.arange(qxyz.shape[0]), nthreads)[:, 1:]
+    E = ep + ec
+    new = qxyz + (np.sign(q) * params.mobility * params.dt)[:, None] * E
+    return new, sigma, E
