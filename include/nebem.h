@@ -1,0 +1,202 @@
+/*
+ * nebem.h -- C-ABI of libnebem, the MI355X (gfx950) hot path of the nearly
+ * exact boundary element method (neBEM) for electrostatics.
+ *
+ * The method (paper: "neBEM: A GPU-accelerated Electrostatic Field Solver"):
+ *  - boundaries are cut into flat rectangular and right-triangular elements
+ *    carrying a uniform surface charge density (Sec. 2, zeroth-order BEM);
+ *  - the potential and field of each element are its exact closed-form
+ *    integrals of the free-space Green's function (Sec. 2.1);
+ *  - collocation at element centroids gives K sigma = phi (Eq. Matrix),
+ *    solved for sigma (Algorithm 1, LU factorisation);
+ *  - potential and field anywhere follow by superposition over all
+ *    elements and their periodic copies (Eqs. Potential and Field; Sec. 3,
+ *    PFAtPoint in Sec. 4.1), plus known point charges (Sec. 4.2, Algorithm 2);
+ *  - the dynamic space-charge loop moves charges and re-solves sigma with the
+ *    charges on the right-hand side (Sec. 4.3, Algorithm 4).
+ *
+ * Conventions for every entry point
+ *  - SI units: metres, volts, coulombs, C/m^2, V/m.
+ *  - Every array argument is DEVICE memory on the current HIP device, owned
+ *    by the caller, unless marked "host".  Arrays are structure-of-arrays,
+ *    contiguous, FP64 unless stated.  Matrices are column-major with leading
+ *    dimension n.
+ *  - Work is enqueued on `stream`; outputs are valid after the stream has
+ *    synchronised.  Calls that need a host decision (pivot failure, solver
+ *    convergence, panel validation) synchronise `stream` themselves and say so.
+ *  - Return value 0 = NEBEM_OK, negative = error; nebem_last_error() gives a
+ *    thread-local message.  Validation errors return before any kernel
+ *    launch that writes caller memory.  No C++ exception crosses this ABI.
+ *  - The library keeps no hidden state between calls except inside
+ *    nebem_session objects and a per-device cache of its own kernels' scratch.
+ */
+#ifndef NEBEM_H
+#define NEBEM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nebem_status;
+#define NEBEM_OK 0
+#define NEBEM_EINVAL (-1)    /* bad argument or invalid panel */
+#define NEBEM_ENOMEM (-2)    /* device allocation failed */
+#define NEBEM_ESINGULAR (-3) /* exactly zero pivot in the LU factorisation */
+#define NEBEM_ENOCONV (-4)   /* iterative refinement did not reach ir_tol */
+#define NEBEM_EDEVICE (-5)   /* HIP runtime error */
+#define NEBEM_EBUSY (-6)     /* serving queue full / request exceeds budget */
+
+/* Element kinds (Sec. 2.1: rectangular and right-angled triangular elements) */
+#define NEBEM_RECT 0 /* { o + s u + t w : 0 <= s,t <= 1 } */
+#define NEBEM_RTRI 1 /* { o + s u + t w : s,t >= 0, s + t <= 1 }, right angle at o */
+
+/* Boundary conditions (Sec. 2: Dirichlet on conductors; dielectric interfaces
+ * are a reading -- continuity of the normal displacement, see nebem_assemble) */
+#define NEBEM_CONDUCTOR 0
+#define NEBEM_DIELECTRIC 1
+
+/* Panels, structure of arrays, n entries each.  u and w must be perpendicular
+ * (|u.w| <= 1e-9 |u||w|) and non-zero; the unit normal is n = u x w / |u x w|.
+ * eps_pos / eps_neg: relative permittivity on the +n / -n side (only read for
+ * dielectric panels).  value: conductor potential (only read where needed). */
+typedef struct nebem_panels {
+    int64_t n;
+    const int32_t *kind;
+    const double *ox, *oy, *oz;
+    const double *ux, *uy, *uz;
+    const double *wx, *wy, *wz;
+    const int32_t *bc;
+    const double *value;
+    const double *eps_pos, *eps_neg;
+} nebem_panels;
+
+/* Copies of the base cell (host struct, passed by pointer, copied by the call).
+ * Translations t = i a1 + j a2, -n1 <= i <= n1, -n2 <= j <= n2 (Sec. 3 and
+ * Sec. 5.2: "virtual copies" of a base cell).  Optional reflection planes
+ * x_k = mirror_pos[k] for each axis bit k (1 = x, 2 = y, 4 = z) in
+ * mirror_mask; a copy reflected in a set of planes carries sigma times the
+ * product of their mirror_parity (+1/-1).  copy = t + M(panel).  Every copy
+ * enters both assembly and evaluation; known point charges are not copied.
+ * n1, n2 <= 64. */
+typedef struct nebem_images {
+    double a1[3], a2[3];
+    int32_t n1, n2;
+    int32_t mirror_mask;
+    double mirror_pos[3];
+    int32_t mirror_parity[3];
+} nebem_images;
+
+typedef enum nebem_precision {
+    NEBEM_FP64 = 0,  /* exact closed forms in FP64 everywhere; FP64 LU */
+    NEBEM_MIXED = 1  /* FP64 near field, FP32 far-field correction; FP32 LU + FP64 refinement */
+} nebem_precision;
+
+typedef struct nebem_options {
+    int32_t precision;     /* nebem_precision */
+    double near_factor;    /* mixed: exact FP64 if R < near_factor * D (default 4) */
+    double ir_tol;         /* mixed solve: stop at ||b - A x||_2 / ||b||_2 <= ir_tol (1e-10) */
+    int32_t ir_max_iter;   /* mixed solve: refinement steps (30) */
+    double sc_dt;          /* space charge: time step, s (1e-12) */
+    double sc_mobility;    /* space charge: |v| = mobility |E|, m^2/(V s) (1e-4) */
+    int32_t sc_resolve_every; /* space charge: re-solve sigma every k steps (10) */
+} nebem_options;
+
+typedef struct nebem_solve_info {
+    int32_t ir_iters;     /* refinement steps taken (0 in FP64 mode) */
+    double rel_resid;     /* ||b - A x||_2 / ||b||_2 of the returned x, FP64 (mixed mode; -1 if not computed) */
+} nebem_solve_info;
+
+/* Fills `opt` with the defaults listed above. */
+void nebem_default_options(nebem_options *opt);
+
+/* Influence matrix (Eq. Matrix; collocation at centroids, Sec. 2).  Row i is
+ * the collocation point c_i (cx/cy/cz, n entries each, or all three NULL for
+ * the panel centroids); column j the unit-density panel j with all its
+ * copies.  With k_e = 1/(4 pi eps0):
+ *   conductor row:  A_ij = k_e sum_copies Phi'_j(c_i)
+ *   dielectric row: A_ij = k_e sum_copies n_i . E'_j(c_i)
+ *                          + [i == j] (eps+ + eps-) / (2 eps0 (eps+ - eps-))
+ * where Phi', E' are the exact potential and field integrals of Sec. 2.1.
+ * Panel i's own (untranslated, unreflected) copy is evaluated with c_i taken
+ * exactly in its plane (principal value of the normal field = 0).
+ * A: n x n FP64, column-major, caller-allocated (8 n^2 bytes). */
+nebem_status nebem_assemble(const nebem_panels *panels, const nebem_images *images, const double *cx,
+                            const double *cy, const double *cz, const nebem_options *opt, double *A,
+                            hipStream_t stream);
+
+/* Solves A sigma = b for nrhs right-hand sides (Eq. Matrix; Algorithm 1's LU
+ * factorisation with row pivoting, without forming the inverse).
+ *  FP64 mode: A (n x n, column-major) is overwritten by its LU factors
+ *    (unit lower L below the diagonal, U on and above), ipiv[k] (int32, n
+ *    entries, 0-based) is the row swapped with row k at step k.
+ *  MIXED mode: A is left unchanged; the library factors an FP32 copy and
+ *    refines in FP64 until ||b - A x||_2 <= ir_tol ||b||_2 per column.
+ *    ipiv holds the FP32 factorisation's pivots.
+ * b, sigma: n x nrhs column-major (may alias).  `info` (host, may be NULL)
+ * receives iteration count and residual.  Synchronises `stream`.
+ * Returns NEBEM_ESINGULAR on an exactly zero pivot, NEBEM_ENOCONV if
+ * refinement stalls (sigma then holds the best iterate). */
+nebem_status nebem_solve(double *A, int64_t n, const double *b, int64_t nrhs, double *sigma, int32_t *ipiv,
+                         const nebem_options *opt, nebem_solve_info *info, hipStream_t stream);
+
+/* Re-solves with factors from a previous FP64-mode nebem_solve (the paper
+ * keeps the factorised matrix resident for new right-hand sides, Sec. 4.1). */
+nebem_status nebem_solve_factored(const double *LU, const int32_t *ipiv, int64_t n, const double *b,
+                                  int64_t nrhs, double *sigma, hipStream_t stream);
+
+/* Potential and field at m points (Eqs. Potential and Field; PFAtPoint,
+ * Sec. 4.1) from all panels and their copies:
+ *   phi(P) = k_e sum_j sigma_j sum_copies Phi'_j(P),  E likewise with E'.
+ * px/py/pz: m points; phi/ex/ey/ez: m outputs (any of the four may be NULL
+ * to skip storing it).  sigma: n densities (C/m^2). */
+nebem_status nebem_eval(const nebem_panels *panels, const nebem_images *images, const double *sigma,
+                        const double *px, const double *py, const double *pz, int64_t m, double *phi,
+                        double *ex, double *ey, double *ez, const nebem_options *opt, hipStream_t stream);
+
+/* ---------------------------------------------------------------- sessions
+ * A session keeps one geometry resident: derived panel data, its influence
+ * matrix factors, the boundary values and the current sigma (Sec. 4.1: the
+ * factorised matrix stays in device memory for new right-hand sides). */
+typedef struct nebem_session nebem_session;
+
+/* Copies the panel arrays it needs, assembles and factors A (precision per
+ * opt), solves for the panels' own boundary values (V on conductors, 0 on
+ * dielectric interfaces).  Synchronises `stream`. */
+nebem_status nebem_session_create(const nebem_panels *panels, const nebem_images *images,
+                                  const nebem_options *opt, hipStream_t stream, nebem_session **out);
+void nebem_session_destroy(nebem_session *s);
+int64_t nebem_session_n(const nebem_session *s);
+/* Device pointer to the session's current sigma (n entries, read-only). */
+const double *nebem_session_sigma(const nebem_session *s);
+/* phi/E at points with the session's current sigma (as nebem_eval). */
+nebem_status nebem_session_eval(nebem_session *s, const double *px, const double *py, const double *pz,
+                                int64_t m, double *phi, double *ex, double *ey, double *ez, hipStream_t stream);
+
+/* One step of the dynamic space-charge loop (Sec. 4.3, Algorithm 4; point
+ * charges, Sec. 4.2 and Algorithm 2), in place on nq charges:
+ *  1. if step_index % sc_resolve_every == 0: right-hand side b_i = V_i -
+ *     phi_q(c_i) on conductor rows, -n_i . E_q(c_i) on dielectric rows
+ *     (RHVector with known charges), then sigma = A^-1 b from the resident
+ *     factors;
+ *  2. E at every charge = panel part (all copies) + k_e sum_{j != i}
+ *     q_j (x_i - x_j)/|x_i - x_j|^3 (charges are not copied; coincident
+ *     charges are skipped);
+ *  3. x_i += sign(q_i) mobility E_i dt (all fields from start-of-step
+ *     positions).
+ * qx/qy/qz: positions (updated), q: charges (C).  ex/ey/ez (may be NULL):
+ * the field used for the move.  Charge-charge sums run in FP32 per pair with
+ * FP64 accumulation; the panel part runs in the session's precision. */
+nebem_status nebem_spacecharge_step(nebem_session *s, double *qx, double *qy, double *qz, const double *q,
+                                    int64_t nq, int32_t step_index, double *ex, double *ey, double *ez,
+                                    hipStream_t stream);
+
+/* Thread-local description of the last error (never NULL). */
+const char *nebem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NEBEM_H */

@@ -60,6 +60,8 @@ def _load():
     lib.oracle_panel_gauss.argtypes = [ctypes.c_int, P, P, P, P, P]
     lib.oracle_eval.argtypes = [i64, P, P, P, P, P, ctypes.POINTER(_Images), i64, P, P, ctypes.c_int]
     lib.oracle_assemble.argtypes = [i64, P, P, P, P, P, P, P, ctypes.POINTER(_Images), P, P, ctypes.c_int]
+    lib.oracle_assemble_rows.argtypes = [i64, P, P, P, P, P, P, P, ctypes.POINTER(_Images), P, i64, P, P,
+                                         ctypes.c_int]
     lib.oracle_coulomb.argtypes = [i64, P, P, i64, P, P, P, ctypes.c_int]
     lib.oracle_ke.restype = ctypes.c_double
     lib.oracle_eps0.restype = ctypes.c_double
@@ -149,6 +151,23 @@ def assemble(geom, colloc=None, nthreads: int = 0) -> np.ndarray:
     lib.oracle_assemble(n, _p(kind), _p(o), _p(u), _p(w), _p(bc), _p(ep), _p(en), ctypes.byref(im),
                         _p(c), _p(A), int(nthreads))
     return A.reshape((n, n), order="F")
+
+
+def assemble_rows(geom, rows, colloc=None, nthreads: int = 0) -> np.ndarray:
+    """Selected rows of the influence matrix, [len(rows), n]."""
+    lib = _load()
+    n = geom.n
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.zeros((rows.shape[0], n))
+    kind = np.ascontiguousarray(geom.kind, dtype=np.int32)
+    bc = np.ascontiguousarray(geom.bc, dtype=np.int32)
+    o, u, w = _f64(geom.o), _f64(geom.u), _f64(geom.w)
+    ep, en = _f64(geom.eps_pos), _f64(geom.eps_neg)
+    c = None if colloc is None else _f64(colloc, (-1, 3))
+    im = _images(geom.images)
+    lib.oracle_assemble_rows(n, _p(kind), _p(o), _p(u), _p(w), _p(bc), _p(ep), _p(en), ctypes.byref(im),
+                             _p(c), rows.shape[0], _p(rows), _p(out), int(nthreads))
+    return out
 
 
 def coulomb(targets, sources, q, self_index=None, nthreads: int = 0) -> np.ndarray:

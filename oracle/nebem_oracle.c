@@ -367,16 +367,19 @@ void oracle_eval(int64_t n, const int32_t *kind, const double *o, const double *
  *   eps+ (E_pv.n + sigma_i/2eps0) = eps- (E_pv.n - sigma_i/2eps0).
  * Collocation points: colloc (n x 3) or, if NULL, the panel centroids.  Row i
  * treats its own panel (identity copy) as lying exactly in its plane. */
-void oracle_assemble(int64_t n, const int32_t *kind, const double *o, const double *u, const double *w,
-                     const int32_t *bc, const double *eps_pos, const double *eps_neg, const oracle_images *im,
-                     const double *colloc, double *A, int nthreads)
+/* Rows `rows[0..nrows)` of the influence matrix, out[r][j] row-major
+ * (nrows x n).  Same definitions as oracle_assemble. */
+void oracle_assemble_rows(int64_t n, const int32_t *kind, const double *o, const double *u, const double *w,
+                          const int32_t *bc, const double *eps_pos, const double *eps_neg, const oracle_images *im,
+                          const double *colloc, int64_t nrows, const int64_t *rows, double *out, int nthreads)
 {
     gl_init();
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(static)
 #endif
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t rr = 0; rr < nrows; ++rr) {
+        const int64_t i = rows[rr];
         double ci[3], ni[3];
         double f = (kind[i] == 0) ? 0.5 : (1.0 / 3.0);
         for (int k = 0; k < 3; ++k)
@@ -394,9 +397,24 @@ void oracle_assemble(int64_t n, const int32_t *kind, const double *o, const doub
                 a = KE * (ni[0] * v[1] + ni[1] * v[2] + ni[2] * v[3]);
                 if (i == j) a += (eps_pos[i] + eps_neg[i]) / (2.0 * EPS0 * (eps_pos[i] - eps_neg[i]));
             }
-            A[i + j * n] = a;
+            out[rr * n + j] = a;
         }
     }
+}
+
+/* Whole influence matrix, column-major A[i + j*n]. */
+void oracle_assemble(int64_t n, const int32_t *kind, const double *o, const double *u, const double *w,
+                     const int32_t *bc, const double *eps_pos, const double *eps_neg, const oracle_images *im,
+                     const double *colloc, double *A, int nthreads)
+{
+    double *rowbuf = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n);
+    int64_t *rows = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) rows[i] = i;
+    oracle_assemble_rows(n, kind, o, u, w, bc, eps_pos, eps_neg, im, colloc, n, rows, rowbuf, nthreads);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) A[i + j * n] = rowbuf[i * n + j];
+    free(rowbuf);
+    free(rows);
 }
 
 /* ------------------------------------------------------- point charges */

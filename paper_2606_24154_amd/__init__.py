@@ -1,0 +1,222 @@
+"""Python binding of libnebem (the C-ABI declared in include/nebem.h).
+
+Argument marshalling only: torch tensors provide device memory and streams,
+every step of the computation runs in the library's HIP kernels.  The
+library must be built (``__graft_entry__.build()``); importing this package
+without it raises ImportError -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnebem.so")
+
+NEBEM_OK = 0
+NEBEM_EINVAL = -1
+NEBEM_ENOMEM = -2
+NEBEM_ESINGULAR = -3
+NEBEM_ENOCONV = -4
+NEBEM_EDEVICE = -5
+NEBEM_EBUSY = -6
+FP64 = 0
+MIXED = 1
+
+EXPORTED = (
+    "nebem_default_options", "nebem_assemble", "nebem_solve", "nebem_solve_factored", "nebem_eval",
+    "nebem_session_create", "nebem_session_destroy", "nebem_session_n", "nebem_session_sigma",
+    "nebem_session_eval", "nebem_spacecharge_step", "nebem_last_error",
+)
+
+
+class NebemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"nebem error {code}: {msg}")
+        self.code = code
+
+
+class Panels(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("kind", ctypes.c_void_p),
+                ("ox", ctypes.c_void_p), ("oy", ctypes.c_void_p), ("oz", ctypes.c_void_p),
+                ("ux", ctypes.c_void_p), ("uy", ctypes.c_void_p), ("uz", ctypes.c_void_p),
+                ("wx", ctypes.c_void_p), ("wy", ctypes.c_void_p), ("wz", ctypes.c_void_p),
+                ("bc", ctypes.c_void_p), ("value", ctypes.c_void_p),
+                ("eps_pos", ctypes.c_void_p), ("eps_neg", ctypes.c_void_p)]
+
+
+class ImagesC(ctypes.Structure):
+    _fields_ = [("a1", ctypes.c_double * 3), ("a2", ctypes.c_double * 3),
+                ("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("mirror_mask", ctypes.c_int32),
+                ("mirror_pos", ctypes.c_double * 3), ("mirror_parity", ctypes.c_int32 * 3)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("near_factor", ctypes.c_double),
+                ("ir_tol", ctypes.c_double), ("ir_max_iter", ctypes.c_int32),
+                ("sc_dt", ctypes.c_double), ("sc_mobility", ctypes.c_double),
+                ("sc_resolve_every", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("ir_iters", ctypes.c_int32), ("rel_resid", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    PP, PI, PO = ctypes.POINTER(Panels), ctypes.POINTER(ImagesC), ctypes.POINTER(Options)
+    lib.nebem_default_options.argtypes = [PO]
+    lib.nebem_default_options.restype = None
+    lib.nebem_last_error.restype = ctypes.c_char_p
+    lib.nebem_assemble.argtypes = [PP, PI, P, P, P, PO, P, P]
+    lib.nebem_solve.argtypes = [P, i64, P, i64, P, P, PO, ctypes.POINTER(SolveInfo), P]
+    lib.nebem_solve_factored.argtypes = [P, P, i64, P, i64, P, P]
+    lib.nebem_eval.argtypes = [PP, PI, P, P, P, P, i64, P, P, P, P, PO, P]
+    for name in ("nebem_assemble", "nebem_solve", "nebem_solve_factored", "nebem_eval"):
+        getattr(lib, name).restype = i32
+    if hasattr(lib, "nebem_session_create"):
+        lib.nebem_session_create.argtypes = [PP, PI, PO, P, ctypes.POINTER(P)]
+        lib.nebem_session_create.restype = i32
+        lib.nebem_session_destroy.argtypes = [P]
+        lib.nebem_session_destroy.restype = None
+        lib.nebem_session_n.argtypes = [P]
+        lib.nebem_session_n.restype = i64
+        lib.nebem_session_sigma.argtypes = [P]
+        lib.nebem_session_sigma.restype = P
+        lib.nebem_session_eval.argtypes = [P, P, P, P, i64, P, P, P, P, P]
+        lib.nebem_session_eval.restype = i32
+        lib.nebem_spacecharge_step.argtypes = [P, P, P, P, P, i64, i32, P, P, P, P]
+        lib.nebem_spacecharge_step.restype = i32
+    return lib
+
+
+lib = _load()
+
+
+def _check(code):
+    if code != NEBEM_OK:
+        raise NebemError(code, lib.nebem_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def options(precision=FP64, **kw) -> Options:
+    o = Options()
+    lib.nebem_default_options(ctypes.byref(o))
+    o.precision = precision
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def images_struct(img) -> ImagesC:
+    s = ImagesC()
+    if img is None:
+        return s
+    for k in range(3):
+        s.a1[k] = float(img.a1[k])
+        s.a2[k] = float(img.a2[k])
+        s.mirror_pos[k] = float(img.mirror_pos[k])
+        s.mirror_parity[k] = int(img.mirror_parity[k])
+    s.n1, s.n2, s.mirror_mask = int(img.n1), int(img.n2), int(img.mirror_mask)
+    return s
+
+
+@dataclass
+class DevicePanels:
+    """A geometry's panel arrays resident on the GPU, plus the C struct that
+    points at them."""
+    tensors: dict
+    n: int
+    images: object
+    struct: Panels
+
+    @classmethod
+    def from_geometry(cls, geom, device="cuda"):
+        import torch
+        soa = geom.soa()
+        t = {}
+        for k, v in soa.items():
+            dt = torch.int32 if v.dtype == np.int32 else torch.float64
+            t[k] = torch.from_numpy(np.ascontiguousarray(v)).to(device=device, dtype=dt)
+        s = Panels()
+        s.n = geom.n
+        for k in ("kind", "ox", "oy", "oz", "ux", "uy", "uz", "wx", "wy", "wz", "bc", "value",
+                  "eps_pos", "eps_neg"):
+            setattr(s, k, t[k].data_ptr())
+        return cls(t, geom.n, geom.images, s)
+
+
+def assemble(dp: DevicePanels, A=None, colloc=None, precision=FP64, stream=None, **opt):
+    """Influence matrix (n x n, column-major in a torch float64 tensor of
+    shape (n, n) whose storage is the transpose: A_t[j, i] = A[i, j])."""
+    import torch
+    n = dp.n
+    if A is None:
+        A = torch.empty((n, n), dtype=torch.float64, device=dp.tensors["ox"].device)
+    im = images_struct(dp.images)
+    o = options(precision, **opt)
+    cx = cy = cz = None
+    if colloc is not None:
+        cx, cy, cz = colloc
+    _check(lib.nebem_assemble(ctypes.byref(dp.struct), ctypes.byref(im), _ptr(cx), _ptr(cy), _ptr(cz),
+                              ctypes.byref(o), _ptr(A), _stream(stream)))
+    return A
+
+
+def solve(A, b, precision=FP64, stream=None, sigma=None, ipiv=None, **opt):
+    """sigma = A^-1 b.  A: (n, n) float64 tensor holding the column-major
+    matrix (as returned by `assemble`); FP64 mode overwrites it with the LU
+    factors.  b: (n,) or (nrhs, n) float64.  Returns (sigma, ipiv, info)."""
+    import torch
+    n = A.shape[0]
+    nrhs = 1 if b.dim() == 1 else b.shape[0]
+    if sigma is None:
+        sigma = torch.empty_like(b)
+    if ipiv is None:
+        ipiv = torch.empty(n, dtype=torch.int32, device=A.device)
+    info = SolveInfo()
+    o = options(precision, **opt)
+    _check(lib.nebem_solve(_ptr(A), n, _ptr(b), nrhs, _ptr(sigma), _ptr(ipiv), ctypes.byref(o),
+                           ctypes.byref(info), _stream(stream)))
+    return sigma, ipiv, info
+
+
+def solve_factored(LU, ipiv, b, stream=None, sigma=None):
+    import torch
+    n = LU.shape[0]
+    nrhs = 1 if b.dim() == 1 else b.shape[0]
+    if sigma is None:
+        sigma = torch.empty_like(b)
+    _check(lib.nebem_solve_factored(_ptr(LU), _ptr(ipiv), n, _ptr(b), nrhs, _ptr(sigma), _stream(stream)))
+    return sigma
+
+
+def eval_points(dp: DevicePanels, sigma, px, py, pz, precision=FP64, stream=None, out=None, **opt):
+    """(phi, ex, ey, ez) float64 tensors at the points."""
+    import torch
+    m = px.shape[0]
+    if out is None:
+        out = tuple(torch.empty(m, dtype=torch.float64, device=px.device) for _ in range(4))
+    im = images_struct(dp.images)
+    o = options(precision, **opt)
+    phi, ex, ey, ez = out
+    _check(lib.nebem_eval(ctypes.byref(dp.struct), ctypes.byref(im), _ptr(sigma), _ptr(px), _ptr(py),
+                          _ptr(pz), m, _ptr(phi), _ptr(ex), _ptr(ey), _ptr(ez), ctypes.byref(o),
+                          _stream(stream)))
+    return out

@@ -1,0 +1,311 @@
+// api.hip -- the C-ABI of libnebem (see include/nebem.h): argument checks,
+// stream-ordered temporaries, geometry preparation and the solve drivers.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lu_internal.hpp"
+#include "nebem_internal.hpp"
+
+namespace nebem {
+
+static thread_local std::string g_err = "no error";
+
+void set_error(const std::string &msg) { g_err = msg; }
+nebem_status fail(nebem_status code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+nebem_status hip_fail(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? NEBEM_ENOMEM : NEBEM_EDEVICE;
+}
+
+// Stream-ordered device buffer owned by one call.
+struct DevBuf {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf()
+    {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+    hipError_t alloc(size_t bytes, hipStream_t stream)
+    {
+        s = stream;
+        return hipMallocAsync(&p, bytes ? bytes : 8, stream);
+    }
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+nebem_status make_img_args(const nebem_images *im, ImgArgs *o)
+{
+    std::memset(o, 0, sizeof(*o));
+    if (!im) {
+        o->nref = 1;
+        o->parity[0] = 1.0;
+        return NEBEM_OK;
+    }
+    if (im->n1 < 0 || im->n2 < 0 || im->n1 > 64 || im->n2 > 64)
+        return fail(NEBEM_EINVAL, "images: n1, n2 must be in [0, 64]");
+    if (im->mirror_mask < 0 || im->mirror_mask > 7) return fail(NEBEM_EINVAL, "images: mirror_mask must be in [0, 7]");
+    for (int k = 0; k < 3; ++k) {
+        if (!std::isfinite(im->a1[k]) || !std::isfinite(im->a2[k]) || !std::isfinite(im->mirror_pos[k]))
+            return fail(NEBEM_EINVAL, "images: non-finite lattice vector or mirror position");
+        if ((im->mirror_mask >> k & 1) && im->mirror_parity[k] != 1 && im->mirror_parity[k] != -1)
+            return fail(NEBEM_EINVAL, "images: mirror_parity must be +1 or -1");
+    }
+    int active[3], na = 0;
+    for (int k = 0; k < 3; ++k)
+        if (im->mirror_mask >> k & 1) active[na++] = k;
+    o->nref = 1 << na;
+    o->n1 = im->n1;
+    o->n2 = im->n2;
+    for (int k = 0; k < 3; ++k) o->mpos[k] = im->mirror_pos[k];
+    for (int r = 0; r < o->nref; ++r) {
+        int axes = 0;
+        double par = 1.0;
+        for (int b = 0; b < na; ++b)
+            if (r >> b & 1) {
+                axes |= 1 << active[b];
+                par *= (double)im->mirror_parity[active[b]];
+            }
+        o->axes[r] = axes;
+        o->parity[r] = par;
+        for (int k = 0; k < 3; ++k) {
+            const double f = (axes >> k & 1) ? -1.0 : 1.0;
+            o->a1[r][k] = f * im->a1[k];
+            o->a2[r][k] = f * im->a2[k];
+        }
+    }
+    return NEBEM_OK;
+}
+
+static nebem_status check_panels(const nebem_panels *p)
+{
+    if (!p) return fail(NEBEM_EINVAL, "panels is NULL");
+    if (p->n < 0 || p->n > (int64_t)INT_MAX / 2) return fail(NEBEM_EINVAL, "panels: n out of range");
+    if (p->n == 0) return NEBEM_OK;
+    if (!p->kind || !p->ox || !p->oy || !p->oz || !p->ux || !p->uy || !p->uz || !p->wx || !p->wy || !p->wz ||
+        !p->bc || !p->eps_pos || !p->eps_neg)
+        return fail(NEBEM_EINVAL, "panels: NULL array");
+    return NEBEM_OK;
+}
+
+static const nebem_options &opts_or_default(const nebem_options *opt, nebem_options &tmp)
+{
+    if (opt) return *opt;
+    nebem_default_options(&tmp);
+    return tmp;
+}
+
+static nebem_status check_options(const nebem_options &o)
+{
+    if (o.precision != NEBEM_FP64 && o.precision != NEBEM_MIXED) return fail(NEBEM_EINVAL, "options: bad precision");
+    if (!(o.near_factor >= 1.0) || !std::isfinite(o.near_factor))
+        return fail(NEBEM_EINVAL, "options: near_factor must be >= 1");
+    if (!(o.ir_tol > 0.0) || o.ir_max_iter < 0) return fail(NEBEM_EINVAL, "options: bad refinement settings");
+    return NEBEM_OK;
+}
+
+// Derived element records for `p` in a stream-ordered buffer; validates the
+// elements (synchronises the stream to read the verdict).
+static nebem_status derive(const nebem_panels *p, hipStream_t s, DevBuf &drec)
+{
+    NEBEM_HIP(drec.alloc((size_t)p->n * R_STRIDE * sizeof(double), s));
+    DevBuf bad;
+    NEBEM_HIP(bad.alloc(2 * sizeof(int), s));
+    NEBEM_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+    NEBEM_HIP(hipMemsetAsync(bad.as<int>() + 1, 0x7f, sizeof(int), s));
+    launch_prep(p, drec.as<double>(), bad.as<int>(), s);
+    NEBEM_HIP(hipGetLastError());
+    int h[2] = {0, 0};
+    NEBEM_HIP(hipMemcpyAsync(h, bad.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    NEBEM_HIP(hipStreamSynchronize(s));
+    if (h[0] != 0) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf,
+                      "%d invalid panel(s), first at index %d (kind/bc out of range, zero or non-perpendicular "
+                      "edges, non-finite data, or bad dielectric permittivities)",
+                      h[0], h[1]);
+        return fail(NEBEM_EINVAL, buf);
+    }
+    return NEBEM_OK;
+}
+
+// host permutation from LAPACK-style sequential row swaps
+static void pivots_to_perm(const std::vector<int> &ipiv, std::vector<int> &perm)
+{
+    const int n = (int)ipiv.size();
+    perm.resize(n);
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    for (int k = 0; k < n; ++k) std::swap(perm[k], perm[ipiv[k]]);
+}
+
+}  // namespace nebem
+
+using namespace nebem;
+
+extern "C" {
+
+void nebem_default_options(nebem_options *o)
+{
+    if (!o) return;
+    o->precision = NEBEM_FP64;
+    o->near_factor = 4.0;
+    o->ir_tol = 1e-10;
+    o->ir_max_iter = 30;
+    o->sc_dt = 1e-12;
+    o->sc_mobility = 1e-4;
+    o->sc_resolve_every = 10;
+}
+
+const char *nebem_last_error(void) { return g_err.c_str(); }
+
+nebem_status nebem_eval(const nebem_panels *panels, const nebem_images *images, const double *sigma,
+                        const double *px, const double *py, const double *pz, int64_t m, double *phi, double *ex,
+                        double *ey, double *ez, const nebem_options *opt, hipStream_t stream)
+{
+    nebem_status st = check_panels(panels);
+    if (st) return st;
+    nebem_options tmp;
+    const nebem_options &o = opts_or_default(opt, tmp);
+    if ((st = check_options(o))) return st;
+    if (m < 0 || m > (int64_t)INT_MAX - 256) return fail(NEBEM_EINVAL, "eval: m out of range");
+    if (m == 0) return NEBEM_OK;
+    if (!px || !py || !pz) return fail(NEBEM_EINVAL, "eval: NULL point array");
+    if (panels->n > 0 && !sigma) return fail(NEBEM_EINVAL, "eval: NULL sigma");
+    ImgArgs ia;
+    if ((st = make_img_args(images, &ia))) return st;
+    if (o.precision != NEBEM_FP64) return fail(NEBEM_EINVAL, "eval: mixed precision is not available in this build");
+    DevBuf drec;
+    if ((st = derive(panels, stream, drec))) return st;
+    launch_eval_fp64(drec.as<double>(), sigma, panels->n, ia, px, py, pz, m, phi, ex, ey, ez, stream);
+    NEBEM_HIP(hipGetLastError());
+    return NEBEM_OK;
+}
+
+nebem_status nebem_assemble(const nebem_panels *panels, const nebem_images *images, const double *cx,
+                            const double *cy, const double *cz, const nebem_options *opt, double *A,
+                            hipStream_t stream)
+{
+    nebem_status st = check_panels(panels);
+    if (st) return st;
+    nebem_options tmp;
+    const nebem_options &o = opts_or_default(opt, tmp);
+    if ((st = check_options(o))) return st;
+    if (!A) return fail(NEBEM_EINVAL, "assemble: NULL matrix");
+    if ((cx == nullptr) != (cy == nullptr) || (cx == nullptr) != (cz == nullptr))
+        return fail(NEBEM_EINVAL, "assemble: collocation arrays must be all NULL or all set");
+    if (panels->n == 0) return NEBEM_OK;
+    ImgArgs ia;
+    if ((st = make_img_args(images, &ia))) return st;
+    if (o.precision != NEBEM_FP64)
+        return fail(NEBEM_EINVAL, "assemble: mixed precision is not available in this build");
+    DevBuf drec;
+    if ((st = derive(panels, stream, drec))) return st;
+    launch_assemble_fp64(drec.as<double>(), panels->n, ia, cx, cy, cz, A, stream);
+    NEBEM_HIP(hipGetLastError());
+    return NEBEM_OK;
+}
+
+nebem_status nebem_solve(double *A, int64_t n, const double *b, int64_t nrhs, double *sigma, int32_t *ipiv,
+                         const nebem_options *opt, nebem_solve_info *info, hipStream_t stream)
+{
+    nebem_options tmp;
+    const nebem_options &o = opts_or_default(opt, tmp);
+    nebem_status st;
+    if ((st = check_options(o))) return st;
+    if (n < 0 || n > 65536 * 4) return fail(NEBEM_EINVAL, "solve: n out of range");
+    if (nrhs < 0 || nrhs > 4096) return fail(NEBEM_EINVAL, "solve: nrhs out of range");
+    if (info) {
+        info->ir_iters = 0;
+        info->rel_resid = -1.0;
+    }
+    if (n == 0 || nrhs == 0) return NEBEM_OK;
+    if (!A || !b || !sigma || !ipiv) return fail(NEBEM_EINVAL, "solve: NULL argument");
+    if (o.precision != NEBEM_FP64)
+        return fail(NEBEM_EINVAL, "solve: mixed precision is not available in this build");
+    const int nn = (int)n;
+    const int nblk = (nn + 255) / 256;
+    DevBuf pval, ws;
+    NEBEM_HIP(pval.alloc((size_t)nblk * sizeof(double), stream));
+    NEBEM_HIP(ws.alloc((size_t)(nblk + 2) * sizeof(int), stream));
+    LUWork w;
+    w.pval = pval.p;
+    w.pidx = ws.as<int>();
+    w.counter = ws.as<int>() + nblk;
+    w.info = ws.as<int>() + nblk + 1;
+    NEBEM_HIP(hipMemsetAsync(w.counter, 0, sizeof(int), stream));
+    NEBEM_HIP(hipMemcpyAsync(w.info, &nn, sizeof(int), hipMemcpyHostToDevice, stream));
+    lu_factor(A, nn, ipiv, w, stream);
+    NEBEM_HIP(hipGetLastError());
+    int hinfo = nn;
+    std::vector<int> hpiv(nn), perm;
+    NEBEM_HIP(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, stream));
+    NEBEM_HIP(hipMemcpyAsync(hpiv.data(), ipiv, (size_t)nn * sizeof(int), hipMemcpyDeviceToHost, stream));
+    NEBEM_HIP(hipStreamSynchronize(stream));
+    if (hinfo < nn) {
+        char buf[96];
+        std::snprintf(buf, sizeof buf, "solve: zero pivot in column %d", hinfo);
+        return fail(NEBEM_ESINGULAR, buf);
+    }
+    pivots_to_perm(hpiv, perm);
+    DevBuf dperm, work, xtmp;
+    NEBEM_HIP(dperm.alloc((size_t)nn * sizeof(int), stream));
+    NEBEM_HIP(hipMemcpyAsync(dperm.p, perm.data(), (size_t)nn * sizeof(int), hipMemcpyHostToDevice, stream));
+    NEBEM_HIP(work.alloc((size_t)nn * nrhs * sizeof(double), stream));
+    double *x = sigma;
+    if (sigma == b) {  // aliasing: permute out of b into a temporary first
+        NEBEM_HIP(xtmp.alloc((size_t)nn * nrhs * sizeof(double), stream));
+        x = xtmp.as<double>();
+    }
+    lu_solve(A, nn, dperm.as<int>(), b, x, work.as<double>(), (int)nrhs, stream);
+    NEBEM_HIP(hipGetLastError());
+    if (x != sigma)
+        NEBEM_HIP(hipMemcpyAsync(sigma, x, (size_t)nn * nrhs * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    NEBEM_HIP(hipStreamSynchronize(stream));  // host vectors above must outlive the copies
+    return NEBEM_OK;
+}
+
+nebem_status nebem_solve_factored(const double *LU, const int32_t *ipiv, int64_t n, const double *b, int64_t nrhs,
+                                  double *sigma, hipStream_t stream)
+{
+    if (n < 0 || n > 65536 * 4 || nrhs < 0 || nrhs > 4096) return fail(NEBEM_EINVAL, "solve_factored: bad sizes");
+    if (n == 0 || nrhs == 0) return NEBEM_OK;
+    if (!LU || !ipiv || !b || !sigma) return fail(NEBEM_EINVAL, "solve_factored: NULL argument");
+    const int nn = (int)n;
+    std::vector<int> hpiv(nn), perm;
+    NEBEM_HIP(hipMemcpyAsync(hpiv.data(), ipiv, (size_t)nn * sizeof(int), hipMemcpyDeviceToHost, stream));
+    NEBEM_HIP(hipStreamSynchronize(stream));
+    for (int k = 0; k < nn; ++k)
+        if (hpiv[k] < k || hpiv[k] >= nn) return fail(NEBEM_EINVAL, "solve_factored: ipiv is not a valid pivot list");
+    pivots_to_perm(hpiv, perm);
+    DevBuf dperm, work, xtmp;
+    NEBEM_HIP(dperm.alloc((size_t)nn * sizeof(int), stream));
+    NEBEM_HIP(hipMemcpyAsync(dperm.p, perm.data(), (size_t)nn * sizeof(int), hipMemcpyHostToDevice, stream));
+    NEBEM_HIP(work.alloc((size_t)nn * nrhs * sizeof(double), stream));
+    double *x = sigma;
+    if (sigma == b) {
+        NEBEM_HIP(xtmp.alloc((size_t)nn * nrhs * sizeof(double), stream));
+        x = xtmp.as<double>();
+    }
+    lu_solve(LU, nn, dperm.as<int>(), b, x, work.as<double>(), (int)nrhs, stream);
+    NEBEM_HIP(hipGetLastError());
+    if (x != sigma)
+        NEBEM_HIP(hipMemcpyAsync(sigma, x, (size_t)nn * nrhs * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    NEBEM_HIP(hipStreamSynchronize(stream));
+    return NEBEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,313 @@
+// field_kernels.hip -- element preparation, field evaluation and influence
+// matrix assembly on gfx950.
+//
+// Work decomposition (both field kernels): one lane owns one observation
+// point (an evaluation point, or a collocation row of the matrix) and keeps
+// its sums in FP64 registers; a workgroup of 256 lanes (4 wave64) streams the
+// derived element records through LDS in tiles, and every lane of the
+// workgroup walks the same element of the tile at the same time, so element
+// data are wave-uniform: they are read from LDS once per wave and moved to
+// scalar registers.  The element kind (rectangle / right triangle) is
+// therefore a uniform branch, and the copy loops (lattice translations and
+// reflections) are uniform loops.  Each point sums elements in index order
+// and copies in lattice order, independent of which other points share its
+// wave: results are deterministic and do not depend on the batch a point
+// arrives in.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "nebem_internal.hpp"
+#include "panel_fp64.hpp"
+
+namespace nebem {
+
+constexpr int kBlock = 256;
+constexpr int kTileE = 64;   // elements per LDS tile, evaluation
+constexpr int kTileA = 32;   // elements (columns) per workgroup, assembly
+
+// wave-uniform copy of a value held identically by all lanes -> SGPRs
+__device__ __forceinline__ double uni(double v)
+{
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    hi = __builtin_amdgcn_readfirstlane(hi);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ------------------------------------------------------------------- prep
+__global__ __launch_bounds__(kBlock) void k_prep(nebem_panels p, double *__restrict__ drec, int *__restrict__ bad)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= p.n) return;
+    const int kind = p.kind[i];
+    const int bc = p.bc[i];
+    const double ox = p.ox[i], oy = p.oy[i], oz = p.oz[i];
+    const double ux = p.ux[i], uy = p.uy[i], uz = p.uz[i];
+    const double wx = p.wx[i], wy = p.wy[i], wz = p.wz[i];
+    const double lu = sqrt(ux * ux + uy * uy + uz * uz);
+    const double lw = sqrt(wx * wx + wy * wy + wz * wz);
+    const double uw = ux * wx + uy * wy + uz * wz;
+    bool ok = (kind == 0 || kind == 1) && (bc == 0 || bc == 1) && lu > 0.0 && lw > 0.0 &&
+              isfinite(lu) && isfinite(lw) && isfinite(ox) && isfinite(oy) && isfinite(oz) &&
+              fabs(uw) <= 1e-9 * lu * lw;
+    double jump = 0.0;
+    if (bc == 1) {
+        const double ep = p.eps_pos[i], en = p.eps_neg[i];
+        ok = ok && ep > 0.0 && en > 0.0 && ep != en && isfinite(ep) && isfinite(en);
+        jump = (ep + en) / (2.0 * kEps0 * (ep - en));
+    }
+    if (!ok) {
+        atomicAdd(&bad[0], 1);
+        atomicMin(&bad[1], (int)i);
+        return;
+    }
+    const double e1x = ux / lu, e1y = uy / lu, e1z = uz / lu;
+    const double c = wx * e1x + wy * e1y + wz * e1z;
+    double vx = wx - c * e1x, vy = wy - c * e1y, vz = wz - c * e1z;
+    const double lz = sqrt(vx * vx + vy * vy + vz * vz);
+    vx /= lz;
+    vy /= lz;
+    vz /= lz;
+    const double e3x = e1y * vz - e1z * vy, e3y = e1z * vx - e1x * vz, e3z = e1x * vy - e1y * vx;
+    const double lx = lu;
+    const double hyp = sqrt(lx * lx + lz * lz);
+    const double f = kind == 0 ? 0.5 : (1.0 / 3.0);
+    double *r = drec + i * R_STRIDE;
+    r[R_OX] = ox;
+    r[R_OY] = oy;
+    r[R_OZ] = oz;
+    r[R_E1X] = e1x;
+    r[R_E1Y] = e1y;
+    r[R_E1Z] = e1z;
+    r[R_E2X] = vx;
+    r[R_E2Y] = vy;
+    r[R_E2Z] = vz;
+    r[R_E3X] = e3x;
+    r[R_E3Y] = e3y;
+    r[R_E3Z] = e3z;
+    r[R_LX] = lx;
+    r[R_LZ] = lz;
+    r[R_HYP] = hyp;
+    r[R_IHYP] = 1.0 / hyp;
+    r[R_CX] = ox + f * (ux + wx);
+    r[R_CY] = oy + f * (uy + wy);
+    r[R_CZ] = oz + f * (uz + wz);
+    r[R_DIAM] = hyp;
+    r[R_AREA] = kind == 0 ? lx * lz : 0.5 * lx * lz;
+    r[R_KIND] = (double)kind;
+    r[R_JUMP] = jump;
+    r[R_BC] = (double)bc;
+}
+
+void launch_prep(const nebem_panels *p, double *drec, int *bad, hipStream_t s)
+{
+    if (p->n <= 0) return;
+    const unsigned g = (unsigned)((p->n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_prep, dim3(g), dim3(kBlock), 0, s, *p, drec, bad);
+}
+
+// ------------------------------------------------------------- one element
+// Uniform element data, loaded from an LDS record.
+struct Elem {
+    double ox, oy, oz, e1x, e1y, e1z, e2x, e2y, e2z, e3x, e3y, e3z;
+    double lx, lz, hyp, ihyp;
+    int kind;
+};
+
+__device__ __forceinline__ Elem load_elem(const double *d)
+{
+    Elem e;
+    e.ox = uni(d[R_OX]);
+    e.oy = uni(d[R_OY]);
+    e.oz = uni(d[R_OZ]);
+    e.e1x = uni(d[R_E1X]);
+    e.e1y = uni(d[R_E1Y]);
+    e.e1z = uni(d[R_E1Z]);
+    e.e2x = uni(d[R_E2X]);
+    e.e2y = uni(d[R_E2Y]);
+    e.e2z = uni(d[R_E2Z]);
+    e.e3x = uni(d[R_E3X]);
+    e.e3y = uni(d[R_E3Y]);
+    e.e3z = uni(d[R_E3Z]);
+    e.lx = uni(d[R_LX]);
+    e.lz = uni(d[R_LZ]);
+    e.hyp = uni(d[R_HYP]);
+    e.ihyp = uni(d[R_IHYP]);
+    e.kind = uni((int)d[R_KIND]);
+    return e;
+}
+
+// Sum over lattice translations of one element, local frame; (X0,Z0,H0) is
+// the (reflected) point in the element frame for the zero translation, and
+// (aX,aZ,aH), (bX,bZ,bH) the lattice vectors in that frame.  `self` zeroes H
+// for the zero translation (collocation point on its own element).
+template <int KIND>
+__device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, double X0, double Z0, double H0,
+                                                 double aX, double aZ, double aH, double bX, double bZ,
+                                                 double bH, bool self, double &sp, double &sx, double &sz,
+                                                 double &sn)
+{
+#pragma unroll 1
+    for (int i1 = -n1; i1 <= n1; ++i1) {
+        const double f1 = -(double)i1;
+        const double X1 = fma(f1, aX, X0), Z1 = fma(f1, aZ, Z0), H1 = fma(f1, aH, H0);
+#pragma unroll 1
+        for (int i2 = -n2; i2 <= n2; ++i2) {
+            const double f2 = -(double)i2;
+            const double X = fma(f2, bX, X1), Z = fma(f2, bZ, Z1);
+            double H = fma(f2, bH, H1);
+            H = (self && i1 == 0 && i2 == 0) ? 0.0 : H;
+            Kern k;
+            if (KIND == 0)
+                k = rect_fp64(X, H, Z, e.lx, e.lz);
+            else
+                k = rtri_fp64(X, H, Z, e.lx, e.lz, e.hyp, e.ihyp);
+            sp += k.phi;
+            sx += k.ex;
+            sz += k.ez;
+            sn += k.en;
+        }
+    }
+}
+
+// phi', E' (global frame) of one element with all its copies at P.
+__device__ __forceinline__ void element_copies_fp64(const Elem &e, const ImgArgs &img, double Px, double Py,
+                                                    double Pz, bool self, double &ophi, double &oex,
+                                                    double &oey, double &oez)
+{
+    ophi = oex = oey = oez = 0.0;
+    for (int r = 0; r < img.nref; ++r) {
+        const int ax = img.axes[r];
+        const double Qx = (ax & 1) ? 2.0 * img.mpos[0] - Px : Px;
+        const double Qy = (ax & 2) ? 2.0 * img.mpos[1] - Py : Py;
+        const double Qz = (ax & 4) ? 2.0 * img.mpos[2] - Pz : Pz;
+        const double rx = Qx - e.ox, ry = Qy - e.oy, rz = Qz - e.oz;
+        const double X0 = rx * e.e1x + ry * e.e1y + rz * e.e1z;
+        const double Z0 = rx * e.e2x + ry * e.e2y + rz * e.e2z;
+        const double H0 = rx * e.e3x + ry * e.e3y + rz * e.e3z;
+        const double *a = img.a1[r], *b = img.a2[r];
+        const double aX = a[0] * e.e1x + a[1] * e.e1y + a[2] * e.e1z;
+        const double aZ = a[0] * e.e2x + a[1] * e.e2y + a[2] * e.e2z;
+        const double aH = a[0] * e.e3x + a[1] * e.e3y + a[2] * e.e3z;
+        const double bX = b[0] * e.e1x + b[1] * e.e1y + b[2] * e.e1z;
+        const double bZ = b[0] * e.e2x + b[1] * e.e2y + b[2] * e.e2z;
+        const double bH = b[0] * e.e3x + b[1] * e.e3y + b[2] * e.e3z;
+        double sp = 0.0, sx = 0.0, sz = 0.0, sn = 0.0;
+        const bool s = self && r == 0;
+        if (e.kind == 0)
+            sum_translations<0>(e, img.n1, img.n2, X0, Z0, H0, aX, aZ, aH, bX, bZ, bH, s, sp, sx, sz, sn);
+        else
+            sum_translations<1>(e, img.n1, img.n2, X0, Z0, H0, aX, aZ, aH, bX, bZ, bH, s, sp, sx, sz, sn);
+        double gx = sx * e.e1x + sz * e.e2x + sn * e.e3x;
+        double gy = sx * e.e1y + sz * e.e2y + sn * e.e3y;
+        double gz = sx * e.e1z + sz * e.e2z + sn * e.e3z;
+        gx = (ax & 1) ? -gx : gx;
+        gy = (ax & 2) ? -gy : gy;
+        gz = (ax & 4) ? -gz : gz;
+        const double par = img.parity[r];
+        ophi += par * sp;
+        oex += par * gx;
+        oey += par * gy;
+        oez += par * gz;
+    }
+}
+
+// -------------------------------------------------------------- evaluation
+__global__ __launch_bounds__(kBlock) void k_eval_fp64(const double *__restrict__ drec,
+                                                       const double *__restrict__ sigma, int n, ImgArgs img,
+                                                       const double *__restrict__ px,
+                                                       const double *__restrict__ py,
+                                                       const double *__restrict__ pz, int m,
+                                                       double *__restrict__ phi, double *__restrict__ ex,
+                                                       double *__restrict__ ey, double *__restrict__ ez)
+{
+    __shared__ double t_rec[kTileE * R_STRIDE];
+    __shared__ double t_sig[kTileE];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const bool act = i < m;
+    const double Px = act ? px[i] : 0.0;
+    const double Py = act ? py[i] : 0.0;
+    const double Pz = act ? pz[i] : 0.0;
+    double aphi = 0.0, aex = 0.0, aey = 0.0, aez = 0.0;
+    for (int base = 0; base < n; base += kTileE) {
+        const int cnt = min(kTileE, n - base);
+        __syncthreads();
+        for (int k = threadIdx.x; k < cnt * R_STRIDE; k += kBlock)
+            t_rec[k] = drec[(size_t)base * R_STRIDE + k];
+        if (threadIdx.x < cnt) t_sig[threadIdx.x] = sigma[base + threadIdx.x];
+        __syncthreads();
+        for (int p = 0; p < cnt; ++p) {
+            const Elem e = load_elem(t_rec + p * R_STRIDE);
+            double cp, cx, cy, cz;
+            element_copies_fp64(e, img, Px, Py, Pz, false, cp, cx, cy, cz);
+            const double sg = uni(t_sig[p]);
+            aphi = fma(sg, cp, aphi);
+            aex = fma(sg, cx, aex);
+            aey = fma(sg, cy, aey);
+            aez = fma(sg, cz, aez);
+        }
+    }
+    if (act) {
+        if (phi) phi[i] = kKe * aphi;
+        if (ex) ex[i] = kKe * aex;
+        if (ey) ey[i] = kKe * aey;
+        if (ez) ez[i] = kKe * aez;
+    }
+}
+
+void launch_eval_fp64(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, const double *px,
+                      const double *py, const double *pz, int64_t m, double *phi, double *ex, double *ey,
+                      double *ez, hipStream_t s)
+{
+    if (m <= 0) return;
+    const unsigned g = (unsigned)((m + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_eval_fp64, dim3(g), dim3(kBlock), 0, s, drec, sigma, (int)n, img, px, py, pz, (int)m,
+                       phi, ex, ey, ez);
+}
+
+// ---------------------------------------------------------------- assembly
+// Grid: x over blocks of 256 rows, y over blocks of kTileA columns.  Each
+// lane writes A[i + j n] for its row i and the block's columns j: the 256
+// lanes of a workgroup store 256 consecutive doubles of a column (2 KB).
+__global__ __launch_bounds__(kBlock) void k_assemble_fp64(const double *__restrict__ drec, int n, ImgArgs img,
+                                                           const double *__restrict__ cx,
+                                                           const double *__restrict__ cy,
+                                                           const double *__restrict__ cz,
+                                                           double *__restrict__ A)
+{
+    __shared__ double t_rec[kTileA * R_STRIDE];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int j0 = blockIdx.y * kTileA;
+    const int cnt = min(kTileA, n - j0);
+    for (int k = threadIdx.x; k < cnt * R_STRIDE; k += kBlock) t_rec[k] = drec[(size_t)j0 * R_STRIDE + k];
+    __syncthreads();
+    if (i >= n) return;
+    const double *ri = drec + (size_t)i * R_STRIDE;
+    const double Px = cx ? cx[i] : ri[R_CX];
+    const double Py = cy ? cy[i] : ri[R_CY];
+    const double Pz = cz ? cz[i] : ri[R_CZ];
+    const bool diel = ri[R_BC] != 0.0;
+    const double nx = ri[R_E3X], ny = ri[R_E3Y], nz = ri[R_E3Z];
+    const double jump = ri[R_JUMP];
+    for (int p = 0; p < cnt; ++p) {
+        const int j = j0 + p;
+        const Elem e = load_elem(t_rec + p * R_STRIDE);
+        double cp, gx, gy, gz;
+        element_copies_fp64(e, img, Px, Py, Pz, i == j, cp, gx, gy, gz);
+        double a = diel ? kKe * (nx * gx + ny * gy + nz * gz) : kKe * cp;
+        a += (diel && i == j) ? jump : 0.0;
+        A[(size_t)j * n + i] = a;
+    }
+}
+
+void launch_assemble_fp64(const double *drec, int64_t n, const ImgArgs &img, const double *cx, const double *cy,
+                          const double *cz, double *A, hipStream_t s)
+{
+    if (n <= 0) return;
+    const dim3 g((unsigned)((n + kBlock - 1) / kBlock), (unsigned)((n + kTileA - 1) / kTileA));
+    hipLaunchKernelGGL(k_assemble_fp64, g, dim3(kBlock), 0, s, drec, (int)n, img, cx, cy, cz, A);
+}
+
+}  // namespace nebem

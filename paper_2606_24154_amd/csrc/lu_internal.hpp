@@ -1,0 +1,29 @@
+// lu_internal.hpp -- dense LU factorisation / solve launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace nebem {
+
+constexpr int kNB = 64;  // LU panel width
+
+// Device scratch of one factorisation: per-workgroup pivot candidates
+// (ceil(n/256) entries), a completion counter (must start at 0; every panel
+// launch leaves it at 0) and `info` (must start at n; receives the first
+// column with a zero pivot).
+struct LUWork {
+    void *pval;
+    int *pidx;
+    int *counter;
+    int *info;
+};
+
+void lu_factor(double *A, int n, int *ipiv, LUWork &w, hipStream_t s);
+void lu_factor(float *A, int n, int *ipiv, LUWork &w, hipStream_t s);
+// X = A^-1 B with the row permutation perm (X[i] = (P B)[i] = B[perm[i]]);
+// W is an n x nrhs workspace of the solve's type.
+void lu_solve(const double *LU, int n, const int *perm, const double *B, double *X, double *W, int nrhs,
+              hipStream_t s);
+void lu_solve(const float *LU, int n, const int *perm, const double *B, float *X, float *W, int nrhs,
+              hipStream_t s);
+
+}  // namespace nebem

@@ -1,0 +1,73 @@
+// nebem_internal.hpp -- declarations shared by the library's translation
+// units (host launchers, device record layout, error plumbing).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "nebem.h"
+
+namespace nebem {
+
+constexpr double kEps0 = 8.8541878128e-12;  // vacuum permittivity, F/m
+constexpr double kKe = 1.0 / (4.0 * 3.14159265358979323846 * kEps0);
+
+// Derived element record in HBM, 24 doubles (192 B) per element, built once
+// per geometry by the prep kernel and streamed through LDS by the field
+// kernels.
+enum DRec : int {
+    R_OX = 0, R_OY, R_OZ,      // corner o
+    R_E1X, R_E1Y, R_E1Z,       // unit vector along u
+    R_E2X, R_E2Y, R_E2Z,       // unit vector along w
+    R_E3X, R_E3Y, R_E3Z,       // unit normal e1 x e2
+    R_LX, R_LZ,                // |u|, |w|
+    R_HYP, R_IHYP,             // hypotenuse sqrt(lx^2+lz^2) and its inverse
+    R_CX, R_CY, R_CZ,          // centroid
+    R_DIAM,                    // diameter (rect diagonal / triangle hypotenuse)
+    R_AREA,                    // area
+    R_KIND,                    // 0 rectangle, 1 right triangle (as double)
+    R_JUMP,                    // dielectric diagonal term (eps+ + eps-)/(2 eps0 (eps+ - eps-)), else 0
+    R_BC,                      // 0 conductor, 1 dielectric (as double)
+    R_STRIDE = 24
+};
+
+// Copies of the base cell prepared for kernels: for each of up to 8
+// reflection combinations, the reflected lattice vectors M(a1), M(a2), the
+// reflected axis mask and the sign carried by sigma.
+struct ImgArgs {
+    double a1[8][3];
+    double a2[8][3];
+    double mpos[3];
+    double parity[8];
+    int axes[8];
+    int nref;
+    int n1, n2;
+};
+
+// thread-local error text
+void set_error(const std::string &msg);
+nebem_status fail(nebem_status code, const std::string &msg);
+nebem_status hip_fail(hipError_t e, const char *what);
+
+#define NEBEM_HIP(call)                                             \
+    do {                                                            \
+        hipError_t _e = (call);                                     \
+        if (_e != hipSuccess) return ::nebem::hip_fail(_e, #call);  \
+    } while (0)
+
+nebem_status make_img_args(const nebem_images *im, ImgArgs *out);
+
+// ---- field kernels (field_kernels.hip)
+// Builds derived records; writes bad_count[0] = number of invalid elements,
+// bad_count[1] = first invalid index (or n).  bad_count must be zeroed/set
+// to {0, n} by the caller.
+void launch_prep(const nebem_panels *p, double *drec, int *bad, hipStream_t s);
+void launch_eval_fp64(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, const double *px,
+                      const double *py, const double *pz, int64_t m, double *phi, double *ex, double *ey,
+                      double *ez, hipStream_t s);
+// A (n x n col-major).  cx/cy/cz may be null (centroids).
+void launch_assemble_fp64(const double *drec, int64_t n, const ImgArgs &img, const double *cx, const double *cy,
+                          const double *cz, double *A, hipStream_t s);
+
+}  // namespace nebem

@@ -1,0 +1,142 @@
+// panel_fp64.hpp -- exact potential/field integrals of one uniformly charged
+// rectangle or right triangle, FP64, for gfx950 device code.
+//
+// Paper Sec. 2.1: the potential of a unit-density flat element is
+//   Phi'(P) = integral over the element of dA / |P - s|
+// and its field E'(P) = integral of (P - s)/|P - s|^3 dA; neBEM evaluates both
+// in closed form for rectangles and right-angled triangles.
+//
+// Local frame of an element: e1 along its first edge u (length lx), e2 along
+// its second edge w (length lz), e3 = e1 x e2.  The observation point is
+// (X, Z, H) = ((P-o).e1, (P-o).e2, (P-o).e3).  Vertices are counter-clockwise
+// about e3: rectangle (0,0) (lx,0) (lx,lz) (0,lz); right triangle (0,0)
+// (lx,0) (0,lz).
+//
+// Closed form used here (sum over edges k with outward in-plane normal m_k,
+// signed in-plane distance p_k from the projected point to the edge line):
+//   Phi' = sum_k p_k Lam_k - H Omega
+//   E'   = sum_k m_k Lam_k + Omega e3
+// with Omega the signed solid angle the element subtends (positive for H > 0)
+// and Lam_k = ln((R_b + R_a + L_k)/(R_b + R_a - L_k)) for an edge of length
+// L_k between vertices at distances R_a, R_b from P, formed as
+// log1p(2 L / (R_a + R_b - L)) -- accurate far from the element, where the
+// argument is small -- with R_a + R_b - L assembled from two non-negative
+// parts so that it stays accurate near the edge's line as well.  The solid
+// angle of a triangle is the Van Oosterom-Strackee formula (IEEE Trans. Biomed. Eng. 30(2):125-126, 1983),
+//   tan(Omega/2) = [R1 R2 R3] / (r1 r2 r3 + (R1.R2) r3 + (R1.R3) r2 + (R2.R3) r1)
+// with R_i = P - V_i; for a planar triangle the triple product is exactly
+// H * (2 * area), so no cancellation arises far away.  A rectangle is two such
+// triangles sharing the diagonal; their half-angles are added through one
+// atan2 of the product (D1 + iN)(D2 + iN).
+//
+// On the element plane (H == 0) the normal field is given its principal value
+// 0 (the mean of the one-sided limits +-2 pi); Phi' is continuous there.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace nebem {
+
+struct Kern {
+    double phi;  // Phi'
+    double ex;   // E' along e1
+    double ez;   // E' along e2
+    double en;   // E' along e3 (= Omega)
+};
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ln((s + L)/(s - L)), s = R_a + R_b, for an edge of length L whose start
+// and end points lie at along-edge coordinates lm and lp = lm + L (relative
+// to the foot of the perpendicular from P to the edge's line) and distances
+// Rm, Rp from P; rho2 is the squared distance from P to that line.  s - L is
+// formed as (Rp - lp) + (Rm + lm), each term without cancellation
+// (R - l = rho2 / (R + l) when l > 0, R + l = rho2 / (R - l) when l < 0),
+// which keeps full accuracy for points close to the edge's line.
+__device__ __forceinline__ double edge_log(double lm, double lp, double Rm, double Rp, double rho2, double L)
+{
+    const bool pp = lp > 0.0, mn = lm < 0.0;
+    const double np = pp ? rho2 : Rp - lp;
+    const double dp = pp ? Rp + lp : 1.0;
+    const double nm = mn ? rho2 : Rm + lm;
+    const double dm = mn ? Rm - lm : 1.0;
+    return log1p((L + L) * dp * dm / (np * dm + nm * dp));
+}
+
+// Solid-angle branch repair: the true half-angle has the sign of N and
+// magnitude <= pi; atan2 of the product can land on the other side of the
+// branch cut when it is near +-pi.
+__device__ __forceinline__ double half_angle_fix(double half, double N)
+{
+    half = (N > 0.0 && half < -0.5 * kPi) ? half + 2.0 * kPi : half;
+    half = (N < 0.0 && half > 0.5 * kPi) ? half - 2.0 * kPi : half;
+    return half;
+}
+
+__device__ __forceinline__ Kern rect_fp64(double X, double H, double Z, double lx, double lz)
+{
+    const double H2 = H * H;
+    const double xm = X - lx, zm = Z - lz;
+    const double X2 = X * X, Z2 = Z * Z, xm2 = xm * xm, zm2 = zm * zm;
+    const double r00 = sqrt(X2 + Z2 + H2);
+    const double r10 = sqrt(xm2 + Z2 + H2);
+    const double r11 = sqrt(xm2 + zm2 + H2);
+    const double r01 = sqrt(X2 + zm2 + H2);
+    // edges (start -> end, outward normal m, distance p of the projected point
+    // from the edge line, inside positive):
+    //   0 (0,0)->(lx,0)   m=(0,-1) p=Z     1 (lx,0)->(lx,lz) m=(1,0) p=lx-X
+    //   2 (lx,lz)->(0,lz) m=(0,1)  p=lz-Z  3 (0,lz)->(0,0)   m=(-1,0) p=X
+    const double L0 = edge_log(-X, -xm, r00, r10, Z2 + H2, lx);
+    const double L1 = edge_log(-Z, -zm, r10, r11, xm2 + H2, lz);
+    const double L2 = edge_log(xm, X, r11, r01, zm2 + H2, lx);
+    const double L3 = edge_log(zm, Z, r01, r00, X2 + H2, lz);
+    // triangles (c00,c10,c11) and (c00,c11,c01), both with [R1 R2 R3] = H lx lz
+    const double N = H * lx * lz;
+    const double d00_10 = X * xm + Z2 + H2;
+    const double d00_11 = X * xm + Z * zm + H2;
+    const double d10_11 = xm2 + Z * zm + H2;
+    const double d00_01 = X2 + Z * zm + H2;
+    const double d11_01 = X * xm + zm2 + H2;
+    const double D1 = r00 * r10 * r11 + d00_10 * r11 + d00_11 * r10 + d10_11 * r00;
+    const double D2 = r00 * r11 * r01 + d00_11 * r01 + d00_01 * r11 + d11_01 * r00;
+    double half = atan2(N * (D1 + D2), D1 * D2 - N * N);
+    half = half_angle_fix(half, N);
+    const double omega = (H == 0.0) ? 0.0 : 2.0 * half;
+    Kern k;
+    k.phi = Z * L0 + (lx - X) * L1 + (lz - Z) * L2 + X * L3 - H * omega;
+    k.ex = L1 - L3;
+    k.ez = L2 - L0;
+    k.en = omega;
+    return k;
+}
+
+__device__ __forceinline__ Kern rtri_fp64(double X, double H, double Z, double lx, double lz, double hyp,
+                                          double ihyp)
+{
+    const double H2 = H * H;
+    const double xm = X - lx, zm = Z - lz;
+    const double X2 = X * X, Z2 = Z * Z;
+    const double r0 = sqrt(X2 + Z2 + H2);
+    const double r1 = sqrt(xm * xm + Z2 + H2);
+    const double r2 = sqrt(X2 + zm * zm + H2);
+    // edges: 0 (0,0)->(lx,0) m=(0,-1) p=Z;  1 (lx,0)->(0,lz) m=(lz,lx)/hyp
+    //        p=(lx lz - X lz - Z lx)/hyp;   2 (0,lz)->(0,0) m=(-1,0) p=X
+    const double P1 = (lx * lz - X * lz - Z * lx) * ihyp;
+    const double L0 = edge_log(-X, -xm, r0, r1, Z2 + H2, lx);
+    const double L1 = edge_log((lx * xm - lz * Z) * ihyp, (lx * X - lz * zm) * ihyp, r1, r2, P1 * P1 + H2, hyp);
+    const double L2 = edge_log(zm, Z, r2, r0, X2 + H2, lz);
+    const double N = H * lx * lz;
+    const double d01 = X * xm + Z2 + H2;
+    const double d02 = X2 + Z * zm + H2;
+    const double d12 = X * xm + Z * zm + H2;
+    const double D = r0 * r1 * r2 + d01 * r2 + d02 * r1 + d12 * r0;
+    const double omega = (H == 0.0) ? 0.0 : 2.0 * atan2(N, D);
+    const double L1h = L1 * ihyp;
+    Kern k;
+    k.phi = Z * L0 + P1 * L1 + X * L2 - H * omega;
+    k.ex = lz * L1h - L2;
+    k.ez = lx * L1h - L0;
+    k.en = omega;
+    return k;
+}
+
+}  // namespace nebem

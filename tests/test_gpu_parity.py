@@ -1,0 +1,312 @@
+"""Parity of the HIP path (through the C-ABI) against the CPU oracle.
+
+FP64 bar (stated in the path's requirements): 1e-10 relative on phi and E,
+pointwise, on points where |phi_ref| >= 1e-3 max|phi_ref| (|E_ref| likewise);
+single-element kernels are held to the same bound at every distance.
+Matrices: entry-wise relative to the row's largest entry.  Solves: residual
+and forward error bounded by the condition number.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import GeometryBuilder, Images, gem_cell, parallel_plates, uniform_points
+from synth.geometry import CONDUCTOR, DIELECTRIC
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def nb():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    import paper_2606_24154_amd as nb
+    return nb
+
+
+DEV = "cuda:0"
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype=dtype)
+
+
+def gpu_eval(nb, geom, sigma, pts, **kw):
+    dp = nb.DevicePanels.from_geometry(geom, DEV)
+    out = nb.eval_points(dp, dev(sigma), dev(pts[:, 0]), dev(pts[:, 1]), dev(pts[:, 2]), **kw)
+    torch.cuda.synchronize()
+    return np.column_stack([t.cpu().numpy() for t in out])
+
+
+def rel_errors(got, ref, floor=1e-3):
+    """max pointwise relative error of phi and |E| on non-negligible points"""
+    ap = np.abs(ref[:, 0])
+    sel = ap >= floor * ap.max()
+    ephi = np.max(np.abs(got[sel, 0] - ref[sel, 0]) / ap[sel])
+    en = np.linalg.norm(ref[:, 1:], axis=1)
+    sel = en >= floor * en.max()
+    eE = np.max(np.linalg.norm(got[sel, 1:] - ref[sel, 1:], axis=1) / en[sel])
+    return ephi, eE
+
+
+def _rot(rng):
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    return q * np.sign(np.diag(r))
+
+
+# ------------------------------------------------------------ single panels
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_single_panel_all_distances(nb, kind):
+    """Unit-density element vs the oracle at distances 1e-3 D .. 1e3 D,
+    including points just above/below the plane inside and outside it."""
+    rng = np.random.default_rng(40 + kind)
+    worst = [0.0, 0.0]
+    for trial in range(6):
+        Q = _rot(rng)
+        lx, lz = rng.uniform(2e-6, 40e-6, 2)
+        o = rng.uniform(-1e-3, 1e-3, 3)
+        u, w = lx * Q[:, 0], lz * Q[:, 1]
+        b = GeometryBuilder()
+        (b.rect if kind == 0 else b.right_tri)(o, u, w)
+        g = b.build("one", Images(), o - 1, o + 1)
+        D = math.hypot(lx, lz)
+        c = o + (0.5 if kind == 0 else 1 / 3) * (u + w)
+        m = 3000
+        d = rng.standard_normal((m, 3))
+        d /= np.linalg.norm(d, axis=1)[:, None]
+        R = D * 10 ** rng.uniform(-3, 3, m)
+        pts = c + R[:, None] * d
+        # near-plane points over and beside the element
+        k = m // 5
+        s, t = rng.uniform(-0.3, 1.3, (2, k))
+        n = np.cross(u, w) / np.linalg.norm(np.cross(u, w))
+        h = D * 10 ** rng.uniform(-6, -1, k) * rng.choice([-1, 1], k)
+        pts[:k] = o + s[:, None] * u + t[:, None] * w + h[:, None] * n
+        sigma = np.array([1.0])
+        got = gpu_eval(nb, g, sigma, pts)
+        ref = oracle.eval_points(g, sigma, pts)
+        ephi = np.abs(got[:, 0] - ref[:, 0]) / np.abs(ref[:, 0])
+        eE = np.linalg.norm(got[:, 1:] - ref[:, 1:], axis=1) / np.linalg.norm(ref[:, 1:], axis=1)
+        worst = [max(worst[0], ephi.max()), max(worst[1], eE.max())]
+    assert worst[0] < 1e-10 and worst[1] < 1e-10, worst
+
+
+# -------------------------------------------------------- parallel plates
+
+@pytest.fixture(scope="module")
+def plates_ref():
+    g = parallel_plates()
+    A = oracle.assemble(g)
+    s = oracle.solve(A, g.rhs())
+    pts = uniform_points(g.box_lo, g.box_hi, 4096, 0)
+    f = oracle.eval_points(g, s, pts)
+    return g, A, s, pts, f
+
+
+def test_plates_assembly(nb, plates_ref):
+    g, A_ref, _, _, _ = plates_ref
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    At = nb.assemble(dp)
+    torch.cuda.synchronize()
+    A = At.cpu().numpy().T
+    err = np.abs(A - A_ref) / np.abs(A_ref).max(axis=1, keepdims=True)
+    assert err.max() < 1e-12, err.max()
+
+
+def test_plates_solve_and_eval(nb, plates_ref):
+    g, A_ref, s_ref, pts, f_ref = plates_ref
+    At = dev(np.ascontiguousarray(A_ref.T))  # column-major storage
+    b = dev(g.rhs())
+    sigma, ipiv, info = nb.solve(At, b)
+    torch.cuda.synchronize()
+    s = sigma.cpu().numpy()
+    kappa = np.linalg.cond(A_ref, 1)
+    assert np.abs(s - s_ref).max() <= 50 * kappa * 2.2e-16 * np.abs(s_ref).max()
+    got = gpu_eval(nb, g, s_ref, pts)
+    ephi, eE = rel_errors(got, f_ref)
+    assert ephi < 1e-10 and eE < 1e-10, (ephi, eE)
+
+
+def test_plates_end_to_end(nb, plates_ref):
+    """assemble -> solve -> eval entirely on the GPU vs the oracle pipeline."""
+    g, _, s_ref, pts, f_ref = plates_ref
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    At = nb.assemble(dp)
+    sigma, _, _ = nb.solve(At, dev(g.rhs()))
+    out = nb.eval_points(dp, sigma, dev(pts[:, 0]), dev(pts[:, 1]), dev(pts[:, 2]))
+    torch.cuda.synchronize()
+    got = np.column_stack([t.cpu().numpy() for t in out])
+    ephi, eE = rel_errors(got, f_ref)
+    assert ephi < 1e-10 and eE < 1e-10, (ephi, eE)
+
+
+# ---------------------------------------------------- copies and mirrors
+
+def _mixed_geometry(rng, n=24, bc_mix=True):
+    b = GeometryBuilder()
+    for i in range(n):
+        Q = _rot(rng)
+        o = rng.uniform(-0.4e-3, 0.4e-3, 3)
+        lx, lz = rng.uniform(10e-6, 60e-6, 2)
+        kw = dict(bc=CONDUCTOR, value=float(rng.uniform(-100, 100)))
+        if bc_mix and i % 3 == 2:
+            kw = dict(bc=DIELECTRIC, eps_pos=1.0, eps_neg=float(rng.uniform(2, 5)))
+        (b.rect if i % 2 else b.right_tri)(o, lx * Q[:, 0], lz * Q[:, 1], **kw)
+    return b.build("mixed", Images(), (-1e-3,) * 3, (1e-3,) * 3)
+
+
+def test_lattice_and_mirror_copies(nb):
+    rng = np.random.default_rng(50)
+    g = _mixed_geometry(rng)
+    sigma = rng.uniform(-1e-6, 1e-6, g.n)
+    pts = uniform_points((-0.6e-3,) * 3, (0.6e-3,) * 3, 777, 51)
+    for im in (Images(a1=np.array([1e-3, 0, 0]), a2=np.array([0.3e-3, 0.9e-3, 0.0]), n1=3, n2=2),
+               Images(mirror_mask=5, mirror_pos=np.array([0.7e-3, 0, -0.6e-3]),
+                      mirror_parity=np.array([-1, 1, 1], dtype=np.int32)),
+               Images(a1=np.array([1.1e-3, 0, 0]), a2=np.array([0, 1.2e-3, 0]), n1=2, n2=1, mirror_mask=4,
+                      mirror_pos=np.array([0, 0, -0.8e-3]), mirror_parity=np.array([1, 1, -1], dtype=np.int32))):
+        gi = g.with_images(im)
+        got = gpu_eval(nb, gi, sigma, pts)
+        ref = oracle.eval_points(gi, sigma, pts)
+        ephi, eE = rel_errors(got, ref)
+        assert ephi < 1e-10 and eE < 1e-10, (im, ephi, eE)
+
+
+def test_assembly_with_dielectric_rows_and_copies(nb):
+    rng = np.random.default_rng(52)
+    g = _mixed_geometry(rng, n=40).with_images(
+        Images(a1=np.array([1e-3, 0, 0]), a2=np.array([0.5e-3, 0.85e-3, 0]), n1=2, n2=2))
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    A = nb.assemble(dp).cpu().numpy().T
+    A_ref = oracle.assemble(g)
+    err = np.abs(A - A_ref) / np.abs(A_ref).max(axis=1, keepdims=True)
+    assert err.max() < 1e-11, err.max()
+
+
+# ------------------------------------------------------------ GEM geometry
+
+@pytest.fixture(scope="module")
+def gem():
+    return gem_cell()
+
+
+def test_gem_assembly_sampled_rows(nb, gem):
+    """Full 8064 x 8064 assembly with 121 copies on the GPU; 12 sampled rows
+    (conductor and dielectric) against the oracle."""
+    g = gem
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    At = nb.assemble(dp)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(53)
+    rows = np.concatenate([rng.choice(np.where(g.bc == 0)[0], 6, replace=False),
+                           rng.choice(np.where(g.bc == 1)[0], 6, replace=False), [0, g.n - 1]])
+    ref = oracle.assemble_rows(g, rows)
+    got = At[:, torch.from_numpy(rows).to(DEV)].cpu().numpy().T
+    err = np.abs(got - ref) / np.abs(ref).max(axis=1, keepdims=True)
+    assert err.max() < 1e-11, err.max()
+    # backward error of the GPU solve on the GPU-assembled matrix
+    A64 = At.cpu().numpy().T.copy()
+    b = dev(g.rhs())
+    sigma, _, _ = nb.solve(At, b)
+    s = sigma.cpu().numpy()
+    r = A64 @ s - g.rhs()
+    assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(A64, 1) * np.linalg.norm(s)
+
+
+def test_gem_eval_sampled_points(nb, gem):
+    g = gem
+    rng = np.random.default_rng(54)
+    sigma = rng.normal(0, 1e-5, g.n)
+    from synth import gem_eval_points
+    pts = gem_eval_points(g, 2000, seed=1)
+    got = gpu_eval(nb, g, sigma, pts)
+    idx = rng.choice(len(pts), 48, replace=False)
+    ref = oracle.eval_points(g, sigma, pts[idx])
+    ephi, eE = rel_errors(got[idx], ref)
+    assert ephi < 1e-10 and eE < 1e-10, (ephi, eE)
+
+
+# ------------------------------------------------------------------- solve
+
+@pytest.mark.parametrize("n", [1, 5, 63, 64, 65, 130, 257, 777])
+def test_lu_random(nb, n):
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, n)) + np.eye(n) * 0.5
+    B = rng.standard_normal((3, n))
+    At = dev(np.ascontiguousarray(A.T))
+    X, ipiv, info = nb.solve(At, dev(B))
+    torch.cuda.synchronize()
+    X = X.cpu().numpy()
+    ref = np.linalg.solve(A, B.T).T
+    kappa = np.linalg.cond(A, 1)
+    assert np.abs(X - ref).max() <= 100 * kappa * 2.2e-16 * max(1.0, np.abs(ref).max())
+    # factors reproduce P A = L U
+    LU = At.cpu().numpy().T
+    L = np.tril(LU, -1) + np.eye(n)
+    U = np.triu(LU)
+    piv = ipiv.cpu().numpy()
+    PA = A.copy()
+    for k in range(n):
+        PA[[k, piv[k]]] = PA[[piv[k], k]]
+    assert np.abs(L @ U - PA).max() <= 1e-13 * n * np.abs(A).max()
+    # partial pivoting: every multiplier bounded by 1
+    assert np.abs(np.tril(LU, -1)).max() <= 1.0
+    # re-solve from the resident factors
+    X2 = nb.solve_factored(At, ipiv, dev(B)).cpu().numpy()
+    assert np.array_equal(X2, X)
+
+
+def test_lu_singular(nb):
+    n = 70
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((n, n))
+    A[:, 40] = A[:, 3]  # rank deficient
+    A[:, 40] -= A[:, 3]
+    At = dev(np.ascontiguousarray(A.T))
+    with pytest.raises(nb.NebemError) as e:
+        nb.solve(At, dev(np.ones(n)))
+    assert e.value.code == nb.NEBEM_ESINGULAR
+
+
+# ------------------------------------------------------- edges and errors
+
+def test_invalid_panel_rejected(nb):
+    b = GeometryBuilder()
+    b.rect((0, 0, 0), (1e-5, 0, 0), (0, 1e-5, 0))
+    g = b.build("bad", Images(), (-1,) * 3, (1,) * 3)
+    g.w[0] = [1e-6, 1e-5, 0]  # not perpendicular to u
+    with pytest.raises(nb.NebemError) as e:
+        gpu_eval(nb, g, np.ones(1), np.zeros((3, 3)))
+    assert e.value.code == nb.NEBEM_EINVAL
+
+
+def test_empty_and_ragged(nb):
+    g = parallel_plates(n=3)
+    rng = np.random.default_rng(4)
+    sigma = rng.normal(size=g.n)
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    e = torch.empty(0, dtype=torch.float64, device=DEV)
+    out = nb.eval_points(dp, dev(sigma), e, e, e)
+    assert all(t.numel() == 0 for t in out)
+    for m in (1, 255, 257, 1000):
+        pts = uniform_points(g.box_lo, g.box_hi, m, m)
+        got = gpu_eval(nb, g, sigma, pts)
+        ref = oracle.eval_points(g, sigma, pts)
+        ephi, eE = rel_errors(got, ref)
+        assert ephi < 1e-10 and eE < 1e-10
+
+
+def test_deterministic_and_batch_independent(nb):
+    g = gem_cell().subset(np.arange(0, 8064, 7)).with_images(Images())
+    rng = np.random.default_rng(5)
+    sigma = rng.normal(size=g.n)
+    pts = uniform_points((0, 0, 1e-4), (1.4e-4, 1.2e-4, 1e-3), 3000, 6)
+    a = gpu_eval(nb, g, sigma, pts)
+    b = gpu_eval(nb, g, sigma, pts)
+    assert np.array_equal(a, b)
+    c = gpu_eval(nb, g, sigma, pts[1234:1500])
+    assert np.array_equal(c, a[1234:1500])
