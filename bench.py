@@ -47,6 +47,7 @@ def parse():
     p.add_argument("--points", type=int, default=1_000_000)
     p.add_argument("--cpu-sample", type=int, default=192, help="points in the oracle's timed sample")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     return p.parse_args()
@@ -108,13 +109,17 @@ def main():
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     stage = {"assemble": [], "solve": [], "eval": []}
 
+    prec = nb.MIXED if args.precision == "mixed" else nb.FP64
+    info = {}
+
     def step():
         ev[0].record(stream)
-        nb.assemble(dp, A=A)
+        nb.assemble(dp, A=A, precision=prec)
         ev[1].record(stream)
-        nb.solve(A, b, sigma=sigma, ipiv=ipiv)
+        _, _, si = nb.solve(A, b, sigma=sigma, ipiv=ipiv, precision=prec)
+        info["ir_iters"], info["rel_resid"] = si.ir_iters, si.rel_resid
         ev[2].record(stream)
-        nb.eval_points(dp, sigma, px, py, pz, out=out)
+        nb.eval_points(dp, sigma, px, py, pz, out=out, precision=prec)
         ev[3].record(stream)
 
     for _ in range(args.warmup):
@@ -137,7 +142,7 @@ def main():
     eval_rate = inter_eval / (ms["eval"] * 1e-3)
 
     roof = None
-    if FLOPS_PER_INTERACTION is not None:
+    if FLOPS_PER_INTERACTION is not None and prec == nb.FP64:
         ach = FLOPS_PER_INTERACTION * inter_eval / (ms["eval"] * 1e-3)
         roof = {"bound": "alu", "kernel": "k_eval_fp64", "achieved": ach / 1e12, "peak": FP64_VALU_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK,
@@ -154,11 +159,11 @@ def main():
         "metric": "elem-point interactions/s (FP64 vs mixed @1e-6 rel); p50/p99 serve latency",
         "value": value, "unit": "interactions/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if prec == nb.FP64 else "f64+f32", "data": "synthetic",
         "config": {"workload": f"gem_cell: N={n} elements, C={C} copies, M={M} points; "
-                               "assemble + LU solve + evaluate, FP64",
+                               f"assemble + LU solve + evaluate, {args.precision}",
                    "elements": n, "copies": C, "points": M},
-        "stages_ms": ms, "eval_interactions_per_s": eval_rate,
+        "stages_ms": ms, "eval_interactions_per_s": eval_rate, "solve_info": info,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

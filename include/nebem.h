@@ -27,8 +27,9 @@
  *  - Return value 0 = NEBEM_OK, negative = error; nebem_last_error() gives a
  *    thread-local message.  Validation errors return before any kernel
  *    launch that writes caller memory.  No C++ exception crosses this ABI.
- *  - The library keeps no hidden state between calls except inside
- *    nebem_session objects and a per-device cache of its own kernels' scratch.
+ *  - The library keeps no state between calls except inside nebem_session
+ *    objects.  Stateless calls allocate their temporaries stream-ordered
+ *    (hipMallocAsync / hipFreeAsync on `stream`).
  */
 #ifndef NEBEM_H
 #define NEBEM_H
@@ -162,15 +163,22 @@ nebem_status nebem_eval(const nebem_panels *panels, const nebem_images *images, 
  * factorised matrix stays in device memory for new right-hand sides). */
 typedef struct nebem_session nebem_session;
 
-/* Copies the panel arrays it needs, assembles and factors A (precision per
- * opt), solves for the panels' own boundary values (V on conductors, 0 on
- * dielectric interfaces).  Synchronises `stream`. */
+/* Builds the derived element records, assembles and factors A (precision
+ * per opt), solves for the panels' own boundary values (V on conductors, 0 on
+ * dielectric interfaces).  The panel arrays are not referenced after the
+ * call.  Synchronises `stream`.  Returns NEBEM_ENOCONV together with a usable
+ * session if the mixed-precision refinement of that first solve stalled. */
 nebem_status nebem_session_create(const nebem_panels *panels, const nebem_images *images,
                                   const nebem_options *opt, hipStream_t stream, nebem_session **out);
 void nebem_session_destroy(nebem_session *s);
 int64_t nebem_session_n(const nebem_session *s);
 /* Device pointer to the session's current sigma (n entries, read-only). */
 const double *nebem_session_sigma(const nebem_session *s);
+/* Replaces the session's sigma by A^-1 b for a new right-hand side b (n
+ * entries), e.g. a weighting-field set-up: unit potential on one readout,
+ * zero elsewhere (Sec. 2.1).  `info` (host, may be NULL) as in nebem_solve.
+ * Synchronises `stream`. */
+nebem_status nebem_session_solve(nebem_session *s, const double *b, nebem_solve_info *info, hipStream_t stream);
 /* phi/E at points with the session's current sigma (as nebem_eval). */
 nebem_status nebem_session_eval(nebem_session *s, const double *px, const double *py, const double *pz,
                                 int64_t m, double *phi, double *ex, double *ey, double *ez, hipStream_t stream);
@@ -192,6 +200,53 @@ nebem_status nebem_session_eval(nebem_session *s, const double *px, const double
 nebem_status nebem_spacecharge_step(nebem_session *s, double *qx, double *qy, double *qz, const double *q,
                                     int64_t nq, int32_t step_index, double *ex, double *ey, double *ez,
                                     hipStream_t stream);
+
+/* ----------------------------------------------------------------- serving
+ * Continuous-batching evaluation service over resident sessions.  Clients
+ * submit batches of points (host arrays) naming one of the server's
+ * sessions; a worker thread admits requests in arrival order while their
+ * staging (56 bytes per point) fits the device budget, cuts the admitted
+ * requests into 256-point work items, and evaluates work items of several
+ * requests and geometries in each kernel launch (round-robin, up to
+ * batch_interactions element-copy x point pairs per launch).  Requests that
+ * arrive while others are on the GPU join at the next launch.  A point's
+ * result is bit-identical to nebem_session_eval on the same session,
+ * whatever else shares its launch. */
+typedef struct nebem_server nebem_server;
+typedef struct nebem_server_options {
+    int64_t hbm_budget;         /* bytes of device staging for admitted requests (256 MiB) */
+    double batch_interactions;  /* work per launch, interactions (4e10) */
+    int32_t max_items;          /* work items per launch (16384) */
+} nebem_server_options;
+typedef struct nebem_request_stats {
+    double t_submit, t_admit, t_done; /* host steady-clock seconds */
+    int64_t points;
+} nebem_request_stats;
+typedef struct nebem_server_counters {
+    int64_t launches, points_done;
+    double interactions; /* evaluated so far */
+    double busy_s;       /* worker time spent in launches */
+    int64_t queued, active;
+} nebem_server_counters;
+
+void nebem_server_default_options(nebem_server_options *opt);
+/* All sessions must share precision and near_factor and live on the current
+ * device; they must outlive the server.  Starts the worker thread. */
+nebem_status nebem_server_create(nebem_session *const *sessions, int32_t nsessions, const nebem_server_options *opt,
+                                 nebem_server **out);
+/* Queues m points (HOST arrays px/py/pz, read until the request completes)
+ * on session `geometry`; results go to the HOST arrays phi/ex/ey/ez (any may
+ * be NULL).  Returns a ticket.  NEBEM_EBUSY if the request alone exceeds the
+ * budget or the server is shutting down. */
+nebem_status nebem_server_submit(nebem_server *s, int32_t geometry, const double *px, const double *py,
+                                 const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
+                                 int64_t *ticket);
+/* Blocks until the ticket's request has completed and its results are in the
+ * host arrays; fills `stats` (may be NULL).  Each ticket is waited once. */
+nebem_status nebem_server_wait(nebem_server *s, int64_t ticket, nebem_request_stats *stats);
+nebem_status nebem_server_stats(nebem_server *s, nebem_server_counters *out);
+/* Finishes every submitted request, stops the worker and frees the server. */
+void nebem_server_destroy(nebem_server *s);
 
 /* Thread-local description of the last error (never NULL). */
 const char *nebem_last_error(void);

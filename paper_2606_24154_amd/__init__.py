@@ -29,7 +29,9 @@ MIXED = 1
 EXPORTED = (
     "nebem_default_options", "nebem_assemble", "nebem_solve", "nebem_solve_factored", "nebem_eval",
     "nebem_session_create", "nebem_session_destroy", "nebem_session_n", "nebem_session_sigma",
-    "nebem_session_eval", "nebem_spacecharge_step", "nebem_last_error",
+    "nebem_session_solve", "nebem_session_eval", "nebem_spacecharge_step", "nebem_last_error",
+    "nebem_server_default_options", "nebem_server_create", "nebem_server_submit", "nebem_server_wait",
+    "nebem_server_stats", "nebem_server_destroy",
 )
 
 
@@ -65,6 +67,22 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("ir_iters", ctypes.c_int32), ("rel_resid", ctypes.c_double)]
 
 
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("batch_interactions", ctypes.c_double),
+                ("max_items", ctypes.c_int32)]
+
+
+class RequestStats(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("points", ctypes.c_int64)]
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("points_done", ctypes.c_int64),
+                ("interactions", ctypes.c_double), ("busy_s", ctypes.c_double),
+                ("queued", ctypes.c_int64), ("active", ctypes.c_int64)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
@@ -80,19 +98,32 @@ def _load():
     lib.nebem_eval.argtypes = [PP, PI, P, P, P, P, i64, P, P, P, P, PO, P]
     for name in ("nebem_assemble", "nebem_solve", "nebem_solve_factored", "nebem_eval"):
         getattr(lib, name).restype = i32
-    if hasattr(lib, "nebem_session_create"):
-        lib.nebem_session_create.argtypes = [PP, PI, PO, P, ctypes.POINTER(P)]
-        lib.nebem_session_create.restype = i32
-        lib.nebem_session_destroy.argtypes = [P]
-        lib.nebem_session_destroy.restype = None
-        lib.nebem_session_n.argtypes = [P]
-        lib.nebem_session_n.restype = i64
-        lib.nebem_session_sigma.argtypes = [P]
-        lib.nebem_session_sigma.restype = P
-        lib.nebem_session_eval.argtypes = [P, P, P, P, i64, P, P, P, P, P]
-        lib.nebem_session_eval.restype = i32
-        lib.nebem_spacecharge_step.argtypes = [P, P, P, P, P, i64, i32, P, P, P, P]
-        lib.nebem_spacecharge_step.restype = i32
+    lib.nebem_session_create.argtypes = [PP, PI, PO, P, ctypes.POINTER(P)]
+    lib.nebem_session_create.restype = i32
+    lib.nebem_session_destroy.argtypes = [P]
+    lib.nebem_session_destroy.restype = None
+    lib.nebem_session_n.argtypes = [P]
+    lib.nebem_session_n.restype = i64
+    lib.nebem_session_sigma.argtypes = [P]
+    lib.nebem_session_sigma.restype = P
+    lib.nebem_session_solve.argtypes = [P, P, ctypes.POINTER(SolveInfo), P]
+    lib.nebem_session_solve.restype = i32
+    lib.nebem_session_eval.argtypes = [P, P, P, P, i64, P, P, P, P, P]
+    lib.nebem_session_eval.restype = i32
+    lib.nebem_spacecharge_step.argtypes = [P, P, P, P, P, i64, i32, P, P, P, P]
+    lib.nebem_spacecharge_step.restype = i32
+    lib.nebem_server_default_options.argtypes = [ctypes.POINTER(ServerOptions)]
+    lib.nebem_server_default_options.restype = None
+    lib.nebem_server_create.argtypes = [ctypes.POINTER(P), i32, ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]
+    lib.nebem_server_create.restype = i32
+    lib.nebem_server_submit.argtypes = [P, i32, P, P, P, i64, P, P, P, P, ctypes.POINTER(i64)]
+    lib.nebem_server_submit.restype = i32
+    lib.nebem_server_wait.argtypes = [P, i64, ctypes.POINTER(RequestStats)]
+    lib.nebem_server_wait.restype = i32
+    lib.nebem_server_stats.argtypes = [P, ctypes.POINTER(ServerCounters)]
+    lib.nebem_server_stats.restype = i32
+    lib.nebem_server_destroy.argtypes = [P]
+    lib.nebem_server_destroy.restype = None
     return lib
 
 
@@ -220,3 +251,140 @@ def eval_points(dp: DevicePanels, sigma, px, py, pz, precision=FP64, stream=None
                           _ptr(pz), m, _ptr(phi), _ptr(ex), _ptr(ey), _ptr(ez), ctypes.byref(o),
                           _stream(stream)))
     return out
+
+
+class Session:
+    """A geometry kept resident on the GPU: element records, factored
+    influence matrix and the current surface charge densities."""
+
+    def __init__(self, dp: DevicePanels, precision=FP64, stream=None, **opt):
+        self.dp = dp
+        self.n = dp.n
+        self.options = options(precision, **opt)
+        self.precision = precision
+        im = images_struct(dp.images)
+        h = ctypes.c_void_p()
+        code = lib.nebem_session_create(ctypes.byref(dp.struct), ctypes.byref(im), ctypes.byref(self.options),
+                                        _stream(stream), ctypes.byref(h))
+        if code not in (NEBEM_OK, NEBEM_ENOCONV):
+            _check(code)
+        self.handle = h
+        self.create_status = code
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.nebem_session_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sigma(self):
+        """Copy of the current sigma (float64 device tensor)."""
+        import torch
+        view = _DeviceArray(lib.nebem_session_sigma(self.handle), self.n)
+        torch.cuda.synchronize()
+        return torch.as_tensor(view, device=self.dp.tensors["ox"].device).clone()
+
+    def solve(self, b, stream=None):
+        info = SolveInfo()
+        code = lib.nebem_session_solve(self.handle, _ptr(b), ctypes.byref(info), _stream(stream))
+        if code not in (NEBEM_OK, NEBEM_ENOCONV):
+            _check(code)
+        return code, info
+
+    def eval_points(self, px, py, pz, stream=None, out=None):
+        import torch
+        m = px.shape[0]
+        if out is None:
+            out = tuple(torch.empty(m, dtype=torch.float64, device=px.device) for _ in range(4))
+        phi, ex, ey, ez = out
+        _check(lib.nebem_session_eval(self.handle, _ptr(px), _ptr(py), _ptr(pz), m, _ptr(phi), _ptr(ex),
+                                      _ptr(ey), _ptr(ez), _stream(stream)))
+        return out
+
+    def spacecharge_step(self, qx, qy, qz, q, step_index, E=None, stream=None):
+        """One explicit step of the dynamic space-charge loop, in place on
+        (qx, qy, qz); returns the status (OK or ENOCONV)."""
+        nq = qx.shape[0]
+        ex = ey = ez = None
+        if E is not None:
+            ex, ey, ez = E
+        code = lib.nebem_spacecharge_step(self.handle, _ptr(qx), _ptr(qy), _ptr(qz), _ptr(q), nq,
+                                          int(step_index), _ptr(ex), _ptr(ey), _ptr(ez), _stream(stream))
+        if code not in (NEBEM_OK, NEBEM_ENOCONV):
+            _check(code)
+        return code
+
+
+class _DeviceArray:
+    """float64 device array at a raw address (array-interface view, used
+    only to copy the data out)."""
+
+    def __init__(self, ptr, n):
+        self.__cuda_array_interface__ = {"shape": (int(n),), "typestr": "<f8", "data": (int(ptr), False),
+                                         "version": 2, "strides": None}
+
+
+def _np_ptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+class Server:
+    """Continuous-batching evaluation service over resident sessions (host
+    numpy arrays in and out; the arrays must stay alive until `wait`)."""
+
+    def __init__(self, sessions, hbm_budget=None, batch_interactions=None, max_items=None):
+        o = ServerOptions()
+        lib.nebem_server_default_options(ctypes.byref(o))
+        if hbm_budget is not None:
+            o.hbm_budget = int(hbm_budget)
+        if batch_interactions is not None:
+            o.batch_interactions = float(batch_interactions)
+        if max_items is not None:
+            o.max_items = int(max_items)
+        self.sessions = list(sessions)
+        arr = (ctypes.c_void_p * len(self.sessions))(*[s.handle for s in self.sessions])
+        h = ctypes.c_void_p()
+        _check(lib.nebem_server_create(arr, len(self.sessions), ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, geometry, pts, want=("phi", "ex", "ey", "ez")):
+        """pts: (m, 3) float64.  Returns a ticket; results via wait()."""
+        m = pts.shape[0]
+        cols = [np.ascontiguousarray(pts[:, k], dtype=np.float64) for k in range(3)]
+        outs = {k: (np.empty(m) if k in want else None) for k in ("phi", "ex", "ey", "ez")}
+        t = ctypes.c_int64()
+        _check(lib.nebem_server_submit(self.handle, int(geometry), *[_np_ptr(c) for c in cols], m,
+                                       _np_ptr(outs["phi"]), _np_ptr(outs["ex"]), _np_ptr(outs["ey"]),
+                                       _np_ptr(outs["ez"]), ctypes.byref(t)))
+        self._keep[t.value] = (cols, outs)
+        return t.value
+
+    def wait(self, ticket):
+        """Blocks until the request is done; returns (results dict, stats)."""
+        st = RequestStats()
+        code = lib.nebem_server_wait(self.handle, int(ticket), ctypes.byref(st))
+        cols, outs = self._keep.pop(ticket)
+        _check(code)
+        return outs, st
+
+    def counters(self):
+        c = ServerCounters()
+        _check(lib.nebem_server_stats(self.handle, ctypes.byref(c)))
+        return c
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.nebem_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

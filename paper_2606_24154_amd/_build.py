@@ -10,7 +10,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libnebem.so")
 
-SOURCES = ["field_kernels.hip", "lu_kernels.hip", "api.hip"]
+SOURCES = ["field_kernels.hip", "lu_kernels.hip", "refine_kernels.hip", "solver.hip", "charge_kernels.hip",
+           "session.hip", "server.hip", "api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

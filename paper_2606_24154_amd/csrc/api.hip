@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "host_util.hpp"
 #include "lu_internal.hpp"
 #include "nebem_internal.hpp"
 
@@ -27,26 +28,6 @@ nebem_status hip_fail(hipError_t e, const char *what)
     g_err = std::string(what) + ": " + hipGetErrorString(e);
     return e == hipErrorOutOfMemory ? NEBEM_ENOMEM : NEBEM_EDEVICE;
 }
-
-// Stream-ordered device buffer owned by one call.
-struct DevBuf {
-    void *p = nullptr;
-    hipStream_t s = nullptr;
-    DevBuf() = default;
-    DevBuf(const DevBuf &) = delete;
-    DevBuf &operator=(const DevBuf &) = delete;
-    ~DevBuf()
-    {
-        if (p) (void)hipFreeAsync(p, s);
-    }
-    hipError_t alloc(size_t bytes, hipStream_t stream)
-    {
-        s = stream;
-        return hipMallocAsync(&p, bytes ? bytes : 8, stream);
-    }
-    template <typename T>
-    T *as() const { return static_cast<T *>(p); }
-};
 
 nebem_status make_img_args(const nebem_images *im, ImgArgs *o)
 {
@@ -91,7 +72,7 @@ nebem_status make_img_args(const nebem_images *im, ImgArgs *o)
     return NEBEM_OK;
 }
 
-static nebem_status check_panels(const nebem_panels *p)
+nebem_status check_panels(const nebem_panels *p)
 {
     if (!p) return fail(NEBEM_EINVAL, "panels is NULL");
     if (p->n < 0 || p->n > (int64_t)INT_MAX / 2) return fail(NEBEM_EINVAL, "panels: n out of range");
@@ -109,7 +90,7 @@ static const nebem_options &opts_or_default(const nebem_options *opt, nebem_opti
     return tmp;
 }
 
-static nebem_status check_options(const nebem_options &o)
+nebem_status check_options(const nebem_options &o)
 {
     if (o.precision != NEBEM_FP64 && o.precision != NEBEM_MIXED) return fail(NEBEM_EINVAL, "options: bad precision");
     if (!(o.near_factor >= 1.0) || !std::isfinite(o.near_factor))
@@ -120,7 +101,7 @@ static nebem_status check_options(const nebem_options &o)
 
 // Derived element records for `p` in a stream-ordered buffer; validates the
 // elements (synchronises the stream to read the verdict).
-static nebem_status derive(const nebem_panels *p, hipStream_t s, DevBuf &drec)
+nebem_status derive(const nebem_panels *p, hipStream_t s, DevBuf &drec)
 {
     NEBEM_HIP(drec.alloc((size_t)p->n * R_STRIDE * sizeof(double), s));
     DevBuf bad;
@@ -144,7 +125,7 @@ static nebem_status derive(const nebem_panels *p, hipStream_t s, DevBuf &drec)
 }
 
 // host permutation from LAPACK-style sequential row swaps
-static void pivots_to_perm(const std::vector<int> &ipiv, std::vector<int> &perm)
+void pivots_to_perm(const std::vector<int> &ipiv, std::vector<int> &perm)
 {
     const int n = (int)ipiv.size();
     perm.resize(n);
@@ -187,10 +168,10 @@ nebem_status nebem_eval(const nebem_panels *panels, const nebem_images *images, 
     if (panels->n > 0 && !sigma) return fail(NEBEM_EINVAL, "eval: NULL sigma");
     ImgArgs ia;
     if ((st = make_img_args(images, &ia))) return st;
-    if (o.precision != NEBEM_FP64) return fail(NEBEM_EINVAL, "eval: mixed precision is not available in this build");
     DevBuf drec;
     if ((st = derive(panels, stream, drec))) return st;
-    launch_eval_fp64(drec.as<double>(), sigma, panels->n, ia, px, py, pz, m, phi, ex, ey, ez, stream);
+    launch_eval(drec.as<double>(), sigma, panels->n, ia, o.precision == NEBEM_MIXED, o.near_factor, px, py, pz, m,
+                phi, ex, ey, ez, stream);
     NEBEM_HIP(hipGetLastError());
     return NEBEM_OK;
 }
@@ -210,11 +191,10 @@ nebem_status nebem_assemble(const nebem_panels *panels, const nebem_images *imag
     if (panels->n == 0) return NEBEM_OK;
     ImgArgs ia;
     if ((st = make_img_args(images, &ia))) return st;
-    if (o.precision != NEBEM_FP64)
-        return fail(NEBEM_EINVAL, "assemble: mixed precision is not available in this build");
     DevBuf drec;
     if ((st = derive(panels, stream, drec))) return st;
-    launch_assemble_fp64(drec.as<double>(), panels->n, ia, cx, cy, cz, A, stream);
+    launch_assemble(drec.as<double>(), panels->n, ia, o.precision == NEBEM_MIXED, o.near_factor, cx, cy, cz, A,
+                    stream);
     NEBEM_HIP(hipGetLastError());
     return NEBEM_OK;
 }
@@ -234,48 +214,42 @@ nebem_status nebem_solve(double *A, int64_t n, const double *b, int64_t nrhs, do
     }
     if (n == 0 || nrhs == 0) return NEBEM_OK;
     if (!A || !b || !sigma || !ipiv) return fail(NEBEM_EINVAL, "solve: NULL argument");
-    if (o.precision != NEBEM_FP64)
-        return fail(NEBEM_EINVAL, "solve: mixed precision is not available in this build");
     const int nn = (int)n;
-    const int nblk = (nn + 255) / 256;
-    DevBuf pval, ws;
-    NEBEM_HIP(pval.alloc((size_t)nblk * sizeof(double), stream));
-    NEBEM_HIP(ws.alloc((size_t)(nblk + 2) * sizeof(int), stream));
-    LUWork w;
-    w.pval = pval.p;
-    w.pidx = ws.as<int>();
-    w.counter = ws.as<int>() + nblk;
-    w.info = ws.as<int>() + nblk + 1;
-    NEBEM_HIP(hipMemsetAsync(w.counter, 0, sizeof(int), stream));
-    NEBEM_HIP(hipMemcpyAsync(w.info, &nn, sizeof(int), hipMemcpyHostToDevice, stream));
-    lu_factor(A, nn, ipiv, w, stream);
-    NEBEM_HIP(hipGetLastError());
-    int hinfo = nn;
-    std::vector<int> hpiv(nn), perm;
-    NEBEM_HIP(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, stream));
-    NEBEM_HIP(hipMemcpyAsync(hpiv.data(), ipiv, (size_t)nn * sizeof(int), hipMemcpyDeviceToHost, stream));
-    NEBEM_HIP(hipStreamSynchronize(stream));
-    if (hinfo < nn) {
-        char buf[96];
-        std::snprintf(buf, sizeof buf, "solve: zero pivot in column %d", hinfo);
-        return fail(NEBEM_ESINGULAR, buf);
-    }
-    pivots_to_perm(hpiv, perm);
-    DevBuf dperm, work, xtmp;
+    std::vector<int> perm;
+    DevBuf dperm;
     NEBEM_HIP(dperm.alloc((size_t)nn * sizeof(int), stream));
-    NEBEM_HIP(hipMemcpyAsync(dperm.p, perm.data(), (size_t)nn * sizeof(int), hipMemcpyHostToDevice, stream));
-    NEBEM_HIP(work.alloc((size_t)nn * nrhs * sizeof(double), stream));
-    double *x = sigma;
-    if (sigma == b) {  // aliasing: permute out of b into a temporary first
-        NEBEM_HIP(xtmp.alloc((size_t)nn * nrhs * sizeof(double), stream));
-        x = xtmp.as<double>();
+    if (o.precision == NEBEM_FP64) {
+        if ((st = factor_fp64(A, nn, ipiv, perm, stream))) return st;
+        NEBEM_HIP(hipMemcpyAsync(dperm.p, perm.data(), (size_t)nn * sizeof(int), hipMemcpyHostToDevice, stream));
+        if ((st = solve_fp64(A, nn, dperm.as<int>(), b, (int)nrhs, sigma, stream))) return st;
+        NEBEM_HIP(hipStreamSynchronize(stream));  // perm (host) must outlive the copy
+        return NEBEM_OK;
     }
-    lu_solve(A, nn, dperm.as<int>(), b, x, work.as<double>(), (int)nrhs, stream);
-    NEBEM_HIP(hipGetLastError());
-    if (x != sigma)
-        NEBEM_HIP(hipMemcpyAsync(sigma, x, (size_t)nn * nrhs * sizeof(double), hipMemcpyDeviceToDevice, stream));
-    NEBEM_HIP(hipStreamSynchronize(stream));  // host vectors above must outlive the copies
-    return NEBEM_OK;
+    DevBuf a32, scale, bcopy;
+    NEBEM_HIP(a32.alloc((size_t)nn * nn * sizeof(float), stream));
+    NEBEM_HIP(scale.alloc((size_t)nn * sizeof(double), stream));
+    if ((st = factor_mixed(A, nn, a32.as<float>(), scale.as<double>(), ipiv, perm, stream))) return st;
+    NEBEM_HIP(hipMemcpyAsync(dperm.p, perm.data(), (size_t)nn * sizeof(int), hipMemcpyHostToDevice, stream));
+    const double *bb = b;
+    if (sigma == b) {  // the refinement reads b after writing x
+        NEBEM_HIP(bcopy.alloc((size_t)nn * nrhs * sizeof(double), stream));
+        NEBEM_HIP(hipMemcpyAsync(bcopy.p, b, (size_t)nn * nrhs * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        bb = bcopy.as<double>();
+    }
+    nebem_status worst = NEBEM_OK;
+    nebem_solve_info agg = {0, 0.0};
+    for (int64_t q = 0; q < nrhs; ++q) {
+        nebem_solve_info ci;
+        st = solve_mixed(A, a32.as<float>(), scale.as<double>(), dperm.as<int>(), nn, bb + q * n, sigma + q * n,
+                         o.ir_tol, o.ir_max_iter, &ci, stream);
+        if (st && st != NEBEM_ENOCONV) return st;
+        if (st) worst = st;
+        agg.ir_iters = ci.ir_iters > agg.ir_iters ? ci.ir_iters : agg.ir_iters;
+        agg.rel_resid = ci.rel_resid > agg.rel_resid ? ci.rel_resid : agg.rel_resid;
+    }
+    if (info) *info = agg;
+    NEBEM_HIP(hipStreamSynchronize(stream));
+    return worst;
 }
 
 nebem_status nebem_solve_factored(const double *LU, const int32_t *ipiv, int64_t n, const double *b, int64_t nrhs,
@@ -291,21 +265,12 @@ nebem_status nebem_solve_factored(const double *LU, const int32_t *ipiv, int64_t
     for (int k = 0; k < nn; ++k)
         if (hpiv[k] < k || hpiv[k] >= nn) return fail(NEBEM_EINVAL, "solve_factored: ipiv is not a valid pivot list");
     pivots_to_perm(hpiv, perm);
-    DevBuf dperm, work, xtmp;
+    DevBuf dperm;
     NEBEM_HIP(dperm.alloc((size_t)nn * sizeof(int), stream));
     NEBEM_HIP(hipMemcpyAsync(dperm.p, perm.data(), (size_t)nn * sizeof(int), hipMemcpyHostToDevice, stream));
-    NEBEM_HIP(work.alloc((size_t)nn * nrhs * sizeof(double), stream));
-    double *x = sigma;
-    if (sigma == b) {
-        NEBEM_HIP(xtmp.alloc((size_t)nn * nrhs * sizeof(double), stream));
-        x = xtmp.as<double>();
-    }
-    lu_solve(LU, nn, dperm.as<int>(), b, x, work.as<double>(), (int)nrhs, stream);
-    NEBEM_HIP(hipGetLastError());
-    if (x != sigma)
-        NEBEM_HIP(hipMemcpyAsync(sigma, x, (size_t)nn * nrhs * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    nebem_status st = solve_fp64(LU, nn, dperm.as<int>(), b, (int)nrhs, sigma, stream);
     NEBEM_HIP(hipStreamSynchronize(stream));
-    return NEBEM_OK;
+    return st;
 }
 
 }  // extern "C"

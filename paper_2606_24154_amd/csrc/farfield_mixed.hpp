@@ -1,0 +1,146 @@
+// farfield_mixed.hpp -- far-field potential/field of one element copy for the
+// mixed-precision path: FP64 monopole plus an FP32 quadrature correction.
+//
+// Far from an element (R >= near_factor * D, R = distance to its centroid,
+// D = its diameter) the integrand of Sec. 2.1 is smooth, and a quadrature
+// rule with nodes s_k = c + delta_k and weights w_k (sum 1) gives
+//   Phi' = A sum_k w_k / R_k,   E' = A sum_k w_k (p - delta_k) / R_k^3
+// with p = P - c, R_k = |p - delta_k|.  The centroid term A/R_c is evaluated
+// in FP64; the remainder is carried in FP32 in difference form so that no
+// cancellation happens against the monopole:
+//   1/R_k - 1/R_c = t_k / (R_k R_c),  t_k = R_c - R_k = (2 p.delta_k - |delta_k|^2)/(R_c + R_k)
+//   1/R_k^3 - 1/R_c^3 = t_k / (R_k R_c) (1/R_k^2 + 1/(R_k R_c) + 1/R_c^2).
+// Its FP32 rounding is then relative to the correction, itself O((D/R)^2)
+// of the monopole.
+//
+// Rules (truncation error of E per element, measured against the exact
+// integral, <= 4e-7 at R = 4 D and falling as a power of D/R):
+//   rectangle      4 D <= R < 24 D: 3 x 3 Gauss-Legendre; R >= 24 D: 2 x 2
+//   right triangle 4 D <= R < 48 D: Radon's 7-point degree-5 rule;
+//                  R >= 48 D: the 3-point interior degree-2 rule
+// (J. Radon, Monatsh. Math. 52:286-300, 1948; tabulated with the 3-point
+// rule in A. H. Stroud, Approximate Calculation of Multiple Integrals, 1971).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "panel_fp64.hpp"
+
+namespace nebem {
+
+// Gauss-Legendre nodes/weights on [0, 1]
+struct GL2 {
+    static constexpr int n = 2;
+    static constexpr float x[2] = {0.21132486540518711775f, 0.78867513459481288225f};
+    static constexpr float w[2] = {0.5f, 0.5f};
+};
+struct GL3 {
+    static constexpr int n = 3;
+    static constexpr float x[3] = {0.11270166537925831148f, 0.5f, 0.88729833462074168852f};
+    static constexpr float w[3] = {0.27777777777777777778f, 0.44444444444444444444f, 0.27777777777777777778f};
+};
+
+// triangle rules in (s, t) on s, t >= 0, s + t <= 1 (area coordinates of the
+// vertices o + u and o + w); weights sum to 1
+struct TriR7 {
+    static constexpr int n = 7;
+    static constexpr float s[7] = {0.33333333333333333333f, 0.05971587178976982045f, 0.47014206410511508977f,
+                                   0.47014206410511508977f, 0.79742698535308732240f, 0.10128650732345633880f,
+                                   0.10128650732345633880f};
+    static constexpr float t[7] = {0.33333333333333333333f, 0.47014206410511508977f, 0.05971587178976982045f,
+                                   0.47014206410511508977f, 0.10128650732345633880f, 0.79742698535308732240f,
+                                   0.10128650732345633880f};
+    static constexpr float w[7] = {0.225f, 0.13239415278850618074f, 0.13239415278850618074f,
+                                   0.13239415278850618074f, 0.12593918054482715260f, 0.12593918054482715260f,
+                                   0.12593918054482715260f};
+};
+struct TriR3 {
+    static constexpr int n = 3;
+    static constexpr float s[3] = {0.66666666666666666667f, 0.16666666666666666667f, 0.16666666666666666667f};
+    static constexpr float t[3] = {0.16666666666666666667f, 0.66666666666666666667f, 0.16666666666666666667f};
+    static constexpr float w[3] = {0.33333333333333333333f, 0.33333333333333333333f, 0.33333333333333333333f};
+};
+
+// FP32 correction accumulators over the nodes of one rule
+struct FarAcc {
+    float cphi;  // sum w t/R_k                         (x A/R_c  -> potential correction)
+    float gp;    // sum w t/R_k (1/R_k^2 + 1/(R_k R_c) + 1/R_c^2)   (x A p/R_c)
+    float gx, gz;  // sum w delta/R_k^3                 (x -A)
+};
+
+__device__ __forceinline__ void far_node(float px, float pz, float rc2, float rc, float ic, float ic2, float dx,
+                                         float dz, float w, FarAcc &a)
+{
+    const float d = fmaf(px, dx, pz * dz);
+    const float num = fmaf(2.0f, d, -fmaf(dx, dx, dz * dz));  // 2 p.delta - |delta|^2
+    const float rk2 = rc2 - num;
+    const float ik = __builtin_amdgcn_rsqf(rk2);
+    const float rk = rk2 * ik;
+    const float t = num * __builtin_amdgcn_rcpf(rc + rk);  // R_c - R_k
+    const float wq = w * (t * ik);
+    a.cphi += wq;
+    a.gp = fmaf(wq, fmaf(ik, ik + ic, ic2), a.gp);
+    const float w3 = w * (ik * ik * ik);
+    a.gx = fmaf(w3, dx, a.gx);
+    a.gz = fmaf(w3, dz, a.gz);
+}
+
+// p = (px, pz, ph): point relative to the element centroid in the element
+// frame (FP64); rc2 = |p|^2.  Adds Phi', E' (local frame) to (sp, sx, sz, sn).
+template <int KIND>
+__device__ __forceinline__ void far_mixed(double px, double pz, double ph, double rc2, double lx, double lz,
+                                          double area, double tier2, double &sp, double &sx, double &sz,
+                                          double &sn)
+{
+    const float fx = (float)px, fz = (float)pz;
+    const float frc2 = (float)rc2;
+    const float fic = __builtin_amdgcn_rsqf(frc2);
+    const float frc = frc2 * fic;
+    const float fic2 = fic * fic;
+    const float flx = (float)lx, flz = (float)lz;
+    FarAcc a = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (KIND == 0) {
+        if (rc2 < tier2) {
+#pragma unroll
+            for (int i = 0; i < GL3::n; ++i)
+#pragma unroll
+                for (int j = 0; j < GL3::n; ++j)
+                    far_node(fx, fz, frc2, frc, fic, fic2, flx * (GL3::x[i] - 0.5f), flz * (GL3::x[j] - 0.5f),
+                             GL3::w[i] * GL3::w[j], a);
+        } else {
+#pragma unroll
+            for (int i = 0; i < GL2::n; ++i)
+#pragma unroll
+                for (int j = 0; j < GL2::n; ++j)
+                    far_node(fx, fz, frc2, frc, fic, fic2, flx * (GL2::x[i] - 0.5f), flz * (GL2::x[j] - 0.5f),
+                             GL2::w[i] * GL2::w[j], a);
+        }
+    } else {
+        const float third = 0.33333333333333333333f;
+        if (rc2 < tier2) {
+#pragma unroll
+            for (int k = 0; k < TriR7::n; ++k)
+                far_node(fx, fz, frc2, frc, fic, fic2, flx * (TriR7::s[k] - third), flz * (TriR7::t[k] - third),
+                         TriR7::w[k], a);
+        } else {
+#pragma unroll
+            for (int k = 0; k < TriR3::n; ++k)
+                far_node(fx, fz, frc2, frc, fic, fic2, flx * (TriR3::s[k] - third), flz * (TriR3::t[k] - third),
+                         TriR3::w[k], a);
+        }
+    }
+    // FP64 monopole: 1/R_c from the FP32 estimate by two Newton steps
+    double ir = (double)fic;
+    ir = ir * (1.5 - 0.5 * rc2 * ir * ir);
+    ir = ir * (1.5 - 0.5 * rc2 * ir * ir);
+    const double air = area * ir;
+    const double air3 = air * ir * ir;
+    // corrections (FP32), promoted and added
+    const float cf = fic * a.cphi;      // sum w (1/R_k - 1/R_c)
+    const float gf = fic * a.gp;        // sum w (1/R_k^3 - 1/R_c^3)
+    sp += air + area * (double)cf;
+    sx += air3 * px + area * (double)(fx * gf - a.gx);
+    sz += air3 * pz + area * (double)(fz * gf - a.gz);
+    sn += air3 * ph + area * (double)((float)ph * gf);
+}
+
+}  // namespace nebem

@@ -18,6 +18,7 @@
 #include <cmath>
 
 #include "nebem_internal.hpp"
+#include "farfield_mixed.hpp"
 #include "panel_fp64.hpp"
 
 namespace nebem {
@@ -113,6 +114,7 @@ void launch_prep(const nebem_panels *p, double *drec, int *bad, hipStream_t s)
 struct Elem {
     double ox, oy, oz, e1x, e1y, e1z, e2x, e2y, e2z, e3x, e3y, e3z;
     double lx, lz, hyp, ihyp;
+    double diam, area;
     int kind;
 };
 
@@ -135,6 +137,8 @@ __device__ __forceinline__ Elem load_elem(const double *d)
     e.lz = uni(d[R_LZ]);
     e.hyp = uni(d[R_HYP]);
     e.ihyp = uni(d[R_IHYP]);
+    e.diam = uni(d[R_DIAM]);
+    e.area = uni(d[R_AREA]);
     e.kind = uni((int)d[R_KIND]);
     return e;
 }
@@ -143,12 +147,21 @@ __device__ __forceinline__ Elem load_elem(const double *d)
 // the (reflected) point in the element frame for the zero translation, and
 // (aX,aZ,aH), (bX,bZ,bH) the lattice vectors in that frame.  `self` zeroes H
 // for the zero translation (collocation point on its own element).
-template <int KIND>
+// MIXED: copies with R >= near_factor * D take the FP64-monopole + FP32
+// quadrature far field (per lane), the others the exact FP64 closed form.
+struct MixParams {
+    double near2;   // (near_factor D)^2
+    double tier2;   // squared distance beyond which the cheaper far rule is used
+};
+
+template <int KIND, bool MIXED>
 __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, double X0, double Z0, double H0,
                                                  double aX, double aZ, double aH, double bX, double bZ,
-                                                 double bH, bool self, double &sp, double &sx, double &sz,
-                                                 double &sn)
+                                                 double bH, bool self, const MixParams &mp, double &sp,
+                                                 double &sx, double &sz, double &sn)
 {
+    const double cxl = KIND == 0 ? 0.5 * e.lx : e.lx * (1.0 / 3.0);
+    const double czl = KIND == 0 ? 0.5 * e.lz : e.lz * (1.0 / 3.0);
 #pragma unroll 1
     for (int i1 = -n1; i1 <= n1; ++i1) {
         const double f1 = -(double)i1;
@@ -159,6 +172,14 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
             const double X = fma(f2, bX, X1), Z = fma(f2, bZ, Z1);
             double H = fma(f2, bH, H1);
             H = (self && i1 == 0 && i2 == 0) ? 0.0 : H;
+            if (MIXED) {
+                const double px = X - cxl, pz = Z - czl;
+                const double rc2 = px * px + pz * pz + H * H;
+                if (rc2 >= mp.near2) {
+                    far_mixed<KIND>(px, pz, H, rc2, e.lx, e.lz, e.area, mp.tier2, sp, sx, sz, sn);
+                    continue;
+                }
+            }
             Kern k;
             if (KIND == 0)
                 k = rect_fp64(X, H, Z, e.lx, e.lz);
@@ -173,10 +194,18 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
 }
 
 // phi', E' (global frame) of one element with all its copies at P.
-__device__ __forceinline__ void element_copies_fp64(const Elem &e, const ImgArgs &img, double Px, double Py,
-                                                    double Pz, bool self, double &ophi, double &oex,
-                                                    double &oey, double &oez)
+template <bool MIXED>
+__device__ __forceinline__ void element_copies(const Elem &e, const ImgArgs &img, double Px, double Py, double Pz,
+                                               bool self, double near_factor, double &ophi, double &oex,
+                                               double &oey, double &oez)
 {
+    MixParams mp;
+    if (MIXED) {
+        const double nd = near_factor * e.diam;
+        const double td = (e.kind == 0 ? 24.0 : 48.0) * e.diam;
+        mp.near2 = nd * nd;
+        mp.tier2 = td * td;
+    }
     ophi = oex = oey = oez = 0.0;
     for (int r = 0; r < img.nref; ++r) {
         const int ax = img.axes[r];
@@ -197,9 +226,11 @@ __device__ __forceinline__ void element_copies_fp64(const Elem &e, const ImgArgs
         double sp = 0.0, sx = 0.0, sz = 0.0, sn = 0.0;
         const bool s = self && r == 0;
         if (e.kind == 0)
-            sum_translations<0>(e, img.n1, img.n2, X0, Z0, H0, aX, aZ, aH, bX, bZ, bH, s, sp, sx, sz, sn);
+            sum_translations<0, MIXED>(e, img.n1, img.n2, X0, Z0, H0, aX, aZ, aH, bX, bZ, bH, s, mp, sp, sx, sz,
+                                       sn);
         else
-            sum_translations<1>(e, img.n1, img.n2, X0, Z0, H0, aX, aZ, aH, bX, bZ, bH, s, sp, sx, sz, sn);
+            sum_translations<1, MIXED>(e, img.n1, img.n2, X0, Z0, H0, aX, aZ, aH, bX, bZ, bH, s, mp, sp, sx, sz,
+                                       sn);
         double gx = sx * e.e1x + sz * e.e2x + sn * e.e3x;
         double gy = sx * e.e1y + sz * e.e2y + sn * e.e3y;
         double gz = sx * e.e1z + sz * e.e2z + sn * e.e3z;
@@ -215,17 +246,18 @@ __device__ __forceinline__ void element_copies_fp64(const Elem &e, const ImgArgs
 }
 
 // -------------------------------------------------------------- evaluation
-__global__ __launch_bounds__(kBlock) void k_eval_fp64(const double *__restrict__ drec,
-                                                       const double *__restrict__ sigma, int n, ImgArgs img,
-                                                       const double *__restrict__ px,
-                                                       const double *__restrict__ py,
-                                                       const double *__restrict__ pz, int m,
-                                                       double *__restrict__ phi, double *__restrict__ ex,
-                                                       double *__restrict__ ey, double *__restrict__ ez)
+// One workgroup's share of an evaluation: points [base, base + 256) of the
+// m points, all elements and copies, FP64 sums per lane.
+template <bool MIXED>
+__device__ __forceinline__ void eval_block(const double *__restrict__ drec, const double *__restrict__ sigma, int n,
+                                           const ImgArgs &img, double near_factor, const double *__restrict__ px,
+                                           const double *__restrict__ py, const double *__restrict__ pz, int m,
+                                           int base_pt, double *__restrict__ phi, double *__restrict__ ex,
+                                           double *__restrict__ ey, double *__restrict__ ez)
 {
     __shared__ double t_rec[kTileE * R_STRIDE];
     __shared__ double t_sig[kTileE];
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int i = base_pt + threadIdx.x;
     const bool act = i < m;
     const double Px = act ? px[i] : 0.0;
     const double Py = act ? py[i] : 0.0;
@@ -241,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_fp64(const double *__restrict__
         for (int p = 0; p < cnt; ++p) {
             const Elem e = load_elem(t_rec + p * R_STRIDE);
             double cp, cx, cy, cz;
-            element_copies_fp64(e, img, Px, Py, Pz, false, cp, cx, cy, cz);
+            element_copies<MIXED>(e, img, Px, Py, Pz, false, near_factor, cp, cx, cy, cz);
             const double sg = uni(t_sig[p]);
             aphi = fma(sg, cp, aphi);
             aex = fma(sg, cx, aex);
@@ -257,25 +289,63 @@ __global__ __launch_bounds__(kBlock) void k_eval_fp64(const double *__restrict__
     }
 }
 
-void launch_eval_fp64(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, const double *px,
-                      const double *py, const double *pz, int64_t m, double *phi, double *ex, double *ey,
-                      double *ez, hipStream_t s)
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_eval(const double *__restrict__ drec, const double *__restrict__ sigma,
+                                                  int n, ImgArgs img, double near_factor,
+                                                  const double *__restrict__ px, const double *__restrict__ py,
+                                                  const double *__restrict__ pz, int m, double *__restrict__ phi,
+                                                  double *__restrict__ ex, double *__restrict__ ey,
+                                                  double *__restrict__ ez)
+{
+    eval_block<MIXED>(drec, sigma, n, img, near_factor, px, py, pz, m, blockIdx.x * kBlock, phi, ex, ey, ez);
+}
+
+// Continuous-batching evaluation: workgroup b takes work item b -- up to 256
+// points of one request on one resident geometry.  The per-point arithmetic
+// is eval_block's, so a point's result does not depend on which other
+// requests share the launch.
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_eval_worklist(const WorkItem *__restrict__ items,
+                                                           const ImgArgs *__restrict__ imgs, double near_factor)
+{
+    const WorkItem &w = items[blockIdx.x];
+    eval_block<MIXED>(w.drec, w.sigma, w.n, imgs[w.geom], near_factor, w.px, w.py, w.pz, w.count, 0, w.phi, w.ex,
+                      w.ey, w.ez);
+}
+
+void launch_eval_worklist(const WorkItem *items, int nitems, const ImgArgs *imgs, int mixed, double near_factor,
+                          hipStream_t s)
+{
+    if (nitems <= 0) return;
+    if (mixed)
+        hipLaunchKernelGGL(k_eval_worklist<true>, dim3(nitems), dim3(kBlock), 0, s, items, imgs, near_factor);
+    else
+        hipLaunchKernelGGL(k_eval_worklist<false>, dim3(nitems), dim3(kBlock), 0, s, items, imgs, near_factor);
+}
+
+void launch_eval(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
+                 double near_factor, const double *px, const double *py, const double *pz, int64_t m, double *phi,
+                 double *ex, double *ey, double *ez, hipStream_t s)
 {
     if (m <= 0) return;
     const unsigned g = (unsigned)((m + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_eval_fp64, dim3(g), dim3(kBlock), 0, s, drec, sigma, (int)n, img, px, py, pz, (int)m,
-                       phi, ex, ey, ez);
+    if (mixed)
+        hipLaunchKernelGGL(k_eval<true>, dim3(g), dim3(kBlock), 0, s, drec, sigma, (int)n, img, near_factor, px,
+                           py, pz, (int)m, phi, ex, ey, ez);
+    else
+        hipLaunchKernelGGL(k_eval<false>, dim3(g), dim3(kBlock), 0, s, drec, sigma, (int)n, img, near_factor, px,
+                           py, pz, (int)m, phi, ex, ey, ez);
 }
 
 // ---------------------------------------------------------------- assembly
 // Grid: x over blocks of 256 rows, y over blocks of kTileA columns.  Each
 // lane writes A[i + j n] for its row i and the block's columns j: the 256
 // lanes of a workgroup store 256 consecutive doubles of a column (2 KB).
-__global__ __launch_bounds__(kBlock) void k_assemble_fp64(const double *__restrict__ drec, int n, ImgArgs img,
-                                                           const double *__restrict__ cx,
-                                                           const double *__restrict__ cy,
-                                                           const double *__restrict__ cz,
-                                                           double *__restrict__ A)
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_assemble(const double *__restrict__ drec, int n, ImgArgs img,
+                                                      double near_factor, const double *__restrict__ cx,
+                                                      const double *__restrict__ cy, const double *__restrict__ cz,
+                                                      double *__restrict__ A)
 {
     __shared__ double t_rec[kTileA * R_STRIDE];
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -295,19 +365,23 @@ __global__ __launch_bounds__(kBlock) void k_assemble_fp64(const double *__restri
         const int j = j0 + p;
         const Elem e = load_elem(t_rec + p * R_STRIDE);
         double cp, gx, gy, gz;
-        element_copies_fp64(e, img, Px, Py, Pz, i == j, cp, gx, gy, gz);
+        element_copies<MIXED>(e, img, Px, Py, Pz, i == j, near_factor, cp, gx, gy, gz);
         double a = diel ? kKe * (nx * gx + ny * gy + nz * gz) : kKe * cp;
         a += (diel && i == j) ? jump : 0.0;
         A[(size_t)j * n + i] = a;
     }
 }
 
-void launch_assemble_fp64(const double *drec, int64_t n, const ImgArgs &img, const double *cx, const double *cy,
-                          const double *cz, double *A, hipStream_t s)
+void launch_assemble(const double *drec, int64_t n, const ImgArgs &img, int mixed, double near_factor,
+                     const double *cx, const double *cy, const double *cz, double *A, hipStream_t s)
 {
     if (n <= 0) return;
     const dim3 g((unsigned)((n + kBlock - 1) / kBlock), (unsigned)((n + kTileA - 1) / kTileA));
-    hipLaunchKernelGGL(k_assemble_fp64, g, dim3(kBlock), 0, s, drec, (int)n, img, cx, cy, cz, A);
+    if (mixed)
+        hipLaunchKernelGGL(k_assemble<true>, g, dim3(kBlock), 0, s, drec, (int)n, img, near_factor, cx, cy, cz, A);
+    else
+        hipLaunchKernelGGL(k_assemble<false>, g, dim3(kBlock), 0, s, drec, (int)n, img, near_factor, cx, cy, cz,
+                           A);
 }
 
 }  // namespace nebem

@@ -1,0 +1,53 @@
+// host_util.hpp -- host-side helpers shared by the C-ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "nebem_internal.hpp"
+
+namespace nebem {
+
+// Stream-ordered device buffer owned by one call (or one session).
+struct DevBuf {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFreeAsync(p, s);
+        p = nullptr;
+    }
+    hipError_t alloc(size_t bytes, hipStream_t stream)
+    {
+        release();
+        s = stream;
+        return hipMallocAsync(&p, bytes ? bytes : 8, stream);
+    }
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+nebem_status check_panels(const nebem_panels *p);
+nebem_status check_options(const nebem_options &o);
+// Derived element records (validated; synchronises the stream).
+nebem_status derive(const nebem_panels *p, hipStream_t s, DevBuf &drec);
+void pivots_to_perm(const std::vector<int> &ipiv, std::vector<int> &perm);
+
+// Dense solve drivers (solver.hip).  FP64: A is factored in place.
+// MIXED: A untouched; A32 (n*n floats), scale s (n) and perm/ipiv receive the
+// equilibrated FP32 factorisation.
+nebem_status factor_fp64(double *A, int n, int *ipiv, std::vector<int> &perm_host, hipStream_t st);
+nebem_status factor_mixed(const double *A, int n, float *A32, double *s, int *ipiv, std::vector<int> &perm_host,
+                          hipStream_t st);
+// X = A^-1 B for nrhs columns with FP64 factors (perm on device)
+nebem_status solve_fp64(const double *LU, int n, const int *perm, const double *B, int nrhs, double *X,
+                        hipStream_t st);
+// refinement: x solves A x = b to ||b - A x|| <= tol ||b||, one column
+nebem_status solve_mixed(const double *A, const float *LU32, const double *s, const int *perm, int n, const double *b,
+                         double *x, double tol, int max_iter, nebem_solve_info *info, hipStream_t st);
+
+}  // namespace nebem

@@ -58,16 +58,34 @@ nebem_status hip_fail(hipError_t e, const char *what);
 
 nebem_status make_img_args(const nebem_images *im, ImgArgs *out);
 
+// One unit of serving work: up to 256 points of one request on one resident
+// geometry (device pointers).
+struct WorkItem {
+    const double *drec;
+    const double *sigma;
+    const double *px, *py, *pz;
+    double *phi, *ex, *ey, *ez;
+    int n;      // elements of the geometry
+    int geom;   // index into the image-argument array
+    int count;  // points in this item (<= 256)
+    int pad;
+};
+
 // ---- field kernels (field_kernels.hip)
 // Builds derived records; writes bad_count[0] = number of invalid elements,
 // bad_count[1] = first invalid index (or n).  bad_count must be zeroed/set
 // to {0, n} by the caller.
 void launch_prep(const nebem_panels *p, double *drec, int *bad, hipStream_t s);
-void launch_eval_fp64(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, const double *px,
-                      const double *py, const double *pz, int64_t m, double *phi, double *ex, double *ey,
-                      double *ez, hipStream_t s);
+// mixed != 0: copies with R >= near_factor * D use the FP64 monopole + FP32
+// quadrature far field; otherwise the exact FP64 closed forms everywhere.
+void launch_eval(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
+                 double near_factor, const double *px, const double *py, const double *pz, int64_t m, double *phi,
+                 double *ex, double *ey, double *ez, hipStream_t s);
+// items/imgs in device memory
+void launch_eval_worklist(const WorkItem *items, int nitems, const ImgArgs *imgs, int mixed, double near_factor,
+                          hipStream_t s);
 // A (n x n col-major).  cx/cy/cz may be null (centroids).
-void launch_assemble_fp64(const double *drec, int64_t n, const ImgArgs &img, const double *cx, const double *cy,
-                          const double *cz, double *A, hipStream_t s);
+void launch_assemble(const double *drec, int64_t n, const ImgArgs &img, int mixed, double near_factor,
+                     const double *cx, const double *cy, const double *cz, double *A, hipStream_t s);
 
 }  // namespace nebem

@@ -1,0 +1,422 @@
+// server.hip -- continuous-batching field-evaluation service over resident
+// geometries (C-ABI nebem_server_*).
+//
+// Clients (e.g. particle-drift loops, which in the paper query potential and
+// field at millions of points, Sec. 3) submit batches of points on one of the
+// server's resident sessions.  A worker thread runs the scheduling loop:
+//   1. admission: queued requests enter, in arrival order, while their
+//      points and results (56 bytes per point) fit into the device staging
+//      arena of hbm_budget bytes; their points are copied in;
+//   2. batching: the active requests are cut into 256-point work items,
+//      taken round-robin (one item per request per round) until the
+//      iteration's interaction budget is used; items of different requests
+//      and geometries go into ONE launch of the work-list evaluation kernel;
+//   3. completion: a request whose items are all done has its results
+//      copied back to the caller's host arrays, its arena space freed and its
+//      waiter woken; new requests are admitted on the next iteration.
+// Every point is evaluated by the same per-lane code as nebem_session_eval,
+// so a request's results are identical whether it runs alone or in a mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "host_util.hpp"
+#include "nebem_internal.hpp"
+#include "session_internal.hpp"
+
+namespace nebem {
+
+static double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+    int64_t id = 0;
+    int geom = 0;
+    int64_t m = 0;
+    const double *hx = nullptr, *hy = nullptr, *hz = nullptr;
+    double *hphi = nullptr, *hex = nullptr, *hey = nullptr, *hez = nullptr;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    size_t off = 0, bytes = 0;  // arena placement
+    int64_t next = 0;           // first point not yet scheduled
+    int64_t inflight = 0;       // points scheduled in the current launch
+    int64_t done_pts = 0;
+    int status = NEBEM_OK;
+    bool finished = false;
+};
+
+// first-fit allocator over [0, size) with 256-byte granules
+struct Arena {
+    size_t size = 0;
+    std::map<size_t, size_t> free_;  // offset -> length
+    void init(size_t s)
+    {
+        size = s;
+        free_.clear();
+        if (s) free_[0] = s;
+    }
+    bool alloc(size_t bytes, size_t &off)
+    {
+        bytes = (bytes + 255) & ~size_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= bytes) {
+                off = it->first;
+                const size_t rest = it->second - bytes;
+                free_.erase(it);
+                if (rest) free_[off + bytes] = rest;
+                return true;
+            }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = (bytes + 255) & ~size_t(255);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+}  // namespace nebem
+
+struct nebem_server {
+    int device = 0;
+    nebem_server_options opt;
+    std::vector<nebem_session *> geoms;
+    std::vector<int64_t> geom_n;
+    int mixed = 0;
+    double near_factor = 4.0;
+    hipStream_t stream = nullptr;
+    void *arena_dev = nullptr;
+    nebem::Arena arena;
+    nebem::ImgArgs *imgs_dev = nullptr;
+    nebem::WorkItem *items_dev = nullptr;
+    nebem::WorkItem *items_host = nullptr;  // pinned
+    int items_cap = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<nebem::Request *> queue;
+    std::vector<nebem::Request *> active;
+    std::map<int64_t, nebem::Request *> all;
+    int64_t next_id = 1;
+    bool stop = false;
+    std::thread worker;
+    // statistics
+    int64_t launches = 0, points_done = 0;
+    double interactions_done = 0, busy_s = 0;
+    std::string worker_error;
+};
+
+using namespace nebem;
+
+namespace nebem {
+
+static bool admit_locked(nebem_server *s)
+{
+    bool any = false;
+    while (!s->queue.empty()) {
+        Request *r = s->queue.front();
+        size_t off;
+        if (!s->arena.alloc(r->bytes, off)) break;  // head of line waits for space
+        r->off = off;
+        r->t_admit = now_s();
+        s->queue.pop_front();
+        s->active.push_back(r);
+        any = true;
+    }
+    return any;
+}
+
+// device addresses of a request's staging
+static inline double *stage(nebem_server *s, const Request *r, int k)
+{
+    return reinterpret_cast<double *>(static_cast<char *>(s->arena_dev) + r->off) + (size_t)k * r->m;
+}
+
+static void worker_main(nebem_server *s)
+{
+    (void)hipSetDevice(s->device);
+    std::vector<Request *> fresh;
+    for (;;) {
+        std::vector<Request *> act;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->active.empty(); });
+            if (s->stop && s->queue.empty() && s->active.empty()) return;
+            const size_t before = s->active.size();
+            admit_locked(s);
+            fresh.assign(s->active.begin() + before, s->active.end());
+            act = s->active;
+        }
+        // copy the new requests' points in
+        for (Request *r : fresh) {
+            const size_t b = (size_t)r->m * sizeof(double);
+            hipError_t e = hipMemcpyAsync(stage(s, r, 0), r->hx, b, hipMemcpyHostToDevice, s->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(stage(s, r, 1), r->hy, b, hipMemcpyHostToDevice, s->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(stage(s, r, 2), r->hz, b, hipMemcpyHostToDevice, s->stream);
+            if (e != hipSuccess) r->status = NEBEM_EDEVICE;
+        }
+        // build the work list: round-robin, one item per request per round
+        int nitems = 0;
+        double budget = s->opt.batch_interactions;
+        bool progress = true;
+        while (progress && budget > 0.0 && nitems < s->items_cap) {
+            progress = false;
+            for (Request *r : act) {
+                if (r->status != NEBEM_OK || r->next >= r->m || nitems >= s->items_cap) continue;
+                const double per_pt = (double)s->geom_n[r->geom] * s->geoms[r->geom]->img_count;
+                const int cnt = (int)std::min<int64_t>(256, r->m - r->next);
+                WorkItem &w = s->items_host[nitems++];
+                const nebem_session *g = s->geoms[r->geom];
+                w.drec = g->drec.as<double>();
+                w.sigma = g->sigma.as<double>();
+                w.n = (int)g->n;
+                w.geom = r->geom;
+                w.count = cnt;
+                w.pad = 0;
+                w.px = stage(s, r, 0) + r->next;
+                w.py = stage(s, r, 1) + r->next;
+                w.pz = stage(s, r, 2) + r->next;
+                w.phi = stage(s, r, 3) + r->next;
+                w.ex = stage(s, r, 4) + r->next;
+                w.ey = stage(s, r, 5) + r->next;
+                w.ez = stage(s, r, 6) + r->next;
+                r->next += cnt;
+                r->inflight += cnt;
+                budget -= per_pt * cnt;
+                s->interactions_done += per_pt * cnt;
+                progress = true;
+                if (budget <= 0.0) break;
+            }
+        }
+        const double t0 = now_s();
+        if (nitems > 0) {
+            hipError_t e = hipMemcpyAsync(s->items_dev, s->items_host, (size_t)nitems * sizeof(WorkItem),
+                                          hipMemcpyHostToDevice, s->stream);
+            if (e == hipSuccess) {
+                launch_eval_worklist(s->items_dev, nitems, s->imgs_dev, s->mixed, s->near_factor, s->stream);
+                e = hipGetLastError();
+            }
+            if (e != hipSuccess) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->worker_error = hipGetErrorString(e);
+                for (Request *r : act) r->status = NEBEM_EDEVICE;
+            }
+            ++s->launches;
+        }
+        (void)hipStreamSynchronize(s->stream);
+        s->busy_s += now_s() - t0;
+        // retire finished requests
+        std::vector<Request *> done;
+        for (Request *r : act) {
+            r->done_pts += r->inflight;
+            r->inflight = 0;
+            if (r->status != NEBEM_OK || r->done_pts >= r->m) done.push_back(r);
+        }
+        for (Request *r : done) {
+            if (r->status == NEBEM_OK) {
+                const size_t b = (size_t)r->m * sizeof(double);
+                double *dst[4] = {r->hphi, r->hex, r->hey, r->hez};
+                for (int k = 0; k < 4; ++k)
+                    if (dst[k] && hipMemcpy(dst[k], stage(s, r, 3 + k), b, hipMemcpyDeviceToHost) != hipSuccess)
+                        r->status = NEBEM_EDEVICE;
+            }
+            r->t_done = now_s();
+        }
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (Request *r : done) {
+                s->arena.release(r->off, r->bytes);
+                s->active.erase(std::find(s->active.begin(), s->active.end(), r));
+                s->points_done += r->m;
+                r->finished = true;
+            }
+        }
+        if (!done.empty()) s->cv_done.notify_all();
+    }
+}
+
+}  // namespace nebem
+
+extern "C" {
+
+void nebem_server_default_options(nebem_server_options *o)
+{
+    if (!o) return;
+    o->hbm_budget = (int64_t)256 << 20;
+    o->batch_interactions = 4e10;
+    o->max_items = 16384;
+}
+
+nebem_status nebem_server_create(nebem_session *const *sessions, int32_t nsessions, const nebem_server_options *opt,
+                                 nebem_server **out)
+{
+    if (!out) return fail(NEBEM_EINVAL, "server_create: NULL output");
+    *out = nullptr;
+    if (!sessions || nsessions < 1 || nsessions > 64) return fail(NEBEM_EINVAL, "server_create: 1..64 sessions");
+    nebem_server_options o;
+    if (opt)
+        o = *opt;
+    else
+        nebem_server_default_options(&o);
+    if (o.hbm_budget < 4096 || !(o.batch_interactions > 0) || o.max_items < 1 || o.max_items > (1 << 20))
+        return fail(NEBEM_EINVAL, "server_create: bad options");
+    for (int k = 0; k < nsessions; ++k)
+        if (!sessions[k]) return fail(NEBEM_EINVAL, "server_create: NULL session");
+    const int mixed = sessions[0]->opt.precision == NEBEM_MIXED;
+    for (int k = 0; k < nsessions; ++k)
+        if ((sessions[k]->opt.precision == NEBEM_MIXED) != (bool)mixed ||
+            sessions[k]->opt.near_factor != sessions[0]->opt.near_factor)
+            return fail(NEBEM_EINVAL, "server_create: sessions must share precision and near_factor");
+    nebem_server *s = new (std::nothrow) nebem_server;
+    if (!s) return fail(NEBEM_ENOMEM, "server_create: host allocation failed");
+    s->opt = o;
+    s->mixed = mixed;
+    s->near_factor = sessions[0]->opt.near_factor;
+    for (int k = 0; k < nsessions; ++k) {
+        s->geoms.push_back(sessions[k]);
+        s->geom_n.push_back(sessions[k]->n);
+    }
+    auto bail = [&](hipError_t e, const char *what) {
+        nebem_status st = hip_fail(e, what);
+        nebem_server_destroy(s);
+        return st;
+    };
+    hipError_t e;
+    if ((e = hipGetDevice(&s->device)) != hipSuccess) return bail(e, "hipGetDevice");
+    if ((e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) != hipSuccess)
+        return bail(e, "hipStreamCreate");
+    if ((e = hipMalloc(&s->arena_dev, (size_t)o.hbm_budget)) != hipSuccess) return bail(e, "hipMalloc(arena)");
+    s->arena.init((size_t)o.hbm_budget);
+    std::vector<ImgArgs> imgs(nsessions);
+    for (int k = 0; k < nsessions; ++k) imgs[k] = sessions[k]->img;
+    if ((e = hipMalloc((void **)&s->imgs_dev, sizeof(ImgArgs) * nsessions)) != hipSuccess)
+        return bail(e, "hipMalloc(images)");
+    if ((e = hipMemcpy(s->imgs_dev, imgs.data(), sizeof(ImgArgs) * nsessions, hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "hipMemcpy(images)");
+    s->items_cap = o.max_items;
+    if ((e = hipMalloc((void **)&s->items_dev, sizeof(WorkItem) * s->items_cap)) != hipSuccess)
+        return bail(e, "hipMalloc(work list)");
+    if ((e = hipHostMalloc((void **)&s->items_host, sizeof(WorkItem) * s->items_cap, hipHostMallocDefault)) !=
+        hipSuccess)
+        return bail(e, "hipHostMalloc(work list)");
+    s->worker = std::thread(worker_main, s);
+    *out = s;
+    return NEBEM_OK;
+}
+
+nebem_status nebem_server_submit(nebem_server *s, int32_t geometry, const double *px, const double *py,
+                                 const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
+                                 int64_t *ticket)
+{
+    if (!s || !ticket) return fail(NEBEM_EINVAL, "server_submit: NULL argument");
+    if (geometry < 0 || geometry >= (int)s->geoms.size()) return fail(NEBEM_EINVAL, "server_submit: bad geometry");
+    if (m < 1 || m > (int64_t)INT32_MAX) return fail(NEBEM_EINVAL, "server_submit: m out of range");
+    if (!px || !py || !pz) return fail(NEBEM_EINVAL, "server_submit: NULL point array");
+    Request *r = new (std::nothrow) Request;
+    if (!r) return fail(NEBEM_ENOMEM, "server_submit: host allocation failed");
+    r->geom = geometry;
+    r->m = m;
+    r->hx = px;
+    r->hy = py;
+    r->hz = pz;
+    r->hphi = phi;
+    r->hex = ex;
+    r->hey = ey;
+    r->hez = ez;
+    r->bytes = (size_t)m * 7 * sizeof(double);
+    if (r->bytes > (size_t)s->opt.hbm_budget) {
+        delete r;
+        return fail(NEBEM_EBUSY, "server_submit: request larger than the server's HBM budget");
+    }
+    r->t_submit = now_s();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) {
+            delete r;
+            return fail(NEBEM_EBUSY, "server_submit: server is shutting down");
+        }
+        r->id = s->next_id++;
+        s->all[r->id] = r;
+        s->queue.push_back(r);
+    }
+    s->cv_work.notify_one();
+    *ticket = r->id;
+    return NEBEM_OK;
+}
+
+nebem_status nebem_server_wait(nebem_server *s, int64_t ticket, nebem_request_stats *st)
+{
+    if (!s) return fail(NEBEM_EINVAL, "server_wait: NULL server");
+    Request *r = nullptr;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(NEBEM_EINVAL, "server_wait: unknown ticket");
+    r = it->second;
+    s->cv_done.wait(lk, [&] { return r->finished; });
+    if (st) {
+        st->t_submit = r->t_submit;
+        st->t_admit = r->t_admit;
+        st->t_done = r->t_done;
+        st->points = r->m;
+    }
+    const nebem_status code = r->status;
+    s->all.erase(it);
+    delete r;
+    if (code) return fail(code, "server_wait: request failed: " + s->worker_error);
+    return NEBEM_OK;
+}
+
+nebem_status nebem_server_stats(nebem_server *s, nebem_server_counters *out)
+{
+    if (!s || !out) return fail(NEBEM_EINVAL, "server_stats: NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    out->launches = s->launches;
+    out->points_done = s->points_done;
+    out->interactions = s->interactions_done;
+    out->busy_s = s->busy_s;
+    out->queued = (int64_t)s->queue.size();
+    out->active = (int64_t)s->active.size();
+    return NEBEM_OK;
+}
+
+void nebem_server_destroy(nebem_server *s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    for (auto &kv : s->all) delete kv.second;
+    if (s->items_host) (void)hipHostFree(s->items_host);
+    if (s->items_dev) (void)hipFree(s->items_dev);
+    if (s->imgs_dev) (void)hipFree(s->imgs_dev);
+    if (s->arena_dev) (void)hipFree(s->arena_dev);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+}  // extern "C"

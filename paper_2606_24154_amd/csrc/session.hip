@@ -1,0 +1,183 @@
+// session.hip -- resident geometries (C-ABI nebem_session_*) and the dynamic
+// space-charge step.
+//
+// A session holds, in device memory, everything the paper keeps resident
+// between right-hand sides (Sec. 4.1): the derived element records, the
+// influence matrix and its factors (FP64 LU, or for the mixed path the FP64
+// matrix plus the equilibrated FP32 LU), the boundary values and the current
+// surface charge densities.  nebem_spacecharge_step is one time step of the
+// dynamic loop of Sec. 4.3 (Algorithm 4) with point charges (Sec. 4.2).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "charge_internal.hpp"
+#include "host_util.hpp"
+#include "nebem_internal.hpp"
+#include "session_internal.hpp"
+
+using namespace nebem;
+
+namespace nebem {
+
+// sigma = A^-1 b with the session's factors
+static nebem_status session_solve(nebem_session *s, const double *b, hipStream_t st)
+{
+    const int n = (int)s->n;
+    if (s->opt.precision == NEBEM_FP64) {
+        nebem_status e = solve_fp64(s->A.as<double>(), n, s->perm.as<int>(), b, 1, s->sigma.as<double>(), st);
+        s->last_info.ir_iters = 0;
+        s->last_info.rel_resid = -1.0;
+        return e;
+    }
+    return solve_mixed(s->A.as<double>(), s->A32.as<float>(), s->scale.as<double>(), s->perm.as<int>(), n, b,
+                       s->sigma.as<double>(), s->opt.ir_tol, s->opt.ir_max_iter, &s->last_info, st);
+}
+
+static nebem_status session_build(nebem_session *s, const nebem_panels *panels, hipStream_t st)
+{
+    const int64_t n = s->n;
+    const int nn = (int)n;
+    NEBEM_HIP(s->drec.ensure((size_t)n * R_STRIDE * sizeof(double)));
+    {
+        DevBuf tmp;
+        nebem_status e = derive(panels, st, tmp);
+        if (e) return e;
+        NEBEM_HIP(hipMemcpyAsync(s->drec.p, tmp.p, (size_t)n * R_STRIDE * sizeof(double), hipMemcpyDeviceToDevice,
+                                 st));
+    }
+    const bool mixed = s->opt.precision == NEBEM_MIXED;
+    NEBEM_HIP(s->A.ensure((size_t)n * n * sizeof(double)));
+    launch_assemble(s->drec.as<double>(), n, s->img, mixed, s->opt.near_factor, nullptr, nullptr, nullptr,
+                    s->A.as<double>(), st);
+    NEBEM_HIP(hipGetLastError());
+    NEBEM_HIP(s->ipiv.ensure((size_t)n * sizeof(int)));
+    NEBEM_HIP(s->perm.ensure((size_t)n * sizeof(int)));
+    std::vector<int> perm;
+    nebem_status e;
+    if (!mixed) {
+        e = factor_fp64(s->A.as<double>(), nn, s->ipiv.as<int>(), perm, st);
+    } else {
+        NEBEM_HIP(s->A32.ensure((size_t)n * n * sizeof(float)));
+        NEBEM_HIP(s->scale.ensure((size_t)n * sizeof(double)));
+        e = factor_mixed(s->A.as<double>(), nn, s->A32.as<float>(), s->scale.as<double>(), s->ipiv.as<int>(), perm,
+                         st);
+    }
+    if (e) return e;
+    NEBEM_HIP(hipMemcpyAsync(s->perm.p, perm.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice, st));
+    NEBEM_HIP(s->b0.ensure((size_t)n * sizeof(double)));
+    NEBEM_HIP(s->sigma.ensure((size_t)n * sizeof(double)));
+    NEBEM_HIP(s->rhs.ensure((size_t)n * sizeof(double)));
+    launch_boundary_values(panels->bc, panels->value, n, s->b0.as<double>(), st);
+    NEBEM_HIP(hipGetLastError());
+    e = session_solve(s, s->b0.as<double>(), st);
+    NEBEM_HIP(hipStreamSynchronize(st));  // perm (host) must outlive its copy
+    return e;
+}
+
+}  // namespace nebem
+
+extern "C" {
+
+nebem_status nebem_session_create(const nebem_panels *panels, const nebem_images *images, const nebem_options *opt,
+                                  hipStream_t stream, nebem_session **out)
+{
+    if (!out) return fail(NEBEM_EINVAL, "session_create: NULL output");
+    *out = nullptr;
+    nebem_status st = check_panels(panels);
+    if (st) return st;
+    if (panels->n == 0) return fail(NEBEM_EINVAL, "session_create: no panels");
+    if (panels->n > 65536 * 4) return fail(NEBEM_EINVAL, "session_create: too many panels");
+    nebem_options o;
+    if (opt)
+        o = *opt;
+    else
+        nebem_default_options(&o);
+    if ((st = check_options(o))) return st;
+    if (o.sc_resolve_every < 1 || !(o.sc_dt >= 0.0) || !(o.sc_mobility >= 0.0))
+        return fail(NEBEM_EINVAL, "session_create: bad space-charge options");
+    nebem_session *s = new (std::nothrow) nebem_session;
+    if (!s) return fail(NEBEM_ENOMEM, "session_create: host allocation failed");
+    s->n = panels->n;
+    s->opt = o;
+    if ((st = make_img_args(images, &s->img))) {
+        delete s;
+        return st;
+    }
+    s->img_count = (double)s->img.nref * (2 * s->img.n1 + 1) * (2 * s->img.n2 + 1);
+    st = session_build(s, panels, stream);
+    if (st && st != NEBEM_ENOCONV) {
+        (void)hipStreamSynchronize(stream);
+        delete s;
+        return st;
+    }
+    *out = s;
+    return st;
+}
+
+void nebem_session_destroy(nebem_session *s) { delete s; }
+
+int64_t nebem_session_n(const nebem_session *s) { return s ? s->n : 0; }
+
+const double *nebem_session_sigma(const nebem_session *s) { return s ? s->sigma.as<double>() : nullptr; }
+
+nebem_status nebem_session_solve(nebem_session *s, const double *b, nebem_solve_info *info, hipStream_t stream)
+{
+    if (!s || !b) return fail(NEBEM_EINVAL, "session_solve: NULL argument");
+    nebem_status st = session_solve(s, b, stream);
+    if (info) *info = s->last_info;
+    if (!st) NEBEM_HIP(hipStreamSynchronize(stream));
+    return st;
+}
+
+nebem_status nebem_session_eval(nebem_session *s, const double *px, const double *py, const double *pz, int64_t m,
+                                double *phi, double *ex, double *ey, double *ez, hipStream_t stream)
+{
+    if (!s) return fail(NEBEM_EINVAL, "session_eval: NULL session");
+    if (m < 0 || m > (int64_t)INT32_MAX - 256) return fail(NEBEM_EINVAL, "session_eval: m out of range");
+    if (m == 0) return NEBEM_OK;
+    if (!px || !py || !pz) return fail(NEBEM_EINVAL, "session_eval: NULL point array");
+    launch_eval(s->drec.as<double>(), s->sigma.as<double>(), s->n, s->img, s->opt.precision == NEBEM_MIXED,
+                s->opt.near_factor, px, py, pz, m, phi, ex, ey, ez, stream);
+    NEBEM_HIP(hipGetLastError());
+    return NEBEM_OK;
+}
+
+nebem_status nebem_spacecharge_step(nebem_session *s, double *qx, double *qy, double *qz, const double *q, int64_t nq,
+                                    int32_t step_index, double *ex, double *ey, double *ez, hipStream_t stream)
+{
+    if (!s) return fail(NEBEM_EINVAL, "spacecharge_step: NULL session");
+    if (nq < 0 || nq > (int64_t)INT32_MAX - 256) return fail(NEBEM_EINVAL, "spacecharge_step: nq out of range");
+    if (step_index < 0) return fail(NEBEM_EINVAL, "spacecharge_step: negative step index");
+    if (nq > 0 && (!qx || !qy || !qz || !q)) return fail(NEBEM_EINVAL, "spacecharge_step: NULL charge array");
+    if ((ex == nullptr) != (ey == nullptr) || (ex == nullptr) != (ez == nullptr))
+        return fail(NEBEM_EINVAL, "spacecharge_step: field arrays must be all NULL or all set");
+    const int64_t n = s->n;
+    nebem_status st = NEBEM_OK;
+    if (step_index % s->opt.sc_resolve_every == 0) {
+        const int nchunk = charge_rhs_chunks(n, nq);
+        NEBEM_HIP(s->part.ensure((size_t)nchunk * n * sizeof(double)));
+        launch_charge_rhs(s->drec.as<double>(), n, qx, qy, qz, q, nq, s->b0.as<double>(), s->part.as<double>(), nchunk,
+                          s->rhs.as<double>(), stream);
+        NEBEM_HIP(hipGetLastError());
+        st = session_solve(s, s->rhs.as<double>(), stream);
+        if (st && st != NEBEM_ENOCONV) return st;
+    }
+    if (nq == 0) return st;
+    if (!ex) {
+        NEBEM_HIP(s->eb.ensure((size_t)3 * nq * sizeof(double)));
+        ex = s->eb.as<double>();
+        ey = ex + nq;
+        ez = ey + nq;
+    }
+    launch_eval(s->drec.as<double>(), s->sigma.as<double>(), n, s->img, s->opt.precision == NEBEM_MIXED,
+                s->opt.near_factor, qx, qy, qz, nq, nullptr, ex, ey, ez, stream);
+    launch_coulomb_self(qx, qy, qz, q, nq, ex, ey, ez, stream);
+    launch_euler(qx, qy, qz, q, ex, ey, ez, nq, s->opt.sc_mobility * s->opt.sc_dt, stream);
+    NEBEM_HIP(hipGetLastError());
+    return st;
+}
+
+}  // extern "C"

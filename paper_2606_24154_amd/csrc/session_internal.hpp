@@ -1,0 +1,45 @@
+// session_internal.hpp -- the resident-geometry object behind nebem_session.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "nebem_internal.hpp"
+
+namespace nebem {
+
+// plain device allocation owned by a session (freed with the session)
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
+    ~DevMem()
+    {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t ensure(size_t b)
+    {
+        if (b <= bytes && p) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        hipError_t e = hipMalloc(&p, b ? b : 8);
+        if (e == hipSuccess) bytes = b;
+        return e;
+    }
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+}  // namespace nebem
+
+struct nebem_session {
+    int64_t n = 0;
+    double img_count = 1.0;  // copies per element (reflections x translations)
+    nebem_options opt;
+    nebem::ImgArgs img;
+    nebem::DevMem drec, A, A32, scale, ipiv, perm, b0, sigma, rhs, part, eb;
+    nebem_solve_info last_info = {0, -1.0};
+};

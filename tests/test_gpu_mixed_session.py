@@ -1,0 +1,263 @@
+"""Mixed-precision path, resident sessions and the space-charge step on the
+GPU, against the CPU oracle.
+
+Bars: FP64 path 1e-10 relative; mixed path 1e-6 relative (phi and E,
+pointwise on points where the reference is >= 1e-3 of its maximum); the
+mixed solve must reach ||b - A x|| <= 1e-10 ||b||.  Point-charge sums run in
+FP32 per pair with FP64 accumulation: their error is bounded relative to the
+sum of the absolute pair terms (condition-normalised) by 1e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import GeometryBuilder, Images, charge_cloud, gem_cell, gem_eval_points, uniform_points
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def nb():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    import paper_2606_24154_amd as nb
+    return nb
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype=dtype)
+
+
+def cols(pts):
+    return [dev(pts[:, k]) for k in range(3)]
+
+
+def stack(out):
+    torch.cuda.synchronize()
+    return np.column_stack([t.cpu().numpy() for t in out])
+
+
+def rel_errors(got, ref, floor=1e-3):
+    ap = np.abs(ref[:, 0])
+    sel = ap >= floor * ap.max()
+    ephi = np.max(np.abs(got[sel, 0] - ref[sel, 0]) / ap[sel])
+    en = np.linalg.norm(ref[:, 1:], axis=1)
+    sel = en >= floor * en.max()
+    eE = np.max(np.linalg.norm(got[sel, 1:] - ref[sel, 1:], axis=1) / en[sel])
+    return ephi, eE
+
+
+@pytest.fixture(scope="module")
+def small_gem():
+    """Reduced GEM cell (688 elements, 25 copies) for full-pipeline parity."""
+    g = gem_cell(k=16, nr=2, nz_kapton=1, nz_cu=1, nd=2, n_images=2)
+    A = oracle.assemble(g)
+    s = oracle.solve(A, g.rhs())
+    pts = gem_eval_points(g, 600, seed=11)
+    f = oracle.eval_points(g, s, pts)
+    return g, A, s, pts, f
+
+
+# ----------------------------------------------------------------- mixed eval
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_mixed_single_element_far_field(nb, kind):
+    """FP64 monopole + FP32 quadrature correction at R >= 4 D: <= 5e-7 per
+    element copy; exact FP64 below 4 D (<= 1e-10)."""
+    rng = np.random.default_rng(70 + kind)
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))
+    lx, lz = 12e-6, 7e-6
+    o = np.array([1e-4, -2e-4, 3e-4])
+    b = GeometryBuilder()
+    (b.rect if kind == 0 else b.right_tri)(o, lx * q[:, 0], lz * q[:, 1])
+    g = b.build("one", Images(), o - 1, o + 1)
+    D = math.hypot(lx, lz)
+    c = o + (0.5 if kind == 0 else 1 / 3) * (lx * q[:, 0] + lz * q[:, 1])
+    d = rng.standard_normal((4000, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    R = D * 10 ** rng.uniform(-2, 3, 4000)
+    pts = c + R[:, None] * d
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    got = stack(nb.eval_points(dp, dev(np.ones(1)), *cols(pts), precision=nb.MIXED))
+    ref = oracle.eval_points(g, np.ones(1), pts)
+    ep = np.abs(got[:, 0] - ref[:, 0]) / np.abs(ref[:, 0])
+    eE = np.linalg.norm(got[:, 1:] - ref[:, 1:], axis=1) / np.linalg.norm(ref[:, 1:], axis=1)
+    near = R < 4 * D
+    assert ep[near].max() < 1e-10 and eE[near].max() < 1e-10
+    assert ep[~near].max() < 5e-7 and eE[~near].max() < 5e-7, (ep[~near].max(), eE[~near].max())
+
+
+def test_mixed_eval_gem_sampled(nb):
+    g = gem_cell()
+    rng = np.random.default_rng(71)
+    sigma = rng.normal(0, 1e-5, g.n)
+    pts = gem_eval_points(g, 5000, seed=12)
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    got = stack(nb.eval_points(dp, dev(sigma), *cols(pts), precision=nb.MIXED))
+    idx = rng.choice(len(pts), 40, replace=False)
+    ref = oracle.eval_points(g, sigma, pts[idx])
+    ephi, eE = rel_errors(got[idx], ref)
+    assert ephi < 1e-6 and eE < 1e-6, (ephi, eE)
+
+
+def test_mixed_assembly_rows(nb, small_gem):
+    g, A_ref, _, _, _ = small_gem
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    A = nb.assemble(dp, precision=nb.MIXED).cpu().numpy().T
+    err = np.abs(A - A_ref) / np.abs(A_ref).max(axis=1, keepdims=True)
+    assert err.max() < 1e-6, err.max()
+
+
+def test_mixed_solve_refines_to_fp64(nb, small_gem):
+    g, A_ref, s_ref, _, _ = small_gem
+    At = dev(np.ascontiguousarray(A_ref.T))
+    b = g.rhs()
+    sigma, ipiv, info = nb.solve(At, dev(b), precision=nb.MIXED)
+    s = sigma.cpu().numpy()
+    assert 1 <= info.ir_iters <= 30 and info.rel_resid <= 1e-10
+    # the matrix is untouched in mixed mode
+    assert np.array_equal(At.cpu().numpy().T, A_ref)
+    r = A_ref @ s - b
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(b)
+    kappa = np.linalg.cond(A_ref, 1)
+    assert np.abs(s - s_ref).max() <= kappa * 2e-10 * np.abs(s_ref).max()
+
+
+def test_mixed_solve_refinement_error_paths(nb, small_gem):
+    g, A_ref, _, _, _ = small_gem
+    At = dev(np.ascontiguousarray(A_ref.T))
+    with pytest.raises(nb.NebemError) as e:
+        nb.solve(At, dev(g.rhs()), precision=nb.MIXED, ir_max_iter=0)
+    assert e.value.code == nb.NEBEM_ENOCONV
+    with pytest.raises(nb.NebemError) as e:
+        nb.solve(At, dev(g.rhs()), precision=nb.MIXED, ir_tol=1e-30)
+    assert e.value.code == nb.NEBEM_ENOCONV
+
+
+# ------------------------------------------------------------------ sessions
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-6)])
+def test_session_pipeline(nb, small_gem, precision, tol):
+    """assemble -> factor -> solve -> evaluate inside a session, vs the oracle
+    pipeline; then a new right-hand side on the resident factors."""
+    g, A_ref, s_ref, pts, f_ref = small_gem
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    ses = nb.Session(dp, precision=precision)
+    assert ses.create_status == nb.NEBEM_OK
+    s = ses.sigma().cpu().numpy()
+    if precision == nb.FP64:
+        kappa = np.linalg.cond(A_ref, 1)
+        assert np.abs(s - s_ref).max() <= 100 * kappa * 2.2e-16 * np.abs(s_ref).max()
+    got = stack(ses.eval_points(*cols(pts)))
+    ephi, eE = rel_errors(got, f_ref)
+    assert ephi < tol and eE < tol, (ephi, eE)
+    # weighting-field style re-solve: unit potential on the top copper only
+    b = np.where((g.bc == 0) & (g.value == -200.0), 1.0, 0.0)
+    code, info = ses.solve(dev(b))
+    assert code == nb.NEBEM_OK
+    ref_w = oracle.solve(A_ref, b)
+    pw = stack(ses.eval_points(*cols(pts)))
+    fw = oracle.eval_points(g, ref_w, pts)
+    ephi, eE = rel_errors(pw, fw)
+    assert ephi < tol and eE < tol, (ephi, eE)
+    ses.close()
+
+
+# -------------------------------------------------------------- space charge
+
+def _charges(g, n, seed):
+    c = np.array([0.5 * (g.images.a1[0] + g.images.a2[0]), 0.5 * g.images.a2[1], 0.0])
+    return charge_cloud(c, 20e-6, n, seed)
+
+
+def test_spacecharge_step_matches_oracle(nb, small_gem):
+    g, A_ref, s_ref, _, _ = small_gem
+    xyz, q = _charges(g, 2048, 13)
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    ses = nb.Session(dp, precision=nb.FP64)
+    qx, qy, qz = cols(xyz)
+    E = tuple(torch.empty(len(q), dtype=torch.float64, device=DEV) for _ in range(3))
+    ses.spacecharge_step(qx, qy, qz, dev(q), 0, E=E)
+    torch.cuda.synchronize()
+    params = oracle.SpaceChargeParams()
+    new_ref, sig_ref, E_ref = oracle.spacecharge_step(g, A_ref, g.rhs(), s_ref, xyz, q, 0, params)
+    s = ses.sigma().cpu().numpy()
+    assert np.abs(s - sig_ref).max() <= 1e-9 * np.abs(sig_ref).max()
+    Eg = np.column_stack([t.cpu().numpy() for t in E])
+    # condition-normalised error of the charge-charge part: bound by the sum of |pair terms|
+    abs_terms = np.zeros(len(q))
+    d = xyz[:, None, :] - xyz[None, :, :]
+    r = np.linalg.norm(d, axis=2)
+    np.fill_diagonal(r, np.inf)
+    abs_terms = oracle.ke() * (np.abs(q)[None, :] / r**2).sum(axis=1)
+    err = np.linalg.norm(Eg - E_ref, axis=1)
+    assert np.max(err / (abs_terms + np.linalg.norm(E_ref, axis=1))) < 1e-6
+    moved = np.column_stack([t.cpu().numpy() for t in (qx, qy, qz)])
+    disp_ref = np.linalg.norm(new_ref - xyz, axis=1)
+    assert np.max(np.linalg.norm(moved - new_ref, axis=1) / disp_ref) < 1e-5
+    ses.close()
+
+
+def test_spacecharge_newton_third_law_and_resolve_schedule(nb, small_gem):
+    """Charge-charge forces sum to zero; sigma is re-solved only on multiples
+    of sc_resolve_every."""
+    g = small_gem[0]
+    xyz, q = _charges(g, 20000, 14)
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    ses = nb.Session(dp, precision=nb.FP64, sc_resolve_every=3)
+    qx, qy, qz = cols(xyz)
+    qd = dev(q)
+    E = tuple(torch.empty(len(q), dtype=torch.float64, device=DEV) for _ in range(3))
+    s0 = ses.sigma().cpu().numpy()
+    ses.spacecharge_step(qx, qy, qz, qd, 1, E=E)     # no re-solve at step 1
+    assert np.array_equal(ses.sigma().cpu().numpy(), s0)
+    # panel part at the start-of-step positions, to isolate the charge part
+    p0 = cols(xyz)
+    panel = stack(ses.eval_points(*p0))[:, 1:]
+    Ec = np.column_stack([t.cpu().numpy() for t in E]) - panel
+    f = (q[:, None] * Ec).sum(axis=0)
+    scale = np.abs(q[:, None] * Ec).sum()
+    assert np.abs(f).max() < 1e-6 * scale
+    ses.spacecharge_step(qx, qy, qz, qd, 3, E=E)     # re-solve at step 3
+    assert not np.array_equal(ses.sigma().cpu().numpy(), s0)
+    ses.close()
+
+
+def test_spacecharge_deterministic(nb, small_gem):
+    g = small_gem[0]
+    xyz, q = _charges(g, 5000, 15)
+    out = []
+    for _ in range(2):
+        dp = nb.DevicePanels.from_geometry(g, DEV)
+        ses = nb.Session(dp)
+        qx, qy, qz = cols(xyz)
+        for k in range(3):
+            ses.spacecharge_step(qx, qy, qz, dev(q), k)
+        torch.cuda.synchronize()
+        out.append(np.column_stack([t.cpu().numpy() for t in (qx, qy, qz)]))
+        ses.close()
+    assert np.array_equal(out[0], out[1])
+
+
+# ------------------------------------------- full-size run, sampled outputs
+
+def test_gem_full_size_sampled(nb):
+    """The benchmark's configuration (8064 elements, 121 copies, 10^6 points),
+    FP64 and mixed, checked on 24 sampled points against the oracle with a
+    seeded density."""
+    g = gem_cell()
+    rng = np.random.default_rng(72)
+    sigma = rng.normal(0, 1e-5, g.n)
+    pts = gem_eval_points(g, 1_000_000, seed=1)
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    idx = rng.choice(len(pts), 24, replace=False)
+    ref = oracle.eval_points(g, sigma, pts[idx])
+    for prec, tol in ((nb.FP64, 1e-10), (nb.MIXED, 1e-6)):
+        got = stack(nb.eval_points(dp, dev(sigma), *cols(pts), precision=prec))
+        assert np.all(np.isfinite(got))
+        ephi, eE = rel_errors(got[idx], ref)
+        assert ephi < tol and eE < tol, (prec, ephi, eE)
