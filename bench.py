@@ -10,8 +10,11 @@ value = (assembly + evaluation interactions per step) / step time, where an
 interaction is one (observation point, element copy) pair.
 
 Prints one JSON line.  Extra keys: per-stage times, the evaluation kernel's
-roofline (FP64 vector ALU bound), and the CPU oracle timed on this host's
-cores on a bounded sample of the same evaluation.
+roofline (FP64 vector ALU bound), the CPU oracle timed on this host's cores
+on a bounded sample of the same evaluation, the mixed-precision step on the
+same input (rate, speedup, largest relative difference from the FP64
+results), and a bounded serving replay (continuous batching over resident
+sessions, Poisson arrivals) with p50/p99 request latency.
 """
 from __future__ import annotations
 
@@ -44,10 +47,20 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=2)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--points", type=int, default=1_000_000)
+    p.add_argument("--workload", choices=["gem", "thgem", "plates"], default="gem",
+                   help="gem: single-GEM cell (default, the headline figure); thgem: staggered double "
+                        "THGEM, 41 600 elements; plates: 512-element parallel plates")
+    p.add_argument("--points", type=int, default=None, help="evaluation points (default per workload)")
     p.add_argument("--cpu-sample", type=int, default=192, help="points in the oracle's timed sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison step")
+    p.add_argument("--serve-requests", type=int, default=120, help="requests in the serving replay (0: skip)")
+    p.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / estimated saturation rate")
+    p.add_argument("--spacecharge", type=int, default=0, metavar="K",
+                   help="instead of the default step: K steps of the dynamic space-charge loop on the GEM "
+                        "cell with 10^6 charges (first step re-solves)")
+    p.add_argument("--charges", type=int, default=1_000_000)
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     return p.parse_args()
@@ -77,10 +90,97 @@ def cpu_baseline(geom, pts, sigma, n_sample):
                       f"({inter:.3e} interactions, {dt:.1f} s)"}
 
 
+def rel_diff(a, b, floor=1e-3):
+    """max pointwise relative difference of phi and |E| (points where the
+    reference magnitude is >= floor of its maximum)"""
+    ap = np.abs(b[0])
+    sel = ap >= floor * ap.max()
+    ephi = float(np.max(np.abs(a[0][sel] - b[0][sel]) / ap[sel]))
+    en = np.sqrt(b[1] ** 2 + b[2] ** 2 + b[3] ** 2)
+    dn = np.sqrt((a[1] - b[1]) ** 2 + (a[2] - b[2]) ** 2 + (a[3] - b[3]) ** 2)
+    sel = en >= floor * en.max()
+    return ephi, float(np.max(dn[sel] / en[sel]))
+
+
+def serve_replay(nb, geoms, sessions, n_req, load, eval_rate, seed=4):
+    """Config-4 style replay over resident sessions: Poisson arrivals at
+    `load` x the saturation rate estimated from the measured evaluation rate,
+    geometry uniform, sizes log-uniform in [64, 262144], seeded points."""
+    from paper_2606_24154_amd.serving import replay
+    from synth import serve_requests, uniform_points
+    per_pt = np.mean([g.n * g.images.count for g in geoms])
+    mean_pts = (262144 - 64) / np.log(262144 / 64)
+    mu_req = eval_rate / (per_pt * mean_pts)
+    reqs = serve_requests(n_req, rate_hz=load * mu_req, n_geometries=len(geoms), seed=seed)
+    srv = nb.Server(sessions, hbm_budget=1 << 30, batch_interactions=2e10)
+
+    def make_points(g, n, sd):
+        return uniform_points(geoms[g].box_lo, geoms[g].box_hi, n, sd)
+
+    run = replay(srv, reqs, make_points)
+    c = srv.counters()
+    srv.close()
+    return {"requests": n_req, "arrival_rate_hz": load * mu_req, "load": load,
+            "p50_ms": 1e3 * run["p50_s"], "p99_ms": 1e3 * run["p99_s"],
+            "points_per_s": run["points_per_s"], "interactions_per_s": c.interactions / run["span_s"],
+            "launches": int(c.launches), "errors": len(run["errors"])}
+
+
+def spacecharge_bench(args):
+    """Config 3: GEM cell, charges ~ N(hole centre, 20 um), +-e alternating;
+    each step = (re-solve every 10th step) + panel field at every charge +
+    all-pairs charge field + Euler move."""
+    import torch
+
+    import paper_2606_24154_amd as nb
+    from synth import charge_cloud, gem_cell
+
+    dev = torch.device("cuda:0")
+    geom = gem_cell()
+    prec = nb.MIXED if args.precision == "mixed" else nb.FP64
+    ses = nb.Session(nb.DevicePanels.from_geometry(geom, dev), precision=prec)
+    centre = [0.5 * (geom.images.a1[0] + geom.images.a2[0]), 0.5 * geom.images.a2[1], 0.0]
+    xyz, q = charge_cloud(centre, 20e-6, args.charges, seed=3)
+    qx, qy, qz = (torch.from_numpy(np.ascontiguousarray(xyz[:, k])).to(dev) for k in range(3))
+    qd = torch.from_numpy(q).to(dev)
+    E = tuple(torch.empty(len(q), dtype=torch.float64, device=dev) for _ in range(3))
+    stream = torch.cuda.current_stream()
+    # panel-only time at the charges (the same launch the step makes)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    ses.eval_points(qx, qy, qz)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    t_panel = ev[0].elapsed_time(ev[1]) * 1e-3
+    times = []
+    for k in range(args.spacecharge):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ses.spacecharge_step(qx, qy, qz, qd, k, E=E)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    nq = len(q)
+    t_plain = float(np.median(times[1:])) if len(times) > 1 else times[0]
+    pairs = nq * (nq - 1)
+    panel_inter = nq * geom.n * geom.images.count
+    rec = {"metric": "space-charge step time", "value": 1e3 * t_plain, "unit": "ms/step",
+           "higher_is_better": False, "n_gpus": 1, "steps": args.spacecharge, "dtype": args.precision,
+           "config": {"workload": f"gem_cell + {nq} point charges (+-e), N={geom.n}, C={geom.images.count}, "
+                                  f"dt=1 ps, mobility 1e-4 m^2/Vs, re-solve every 10 steps"},
+           "step_ms": [1e3 * t for t in times], "panel_part_ms": 1e3 * t_panel,
+           "panel_interactions_per_s": panel_inter / t_panel,
+           "pair_interactions_per_s": pairs / max(t_plain - t_panel, 1e-9),
+           "resolve_step_ms": 1e3 * times[0]}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.spacecharge:
+        spacecharge_bench(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU sharding is not built "
@@ -89,14 +189,23 @@ def main():
     import torch
 
     import paper_2606_24154_amd as nb
-    from synth import gem_cell, gem_eval_points
+    from synth import gem_cell, gem_eval_points, parallel_plates, thgem_double, thgem_eval_points, uniform_points
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    geom = gem_cell()
+    if args.workload == "gem":
+        geom = gem_cell()
+        M = args.points or 1_000_000
+        pts = gem_eval_points(geom, M, seed=1)
+    elif args.workload == "thgem":
+        geom = thgem_double()
+        M = args.points or 4_000_000
+        pts = thgem_eval_points(geom, M, seed=2)
+    else:
+        geom = parallel_plates()
+        M = args.points or 4096
+        pts = uniform_points(geom.box_lo, geom.box_hi, M, 0)
     n, C = geom.n, geom.images.count
-    M = args.points
-    pts = gem_eval_points(geom, M, seed=1)
     dp = nb.DevicePanels.from_geometry(geom, dev)
     px, py, pz = (torch.from_numpy(np.ascontiguousarray(pts[:, k])).to(dev) for k in range(3))
     b = torch.from_numpy(geom.rhs()).to(dev)
@@ -142,12 +251,44 @@ def main():
     eval_rate = inter_eval / (ms["eval"] * 1e-3)
 
     roof = None
-    if FLOPS_PER_INTERACTION is not None and prec == nb.FP64:
+    if FLOPS_PER_INTERACTION is not None and prec == nb.FP64 and args.workload == "gem":
         ach = FLOPS_PER_INTERACTION * inter_eval / (ms["eval"] * 1e-3)
         roof = {"bound": "alu", "kernel": "k_eval_fp64", "achieved": ach / 1e12, "peak": FP64_VALU_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK,
-                "traffic": EVAL_TRAFFIC_BYTES if M == 1_000_000 else None,
+                "traffic": EVAL_TRAFFIC_BYTES if (M == 1_000_000 and args.workload == "gem") else None,
                 "flops_per_interaction": FLOPS_PER_INTERACTION}
+
+    mixed = None
+    if not args.no_mixed and prec == nb.FP64:
+        torch.cuda.synchronize()
+        ref = [t.cpu().numpy() for t in out]
+        t1 = time.perf_counter()
+        nb.assemble(dp, A=A, precision=nb.MIXED)
+        _, _, si = nb.solve(A, b, sigma=sigma, ipiv=ipiv, precision=nb.MIXED)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        nb.eval_points(dp, sigma, px, py, pz, out=out, precision=nb.MIXED)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dt_m = time.perf_counter() - t1
+        got = [t.cpu().numpy() for t in out]
+        ephi, eE = rel_diff(got, ref)
+        mixed = {"value": (inter_asm + inter_eval) / dt_m, "ms_per_step": 1e3 * dt_m,
+                 "eval_interactions_per_s": inter_eval / (e0.elapsed_time(e1) * 1e-3),
+                 "speedup_vs_fp64": ms_step / (1e3 * dt_m), "ir_iters": si.ir_iters,
+                 "rel_resid": si.rel_resid, "max_rel_diff_vs_fp64": {"phi": ephi, "E": eE}}
+
+    serve = None
+    if args.serve_requests > 0 and prec == nb.FP64 and args.workload == "gem":
+        from synth import parallel_plates
+        geoms = [parallel_plates(), geom]
+        serve = {}
+        for name, pr in (("fp64", nb.FP64), ("mixed", nb.MIXED)):
+            ses = [nb.Session(nb.DevicePanels.from_geometry(g, dev), precision=pr) for g in geoms]
+            serve[name] = serve_replay(nb, geoms, ses, args.serve_requests, args.serve_load, eval_rate)
+            for x in ses:
+                x.close()
 
     cpu = None
     if not args.no_cpu:
@@ -160,11 +301,11 @@ def main():
         "value": value, "unit": "interactions/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if prec == nb.FP64 else "f64+f32", "data": "synthetic",
-        "config": {"workload": f"gem_cell: N={n} elements, C={C} copies, M={M} points; "
+        "config": {"workload": f"{geom.name}: N={n} elements, C={C} copies, M={M} points; "
                                f"assemble + LU solve + evaluate, {args.precision}",
                    "elements": n, "copies": C, "points": M},
         "stages_ms": ms, "eval_interactions_per_s": eval_rate, "solve_info": info,
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu, "mixed": mixed, "serve": serve,
     }
     print(json.dumps(rec), flush=True)
 

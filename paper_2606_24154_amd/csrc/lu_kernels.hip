@@ -296,23 +296,27 @@ __global__ __launch_bounds__(256) void k_trsv_step(const T *__restrict__ LU, int
             y[rr][q] = X[(size_t)(rc + q) * n + b0 + rr];
         }
         __syncthreads();
-        if (tid < nr) {
-            const int q = tid;
-            if (lower) {
-                for (int i = 0; i < bsz; ++i) {
-                    TX s = y[i][q];
-                    for (int j = 0; j < i; ++j) s -= D[i][j] * y[j][q];
-                    y[i][q] = s;
+        // diagonal block: column-oriented substitution, the updates of the
+        // remaining rows of step i spread over the threads (row x rhs pairs)
+        if (lower) {
+            for (int i = 0; i < bsz - 1; ++i) {
+                for (int e = tid; e < (bsz - 1 - i) * nr; e += 256) {
+                    const int r = i + 1 + e % (bsz - 1 - i), q = e / (bsz - 1 - i);
+                    y[r][q] -= D[r][i] * y[i][q];
                 }
-            } else {
-                for (int i = bsz - 1; i >= 0; --i) {
-                    TX s = y[i][q];
-                    for (int j = i + 1; j < bsz; ++j) s -= D[i][j] * y[j][q];
-                    y[i][q] = s / D[i][i];
+                __syncthreads();
+            }
+        } else {
+            for (int i = bsz - 1; i >= 0; --i) {
+                if (tid < nr) y[i][tid] /= D[i][i];
+                __syncthreads();
+                for (int e = tid; e < i * nr; e += 256) {
+                    const int r = e % i, q = e / i;
+                    y[r][q] -= D[r][i] * y[i][q];
                 }
+                __syncthreads();
             }
         }
-        __syncthreads();
         if (blockIdx.x == 0)
             for (int e = tid; e < bsz * nr; e += 256) {
                 const int rr = e % bsz, q = e / bsz;

@@ -34,6 +34,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "fastmath_fp64.hpp"
+
 namespace nebem {
 
 struct Kern {
@@ -59,7 +61,7 @@ __device__ __forceinline__ double edge_log(double lm, double lp, double Rm, doub
     const double dp = pp ? Rp + lp : 1.0;
     const double nm = mn ? rho2 : Rm + lm;
     const double dm = mn ? Rm - lm : 1.0;
-    return log1p((L + L) * dp * dm / (np * dm + nm * dp));
+    return log1p_ratio((L + L) * dp * dm, np * dm + nm * dp);
 }
 
 // Solid-angle branch repair: the true half-angle has the sign of N and
@@ -77,10 +79,10 @@ __device__ __forceinline__ Kern rect_fp64(double X, double H, double Z, double l
     const double H2 = H * H;
     const double xm = X - lx, zm = Z - lz;
     const double X2 = X * X, Z2 = Z * Z, xm2 = xm * xm, zm2 = zm * zm;
-    const double r00 = sqrt(X2 + Z2 + H2);
-    const double r10 = sqrt(xm2 + Z2 + H2);
-    const double r11 = sqrt(xm2 + zm2 + H2);
-    const double r01 = sqrt(X2 + zm2 + H2);
+    const double r00 = sqrt64(X2 + Z2 + H2);
+    const double r10 = sqrt64(xm2 + Z2 + H2);
+    const double r11 = sqrt64(xm2 + zm2 + H2);
+    const double r01 = sqrt64(X2 + zm2 + H2);
     // edges (start -> end, outward normal m, distance p of the projected point
     // from the edge line, inside positive):
     //   0 (0,0)->(lx,0)   m=(0,-1) p=Z     1 (lx,0)->(lx,lz) m=(1,0) p=lx-X
@@ -98,7 +100,7 @@ __device__ __forceinline__ Kern rect_fp64(double X, double H, double Z, double l
     const double d11_01 = X * xm + zm2 + H2;
     const double D1 = r00 * r10 * r11 + d00_10 * r11 + d00_11 * r10 + d10_11 * r00;
     const double D2 = r00 * r11 * r01 + d00_11 * r01 + d00_01 * r11 + d11_01 * r00;
-    double half = atan2(N * (D1 + D2), D1 * D2 - N * N);
+    double half = atan2_64(N * (D1 + D2), D1 * D2 - N * N);
     half = half_angle_fix(half, N);
     const double omega = (H == 0.0) ? 0.0 : 2.0 * half;
     Kern k;
@@ -115,9 +117,9 @@ __device__ __forceinline__ Kern rtri_fp64(double X, double H, double Z, double l
     const double H2 = H * H;
     const double xm = X - lx, zm = Z - lz;
     const double X2 = X * X, Z2 = Z * Z;
-    const double r0 = sqrt(X2 + Z2 + H2);
-    const double r1 = sqrt(xm * xm + Z2 + H2);
-    const double r2 = sqrt(X2 + zm * zm + H2);
+    const double r0 = sqrt64(X2 + Z2 + H2);
+    const double r1 = sqrt64(xm * xm + Z2 + H2);
+    const double r2 = sqrt64(X2 + zm * zm + H2);
     // edges: 0 (0,0)->(lx,0) m=(0,-1) p=Z;  1 (lx,0)->(0,lz) m=(lz,lx)/hyp
     //        p=(lx lz - X lz - Z lx)/hyp;   2 (0,lz)->(0,0) m=(-1,0) p=X
     const double P1 = (lx * lz - X * lz - Z * lx) * ihyp;
@@ -129,7 +131,7 @@ __device__ __forceinline__ Kern rtri_fp64(double X, double H, double Z, double l
     const double d02 = X2 + Z * zm + H2;
     const double d12 = X * xm + Z * zm + H2;
     const double D = r0 * r1 * r2 + d01 * r2 + d02 * r1 + d12 * r0;
-    const double omega = (H == 0.0) ? 0.0 : 2.0 * atan2(N, D);
+    const double omega = (H == 0.0) ? 0.0 : 2.0 * atan2_64(N, D);
     const double L1h = L1 * ihyp;
     Kern k;
     k.phi = Z * L0 + P1 * L1 + X * L2 - H * omega;

@@ -155,7 +155,10 @@ def test_session_pipeline(nb, small_gem, precision, tol):
     got = stack(ses.eval_points(*cols(pts)))
     ephi, eE = rel_errors(got, f_ref)
     assert ephi < tol and eE < tol, (ephi, eE)
-    # weighting-field style re-solve: unit potential on the top copper only
+    # weighting-field style re-solve: unit potential on the top copper only.
+    # Two independent pipelines differ by the solve's forward error (c kappa u
+    # relative in sigma); the weighting potential is small in much of the
+    # gap, so the end-to-end bound scales with kappa_1(A).
     b = np.where((g.bc == 0) & (g.value == -200.0), 1.0, 0.0)
     code, info = ses.solve(dev(b))
     assert code == nb.NEBEM_OK
@@ -163,7 +166,9 @@ def test_session_pipeline(nb, small_gem, precision, tol):
     pw = stack(ses.eval_points(*cols(pts)))
     fw = oracle.eval_points(g, ref_w, pts)
     ephi, eE = rel_errors(pw, fw)
-    assert ephi < tol and eE < tol, (ephi, eE)
+    kappa = np.linalg.cond(A_ref, 1)
+    tol_w = max(tol, 10 * kappa * 2.2e-16)
+    assert ephi < tol_w and eE < tol_w, (ephi, eE, kappa)
     ses.close()
 
 
