@@ -33,11 +33,11 @@ sys.path.insert(0, ROOT)
 # this workload, from rocprofv3 counters (64 x (ADD + MUL + TRANS + 2 FMA)
 # FP64 instructions of one evaluation launch / its interactions); see the
 # profile summaries committed under profiles/.
-FLOPS_PER_INTERACTION = 614.0
+FLOPS_PER_INTERACTION = 333.6
 # HBM bytes per evaluation launch at the default workload (FETCH_SIZE x 2 +
 # WRITE_SIZE x 1, the factors that make a plain 1 GiB copy read 1 GiB and
 # write 1 GiB); None when not measured for the current kernel.
-EVAL_TRAFFIC_BYTES = 6.912e7
+EVAL_TRAFFIC_BYTES = 6.907e7
 FP64_VALU_PEAK = 78.6e12      # MI355X, FLOP/s
 HBM_PEAK = 8.0e12             # B/s
 
@@ -112,7 +112,7 @@ def serve_replay(nb, geoms, sessions, n_req, load, eval_rate, seed=4):
     mean_pts = (262144 - 64) / np.log(262144 / 64)
     mu_req = eval_rate / (per_pt * mean_pts)
     reqs = serve_requests(n_req, rate_hz=load * mu_req, n_geometries=len(geoms), seed=seed)
-    srv = nb.Server(sessions, hbm_budget=1 << 30, batch_interactions=2e10)
+    srv = nb.Server(sessions)
 
     def make_points(g, n, sd):
         return uniform_points(geoms[g].box_lo, geoms[g].box_hi, n, sd)

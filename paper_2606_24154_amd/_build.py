@@ -42,7 +42,8 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for p in procs:
         _wait(p)
     tmp = LIB + ".tmp"
-    subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], check=True)
+    subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,--no-undefined", *objs, "-o", tmp],
+                   check=True)
     os.replace(tmp, LIB)
     return LIB
 

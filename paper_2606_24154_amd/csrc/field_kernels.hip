@@ -246,14 +246,16 @@ __device__ __forceinline__ void element_copies(const Elem &e, const ImgArgs &img
 }
 
 // -------------------------------------------------------------- evaluation
-// One workgroup's share of an evaluation: points [base, base + 256) of the
-// m points, all elements and copies, FP64 sums per lane.
-template <bool MIXED>
+// One workgroup's share of an evaluation: points [base, base + BS) of the
+// m points, all n elements (records drec, densities sigma) and their copies,
+// FP64 sums per lane; outputs scaled by `scale`.
+template <bool MIXED, int BS>
 __device__ __forceinline__ void eval_block(const double *__restrict__ drec, const double *__restrict__ sigma, int n,
                                            const ImgArgs &img, double near_factor, const double *__restrict__ px,
                                            const double *__restrict__ py, const double *__restrict__ pz, int m,
-                                           int base_pt, double *__restrict__ phi, double *__restrict__ ex,
-                                           double *__restrict__ ey, double *__restrict__ ez)
+                                           int base_pt, double scale, double *__restrict__ phi,
+                                           double *__restrict__ ex, double *__restrict__ ey,
+                                           double *__restrict__ ez)
 {
     __shared__ double t_rec[kTileE * R_STRIDE];
     __shared__ double t_sig[kTileE];
@@ -266,9 +268,8 @@ __device__ __forceinline__ void eval_block(const double *__restrict__ drec, cons
     for (int base = 0; base < n; base += kTileE) {
         const int cnt = min(kTileE, n - base);
         __syncthreads();
-        for (int k = threadIdx.x; k < cnt * R_STRIDE; k += kBlock)
-            t_rec[k] = drec[(size_t)base * R_STRIDE + k];
-        if (threadIdx.x < cnt) t_sig[threadIdx.x] = sigma[base + threadIdx.x];
+        for (int k = threadIdx.x; k < cnt * R_STRIDE; k += BS) t_rec[k] = drec[(size_t)base * R_STRIDE + k];
+        for (int k = threadIdx.x; k < cnt; k += BS) t_sig[k] = sigma[base + k];
         __syncthreads();
         for (int p = 0; p < cnt; ++p) {
             const Elem e = load_elem(t_rec + p * R_STRIDE);
@@ -282,10 +283,10 @@ __device__ __forceinline__ void eval_block(const double *__restrict__ drec, cons
         }
     }
     if (act) {
-        if (phi) phi[i] = kKe * aphi;
-        if (ex) ex[i] = kKe * aex;
-        if (ey) ey[i] = kKe * aey;
-        if (ez) ez[i] = kKe * aez;
+        if (phi) phi[i] = scale * aphi;
+        if (ex) ex[i] = scale * aex;
+        if (ey) ey[i] = scale * aey;
+        if (ez) ez[i] = scale * aez;
     }
 }
 
@@ -297,30 +298,8 @@ __global__ __launch_bounds__(kBlock) void k_eval(const double *__restrict__ drec
                                                   double *__restrict__ ex, double *__restrict__ ey,
                                                   double *__restrict__ ez)
 {
-    eval_block<MIXED>(drec, sigma, n, img, near_factor, px, py, pz, m, blockIdx.x * kBlock, phi, ex, ey, ez);
-}
-
-// Continuous-batching evaluation: workgroup b takes work item b -- up to 256
-// points of one request on one resident geometry.  The per-point arithmetic
-// is eval_block's, so a point's result does not depend on which other
-// requests share the launch.
-template <bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_eval_worklist(const WorkItem *__restrict__ items,
-                                                           const ImgArgs *__restrict__ imgs, double near_factor)
-{
-    const WorkItem &w = items[blockIdx.x];
-    eval_block<MIXED>(w.drec, w.sigma, w.n, imgs[w.geom], near_factor, w.px, w.py, w.pz, w.count, 0, w.phi, w.ex,
-                      w.ey, w.ez);
-}
-
-void launch_eval_worklist(const WorkItem *items, int nitems, const ImgArgs *imgs, int mixed, double near_factor,
-                          hipStream_t s)
-{
-    if (nitems <= 0) return;
-    if (mixed)
-        hipLaunchKernelGGL(k_eval_worklist<true>, dim3(nitems), dim3(kBlock), 0, s, items, imgs, near_factor);
-    else
-        hipLaunchKernelGGL(k_eval_worklist<false>, dim3(nitems), dim3(kBlock), 0, s, items, imgs, near_factor);
+    eval_block<MIXED, kBlock>(drec, sigma, n, img, near_factor, px, py, pz, m, blockIdx.x * kBlock, kKe, phi, ex, ey,
+                              ez);
 }
 
 void launch_eval(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
@@ -335,6 +314,49 @@ void launch_eval(const double *drec, const double *sigma, int64_t n, const ImgAr
     else
         hipLaunchKernelGGL(k_eval<false>, dim3(g), dim3(kBlock), 0, s, drec, sigma, (int)n, img, near_factor, px,
                            py, pz, (int)m, phi, ex, ey, ez);
+}
+
+// Continuous-batching evaluation: workgroup (one wave) b takes work item b --
+// up to 64 points of one request against one segment of the elements of one
+// resident geometry -- and writes the segment's unscaled partial sums.  The
+// per-point arithmetic does not depend on which other items share the launch.
+template <bool MIXED>
+__global__ __launch_bounds__(64) void k_eval_items(const WorkItem *__restrict__ items,
+                                                    const ImgArgs *__restrict__ imgs, double near_factor)
+{
+    const WorkItem &w = items[blockIdx.x];
+    eval_block<MIXED, 64>(w.drec, w.sigma, w.n, imgs[w.geom], near_factor, w.px, w.py, w.pz, w.count, 0, 1.0,
+                          w.phi, w.ex, w.ey, w.ez);
+}
+
+void launch_eval_items(const WorkItem *items, int nitems, const ImgArgs *imgs, int mixed, double near_factor,
+                       hipStream_t s)
+{
+    if (nitems <= 0) return;
+    if (mixed)
+        hipLaunchKernelGGL(k_eval_items<true>, dim3(nitems), dim3(64), 0, s, items, imgs, near_factor);
+    else
+        hipLaunchKernelGGL(k_eval_items<false>, dim3(nitems), dim3(64), 0, s, items, imgs, near_factor);
+}
+
+// out[k][i] = k_e sum_{s < nseg} part[(s * 4 + k) * m + i], k = phi, ex, ey, ez
+__global__ __launch_bounds__(kBlock) void k_reduce_segments(const double *__restrict__ part, int nseg, int m,
+                                                             double *__restrict__ out)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m) return;
+    for (int k = 0; k < 4; ++k) {
+        double acc = 0.0;
+        for (int s = 0; s < nseg; ++s) acc += part[((size_t)s * 4 + k) * m + i];
+        out[(size_t)k * m + i] = kKe * acc;
+    }
+}
+
+void launch_reduce_segments(const double *part, int nseg, int64_t m, double *out, hipStream_t s)
+{
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_reduce_segments, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, part, nseg,
+                       (int)m, out);
 }
 
 // ---------------------------------------------------------------- assembly

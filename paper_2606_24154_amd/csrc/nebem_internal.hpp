@@ -58,16 +58,17 @@ nebem_status hip_fail(hipError_t e, const char *what);
 
 nebem_status make_img_args(const nebem_images *im, ImgArgs *out);
 
-// One unit of serving work: up to 256 points of one request on one resident
-// geometry (device pointers).
+// One unit of serving work: up to 64 points of one request against one
+// segment of the elements of one resident geometry (device pointers; drec and
+// sigma already offset to the segment's first element).
 struct WorkItem {
     const double *drec;
     const double *sigma;
     const double *px, *py, *pz;
-    double *phi, *ex, *ey, *ez;
-    int n;      // elements of the geometry
+    double *phi, *ex, *ey, *ez;  // the segment's partial sums (unscaled)
+    int n;      // elements in the segment
     int geom;   // index into the image-argument array
-    int count;  // points in this item (<= 256)
+    int count;  // points in this item (<= 64)
     int pad;
 };
 
@@ -81,9 +82,11 @@ void launch_prep(const nebem_panels *p, double *drec, int *bad, hipStream_t s);
 void launch_eval(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
                  double near_factor, const double *px, const double *py, const double *pz, int64_t m, double *phi,
                  double *ex, double *ey, double *ez, hipStream_t s);
-// items/imgs in device memory
-void launch_eval_worklist(const WorkItem *items, int nitems, const ImgArgs *imgs, int mixed, double near_factor,
-                          hipStream_t s);
+// items/imgs in device memory; one 64-lane workgroup per item
+void launch_eval_items(const WorkItem *items, int nitems, const ImgArgs *imgs, int mixed, double near_factor,
+                       hipStream_t s);
+// out (4 x m) = k_e * sum over nseg segments of part (nseg x 4 x m), fixed order
+void launch_reduce_segments(const double *part, int nseg, int64_t m, double *out, hipStream_t s);
 // A (n x n col-major).  cx/cy/cz may be null (centroids).
 void launch_assemble(const double *drec, int64_t n, const ImgArgs &img, int mixed, double near_factor,
                      const double *cx, const double *cy, const double *cz, double *A, hipStream_t s);

@@ -7,15 +7,20 @@
 //   1. admission: queued requests enter, in arrival order, while their
 //      points and results (56 bytes per point) fit into the device staging
 //      arena of hbm_budget bytes; their points are copied in;
-//   2. batching: the active requests are cut into 256-point work items,
-//      taken round-robin (one item per request per round) until the
-//      iteration's interaction budget is used; items of different requests
-//      and geometries go into ONE launch of the work-list evaluation kernel;
-//   3. completion: a request whose items are all done has its results
-//      copied back to the caller's host arrays, its arena space freed and its
-//      waiter woken; new requests are admitted on the next iteration.
-// Every point is evaluated by the same per-lane code as nebem_session_eval,
-// so a request's results are identical whether it runs alone or in a mix.
+//   2. batching: the active requests are cut into work items of 64 points x
+//      one segment of the geometry's elements (each geometry's element range
+//      is split into a fixed number of segments of about kSegWork
+//      interactions per point, so that one heavy point is not a long serial
+//      chain in a single lane), taken round-robin (one item per request per
+//      round) until the iteration's interaction budget is used; items of
+//      different requests and geometries go into ONE launch;
+//   3. completion: a request whose items are all done has its segment
+//      partial sums reduced in a fixed order, its results copied back to the
+//      caller's host arrays, its arena space freed and its waiter woken; new
+//      requests are admitted on the next iteration.
+// Each point's partial sums and their reduction have a fixed order that does
+// not depend on the other requests, so a request's results are identical
+// whether it runs alone or in a mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,6 +40,9 @@
 
 namespace nebem {
 
+constexpr double kSegWork = 1.2e5;  // interactions per point per element segment
+constexpr int kMaxSeg = 64;
+
 static double now_s()
 {
     using namespace std::chrono;
@@ -49,9 +57,11 @@ struct Request {
     double *hphi = nullptr, *hex = nullptr, *hey = nullptr, *hez = nullptr;
     double t_submit = 0, t_admit = 0, t_done = 0;
     size_t off = 0, bytes = 0;  // arena placement
-    int64_t next = 0;           // first point not yet scheduled
-    int64_t inflight = 0;       // points scheduled in the current launch
-    int64_t done_pts = 0;
+    int nseg = 1;               // element segments of its geometry
+    int64_t nitems = 0;         // 64-point chunks x segments
+    int64_t next = 0;           // first item not yet scheduled
+    int64_t inflight = 0;       // items scheduled in the current launch
+    int64_t done_items = 0;
     int status = NEBEM_OK;
     bool finished = false;
 };
@@ -105,6 +115,8 @@ struct nebem_server {
     nebem_server_options opt;
     std::vector<nebem_session *> geoms;
     std::vector<int64_t> geom_n;
+    std::vector<int> geom_nseg;   // element segments per geometry
+    std::vector<int> geom_segsz;  // elements per segment (last may be shorter)
     int mixed = 0;
     double near_factor = 4.0;
     hipStream_t stream = nullptr;
@@ -148,7 +160,8 @@ static bool admit_locked(nebem_server *s)
     return any;
 }
 
-// device addresses of a request's staging
+// device addresses of a request's staging: columns 0-2 points, 3-6 results,
+// then nseg x 4 columns of segment partial sums
 static inline double *stage(nebem_server *s, const Request *r, int k)
 {
     return reinterpret_cast<double *>(static_cast<char *>(s->arena_dev) + r->off) + (size_t)k * r->m;
@@ -184,28 +197,33 @@ static void worker_main(nebem_server *s)
         while (progress && budget > 0.0 && nitems < s->items_cap) {
             progress = false;
             for (Request *r : act) {
-                if (r->status != NEBEM_OK || r->next >= r->m || nitems >= s->items_cap) continue;
-                const double per_pt = (double)s->geom_n[r->geom] * s->geoms[r->geom]->img_count;
-                const int cnt = (int)std::min<int64_t>(256, r->m - r->next);
-                WorkItem &w = s->items_host[nitems++];
+                if (r->status != NEBEM_OK || r->next >= r->nitems || nitems >= s->items_cap) continue;
                 const nebem_session *g = s->geoms[r->geom];
-                w.drec = g->drec.as<double>();
-                w.sigma = g->sigma.as<double>();
-                w.n = (int)g->n;
+                const int64_t chunk = r->next / r->nseg;
+                const int seg = (int)(r->next % r->nseg);
+                const int64_t p0 = chunk * 64;
+                const int cnt = (int)std::min<int64_t>(64, r->m - p0);
+                const int e0 = seg * s->geom_segsz[r->geom];
+                const int ne = (int)std::min<int64_t>(s->geom_segsz[r->geom], g->n - e0);
+                WorkItem &w = s->items_host[nitems++];
+                w.drec = g->drec.as<double>() + (size_t)e0 * R_STRIDE;
+                w.sigma = g->sigma.as<double>() + e0;
+                w.n = ne;
                 w.geom = r->geom;
                 w.count = cnt;
                 w.pad = 0;
-                w.px = stage(s, r, 0) + r->next;
-                w.py = stage(s, r, 1) + r->next;
-                w.pz = stage(s, r, 2) + r->next;
-                w.phi = stage(s, r, 3) + r->next;
-                w.ex = stage(s, r, 4) + r->next;
-                w.ey = stage(s, r, 5) + r->next;
-                w.ez = stage(s, r, 6) + r->next;
-                r->next += cnt;
-                r->inflight += cnt;
-                budget -= per_pt * cnt;
-                s->interactions_done += per_pt * cnt;
+                w.px = stage(s, r, 0) + p0;
+                w.py = stage(s, r, 1) + p0;
+                w.pz = stage(s, r, 2) + p0;
+                w.phi = stage(s, r, 7 + 4 * seg) + p0;
+                w.ex = stage(s, r, 8 + 4 * seg) + p0;
+                w.ey = stage(s, r, 9 + 4 * seg) + p0;
+                w.ez = stage(s, r, 10 + 4 * seg) + p0;
+                r->next += 1;
+                r->inflight += 1;
+                const double work = (double)ne * g->img_count * cnt;
+                budget -= work;
+                s->interactions_done += work;
                 progress = true;
                 if (budget <= 0.0) break;
             }
@@ -215,7 +233,7 @@ static void worker_main(nebem_server *s)
             hipError_t e = hipMemcpyAsync(s->items_dev, s->items_host, (size_t)nitems * sizeof(WorkItem),
                                           hipMemcpyHostToDevice, s->stream);
             if (e == hipSuccess) {
-                launch_eval_worklist(s->items_dev, nitems, s->imgs_dev, s->mixed, s->near_factor, s->stream);
+                launch_eval_items(s->items_dev, nitems, s->imgs_dev, s->mixed, s->near_factor, s->stream);
                 e = hipGetLastError();
             }
             if (e != hipSuccess) {
@@ -225,15 +243,17 @@ static void worker_main(nebem_server *s)
             }
             ++s->launches;
         }
-        (void)hipStreamSynchronize(s->stream);
-        s->busy_s += now_s() - t0;
-        // retire finished requests
+        // retire finished requests: reduce their segments, copy results back
         std::vector<Request *> done;
         for (Request *r : act) {
-            r->done_pts += r->inflight;
+            r->done_items += r->inflight;
             r->inflight = 0;
-            if (r->status != NEBEM_OK || r->done_pts >= r->m) done.push_back(r);
+            if (r->status != NEBEM_OK || r->done_items >= r->nitems) done.push_back(r);
         }
+        for (Request *r : done)
+            if (r->status == NEBEM_OK) launch_reduce_segments(stage(s, r, 7), r->nseg, r->m, stage(s, r, 3), s->stream);
+        (void)hipStreamSynchronize(s->stream);
+        s->busy_s += now_s() - t0;
         for (Request *r : done) {
             if (r->status == NEBEM_OK) {
                 const size_t b = (size_t)r->m * sizeof(double);
@@ -264,9 +284,9 @@ extern "C" {
 void nebem_server_default_options(nebem_server_options *o)
 {
     if (!o) return;
-    o->hbm_budget = (int64_t)256 << 20;
-    o->batch_interactions = 4e10;
-    o->max_items = 16384;
+    o->hbm_budget = (int64_t)2 << 30;
+    o->batch_interactions = 5e10;
+    o->max_items = 65536;
 }
 
 nebem_status nebem_server_create(nebem_session *const *sessions, int32_t nsessions, const nebem_server_options *opt,
@@ -297,6 +317,13 @@ nebem_status nebem_server_create(nebem_session *const *sessions, int32_t nsessio
     for (int k = 0; k < nsessions; ++k) {
         s->geoms.push_back(sessions[k]);
         s->geom_n.push_back(sessions[k]->n);
+        const double per_pt = (double)sessions[k]->n * sessions[k]->img_count;
+        int nseg = (int)(per_pt / kSegWork + 0.5);
+        nseg = nseg < 1 ? 1 : (nseg > kMaxSeg ? kMaxSeg : nseg);
+        if (nseg > sessions[k]->n) nseg = (int)sessions[k]->n;
+        const int segsz = (int)((sessions[k]->n + nseg - 1) / nseg);
+        s->geom_segsz.push_back(segsz);
+        s->geom_nseg.push_back((int)((sessions[k]->n + segsz - 1) / segsz));
     }
     auto bail = [&](hipError_t e, const char *what) {
         nebem_status st = hip_fail(e, what);
@@ -345,7 +372,9 @@ nebem_status nebem_server_submit(nebem_server *s, int32_t geometry, const double
     r->hex = ex;
     r->hey = ey;
     r->hez = ez;
-    r->bytes = (size_t)m * 7 * sizeof(double);
+    r->nseg = s->geom_nseg[geometry];
+    r->nitems = ((m + 63) / 64) * r->nseg;
+    r->bytes = (size_t)m * (7 + 4 * (size_t)r->nseg) * sizeof(double);
     if (r->bytes > (size_t)s->opt.hbm_budget) {
         delete r;
         return fail(NEBEM_EBUSY, "server_submit: request larger than the server's HBM budget");
