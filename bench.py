@@ -231,16 +231,24 @@ def main():
         nb.eval_points(dp, sigma, px, py, pz, out=out, precision=prec)
         ev[3].record(stream)
 
-    for _ in range(args.warmup):
+    def progress(tag):
+        print(f"[bench] {tag}: assemble {ev[0].elapsed_time(ev[1]):.1f} ms, solve "
+              f"{ev[1].elapsed_time(ev[2]):.1f} ms, eval {ev[2].elapsed_time(ev[3]):.1f} ms",
+              file=sys.stderr, flush=True)
+
+    for w in range(args.warmup):
         step()
+        torch.cuda.synchronize()
+        progress(f"warmup {w}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         step()
         torch.cuda.synchronize()
         stage["assemble"].append(ev[0].elapsed_time(ev[1]))
         stage["solve"].append(ev[1].elapsed_time(ev[2]))
         stage["eval"].append(ev[2].elapsed_time(ev[3]))
+        progress(f"step {k}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = 1e3 * dt / args.steps
@@ -274,6 +282,7 @@ def main():
         dt_m = time.perf_counter() - t1
         got = [t.cpu().numpy() for t in out]
         ephi, eE = rel_diff(got, ref)
+        print(f"[bench] mixed step: {1e3 * dt_m:.1f} ms", file=sys.stderr, flush=True)
         mixed = {"value": (inter_asm + inter_eval) / dt_m, "ms_per_step": 1e3 * dt_m,
                  "eval_interactions_per_s": inter_eval / (e0.elapsed_time(e1) * 1e-3),
                  "speedup_vs_fp64": ms_step / (1e3 * dt_m), "ir_iters": si.ir_iters,

@@ -266,3 +266,20 @@ def test_gem_full_size_sampled(nb):
         assert np.all(np.isfinite(got))
         ephi, eE = rel_errors(got[idx], ref)
         assert ephi < tol and eE < tol, (prec, ephi, eE)
+
+
+def test_thgem_sampled(nb):
+    """Double THGEM (41 600 elements, 121 copies): FP64 and mixed evaluation
+    on 16 sampled points against the oracle with a seeded density."""
+    from synth import thgem_double, thgem_eval_points
+    g = thgem_double()
+    rng = np.random.default_rng(73)
+    sigma = rng.normal(0, 1e-5, g.n)
+    pts = thgem_eval_points(g, 4096, seed=2)
+    idx = rng.choice(len(pts), 16, replace=False)
+    ref = oracle.eval_points(g, sigma, pts[idx])
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    for prec, tol in ((nb.FP64, 1e-10), (nb.MIXED, 1e-6)):
+        got = stack(nb.eval_points(dp, dev(sigma), *cols(pts[idx]), precision=prec))
+        ephi, eE = rel_errors(got, ref)
+        assert ephi < tol and eE < tol, (prec, ephi, eE)
