@@ -15,9 +15,18 @@
 //
 // Rules (truncation error of E per element, measured against the exact
 // integral, <= 4e-7 at R = 4 D and falling as a power of D/R):
-//   rectangle      4 D <= R < 24 D: 3 x 3 Gauss-Legendre; R >= 24 D: 2 x 2
+//   rectangle      4 D <= R < 24 D: 3 x 3 Gauss-Legendre; 24 D <= R < 32 D: 2 x 2
 //   right triangle 4 D <= R < 48 D: Radon's 7-point degree-5 rule;
-//                  R >= 48 D: the 3-point interior degree-2 rule
+//                  48 D <= R < 96 D: the 3-point interior degree-2 rule
+// Beyond (rectangle R >= 32 D, triangle R >= 96 D) the correction is the
+// quadrupole term of the multipole expansion about the centroid instead of a
+// quadrature: with the element's second central moments M (per unit area, in
+// its plane; rectangle diag(lx^2, lz^2)/12, right triangle lx^2/18, lz^2/18,
+// off-diagonal -lx lz/36), q = p.M p and t = tr M,
+//   Phi' = A/R + A (3q - R^2 t)/(2 R^5)
+//   E'   = A p/R^3 + A/R^5 [(5 (3q - R^2 t)/(2 R^2) + t) p - 3 M p].
+// Its truncation error there (E: <= 4e-8 rectangle, <= 3.5e-8 triangle) is
+// below the 3-point rule's at 48 D (7e-8).
 // (J. Radon, Monatsh. Math. 52:286-300, 1948; tabulated with the 3-point
 // rule in A. H. Stroud, Approximate Calculation of Multiple Integrals, 1971).
 #pragma once
@@ -141,6 +150,48 @@ __device__ __forceinline__ void far_mixed(double px, double pz, double ph, doubl
     sx += air3 * px + area * (double)(fx * gf - a.gx);
     sz += air3 * pz + area * (double)(fz * gf - a.gz);
     sn += air3 * ph + area * (double)((float)ph * gf);
+}
+
+// Beyond the quadrupole tier: FP64 monopole plus the FP32 quadrupole term.
+template <int KIND>
+__device__ __forceinline__ void far_quadrupole(double px, double pz, double ph, double rc2, double lx, double lz,
+                                               double area, double &sp, double &sx, double &sz, double &sn)
+{
+    const float fx = (float)px, fz = (float)pz, fh = (float)ph;
+    const float frc2 = (float)rc2;
+    const float fic = __builtin_amdgcn_rsqf(frc2);
+    const float fic2 = fic * fic;
+    const float fic5 = fic2 * fic2 * fic;
+    const float flx = (float)lx, flz = (float)lz;
+    float mxx, mzz, mpx, mpz;
+    if (KIND == 0) {
+        mxx = flx * flx * (1.0f / 12.0f);
+        mzz = flz * flz * (1.0f / 12.0f);
+        mpx = mxx * fx;
+        mpz = mzz * fz;
+    } else {
+        mxx = flx * flx * (1.0f / 18.0f);
+        mzz = flz * flz * (1.0f / 18.0f);
+        const float mxz = flx * flz * (-1.0f / 36.0f);
+        mpx = fmaf(mxx, fx, mxz * fz);
+        mpz = fmaf(mxz, fx, mzz * fz);
+    }
+    const float t = mxx + mzz;
+    const float u = fmaf(3.0f, fmaf(fx, mpx, fz * mpz), -frc2 * t);  // 3q - R^2 t
+    const float qphi = 0.5f * u * fic5;
+    const float g = fmaf(2.5f * u, fic2, t);
+    const float qx = fic5 * fmaf(g, fx, -3.0f * mpx);
+    const float qz = fic5 * fmaf(g, fz, -3.0f * mpz);
+    const float qn = fic5 * (g * fh);
+    double ir = (double)fic;
+    ir = ir * (1.5 - 0.5 * rc2 * ir * ir);
+    ir = ir * (1.5 - 0.5 * rc2 * ir * ir);
+    const double air = area * ir;
+    const double air3 = air * ir * ir;
+    sp += air + area * (double)qphi;
+    sx += air3 * px + area * (double)qx;
+    sz += air3 * pz + area * (double)qz;
+    sn += air3 * ph + area * (double)qn;
 }
 
 }  // namespace nebem

@@ -50,6 +50,17 @@ __device__ __forceinline__ double sqrt64(double x)
     return x > 0.0 ? g : 0.0;
 }
 
+// sqrt(x) for x > 0 (no zero test)
+__device__ __forceinline__ double sqrt64_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    return fma(fma(-g, g, x), h, g);
+}
+
 template <int N>
 __device__ __forceinline__ double horner(const double (&c)[N], double z)
 {
@@ -83,6 +94,23 @@ __device__ __forceinline__ double log1p_ratio(double nn, double dd)
     const double z = s * s;
     const double t = fma(s * z, horner(kLogP, z), s + s);
     return fma(ee, kLn2Hi, fma(ee, kLn2Lo, t));
+}
+
+// 2 atanh(t) for 0 <= t <= (sqrt2 - 1)/(sqrt2 + 1): the range of the
+// polynomial above, used directly
+__device__ __forceinline__ double two_atanh_poly(double t)
+{
+    const double z = t * t;
+    return fma(t * z, horner(kLogP, z), t + t);
+}
+
+// atan(t) for |t| <= 0.04 (z <= 0.0016): Taylor series through t^13; the
+// first omitted term is below 1e-18 |t|
+constexpr double kAtanSmall[6] = {-1.0 / 3.0, 1.0 / 5.0, -1.0 / 7.0, 1.0 / 9.0, -1.0 / 11.0, 1.0 / 13.0};
+__device__ __forceinline__ double atan_small(double t)
+{
+    const double z = t * t;
+    return fma(t * z, horner(kAtanSmall, z), t);
 }
 
 // atan2(y, x) with one division: t = min/max of |x|, |y| reduced to

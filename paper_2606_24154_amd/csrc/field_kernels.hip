@@ -149,9 +149,13 @@ __device__ __forceinline__ Elem load_elem(const double *d)
 // for the zero translation (collocation point on its own element).
 // MIXED: copies with R >= near_factor * D take the FP64-monopole + FP32
 // quadrature far field (per lane), the others the exact FP64 closed form.
+// The exact form is taken per lane in its far-regime evaluation when the
+// point is at least kFarDiam diameters from the centroid, else in the
+// cancellation-free general one; the choice depends on the point alone.
 struct MixParams {
     double near2;   // (near_factor D)^2
     double tier2;   // squared distance beyond which the cheaper far rule is used
+    double quad2;   // squared distance beyond which the quadrupole expansion is used
 };
 
 template <int KIND, bool MIXED>
@@ -162,6 +166,7 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
 {
     const double cxl = KIND == 0 ? 0.5 * e.lx : e.lx * (1.0 / 3.0);
     const double czl = KIND == 0 ? 0.5 * e.lz : e.lz * (1.0 / 3.0);
+    const double far2 = (kFarDiam * kFarDiam) * (e.diam * e.diam);
 #pragma unroll 1
     for (int i1 = -n1; i1 <= n1; ++i1) {
         const double f1 = -(double)i1;
@@ -175,16 +180,28 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
             if (MIXED) {
                 const double px = X - cxl, pz = Z - czl;
                 const double rc2 = px * px + pz * pz + H * H;
+                if (rc2 >= mp.quad2) {
+                    far_quadrupole<KIND>(px, pz, H, rc2, e.lx, e.lz, e.area, sp, sx, sz, sn);
+                    continue;
+                }
                 if (rc2 >= mp.near2) {
                     far_mixed<KIND>(px, pz, H, rc2, e.lx, e.lz, e.area, mp.tier2, sp, sx, sz, sn);
                     continue;
                 }
             }
             Kern k;
-            if (KIND == 0)
-                k = rect_fp64(X, H, Z, e.lx, e.lz);
-            else
-                k = rtri_fp64(X, H, Z, e.lx, e.lz, e.hyp, e.ihyp);
+            const double qx = X - cxl, qz = Z - czl;
+            if (qx * qx + qz * qz + H * H >= far2) {
+                if (KIND == 0)
+                    k = rect_far(X, H, Z, e.lx, e.lz);
+                else
+                    k = rtri_far(X, H, Z, e.lx, e.lz, e.hyp, e.ihyp);
+            } else {
+                if (KIND == 0)
+                    k = rect_fp64(X, H, Z, e.lx, e.lz);
+                else
+                    k = rtri_fp64(X, H, Z, e.lx, e.lz, e.hyp, e.ihyp);
+            }
             sp += k.phi;
             sx += k.ex;
             sz += k.ez;
@@ -203,8 +220,10 @@ __device__ __forceinline__ void element_copies(const Elem &e, const ImgArgs &img
     if (MIXED) {
         const double nd = near_factor * e.diam;
         const double td = (e.kind == 0 ? 24.0 : 48.0) * e.diam;
+        const double qd = fmax(nd, (e.kind == 0 ? 32.0 : 96.0) * e.diam);
         mp.near2 = nd * nd;
         mp.tier2 = td * td;
+        mp.quad2 = qd * qd;
     }
     ophi = oex = oey = oez = 0.0;
     for (int r = 0; r < img.nref; ++r) {

@@ -216,56 +216,70 @@ struct Acc<float> {
     static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
 };
 
+constexpr int kGT = 64;  // trailing-update workgroup tile (rows and columns)
+constexpr int kKC = 32;  // K chunk staged in LDS at a time (keeps several workgroups per CU)
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_update(T *__restrict__ A, int n, int k, int kb)
 {
     typedef typename Acc<T>::type V4;
-    constexpr int LD = 64;
-    __shared__ T sL[kNB][LD];  // sL[kk][row]  (L21 tile)
-    __shared__ T sU[kNB][LD];  // sU[kk][col]  (U12 tile)
+    __shared__ T sL[kKC][kGT];  // sL[kk][row] = -L21 tile, one K chunk
+    __shared__ T sU[kKC][kGT];  // sU[kk][col] =  U12 tile
     const int kb4 = (kb + 3) & ~3;
     const int tid = threadIdx.x;
     const int base = k + kb;
     const int m = n - base;
-    const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
-    for (int e = tid; e < kb4 * 64; e += 256) {
-        const int rr = e % 64, kk = e / 64;
-        const int gr = row0 + rr;
-        sL[kk][rr] = (gr < m && kk < kb) ? A[(size_t)(k + kk) * n + base + gr] : T(0);
-    }
-    for (int e = tid; e < kb4 * 64; e += 256) {
-        const int kk = e % kb4, cc = e / kb4;
-        const int gc = col0 + cc;
-        sU[kk][cc] = (gc < m && kk < kb) ? A[(size_t)(base + gc) * n + k + kk] : T(0);
-    }
-    __syncthreads();
+    const int row0 = blockIdx.x * kGT, col0 = blockIdx.y * kGT;
     const int wave = tid >> 6, lane = tid & 63;
     const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;  // wave's 32x32 sub-tile
     const int li = lane & 15, lk = lane >> 4;
+    // The accumulators start from C itself (loads issued before the operand
+    // staging so that the two overlap); the MFMA chain then adds (-L21) U12.
     V4 acc[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
-            for (int v = 0; v < 4; ++v) acc[a][b][v] = T(0);
-    for (int kk = 0; kk < kb; kk += 4) {
-        // A operand: U12 columns (i index), B operand: L21 rows (j index)
-        T ua[2], lb[2];
-        for (int t = 0; t < 2; ++t) {
-            ua[t] = sU[kk + lk][wc + 16 * t + li];
-            lb[t] = sL[kk + lk][wr + 16 * t + li];
-        }
-        for (int tc = 0; tc < 2; ++tc)
-            for (int tr = 0; tr < 2; ++tr) acc[tc][tr] = mfma16(ua[tc], lb[tr], acc[tc][tr]);
-    }
-    // lane holds D'[i][j] for i = Acc::row(lk, v) (column offset), j = li (row offset)
+#pragma unroll
     for (int tc = 0; tc < 2; ++tc)
+#pragma unroll
         for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int gc = col0 + wc + 16 * tc + Acc<T>::row(lk, v);
                 const int gr = row0 + wr + 16 * tr + li;
-                if (gc < m && gr < m) {
-                    T *p = A + (size_t)(base + gc) * n + base + gr;
-                    *p = *p - acc[tc][tr][v];
-                }
+                acc[tc][tr][v] = (gc < m && gr < m) ? A[(size_t)(base + gc) * n + base + gr] : T(0);
+            }
+    for (int k0 = 0; k0 < kb4; k0 += kKC) {
+        const int kc = min(kKC, kb4 - k0);
+        if (k0) __syncthreads();
+        for (int e = tid; e < kc * kGT; e += 256) {
+            const int rr = e % kGT, kk = e / kGT;
+            const int gr = row0 + rr, gk = k0 + kk;
+            sL[kk][rr] = (gr < m && gk < kb) ? -A[(size_t)(k + gk) * n + base + gr] : T(0);
+        }
+        for (int e = tid; e < kc * kGT; e += 256) {
+            const int kk = e % kc, cc = e / kc;
+            const int gc = col0 + cc, gk = k0 + kk;
+            sU[kk][cc] = (gc < m && gk < kb) ? A[(size_t)(base + gc) * n + k + gk] : T(0);
+        }
+        __syncthreads();
+        for (int kk = 0; kk < kc; kk += 4) {
+            // A operand: U12 columns (i index), B operand: -L21 rows (j index)
+            const T u0 = sU[kk + lk][wc + li], u1 = sU[kk + lk][wc + 16 + li];
+            const T l0 = sL[kk + lk][wr + li], l1 = sL[kk + lk][wr + 16 + li];
+            acc[0][0] = mfma16(u0, l0, acc[0][0]);
+            acc[0][1] = mfma16(u0, l1, acc[0][1]);
+            acc[1][0] = mfma16(u1, l0, acc[1][0]);
+            acc[1][1] = mfma16(u1, l1, acc[1][1]);
+        }
+    }
+    // lane holds D'[i][j] for i = Acc::row(lk, v) (column offset), j = li (row offset)
+#pragma unroll
+    for (int tc = 0; tc < 2; ++tc)
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gc = col0 + wc + 16 * tc + Acc<T>::row(lk, v);
+                const int gr = row0 + wr + 16 * tr + li;
+                if (gc < m && gr < m) A[(size_t)(base + gc) * n + base + gr] = acc[tc][tr][v];
             }
 }
 
@@ -363,7 +377,7 @@ void lu_factor_launch(T *A, int n, int *ipiv, LUWork &w, hipStream_t s)
         const int m = n - k - kb;
         if (m > 0) {
             hipLaunchKernelGGL(k_trsm<T>, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, s, A, n, k, kb);
-            const unsigned gt = (unsigned)((m + 63) / 64);
+            const unsigned gt = (unsigned)((m + kGT - 1) / kGT);
             hipLaunchKernelGGL(k_gemm_update<T>, dim3(gt, gt), dim3(256), 0, s, A, n, k, kb);
         }
     }

@@ -141,4 +141,88 @@ __device__ __forceinline__ Kern rtri_fp64(double X, double H, double Z, double l
     return k;
 }
 
+// ------------------------------------------------------------- far regime
+// Same closed forms for a point whose distance R from the element's centroid
+// is at least kFarDiam element diameters D (D bounds every vertex-to-vertex
+// and centroid-to-vertex distance).  Then every vertex distance r_i >= 3R/4
+// >= 3D, so R_a + R_b >= 6 L for every edge: Lam_k = 2 atanh(L/(R_a + R_b))
+// with an argument below 1/6, and nothing cancels.  Each triangle's solid-
+// angle denominator exceeds r1 r2 r3 (1 + 3 (1 - D^2/(2 r_i r_j))) >= 1.6 R^3
+// while |N| <= R D^2/2 <= R^3/32, so every arctangent argument is below 0.02
+// per triangle (0.04 for the rectangle's sum); no octant logic, and N = 0 on
+// the element's plane gives Omega = 0 by itself.  All the divisions share one
+// reciprocal of the product of their denominators.
+constexpr double kFarDiam = 4.0;
+
+__device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx, double lz)
+{
+    const double H2 = H * H;
+    const double xm = X - lx, zm = Z - lz;
+    const double X2 = X * X, Z2 = Z * Z, xm2 = xm * xm, zm2 = zm * zm;
+    const double r00 = sqrt64_pos(X2 + Z2 + H2);
+    const double r10 = sqrt64_pos(xm2 + Z2 + H2);
+    const double r11 = sqrt64_pos(xm2 + zm2 + H2);
+    const double r01 = sqrt64_pos(X2 + zm2 + H2);
+    const double s0 = r00 + r10, s1 = r10 + r11, s2 = r11 + r01, s3 = r01 + r00;
+    const double N = H * lx * lz;
+    const double d00_10 = X * xm + Z2 + H2;
+    const double d00_11 = X * xm + Z * zm + H2;
+    const double d10_11 = xm2 + Z * zm + H2;
+    const double d00_01 = X2 + Z * zm + H2;
+    const double d11_01 = X * xm + zm2 + H2;
+    const double D1 = r00 * r10 * r11 + d00_10 * r11 + d00_11 * r10 + d10_11 * r00;
+    const double D2 = r00 * r11 * r01 + d00_11 * r01 + d00_01 * r11 + d11_01 * r00;
+    const double den = D1 * D2 - N * N;
+    // one reciprocal for 1/s0 .. 1/s3 and 1/den
+    const double a = s0 * s1, b = s2 * s3, ab = a * b;
+    const double inv = rcp64(ab * den);
+    const double iden = ab * inv, iab = den * inv;
+    const double ia = iab * b, ib = iab * a;
+    const double L0 = two_atanh_poly(lx * (ia * s1));
+    const double L1 = two_atanh_poly(lz * (ia * s0));
+    const double L2 = two_atanh_poly(lx * (ib * s3));
+    const double L3 = two_atanh_poly(lz * (ib * s2));
+    const double omega = 2.0 * atan_small(N * (D1 + D2) * iden);
+    Kern k;
+    k.phi = Z * L0 + (lx - X) * L1 + (lz - Z) * L2 + X * L3 - H * omega;
+    k.ex = L1 - L3;
+    k.ez = L2 - L0;
+    k.en = omega;
+    return k;
+}
+
+__device__ __forceinline__ Kern rtri_far(double X, double H, double Z, double lx, double lz, double hyp,
+                                         double ihyp)
+{
+    const double H2 = H * H;
+    const double xm = X - lx, zm = Z - lz;
+    const double X2 = X * X, Z2 = Z * Z;
+    const double r0 = sqrt64_pos(X2 + Z2 + H2);
+    const double r1 = sqrt64_pos(xm * xm + Z2 + H2);
+    const double r2 = sqrt64_pos(X2 + zm * zm + H2);
+    const double s0 = r0 + r1, s1 = r1 + r2, s2 = r2 + r0;
+    const double P1 = (lx * lz - X * lz - Z * lx) * ihyp;
+    const double N = H * lx * lz;
+    const double d01 = X * xm + Z2 + H2;
+    const double d02 = X2 + Z * zm + H2;
+    const double d12 = X * xm + Z * zm + H2;
+    const double D = r0 * r1 * r2 + d01 * r2 + d02 * r1 + d12 * r0;
+    // one reciprocal for 1/s0, 1/s1, 1/s2 and 1/D
+    const double a = s0 * s1, b = a * s2;
+    const double inv = rcp64(b * D);
+    const double iD = b * inv, ib = D * inv;
+    const double ia = ib * s2;
+    const double L0 = two_atanh_poly(lx * (ia * s1));
+    const double L1 = two_atanh_poly(hyp * (ia * s0));
+    const double L2 = two_atanh_poly(lz * (ib * a));
+    const double omega = 2.0 * atan_small(N * iD);
+    const double L1h = L1 * ihyp;
+    Kern k;
+    k.phi = Z * L0 + P1 * L1 + X * L2 - H * omega;
+    k.ex = lz * L1h - L2;
+    k.ez = lx * L1h - L0;
+    k.en = omega;
+    return k;
+}
+
 }  // namespace nebem
