@@ -170,8 +170,17 @@ nebem_status nebem_eval(const nebem_panels *panels, const nebem_images *images, 
     if ((st = make_img_args(images, &ia))) return st;
     DevBuf drec;
     if ((st = derive(panels, stream, drec))) return st;
-    launch_eval(drec.as<double>(), sigma, panels->n, ia, o.precision == NEBEM_MIXED, o.near_factor, px, py, pz, m,
-                phi, ex, ey, ez, stream);
+    if (eval_ordering_pays(m)) {
+        const size_t wb = ordered_eval_workspace(m);
+        if (!wb) return fail(NEBEM_EDEVICE, "eval: ordering workspace query failed");
+        DevBuf ws;
+        if (ws.alloc(wb, stream) != hipSuccess) return fail(NEBEM_ENOMEM, "eval: ordering workspace");
+        NEBEM_HIP(launch_eval_ordered(drec.as<double>(), sigma, panels->n, ia, o.precision == NEBEM_MIXED,
+                                      o.near_factor, px, py, pz, m, phi, ex, ey, ez, ws.p, wb, stream));
+    } else {
+        launch_eval(drec.as<double>(), sigma, panels->n, ia, o.precision == NEBEM_MIXED, o.near_factor, px, py, pz,
+                    m, phi, ex, ey, ez, stream);
+    }
     NEBEM_HIP(hipGetLastError());
     return NEBEM_OK;
 }

@@ -82,6 +82,14 @@ void launch_prep(const nebem_panels *p, double *drec, int *bad, hipStream_t s);
 void launch_eval(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
                  double near_factor, const double *px, const double *py, const double *pz, int64_t m, double *phi,
                  double *ex, double *ey, double *ez, hipStream_t s);
+// ---- evaluation in Morton order of the points (order_kernels.hip); the
+// results are bit-identical to launch_eval's, in the caller's order.
+bool eval_ordering_pays(int64_t m);
+size_t ordered_eval_workspace(int64_t m);  // bytes of device workspace, 0 on error
+hipError_t launch_eval_ordered(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
+                               double near_factor, const double *px, const double *py, const double *pz, int64_t m,
+                               double *phi, double *ex, double *ey, double *ez, void *ws, size_t ws_bytes,
+                               hipStream_t s);
 // items/imgs in device memory; one 64-lane workgroup per item
 void launch_eval_items(const WorkItem *items, int nitems, const ImgArgs *imgs, int mixed, double near_factor,
                        hipStream_t s);

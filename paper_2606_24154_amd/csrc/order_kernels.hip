@@ -1,0 +1,205 @@
+// order_kernels.hip -- evaluation in spatial (Morton) order of the points.
+//
+// The field kernels give every lane one point and walk the elements in the
+// same order for all lanes; a point's arithmetic does not depend on the other
+// points of its wave, so the order in which points are packed into waves
+// changes no bit of any result.  It does change how much work a wave does:
+// the per-lane choice between the near and the far evaluation of an element
+// copy (and, on the mixed path, among the far-field tiers) is a divergent
+// branch, and a wave whose 64 points are scattered over the cell executes
+// several of them for the same copy.  Sorting the points along a Morton curve
+// of their bounding box packs neighbours into a wave, whose lanes then agree
+// on the branch for nearly every copy.  Results are scattered back to the
+// caller's order.
+#include <hip/hip_runtime.h>
+
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+
+#include "nebem_internal.hpp"
+
+namespace nebem {
+
+constexpr int kOB = 256;         // threads per block of the helper kernels
+constexpr int kBoxParts = 256;   // partial bounding boxes (first reduction pass)
+constexpr int64_t kOrderMin = 4096;
+
+// per-block bounding box of a strided share of the points (min / max are
+// exact, so the result does not depend on the reduction order)
+__global__ __launch_bounds__(kOB) void k_bbox_part(const double *__restrict__ px, const double *__restrict__ py,
+                                                   const double *__restrict__ pz, int m, double *__restrict__ part)
+{
+    __shared__ double red[6][kOB];
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int i = blockIdx.x * kOB + threadIdx.x; i < m; i += gridDim.x * kOB) {
+        const double c[3] = {px[i], py[i], pz[i]};
+        for (int k = 0; k < 3; ++k) {
+            v[k] = fmin(v[k], c[k]);
+            v[3 + k] = fmax(v[3 + k], c[k]);
+        }
+    }
+    for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int h = kOB / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            for (int k = 0; k < 6; ++k)
+                red[k][threadIdx.x] = k < 3 ? fmin(red[k][threadIdx.x], red[k][threadIdx.x + h])
+                                            : fmax(red[k][threadIdx.x], red[k][threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// 10-bit coordinate -> bits spread to every third position
+__device__ __forceinline__ unsigned spread3(unsigned x)
+{
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+__device__ __forceinline__ unsigned quant10(double v, double lo, double sc)
+{
+    const double t = (v - lo) * sc;  // NaN coordinates fail both tests -> 0
+    return t >= 1023.0 ? 1023u : (t > 0.0 ? (unsigned)t : 0u);
+}
+
+// keys[i] = Morton code of point i in the box (reduced from nparts partial
+// boxes by every block: nparts x 6 doubles, L2-resident), idx[i] = i
+__global__ __launch_bounds__(kOB) void k_keys(const double *__restrict__ px, const double *__restrict__ py,
+                                              const double *__restrict__ pz, int m,
+                                              const double *__restrict__ part, int nparts,
+                                              unsigned *__restrict__ keys, int *__restrict__ idx)
+{
+    __shared__ double box[6];
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        double b = k < 3 ? INFINITY : -INFINITY;
+        for (int p = 0; p < nparts; ++p) b = k < 3 ? fmin(b, part[p * 6 + k]) : fmax(b, part[p * 6 + k]);
+        box[k] = b;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * kOB + threadIdx.x;
+    if (i >= m) return;
+    unsigned q[3];
+    const double c[3] = {px[i], py[i], pz[i]};
+    for (int k = 0; k < 3; ++k) {
+        const double ext = box[3 + k] - box[k];
+        const double sc = (ext > 0.0 && ext < INFINITY) ? 1024.0 / ext : 0.0;
+        q[k] = quant10(c[k], box[k], sc);
+    }
+    keys[i] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+    idx[i] = i;
+}
+
+__global__ __launch_bounds__(kOB) void k_gather3(const double *__restrict__ px, const double *__restrict__ py,
+                                                 const double *__restrict__ pz, const int *__restrict__ perm, int m,
+                                                 double *__restrict__ sx, double *__restrict__ sy,
+                                                 double *__restrict__ sz)
+{
+    const int k = blockIdx.x * kOB + threadIdx.x;
+    if (k >= m) return;
+    const int i = perm[k];
+    sx[k] = px[i];
+    sy[k] = py[i];
+    sz[k] = pz[i];
+}
+
+// dst_j[perm[k]] = src[j * m + k] for every non-null destination j
+__global__ __launch_bounds__(kOB) void k_scatter4(const double *__restrict__ src, const int *__restrict__ perm, int m,
+                                                  double *__restrict__ d0, double *__restrict__ d1,
+                                                  double *__restrict__ d2, double *__restrict__ d3)
+{
+    const int k = blockIdx.x * kOB + threadIdx.x;
+    if (k >= m) return;
+    const int i = perm[k];
+    const size_t mm = (size_t)m;
+    if (d0) d0[i] = src[k];
+    if (d1) d1[i] = src[mm + k];
+    if (d2) d2[i] = src[2 * mm + k];
+    if (d3) d3[i] = src[3 * mm + k];
+}
+
+namespace {
+struct OrderLayout {
+    size_t keys_in, keys_out, idx_in, perm, pts, out, part, cub, total;
+    size_t cub_bytes;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+hipError_t layout(int64_t m, OrderLayout &L)
+{
+    size_t cub_bytes = 0;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, cub_bytes, (const unsigned *)nullptr,
+                                                      (unsigned *)nullptr, (const int *)nullptr, (int *)nullptr,
+                                                      (int)m, 0, 30);
+    if (e != hipSuccess) return e;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off += align256(b);
+        return o;
+    };
+    L.keys_in = take(4 * (size_t)m);
+    L.keys_out = take(4 * (size_t)m);
+    L.idx_in = take(4 * (size_t)m);
+    L.perm = take(4 * (size_t)m);
+    L.pts = take(24 * (size_t)m);
+    L.out = take(32 * (size_t)m);
+    L.part = take(sizeof(double) * 6 * kBoxParts);
+    L.cub = take(cub_bytes);
+    L.cub_bytes = cub_bytes;
+    L.total = off;
+    return hipSuccess;
+}
+}  // namespace
+
+bool eval_ordering_pays(int64_t m) { return m >= kOrderMin; }
+
+size_t ordered_eval_workspace(int64_t m)
+{
+    OrderLayout L;
+    if (layout(m, L) != hipSuccess) return 0;
+    return L.total;
+}
+
+hipError_t launch_eval_ordered(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
+                               double near_factor, const double *px, const double *py, const double *pz, int64_t m,
+                               double *phi, double *ex, double *ey, double *ez, void *ws, size_t ws_bytes,
+                               hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    OrderLayout L;
+    hipError_t e = layout(m, L);
+    if (e != hipSuccess) return e;
+    if (!ws || ws_bytes < L.total) return hipErrorInvalidValue;
+    char *w = static_cast<char *>(ws);
+    unsigned *keys_in = reinterpret_cast<unsigned *>(w + L.keys_in);
+    unsigned *keys_out = reinterpret_cast<unsigned *>(w + L.keys_out);
+    int *idx_in = reinterpret_cast<int *>(w + L.idx_in);
+    int *perm = reinterpret_cast<int *>(w + L.perm);
+    double *sp = reinterpret_cast<double *>(w + L.pts);
+    double *so = reinterpret_cast<double *>(w + L.out);
+    double *part = reinterpret_cast<double *>(w + L.part);
+    const int mi = (int)m;
+    const unsigned g = (unsigned)((m + kOB - 1) / kOB);
+    const int nparts = (int)std::min<int64_t>(kBoxParts, g);
+    hipLaunchKernelGGL(k_bbox_part, dim3(nparts), dim3(kOB), 0, s, px, py, pz, mi, part);
+    hipLaunchKernelGGL(k_keys, dim3(g), dim3(kOB), 0, s, px, py, pz, mi, part, nparts, keys_in, idx_in);
+    size_t cub_bytes = L.cub_bytes;
+    e = hipcub::DeviceRadixSort::SortPairs(w + L.cub, cub_bytes, keys_in, keys_out, idx_in, perm, mi, 0, 30, s);
+    if (e != hipSuccess) return e;
+    const size_t mm = (size_t)m;
+    hipLaunchKernelGGL(k_gather3, dim3(g), dim3(kOB), 0, s, px, py, pz, perm, mi, sp, sp + mm, sp + 2 * mm);
+    launch_eval(drec, sigma, n, img, mixed, near_factor, sp, sp + mm, sp + 2 * mm, m, phi ? so : nullptr,
+                ex ? so + mm : nullptr, ey ? so + 2 * mm : nullptr, ez ? so + 3 * mm : nullptr, s);
+    hipLaunchKernelGGL(k_scatter4, dim3(g), dim3(kOB), 0, s, so, perm, mi, phi, ex, ey, ez);
+    return hipGetLastError();
+}
+
+}  // namespace nebem

@@ -77,6 +77,26 @@ static nebem_status session_build(nebem_session *s, const nebem_panels *panels, 
     return e;
 }
 
+// Evaluation over the resident geometry; large batches go through the
+// Morton-ordered path with the session's own workspace.
+static nebem_status session_eval_points(nebem_session *s, const double *px, const double *py, const double *pz,
+                                        int64_t m, double *phi, double *ex, double *ey, double *ez, hipStream_t st)
+{
+    const int mixed = s->opt.precision == NEBEM_MIXED;
+    if (eval_ordering_pays(m)) {
+        const size_t wb = ordered_eval_workspace(m);
+        if (!wb) return fail(NEBEM_EDEVICE, "session eval: ordering workspace query failed");
+        NEBEM_HIP(s->ows.ensure(wb));
+        NEBEM_HIP(launch_eval_ordered(s->drec.as<double>(), s->sigma.as<double>(), s->n, s->img, mixed,
+                                      s->opt.near_factor, px, py, pz, m, phi, ex, ey, ez, s->ows.p, s->ows.bytes, st));
+    } else {
+        launch_eval(s->drec.as<double>(), s->sigma.as<double>(), s->n, s->img, mixed, s->opt.near_factor, px, py, pz,
+                    m, phi, ex, ey, ez, st);
+    }
+    NEBEM_HIP(hipGetLastError());
+    return NEBEM_OK;
+}
+
 }  // namespace nebem
 
 extern "C" {
@@ -139,10 +159,7 @@ nebem_status nebem_session_eval(nebem_session *s, const double *px, const double
     if (m < 0 || m > (int64_t)INT32_MAX - 256) return fail(NEBEM_EINVAL, "session_eval: m out of range");
     if (m == 0) return NEBEM_OK;
     if (!px || !py || !pz) return fail(NEBEM_EINVAL, "session_eval: NULL point array");
-    launch_eval(s->drec.as<double>(), s->sigma.as<double>(), s->n, s->img, s->opt.precision == NEBEM_MIXED,
-                s->opt.near_factor, px, py, pz, m, phi, ex, ey, ez, stream);
-    NEBEM_HIP(hipGetLastError());
-    return NEBEM_OK;
+    return session_eval_points(s, px, py, pz, m, phi, ex, ey, ez, stream);
 }
 
 nebem_status nebem_spacecharge_step(nebem_session *s, double *qx, double *qy, double *qz, const double *q, int64_t nq,
@@ -172,8 +189,10 @@ nebem_status nebem_spacecharge_step(nebem_session *s, double *qx, double *qy, do
         ey = ex + nq;
         ez = ey + nq;
     }
-    launch_eval(s->drec.as<double>(), s->sigma.as<double>(), n, s->img, s->opt.precision == NEBEM_MIXED,
-                s->opt.near_factor, qx, qy, qz, nq, nullptr, ex, ey, ez, stream);
+    {
+        const nebem_status se = session_eval_points(s, qx, qy, qz, nq, nullptr, ex, ey, ez, stream);
+        if (se) return se;
+    }
     launch_coulomb_self(qx, qy, qz, q, nq, ex, ey, ez, stream);
     launch_euler(qx, qy, qz, q, ex, ey, ez, nq, s->opt.sc_mobility * s->opt.sc_dt, stream);
     NEBEM_HIP(hipGetLastError());

@@ -41,5 +41,6 @@ struct nebem_session {
     nebem_options opt;
     nebem::ImgArgs img;
     nebem::DevMem drec, A, A32, scale, ipiv, perm, b0, sigma, rhs, part, eb;
+    nebem::DevMem ows;  // workspace of the Morton-ordered evaluation
     nebem_solve_info last_info = {0, -1.0};
 };

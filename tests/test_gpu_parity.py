@@ -41,6 +41,15 @@ def gpu_eval(nb, geom, sigma, pts, **kw):
     return np.column_stack([t.cpu().numpy() for t in out])
 
 
+def cols(pts):
+    return [dev(pts[:, k]) for k in range(3)]
+
+
+def stack(out):
+    torch.cuda.synchronize()
+    return np.column_stack([t.cpu().numpy() for t in out])
+
+
 def rel_errors(got, ref, floor=1e-3):
     """max pointwise relative error of phi and |E| on non-negligible points"""
     ap = np.abs(ref[:, 0])
@@ -310,3 +319,50 @@ def test_deterministic_and_batch_independent(nb):
     assert np.array_equal(a, b)
     c = gpu_eval(nb, g, sigma, pts[1234:1500])
     assert np.array_equal(c, a[1234:1500])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_morton_ordered_eval_bitwise(nb, precision):
+    """Batches of >= 4096 points are evaluated in Morton order of the points
+    and scattered back; each point's arithmetic is independent of its wave
+    neighbours, so the results equal, bit for bit, those of the same points
+    in batches below the threshold (evaluated in the caller's order)."""
+    g = gem_cell(k=16, nr=2, nz_kapton=1, nz_cu=1, nd=2, n_images=2)
+    rng = np.random.default_rng(21)
+    sigma = rng.normal(0, 1e-5, g.n)
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    sg = dev(sigma)
+    for m in (4096, 4097, 9000):
+        pts = uniform_points(g.box_lo, g.box_hi, m, 100 + m)
+        pts[17] = pts[3]  # a duplicated point
+        big = stack(nb.eval_points(dp, sg, *cols(pts), precision=precision))
+        small = np.vstack([stack(nb.eval_points(dp, sg, *cols(pts[k:k + 2000]), precision=precision))
+                           for k in range(0, m, 2000)])
+        assert np.array_equal(big, small), m
+    # all points identical: a box of zero extent
+    pts = np.repeat(uniform_points(g.box_lo, g.box_hi, 1, 5), 5000, axis=0)
+    big = stack(nb.eval_points(dp, sg, *cols(pts), precision=precision))
+    one = stack(nb.eval_points(dp, sg, *cols(pts[:1]), precision=precision))
+    assert np.array_equal(big, np.repeat(one, 5000, axis=0))
+    # against the oracle on a sample of the ordered batch (FP64 bar / mixed bar)
+    pts = uniform_points(g.box_lo, g.box_hi, 6000, 8)
+    got = stack(nb.eval_points(dp, sg, *cols(pts), precision=precision))
+    idx = rng.choice(len(pts), 24, replace=False)
+    ref = oracle.eval_points(g, sigma, pts[idx])
+    ephi, eE = rel_errors(got[idx], ref)
+    tol = 1e-10 if precision == 0 else 1e-6
+    assert ephi < tol and eE < tol, (ephi, eE)
+
+
+def test_morton_ordered_session(nb):
+    """Session evaluation through the ordered path."""
+    g = gem_cell(k=16, nr=2, nz_kapton=1, nz_cu=1, nd=2, n_images=2)
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    ses = nb.Session(dp, precision=0)
+    pts = uniform_points(g.box_lo, g.box_hi, 5000, 3)
+    full = stack(ses.eval_points(*cols(pts)))
+    parts = np.vstack([stack(ses.eval_points(*cols(pts[k:k + 1000]))) for k in range(0, 5000, 1000)])
+    assert np.array_equal(full, parts)
+    ref = stack(nb.eval_points(dp, ses.sigma(), *cols(pts), precision=0))
+    assert np.array_equal(full, ref)
+    ses.close()
