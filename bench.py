@@ -51,7 +51,7 @@ def parse():
                    help="gem: single-GEM cell (default, the headline figure); thgem: staggered double "
                         "THGEM, 41 600 elements; plates: 512-element parallel plates")
     p.add_argument("--points", type=int, default=None, help="evaluation points (default per workload)")
-    p.add_argument("--cpu-sample", type=int, default=192, help="points in the oracle's timed sample")
+    p.add_argument("--cpu-sample", type=int, default=256, help="points in the oracle's timed sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison step")

@@ -205,18 +205,21 @@ nebem_status nebem_spacecharge_step(nebem_session *s, double *qx, double *qy, do
  * Continuous-batching evaluation service over resident sessions.  Clients
  * submit batches of points (host arrays) naming one of the server's
  * sessions; a worker thread admits requests in arrival order while their
- * staging (56 bytes per point) fits the device budget, cuts the admitted
- * requests into 256-point work items, and evaluates work items of several
- * requests and geometries in each kernel launch (round-robin, up to
- * batch_interactions element-copy x point pairs per launch).  Requests that
- * arrive while others are on the GPU join at the next launch.  A point's
- * result is bit-identical to nebem_session_eval on the same session,
- * whatever else shares its launch. */
+ * staging (8 + 4 x nseg doubles per point, nseg = element segments of the
+ * geometry, about N x copies / 1.2e5, at most 64) fits the device budget,
+ * sorts the points of requests of >= 4096 points into Morton order, cuts the
+ * admitted requests into work items of 64 points x one element segment, and
+ * evaluates work items of several requests and geometries in each kernel
+ * launch (round-robin, up to batch_interactions element-copy x point pairs
+ * per launch).  Requests that arrive while others are on the GPU join at the
+ * next launch.  A point's result is bit-identical whatever else shares its
+ * launches, and equal to nebem_session_eval's to rounding (the segment sums
+ * are added in a fixed order of their own). */
 typedef struct nebem_server nebem_server;
 typedef struct nebem_server_options {
-    int64_t hbm_budget;         /* bytes of device staging for admitted requests (256 MiB) */
-    double batch_interactions;  /* work per launch, interactions (4e10) */
-    int32_t max_items;          /* work items per launch (16384) */
+    int64_t hbm_budget;         /* bytes of device staging for admitted requests (2 GiB) */
+    double batch_interactions;  /* work per launch, interactions (5e10) */
+    int32_t max_items;          /* work items per launch (65536) */
 } nebem_server_options;
 typedef struct nebem_request_stats {
     double t_submit, t_admit, t_done; /* host steady-clock seconds */

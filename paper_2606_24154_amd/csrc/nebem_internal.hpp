@@ -85,6 +85,14 @@ void launch_eval(const double *drec, const double *sigma, int64_t n, const ImgAr
 // ---- evaluation in Morton order of the points (order_kernels.hip); the
 // results are bit-identical to launch_eval's, in the caller's order.
 bool eval_ordering_pays(int64_t m);
+// Morton order of m points: s{x,y,z}[k] = p{x,y,z}[perm[k]]; ws of
+// order_points_workspace(m) bytes (0 on error)
+size_t order_points_workspace(int64_t m);
+hipError_t launch_order_points(const double *px, const double *py, const double *pz, int64_t m, double *sx,
+                               double *sy, double *sz, int *perm, void *ws, size_t ws_bytes, hipStream_t s);
+// d_j[perm[k]] = src[j * m + k] for each non-null d_j (j = 0..3)
+void launch_unorder4(const double *src, const int *perm, int64_t m, double *d0, double *d1, double *d2, double *d3,
+                     hipStream_t s);
 size_t ordered_eval_workspace(int64_t m);  // bytes of device workspace, 0 on error
 hipError_t launch_eval_ordered(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
                                double near_factor, const double *px, const double *py, const double *pz, int64_t m,

@@ -125,14 +125,15 @@ __global__ __launch_bounds__(kOB) void k_scatter4(const double *__restrict__ src
 }
 
 namespace {
-struct OrderLayout {
-    size_t keys_in, keys_out, idx_in, perm, pts, out, part, cub, total;
+// scratch of one sort: keys (in/out), identity indices, partial boxes, sort temp
+struct SortLayout {
+    size_t keys_in, keys_out, idx_in, part, cub, total;
     size_t cub_bytes;
 };
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-hipError_t layout(int64_t m, OrderLayout &L)
+hipError_t sort_layout(int64_t m, SortLayout &L)
 {
     size_t cub_bytes = 0;
     hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, cub_bytes, (const unsigned *)nullptr,
@@ -148,9 +149,6 @@ hipError_t layout(int64_t m, OrderLayout &L)
     L.keys_in = take(4 * (size_t)m);
     L.keys_out = take(4 * (size_t)m);
     L.idx_in = take(4 * (size_t)m);
-    L.perm = take(4 * (size_t)m);
-    L.pts = take(24 * (size_t)m);
-    L.out = take(32 * (size_t)m);
     L.part = take(sizeof(double) * 6 * kBoxParts);
     L.cub = take(cub_bytes);
     L.cub_bytes = cub_bytes;
@@ -161,30 +159,25 @@ hipError_t layout(int64_t m, OrderLayout &L)
 
 bool eval_ordering_pays(int64_t m) { return m >= kOrderMin; }
 
-size_t ordered_eval_workspace(int64_t m)
+size_t order_points_workspace(int64_t m)
 {
-    OrderLayout L;
-    if (layout(m, L) != hipSuccess) return 0;
+    SortLayout L;
+    if (sort_layout(m, L) != hipSuccess) return 0;
     return L.total;
 }
 
-hipError_t launch_eval_ordered(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
-                               double near_factor, const double *px, const double *py, const double *pz, int64_t m,
-                               double *phi, double *ex, double *ey, double *ez, void *ws, size_t ws_bytes,
-                               hipStream_t s)
+hipError_t launch_order_points(const double *px, const double *py, const double *pz, int64_t m, double *sx,
+                               double *sy, double *sz, int *perm, void *ws, size_t ws_bytes, hipStream_t s)
 {
     if (m <= 0) return hipSuccess;
-    OrderLayout L;
-    hipError_t e = layout(m, L);
+    SortLayout L;
+    hipError_t e = sort_layout(m, L);
     if (e != hipSuccess) return e;
     if (!ws || ws_bytes < L.total) return hipErrorInvalidValue;
     char *w = static_cast<char *>(ws);
     unsigned *keys_in = reinterpret_cast<unsigned *>(w + L.keys_in);
     unsigned *keys_out = reinterpret_cast<unsigned *>(w + L.keys_out);
     int *idx_in = reinterpret_cast<int *>(w + L.idx_in);
-    int *perm = reinterpret_cast<int *>(w + L.perm);
-    double *sp = reinterpret_cast<double *>(w + L.pts);
-    double *so = reinterpret_cast<double *>(w + L.out);
     double *part = reinterpret_cast<double *>(w + L.part);
     const int mi = (int)m;
     const unsigned g = (unsigned)((m + kOB - 1) / kOB);
@@ -194,11 +187,46 @@ hipError_t launch_eval_ordered(const double *drec, const double *sigma, int64_t 
     size_t cub_bytes = L.cub_bytes;
     e = hipcub::DeviceRadixSort::SortPairs(w + L.cub, cub_bytes, keys_in, keys_out, idx_in, perm, mi, 0, 30, s);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gather3, dim3(g), dim3(kOB), 0, s, px, py, pz, perm, mi, sx, sy, sz);
+    return hipGetLastError();
+}
+
+void launch_unorder4(const double *src, const int *perm, int64_t m, double *d0, double *d1, double *d2, double *d3,
+                     hipStream_t s)
+{
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_scatter4, dim3((unsigned)((m + kOB - 1) / kOB)), dim3(kOB), 0, s, src, perm, (int)m, d0, d1,
+                       d2, d3);
+}
+
+// evaluation workspace: the sort's scratch, then perm, sorted points and
+// sorted results
+size_t ordered_eval_workspace(int64_t m)
+{
+    const size_t w = order_points_workspace(m);
+    if (!w) return 0;
+    return w + align256(4 * (size_t)m) + align256(24 * (size_t)m) + align256(32 * (size_t)m);
+}
+
+hipError_t launch_eval_ordered(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
+                               double near_factor, const double *px, const double *py, const double *pz, int64_t m,
+                               double *phi, double *ex, double *ey, double *ez, void *ws, size_t ws_bytes,
+                               hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    const size_t w0 = order_points_workspace(m);
+    if (!w0) return hipErrorInvalidValue;
+    if (!ws || ws_bytes < ordered_eval_workspace(m)) return hipErrorInvalidValue;
+    char *w = static_cast<char *>(ws);
+    int *perm = reinterpret_cast<int *>(w + w0);
+    double *sp = reinterpret_cast<double *>(w + w0 + align256(4 * (size_t)m));
+    double *so = reinterpret_cast<double *>(w + w0 + align256(4 * (size_t)m) + align256(24 * (size_t)m));
     const size_t mm = (size_t)m;
-    hipLaunchKernelGGL(k_gather3, dim3(g), dim3(kOB), 0, s, px, py, pz, perm, mi, sp, sp + mm, sp + 2 * mm);
+    hipError_t e = launch_order_points(px, py, pz, m, sp, sp + mm, sp + 2 * mm, perm, ws, w0, s);
+    if (e != hipSuccess) return e;
     launch_eval(drec, sigma, n, img, mixed, near_factor, sp, sp + mm, sp + 2 * mm, m, phi ? so : nullptr,
                 ex ? so + mm : nullptr, ey ? so + 2 * mm : nullptr, ez ? so + 3 * mm : nullptr, s);
-    hipLaunchKernelGGL(k_scatter4, dim3(g), dim3(kOB), 0, s, so, perm, mi, phi, ex, ey, ez);
+    launch_unorder4(so, perm, m, phi, ex, ey, ez, s);
     return hipGetLastError();
 }
 

@@ -5,8 +5,12 @@
 // field at millions of points, Sec. 3) submit batches of points on one of the
 // server's resident sessions.  A worker thread runs the scheduling loop:
 //   1. admission: queued requests enter, in arrival order, while their
-//      points and results (56 bytes per point) fit into the device staging
-//      arena of hbm_budget bytes; their points are copied in;
+//      staging (points, results, permutation and per-segment partial sums:
+//      8 + 4 nseg doubles per point) fits into the device arena of
+//      hbm_budget bytes; their points are copied in and, for requests of
+//      4096 points or more, sorted into Morton order on the device (so that
+//      the lanes of a work item share the near/far branches; each lane's
+//      arithmetic is unchanged);
 //   2. batching: the active requests are cut into work items of 64 points x
 //      one segment of the geometry's elements (each geometry's element range
 //      is split into a fixed number of segments of about kSegWork
@@ -15,7 +19,8 @@
 //      round) until the iteration's interaction budget is used; items of
 //      different requests and geometries go into ONE launch;
 //   3. completion: a request whose items are all done has its segment
-//      partial sums reduced in a fixed order, its results copied back to the
+//      partial sums reduced in a fixed order (and scattered back to the
+//      submission order if sorted), its results copied back to the
 //      caller's host arrays, its arena space freed and its waiter woken; new
 //      requests are admitted on the next iteration.
 // Each point's partial sums and their reduction have a fixed order that does
@@ -63,6 +68,7 @@ struct Request {
     int64_t inflight = 0;       // items scheduled in the current launch
     int64_t done_items = 0;
     int status = NEBEM_OK;
+    bool ordered = false;       // points sorted into Morton order on admission
     bool finished = false;
 };
 
@@ -125,6 +131,8 @@ struct nebem_server {
     nebem::ImgArgs *imgs_dev = nullptr;
     nebem::WorkItem *items_dev = nullptr;
     nebem::WorkItem *items_host = nullptr;  // pinned
+    void *sort_ws = nullptr;                // scratch of the point sort (grown on demand)
+    size_t sort_ws_bytes = 0;
     int items_cap = 0;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -160,8 +168,9 @@ static bool admit_locked(nebem_server *s)
     return any;
 }
 
-// device addresses of a request's staging: columns 0-2 points, 3-6 results,
-// then nseg x 4 columns of segment partial sums
+// device addresses of a request's staging: columns 0-2 points (sorted if
+// ordered), 3-6 results, 7 the permutation (int32), then nseg x 4 columns of
+// segment partial sums
 static inline double *stage(nebem_server *s, const Request *r, int k)
 {
     return reinterpret_cast<double *>(static_cast<char *>(s->arena_dev) + r->off) + (size_t)k * r->m;
@@ -182,13 +191,35 @@ static void worker_main(nebem_server *s)
             fresh.assign(s->active.begin() + before, s->active.end());
             act = s->active;
         }
-        // copy the new requests' points in
+        // copy the new requests' points in; large ones land in the result
+        // columns and are sorted into the point columns
         for (Request *r : fresh) {
             const size_t b = (size_t)r->m * sizeof(double);
-            hipError_t e = hipMemcpyAsync(stage(s, r, 0), r->hx, b, hipMemcpyHostToDevice, s->stream);
-            if (e == hipSuccess) e = hipMemcpyAsync(stage(s, r, 1), r->hy, b, hipMemcpyHostToDevice, s->stream);
-            if (e == hipSuccess) e = hipMemcpyAsync(stage(s, r, 2), r->hz, b, hipMemcpyHostToDevice, s->stream);
-            if (e != hipSuccess) r->status = NEBEM_EDEVICE;
+            const int c0 = r->ordered ? 3 : 0;
+            hipError_t e = hipMemcpyAsync(stage(s, r, c0), r->hx, b, hipMemcpyHostToDevice, s->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(stage(s, r, c0 + 1), r->hy, b, hipMemcpyHostToDevice, s->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(stage(s, r, c0 + 2), r->hz, b, hipMemcpyHostToDevice, s->stream);
+            if (e == hipSuccess && r->ordered) {
+                const size_t wb = order_points_workspace(r->m);
+                if (wb == 0) e = hipErrorInvalidValue;
+                if (e == hipSuccess && wb > s->sort_ws_bytes) {
+                    if (s->sort_ws) e = hipStreamSynchronize(s->stream);
+                    if (e == hipSuccess && s->sort_ws) e = hipFree(s->sort_ws);
+                    s->sort_ws = nullptr;
+                    s->sort_ws_bytes = 0;
+                    if (e == hipSuccess) e = hipMalloc(&s->sort_ws, wb);
+                    if (e == hipSuccess) s->sort_ws_bytes = wb;
+                }
+                if (e == hipSuccess)
+                    e = launch_order_points(stage(s, r, 3), stage(s, r, 4), stage(s, r, 5), r->m, stage(s, r, 0),
+                                            stage(s, r, 1), stage(s, r, 2), reinterpret_cast<int *>(stage(s, r, 7)),
+                                            s->sort_ws, s->sort_ws_bytes, s->stream);
+            }
+            if (e != hipSuccess) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->worker_error = hipGetErrorString(e);
+                r->status = NEBEM_EDEVICE;
+            }
         }
         // build the work list: round-robin, one item per request per round
         int nitems = 0;
@@ -215,10 +246,10 @@ static void worker_main(nebem_server *s)
                 w.px = stage(s, r, 0) + p0;
                 w.py = stage(s, r, 1) + p0;
                 w.pz = stage(s, r, 2) + p0;
-                w.phi = stage(s, r, 7 + 4 * seg) + p0;
-                w.ex = stage(s, r, 8 + 4 * seg) + p0;
-                w.ey = stage(s, r, 9 + 4 * seg) + p0;
-                w.ez = stage(s, r, 10 + 4 * seg) + p0;
+                w.phi = stage(s, r, 8 + 4 * seg) + p0;
+                w.ex = stage(s, r, 9 + 4 * seg) + p0;
+                w.ey = stage(s, r, 10 + 4 * seg) + p0;
+                w.ez = stage(s, r, 11 + 4 * seg) + p0;
                 r->next += 1;
                 r->inflight += 1;
                 const double work = (double)ne * g->img_count * cnt;
@@ -250,8 +281,15 @@ static void worker_main(nebem_server *s)
             r->inflight = 0;
             if (r->status != NEBEM_OK || r->done_items >= r->nitems) done.push_back(r);
         }
+        // results of sorted requests end in the first partial-sum columns, in
+        // submission order
         for (Request *r : done)
-            if (r->status == NEBEM_OK) launch_reduce_segments(stage(s, r, 7), r->nseg, r->m, stage(s, r, 3), s->stream);
+            if (r->status == NEBEM_OK) {
+                launch_reduce_segments(stage(s, r, 8), r->nseg, r->m, stage(s, r, 3), s->stream);
+                if (r->ordered)
+                    launch_unorder4(stage(s, r, 3), reinterpret_cast<const int *>(stage(s, r, 7)), r->m,
+                                    stage(s, r, 8), stage(s, r, 9), stage(s, r, 10), stage(s, r, 11), s->stream);
+            }
         (void)hipStreamSynchronize(s->stream);
         s->busy_s += now_s() - t0;
         for (Request *r : done) {
@@ -259,7 +297,8 @@ static void worker_main(nebem_server *s)
                 const size_t b = (size_t)r->m * sizeof(double);
                 double *dst[4] = {r->hphi, r->hex, r->hey, r->hez};
                 for (int k = 0; k < 4; ++k)
-                    if (dst[k] && hipMemcpy(dst[k], stage(s, r, 3 + k), b, hipMemcpyDeviceToHost) != hipSuccess)
+                    if (dst[k] && hipMemcpy(dst[k], stage(s, r, (r->ordered ? 8 : 3) + k), b,
+                                            hipMemcpyDeviceToHost) != hipSuccess)
                         r->status = NEBEM_EDEVICE;
             }
             r->t_done = now_s();
@@ -374,7 +413,8 @@ nebem_status nebem_server_submit(nebem_server *s, int32_t geometry, const double
     r->hez = ez;
     r->nseg = s->geom_nseg[geometry];
     r->nitems = ((m + 63) / 64) * r->nseg;
-    r->bytes = (size_t)m * (7 + 4 * (size_t)r->nseg) * sizeof(double);
+    r->ordered = eval_ordering_pays(m);
+    r->bytes = (size_t)m * (8 + 4 * (size_t)r->nseg) * sizeof(double);
     if (r->bytes > (size_t)s->opt.hbm_budget) {
         delete r;
         return fail(NEBEM_EBUSY, "server_submit: request larger than the server's HBM budget");
@@ -442,6 +482,7 @@ void nebem_server_destroy(nebem_server *s)
     for (auto &kv : s->all) delete kv.second;
     if (s->items_host) (void)hipHostFree(s->items_host);
     if (s->items_dev) (void)hipFree(s->items_dev);
+    if (s->sort_ws) (void)hipFree(s->sort_ws);
     if (s->imgs_dev) (void)hipFree(s->imgs_dev);
     if (s->arena_dev) (void)hipFree(s->arena_dev);
     if (s->stream) (void)hipStreamDestroy(s->stream);

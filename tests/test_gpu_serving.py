@@ -38,7 +38,7 @@ def test_mix_equals_alone_and_admission(nb, precision):
     from paper_2606_24154_amd.serving import replay
     geoms, ses = _sessions(nb, precision)
     # tight budget: only a few mid-size requests fit at once
-    srv = nb.Server(ses, hbm_budget=(7 + 4 * 2) * 8 * 12000, batch_interactions=2e8)
+    srv = nb.Server(ses, hbm_budget=(8 + 4 * 2) * 8 * 12000, batch_interactions=2e8)
     reqs = serve_requests(40, rate_hz=400.0, n_geometries=2, seed=9, n_min=64, n_max=8000)
 
     def make_points(g, n, sd):
@@ -65,7 +65,7 @@ def test_mix_equals_alone_and_admission(nb, precision):
 
 def test_oversized_request_refused(nb):
     geoms, ses = _sessions(nb, 0)
-    srv = nb.Server(ses, hbm_budget=(7 + 4) * 8 * 1000)  # plates: one element segment
+    srv = nb.Server(ses, hbm_budget=(8 + 4) * 8 * 1000)  # plates: one element segment
     with pytest.raises(nb.NebemError) as e:
         srv.submit(0, uniform_points(geoms[0].box_lo, geoms[0].box_hi, 2000, 1))
     assert e.value.code == nb.NEBEM_EBUSY
