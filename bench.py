@@ -61,6 +61,9 @@ def parse():
                    help="instead of the default step: K steps of the dynamic space-charge loop on the GEM "
                         "cell with 10^6 charges (first step re-solves)")
     p.add_argument("--charges", type=int, default=1_000_000)
+    p.add_argument("--serve-matrix", type=int, default=0, metavar="R",
+                   help="serving study instead of the step: R requests over the plates, GEM and double-THGEM "
+                        "geometries, FP64 saturation measured first, then loads 0.5/0.8/0.95 in FP64 and mixed")
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     return p.parse_args()
@@ -126,6 +129,63 @@ def serve_replay(nb, geoms, sessions, n_req, load, eval_rate, seed=4):
             "launches": int(c.launches), "errors": len(run["errors"])}
 
 
+def serve_matrix(args):
+    """Serving over three resident geometries (plates, GEM cell, double
+    THGEM), geometry uniform, sizes log-uniform in [64, 262144]: the FP64
+    saturation rate is measured by submitting every request at once; then
+    Poisson arrivals at 0.5 / 0.8 / 0.95 of it (the same absolute rates for
+    both precisions).  Prints one JSON line."""
+    import torch
+
+    import paper_2606_24154_amd as nb
+    from paper_2606_24154_amd.serving import replay
+    from synth import gem_cell, parallel_plates, serve_requests, thgem_double, uniform_points
+
+    dev = torch.device("cuda:0")
+    geoms = [parallel_plates(), gem_cell(), thgem_double()]
+    n_req = args.serve_matrix
+
+    def make_points(g, n, sd):
+        return uniform_points(geoms[g].box_lo, geoms[g].box_hi, n, sd)
+
+    def log(msg):
+        print(f"[serve] {msg}", file=sys.stderr, flush=True)
+
+    burst = [(0.0, g, n, sd) for (_, g, n, sd) in serve_requests(n_req, 1.0, 3, seed=4)]
+    work = sum(n * geoms[g].n * geoms[g].images.count for (_, g, n, _) in burst)
+    out = {"requests": n_req, "geometries": [g.name for g in geoms],
+           "mean_interactions_per_request": work / n_req}
+    for name, pr in (("fp64", nb.FP64), ("mixed", nb.MIXED)):
+        t0 = time.perf_counter()
+        ses = [nb.Session(nb.DevicePanels.from_geometry(g, dev), precision=pr) for g in geoms]
+        log(f"{name}: sessions ready in {time.perf_counter() - t0:.1f} s")
+        res = {}
+        if name == "fp64":
+            srv = nb.Server(ses)
+            run = replay(srv, burst, make_points)
+            srv.close()
+            sat = work / run["span_s"]
+            out["saturation_interactions_per_s"] = sat
+            out["saturation_requests_per_s"] = n_req / run["span_s"]
+            log(f"fp64 saturation: {sat:.3e} interactions/s over {run['span_s']:.1f} s")
+        for load in (0.5, 0.8, 0.95):
+            rate = load * out["saturation_requests_per_s"]
+            reqs = serve_requests(n_req, rate, 3, seed=4)
+            srv = nb.Server(ses)
+            run = replay(srv, reqs, make_points)
+            c = srv.counters()
+            srv.close()
+            res[str(load)] = {"arrival_rate_hz": rate, "p50_ms": 1e3 * run["p50_s"], "p99_ms": 1e3 * run["p99_s"],
+                              "max_ms": 1e3 * float(run["latency_s"].max()),
+                              "points_per_s": run["points_per_s"], "interactions_per_s": c.interactions / run["span_s"],
+                              "launches": int(c.launches), "errors": len(run["errors"])}
+            log(f"{name} load {load}: p50 {res[str(load)]['p50_ms']:.0f} ms, p99 {res[str(load)]['p99_ms']:.0f} ms")
+        for x in ses:
+            x.close()
+        out[name] = res
+    print(json.dumps({"serve_matrix": out}), flush=True)
+
+
 def spacecharge_bench(args):
     """Config 3: GEM cell, charges ~ N(hole centre, 20 um), +-e alternating;
     each step = (re-solve every 10th step) + panel field at every charge +
@@ -181,6 +241,9 @@ def main():
         return
     if args.spacecharge:
         spacecharge_bench(args)
+        return
+    if args.serve_matrix:
+        serve_matrix(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU sharding is not built "

@@ -92,12 +92,14 @@ typedef struct nebem_images {
 
 typedef enum nebem_precision {
     NEBEM_FP64 = 0,  /* exact closed forms in FP64 everywhere; FP64 LU */
-    NEBEM_MIXED = 1  /* FP64 near field, FP32 far-field correction; FP32 LU + FP64 refinement */
+    NEBEM_MIXED = 1  /* FP64 near field, FP64 monopole + FP32 correction far away; FP32 LU + FP64 refinement */
 } nebem_precision;
 
 typedef struct nebem_options {
     int32_t precision;     /* nebem_precision */
-    double near_factor;    /* mixed: exact FP64 if R < near_factor * D (default 4) */
+    double near_factor;    /* mixed: exact FP64 at least for R < near_factor * D (default 4); the FP32
+                              corrections start at max(near_factor, 24) D for rectangles and
+                              max(near_factor, 48) D for triangles (R from the centroid, D = diameter) */
     double ir_tol;         /* mixed solve: stop at ||b - A x||_2 / ||b||_2 <= ir_tol (1e-10) */
     int32_t ir_max_iter;   /* mixed solve: refinement steps (30) */
     double sc_dt;          /* space charge: time step, s (1e-12) */
@@ -106,7 +108,7 @@ typedef struct nebem_options {
 } nebem_options;
 
 typedef struct nebem_solve_info {
-    int32_t ir_iters;     /* refinement steps taken (0 in FP64 mode) */
+    int32_t ir_iters;     /* refinement step of the returned iterate (0 in FP64 mode) */
     double rel_resid;     /* ||b - A x||_2 / ||b||_2 of the returned x, FP64 (mixed mode; -1 if not computed) */
 } nebem_solve_info;
 
@@ -120,7 +122,8 @@ void nebem_default_options(nebem_options *opt);
  *   conductor row:  A_ij = k_e sum_copies Phi'_j(c_i)
  *   dielectric row: A_ij = k_e sum_copies n_i . E'_j(c_i)
  *                          + [i == j] (eps+ + eps-) / (2 eps0 (eps+ - eps-))
- * where Phi', E' are the exact potential and field integrals of Sec. 2.1.
+ * where Phi', E' are the exact potential and field integrals of Sec. 2.1,
+ * in both precision modes (opt->precision does not change the matrix).
  * Panel i's own (untranslated, unreflected) copy is evaluated with c_i taken
  * exactly in its plane (principal value of the normal field = 0).
  * A: n x n FP64, column-major, caller-allocated (8 n^2 bytes). */
@@ -134,7 +137,10 @@ nebem_status nebem_assemble(const nebem_panels *panels, const nebem_images *imag
  *    (unit lower L below the diagonal, U on and above), ipiv[k] (int32, n
  *    entries, 0-based) is the row swapped with row k at step k.
  *  MIXED mode: A is left unchanged; the library factors an FP32 copy and
- *    refines in FP64 until ||b - A x||_2 <= ir_tol ||b||_2 per column.
+ *    refines in FP64 until ||b - A x||_2 <= ir_tol ||b||_2 per column, and
+ *    further while each step still at least halves the residual (down to
+ *    the FP64 floor, so that x approaches the FP64 solution), returning the
+ *    best iterate.
  *    ipiv holds the FP32 factorisation's pivots.
  * b, sigma: n x nrhs column-major (may alias).  `info` (host, may be NULL)
  * receives iteration count and residual.  Synchronises `stream`.

@@ -202,8 +202,7 @@ nebem_status nebem_assemble(const nebem_panels *panels, const nebem_images *imag
     if ((st = make_img_args(images, &ia))) return st;
     DevBuf drec;
     if ((st = derive(panels, stream, drec))) return st;
-    launch_assemble(drec.as<double>(), panels->n, ia, o.precision == NEBEM_MIXED, o.near_factor, cx, cy, cz, A,
-                    stream);
+    launch_assemble(drec.as<double>(), panels->n, ia, cx, cy, cz, A, stream);
     NEBEM_HIP(hipGetLastError());
     return NEBEM_OK;
 }

@@ -13,11 +13,12 @@
 // Its FP32 rounding is then relative to the correction, itself O((D/R)^2)
 // of the monopole.
 //
-// Rules (truncation error of E per element, measured against the exact
-// integral, <= 4e-7 at R = 4 D and falling as a power of D/R):
-//   rectangle      4 D <= R < 24 D: 3 x 3 Gauss-Legendre; 24 D <= R < 32 D: 2 x 2
-//   right triangle 4 D <= R < 48 D: Radon's 7-point degree-5 rule;
-//                  48 D <= R < 96 D: the 3-point interior degree-2 rule
+// Tiers (per-element truncation error of E against the exact integral,
+// measured; it falls as a power of D/R):
+//   rectangle      24 D <= R < 32 D: 2 x 2 Gauss-Legendre (<= 8e-8)
+//   right triangle 48 D <= R < 96 D: the 3-point interior degree-2 rule
+//                  (<= 7e-8; A. H. Stroud, Approximate Calculation of
+//                  Multiple Integrals, 1971)
 // Beyond (rectangle R >= 32 D, triangle R >= 96 D) the correction is the
 // quadrupole term of the multipole expansion about the centroid instead of a
 // quadrature: with the element's second central moments M (per unit area, in
@@ -25,10 +26,10 @@
 // off-diagonal -lx lz/36), q = p.M p and t = tr M,
 //   Phi' = A/R + A (3q - R^2 t)/(2 R^5)
 //   E'   = A p/R^3 + A/R^5 [(5 (3q - R^2 t)/(2 R^2) + t) p - 3 M p].
-// Its truncation error there (E: <= 4e-8 rectangle, <= 3.5e-8 triangle) is
-// below the 3-point rule's at 48 D (7e-8).
-// (J. Radon, Monatsh. Math. 52:286-300, 1948; tabulated with the 3-point
-// rule in A. H. Stroud, Approximate Calculation of Multiple Integrals, 1971).
+// Its truncation error there (E: <= 5e-8 rectangle, <= 3.5e-8 triangle) is
+// below the 3-point rule's at 48 D.  Nearer copies are evaluated with the
+// exact closed forms (a 3 x 3 or 7-point rule there costs as much as the
+// exact far-regime form and contributed most of the error of sums).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -42,26 +43,9 @@ struct GL2 {
     static constexpr float x[2] = {0.21132486540518711775f, 0.78867513459481288225f};
     static constexpr float w[2] = {0.5f, 0.5f};
 };
-struct GL3 {
-    static constexpr int n = 3;
-    static constexpr float x[3] = {0.11270166537925831148f, 0.5f, 0.88729833462074168852f};
-    static constexpr float w[3] = {0.27777777777777777778f, 0.44444444444444444444f, 0.27777777777777777778f};
-};
 
-// triangle rules in (s, t) on s, t >= 0, s + t <= 1 (area coordinates of the
+// triangle rule in (s, t) on s, t >= 0, s + t <= 1 (area coordinates of the
 // vertices o + u and o + w); weights sum to 1
-struct TriR7 {
-    static constexpr int n = 7;
-    static constexpr float s[7] = {0.33333333333333333333f, 0.05971587178976982045f, 0.47014206410511508977f,
-                                   0.47014206410511508977f, 0.79742698535308732240f, 0.10128650732345633880f,
-                                   0.10128650732345633880f};
-    static constexpr float t[7] = {0.33333333333333333333f, 0.47014206410511508977f, 0.05971587178976982045f,
-                                   0.47014206410511508977f, 0.10128650732345633880f, 0.79742698535308732240f,
-                                   0.10128650732345633880f};
-    static constexpr float w[7] = {0.225f, 0.13239415278850618074f, 0.13239415278850618074f,
-                                   0.13239415278850618074f, 0.12593918054482715260f, 0.12593918054482715260f,
-                                   0.12593918054482715260f};
-};
 struct TriR3 {
     static constexpr int n = 3;
     static constexpr float s[3] = {0.66666666666666666667f, 0.16666666666666666667f, 0.16666666666666666667f};
@@ -97,8 +81,7 @@ __device__ __forceinline__ void far_node(float px, float pz, float rc2, float rc
 // frame (FP64); rc2 = |p|^2.  Adds Phi', E' (local frame) to (sp, sx, sz, sn).
 template <int KIND>
 __device__ __forceinline__ void far_mixed(double px, double pz, double ph, double rc2, double lx, double lz,
-                                          double area, double tier2, double &sp, double &sx, double &sz,
-                                          double &sn)
+                                          double area, double &sp, double &sx, double &sz, double &sn)
 {
     const float fx = (float)px, fz = (float)pz;
     const float frc2 = (float)rc2;
@@ -108,34 +91,18 @@ __device__ __forceinline__ void far_mixed(double px, double pz, double ph, doubl
     const float flx = (float)lx, flz = (float)lz;
     FarAcc a = {0.0f, 0.0f, 0.0f, 0.0f};
     if (KIND == 0) {
-        if (rc2 < tier2) {
 #pragma unroll
-            for (int i = 0; i < GL3::n; ++i)
+        for (int i = 0; i < GL2::n; ++i)
 #pragma unroll
-                for (int j = 0; j < GL3::n; ++j)
-                    far_node(fx, fz, frc2, frc, fic, fic2, flx * (GL3::x[i] - 0.5f), flz * (GL3::x[j] - 0.5f),
-                             GL3::w[i] * GL3::w[j], a);
-        } else {
-#pragma unroll
-            for (int i = 0; i < GL2::n; ++i)
-#pragma unroll
-                for (int j = 0; j < GL2::n; ++j)
-                    far_node(fx, fz, frc2, frc, fic, fic2, flx * (GL2::x[i] - 0.5f), flz * (GL2::x[j] - 0.5f),
-                             GL2::w[i] * GL2::w[j], a);
-        }
+            for (int j = 0; j < GL2::n; ++j)
+                far_node(fx, fz, frc2, frc, fic, fic2, flx * (GL2::x[i] - 0.5f), flz * (GL2::x[j] - 0.5f),
+                         GL2::w[i] * GL2::w[j], a);
     } else {
         const float third = 0.33333333333333333333f;
-        if (rc2 < tier2) {
 #pragma unroll
-            for (int k = 0; k < TriR7::n; ++k)
-                far_node(fx, fz, frc2, frc, fic, fic2, flx * (TriR7::s[k] - third), flz * (TriR7::t[k] - third),
-                         TriR7::w[k], a);
-        } else {
-#pragma unroll
-            for (int k = 0; k < TriR3::n; ++k)
-                far_node(fx, fz, frc2, frc, fic, fic2, flx * (TriR3::s[k] - third), flz * (TriR3::t[k] - third),
-                         TriR3::w[k], a);
-        }
+        for (int k = 0; k < TriR3::n; ++k)
+            far_node(fx, fz, frc2, frc, fic, fic2, flx * (TriR3::s[k] - third), flz * (TriR3::t[k] - third),
+                     TriR3::w[k], a);
     }
     // FP64 monopole: 1/R_c from the FP32 estimate by two Newton steps
     double ir = (double)fic;

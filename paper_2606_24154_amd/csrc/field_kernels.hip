@@ -147,15 +147,17 @@ __device__ __forceinline__ Elem load_elem(const double *d)
 // the (reflected) point in the element frame for the zero translation, and
 // (aX,aZ,aH), (bX,bZ,bH) the lattice vectors in that frame.  `self` zeroes H
 // for the zero translation (collocation point on its own element).
-// MIXED: copies with R >= near_factor * D take the FP64-monopole + FP32
-// quadrature far field (per lane), the others the exact FP64 closed form.
+// MIXED: copies far enough for a low-order FP32 correction to stay within
+// its error budget (R >= 24 D rectangles, 48 D triangles, and never below
+// near_factor D) take the FP64 monopole + FP32 correction far field (per
+// lane); nearer copies take the exact FP64 closed form, which in that band is
+// no more expensive than a higher-order rule would be.
 // The exact form is taken per lane in its far-regime evaluation when the
 // point is at least kFarDiam diameters from the centroid, else in the
 // cancellation-free general one; the choice depends on the point alone.
 struct MixParams {
-    double near2;   // (near_factor D)^2
-    double tier2;   // squared distance beyond which the cheaper far rule is used
-    double quad2;   // squared distance beyond which the quadrupole expansion is used
+    double low2;    // squared distance from which the FP32 low-order rule is used
+    double quad2;   // squared distance from which the quadrupole expansion is used
 };
 
 template <int KIND, bool MIXED>
@@ -184,8 +186,8 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
                     far_quadrupole<KIND>(px, pz, H, rc2, e.lx, e.lz, e.area, sp, sx, sz, sn);
                     continue;
                 }
-                if (rc2 >= mp.near2) {
-                    far_mixed<KIND>(px, pz, H, rc2, e.lx, e.lz, e.area, mp.tier2, sp, sx, sz, sn);
+                if (rc2 >= mp.low2) {
+                    far_mixed<KIND>(px, pz, H, rc2, e.lx, e.lz, e.area, sp, sx, sz, sn);
                     continue;
                 }
             }
@@ -219,10 +221,9 @@ __device__ __forceinline__ void element_copies(const Elem &e, const ImgArgs &img
     MixParams mp;
     if (MIXED) {
         const double nd = near_factor * e.diam;
-        const double td = (e.kind == 0 ? 24.0 : 48.0) * e.diam;
+        const double ld = fmax(nd, (e.kind == 0 ? 24.0 : 48.0) * e.diam);
         const double qd = fmax(nd, (e.kind == 0 ? 32.0 : 96.0) * e.diam);
-        mp.near2 = nd * nd;
-        mp.tier2 = td * td;
+        mp.low2 = ld * ld;
         mp.quad2 = qd * qd;
     }
     ophi = oex = oey = oez = 0.0;
@@ -382,11 +383,12 @@ void launch_reduce_segments(const double *part, int nseg, int64_t m, double *out
 // Grid: x over blocks of 256 rows, y over blocks of kTileA columns.  Each
 // lane writes A[i + j n] for its row i and the block's columns j: the 256
 // lanes of a workgroup store 256 consecutive doubles of a column (2 KB).
-template <bool MIXED>
+// The matrix is assembled with the exact closed forms in both precision
+// modes: it is a small share of a step's interactions, and far-field
+// truncation in its entries would carry into sigma through the solve.
 __global__ __launch_bounds__(kBlock) void k_assemble(const double *__restrict__ drec, int n, ImgArgs img,
-                                                      double near_factor, const double *__restrict__ cx,
-                                                      const double *__restrict__ cy, const double *__restrict__ cz,
-                                                      double *__restrict__ A)
+                                                      const double *__restrict__ cx, const double *__restrict__ cy,
+                                                      const double *__restrict__ cz, double *__restrict__ A)
 {
     __shared__ double t_rec[kTileA * R_STRIDE];
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -406,23 +408,19 @@ __global__ __launch_bounds__(kBlock) void k_assemble(const double *__restrict__ 
         const int j = j0 + p;
         const Elem e = load_elem(t_rec + p * R_STRIDE);
         double cp, gx, gy, gz;
-        element_copies<MIXED>(e, img, Px, Py, Pz, i == j, near_factor, cp, gx, gy, gz);
+        element_copies<false>(e, img, Px, Py, Pz, i == j, 0.0, cp, gx, gy, gz);
         double a = diel ? kKe * (nx * gx + ny * gy + nz * gz) : kKe * cp;
         a += (diel && i == j) ? jump : 0.0;
         A[(size_t)j * n + i] = a;
     }
 }
 
-void launch_assemble(const double *drec, int64_t n, const ImgArgs &img, int mixed, double near_factor,
-                     const double *cx, const double *cy, const double *cz, double *A, hipStream_t s)
+void launch_assemble(const double *drec, int64_t n, const ImgArgs &img, const double *cx, const double *cy,
+                     const double *cz, double *A, hipStream_t s)
 {
     if (n <= 0) return;
     const dim3 g((unsigned)((n + kBlock - 1) / kBlock), (unsigned)((n + kTileA - 1) / kTileA));
-    if (mixed)
-        hipLaunchKernelGGL(k_assemble<true>, g, dim3(kBlock), 0, s, drec, (int)n, img, near_factor, cx, cy, cz, A);
-    else
-        hipLaunchKernelGGL(k_assemble<false>, g, dim3(kBlock), 0, s, drec, (int)n, img, near_factor, cx, cy, cz,
-                           A);
+    hipLaunchKernelGGL(k_assemble, g, dim3(kBlock), 0, s, drec, (int)n, img, cx, cy, cz, A);
 }
 
 }  // namespace nebem

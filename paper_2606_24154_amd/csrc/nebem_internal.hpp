@@ -103,8 +103,8 @@ void launch_eval_items(const WorkItem *items, int nitems, const ImgArgs *imgs, i
                        hipStream_t s);
 // out (4 x m) = k_e * sum over nseg segments of part (nseg x 4 x m), fixed order
 void launch_reduce_segments(const double *part, int nseg, int64_t m, double *out, hipStream_t s);
-// A (n x n col-major).  cx/cy/cz may be null (centroids).
-void launch_assemble(const double *drec, int64_t n, const ImgArgs &img, int mixed, double near_factor,
-                     const double *cx, const double *cy, const double *cz, double *A, hipStream_t s);
+// A (n x n col-major), exact closed forms.  cx/cy/cz may be null (centroids).
+void launch_assemble(const double *drec, int64_t n, const ImgArgs &img, const double *cx, const double *cy,
+                     const double *cz, double *A, hipStream_t s);
 
 }  // namespace nebem

@@ -50,8 +50,7 @@ static nebem_status session_build(nebem_session *s, const nebem_panels *panels, 
     }
     const bool mixed = s->opt.precision == NEBEM_MIXED;
     NEBEM_HIP(s->A.ensure((size_t)n * n * sizeof(double)));
-    launch_assemble(s->drec.as<double>(), n, s->img, mixed, s->opt.near_factor, nullptr, nullptr, nullptr,
-                    s->A.as<double>(), st);
+    launch_assemble(s->drec.as<double>(), n, s->img, nullptr, nullptr, nullptr, s->A.as<double>(), st);
     NEBEM_HIP(hipGetLastError());
     NEBEM_HIP(s->ipiv.ensure((size_t)n * sizeof(int)));
     NEBEM_HIP(s->perm.ensure((size_t)n * sizeof(int)));

@@ -104,12 +104,14 @@ def test_mixed_eval_gem_sampled(nb):
     assert ephi < 1e-6 and eE < 1e-6, (ephi, eE)
 
 
-def test_mixed_assembly_rows(nb, small_gem):
+def test_mixed_assembly_is_exact(nb, small_gem):
+    """The matrix is assembled with the exact closed forms in both modes."""
     g, A_ref, _, _, _ = small_gem
     dp = nb.DevicePanels.from_geometry(g, DEV)
     A = nb.assemble(dp, precision=nb.MIXED).cpu().numpy().T
+    assert np.array_equal(A, nb.assemble(dp, precision=nb.FP64).cpu().numpy().T)
     err = np.abs(A - A_ref) / np.abs(A_ref).max(axis=1, keepdims=True)
-    assert err.max() < 1e-6, err.max()
+    assert err.max() < 1e-10, err.max()
 
 
 def test_mixed_solve_refines_to_fp64(nb, small_gem):
