@@ -1,8 +1,8 @@
 // farfield_mixed.hpp -- far-field potential/field of one element copy for the
 // mixed-precision path: FP64 monopole plus an FP32 quadrature correction.
 //
-// Far from an element (R >= near_factor * D, R = distance to its centroid,
-// D = its diameter) the integrand of Sec. 2.1 is smooth, and a quadrature
+// Far from an element (R = distance to its centroid, D = its diameter, R
+// many D) the integrand of Sec. 2.1 is smooth, and a quadrature
 // rule with nodes s_k = c + delta_k and weights w_k (sum 1) gives
 //   Phi' = A sum_k w_k / R_k,   E' = A sum_k w_k (p - delta_k) / R_k^3
 // with p = P - c, R_k = |p - delta_k|.  The centroid term A/R_c is evaluated

@@ -77,8 +77,10 @@ struct WorkItem {
 // bad_count[1] = first invalid index (or n).  bad_count must be zeroed/set
 // to {0, n} by the caller.
 void launch_prep(const nebem_panels *p, double *drec, int *bad, hipStream_t s);
-// mixed != 0: copies with R >= near_factor * D use the FP64 monopole + FP32
-// quadrature far field; otherwise the exact FP64 closed forms everywhere.
+// mixed != 0: copies beyond the far-field tiers (rectangles >= 24 D,
+// triangles >= 48 D, never below near_factor D) use the FP64 monopole + FP32
+// correction far field, nearer ones the exact FP64 closed forms; mixed == 0:
+// the exact FP64 closed forms everywhere.
 void launch_eval(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
                  double near_factor, const double *px, const double *py, const double *pz, int64_t m, double *phi,
                  double *ex, double *ey, double *ez, hipStream_t s);
