@@ -4,7 +4,8 @@
 
 namespace nebem {
 
-constexpr int kNB = 64;  // LU panel width
+constexpr int kNB = 64;        // LU panel width
+constexpr int kOuterNB = 256;  // LU outer block width (multiple of kNB)
 
 // Device scratch of one factorisation: per-workgroup pivot candidates
 // (ceil(n/256) entries), a completion counter (must start at 0; every panel

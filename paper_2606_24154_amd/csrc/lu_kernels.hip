@@ -4,18 +4,26 @@
 // resident factors).
 //
 // Blocked right-looking factorisation, column-major A with leading
-// dimension n, panel width kNB:
-//   for each panel [k, k+kb):
-//     1. panel factorisation, one launch per column: every workgroup owns 256
-//        consecutive rows; a launch eliminates column c on its rows (scale by
-//        the pivot, rank-1 update of the rest of the panel) and then finds
-//        the largest |a| of column c+1 among its rows; the last workgroup to
-//        finish (atomic counter, no spinning) reduces the per-workgroup maxima,
-//        records the pivot (first index among equal maxima) and swaps the two
-//        rows inside the panel;
-//     2. the same row swaps applied to the columns left and right of the panel;
-//     3. U12 = L11^-1 A12 (unit lower triangular solve, LDS);
-//     4. A22 -= L21 U12 on the matrix cores (MFMA, 16x16x4 tiles).
+// dimension n, in two levels: outer blocks of kOuterNB columns, each
+// factored by panels of kNB columns whose updates stay inside the outer
+// block, followed by one update of the rest of the matrix with the whole
+// outer block (K = kOuterNB), so the trailing matrix is read and written
+// once per outer block instead of once per panel:
+//   for each outer block [K0, K1):
+//     for each panel [k, k+kb) of it:
+//       1. panel factorisation, one launch per column: every workgroup owns
+//          256 consecutive rows; a launch eliminates column c on its rows
+//          (scale by the pivot, rank-1 update of the rest of the panel) and
+//          then finds the largest |a| of column c+1 among its rows; the last
+//          workgroup to finish (atomic counter, no spinning) reduces the
+//          per-workgroup maxima, records the pivot (first index among equal
+//          maxima) and swaps the two rows inside the panel;
+//       2. the same row swaps applied to every column outside the panel;
+//       3. U = L11^-1 A for the columns [k+kb, K1) (unit lower solve, LDS);
+//       4. A -= L21 U on rows [k+kb, n) x columns [k+kb, K1) (MFMA);
+//     5. U12 = L11^-1 A12 for the columns [K1, n), panel by panel (step 3 and
+//        an MFMA update of the outer block's lower rows);
+//     6. A22 -= L21 U12 on rows and columns [K1, n), K = K1 - K0 (MFMA).
 // T = double uses v_mfma_f64_16x16x4_f64, T = float v_mfma_f32_16x16x4_f32.
 #include <hip/hip_runtime.h>
 
@@ -150,15 +158,16 @@ __global__ __launch_bounds__(256) void k_laswp(T *__restrict__ A, int n, int k, 
     }
 }
 
-// U12 = L11^-1 A12 for 64 columns per workgroup (unit lower L11, kb x kb).
+// U = L11^-1 A[k:k+kb, j] for the columns j in [jb, je), 64 per workgroup
+// (unit lower L11 = A[k:k+kb, k:k+kb], kb <= 64).
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsm(T *__restrict__ A, int n, int k, int kb)
+__global__ __launch_bounds__(256) void k_trsm(T *__restrict__ A, int n, int k, int kb, int jb, int je)
 {
     __shared__ T L[kNB][kNB + 1];
     __shared__ T X[kNB][kNB + 1];
     const int tid = threadIdx.x;
-    const int j0 = k + kb + blockIdx.x * 64;
-    const int ncol = min(64, n - j0);
+    const int j0 = jb + blockIdx.x * 64;
+    const int ncol = min(64, je - j0);
     for (int e = tid; e < kb * kb; e += 256) {
         const int rr = e % kb, cc = e / kb;
         L[rr][cc] = A[(size_t)(k + cc) * n + k + rr];
@@ -216,20 +225,38 @@ struct Acc<float> {
     static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
 };
 
-constexpr int kGT = 64;  // trailing-update workgroup tile (rows and columns)
-constexpr int kKC = 32;  // K chunk staged in LDS at a time (keeps several workgroups per CU)
+constexpr int kGT = 64;     // trailing-update workgroup tile (rows and columns)
+constexpr int kKC = 32;     // K chunk staged in LDS at a time (keeps several workgroups per CU)
+constexpr int kXCD = 8;     // accelerator complex dies; workgroups are dealt to them round-robin
+constexpr int kGroupR = 8;  // tile rows per group of the tile order
 
+// C[r0:r1, c0:c1] -= A[r0:r1, k:k+kb] A[k:k+kb, c0:c1] for any kb.  1-D grid
+// of kXCD * per_xcd workgroups: workgroup b works on linear tile
+// (b % kXCD) * per_xcd + b / kXCD, so each die takes one contiguous range of
+// the tile order, and that order walks groups of kGroupR tile rows column by
+// column -- the workgroups a die runs at one time share their L21 and U12
+// tiles in its L2.
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_update(T *__restrict__ A, int n, int k, int kb)
+__global__ __launch_bounds__(256) void k_gemm_update(T *__restrict__ A, int n, int k, int kb, int r0, int r1, int c0,
+                                                     int c1, int per_xcd)
 {
     typedef typename Acc<T>::type V4;
-    __shared__ T sL[kKC][kGT];  // sL[kk][row] = -L21 tile, one K chunk
-    __shared__ T sU[kKC][kGT];  // sU[kk][col] =  U12 tile
-    const int kb4 = (kb + 3) & ~3;
+    // One K chunk of the operands.  Strides chosen so that the 32 lanes of
+    // each half-wave hit distinct LDS banks on the staging stores and on the
+    // MFMA operand loads: -L21 row-major in k (rows contiguous, as in A),
+    // U12 column-major (k contiguous, as in A).
+    __shared__ T sL[kKC][kGT + 16];  // sL[kk][row] = -L21
+    __shared__ T sU[kGT][kKC + 2];   // sU[col][kk] =  U12
+    const int nt_r = (r1 - r0 + kGT - 1) / kGT, nt_c = (c1 - c0 + kGT - 1) / kGT;
+    const int lin = (int)(blockIdx.x % kXCD) * per_xcd + (int)(blockIdx.x / kXCD);
+    if (lin >= nt_r * nt_c) return;  // whole workgroup: padding of the last die's range
+    const int gsz = kGroupR * nt_c;
+    const int first = (lin / gsz) * kGroupR;
+    const int rows_in = min(kGroupR, nt_r - first);
+    const int within = lin % gsz;
+    const int row0 = r0 + (first + within % rows_in) * kGT;
+    const int col0 = c0 + (within / rows_in) * kGT;
     const int tid = threadIdx.x;
-    const int base = k + kb;
-    const int m = n - base;
-    const int row0 = blockIdx.x * kGT, col0 = blockIdx.y * kGT;
     const int wave = tid >> 6, lane = tid & 63;
     const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;  // wave's 32x32 sub-tile
     const int li = lane & 15, lk = lane >> 4;
@@ -244,25 +271,30 @@ __global__ __launch_bounds__(256) void k_gemm_update(T *__restrict__ A, int n, i
             for (int v = 0; v < 4; ++v) {
                 const int gc = col0 + wc + 16 * tc + Acc<T>::row(lk, v);
                 const int gr = row0 + wr + 16 * tr + li;
-                acc[tc][tr][v] = (gc < m && gr < m) ? A[(size_t)(base + gc) * n + base + gr] : T(0);
+                acc[tc][tr][v] = (gc < c1 && gr < r1) ? A[(size_t)gc * n + gr] : T(0);
             }
-    for (int k0 = 0; k0 < kb4; k0 += kKC) {
-        const int kc = min(kKC, kb4 - k0);
+    // K in chunks of kKC; entries past kb are staged as zeros, so every chunk
+    // has the same compile-time shape (index arithmetic by shifts, the MFMA
+    // loop fully unrolled)
+    for (int k0 = 0; k0 < kb; k0 += kKC) {
         if (k0) __syncthreads();
-        for (int e = tid; e < kc * kGT; e += 256) {
+#pragma unroll
+        for (int e = tid; e < kKC * kGT; e += 256) {
             const int rr = e % kGT, kk = e / kGT;
             const int gr = row0 + rr, gk = k0 + kk;
-            sL[kk][rr] = (gr < m && gk < kb) ? -A[(size_t)(k + gk) * n + base + gr] : T(0);
+            sL[kk][rr] = (gr < r1 && gk < kb) ? -A[(size_t)(k + gk) * n + gr] : T(0);
         }
-        for (int e = tid; e < kc * kGT; e += 256) {
-            const int kk = e % kc, cc = e / kc;
+#pragma unroll
+        for (int e = tid; e < kKC * kGT; e += 256) {
+            const int kk = e % kKC, cc = e / kKC;
             const int gc = col0 + cc, gk = k0 + kk;
-            sU[kk][cc] = (gc < m && gk < kb) ? A[(size_t)(base + gc) * n + k + gk] : T(0);
+            sU[cc][kk] = (gc < c1 && gk < kb) ? A[(size_t)gc * n + k + gk] : T(0);
         }
         __syncthreads();
-        for (int kk = 0; kk < kc; kk += 4) {
+#pragma unroll
+        for (int kk = 0; kk < kKC; kk += 4) {
             // A operand: U12 columns (i index), B operand: -L21 rows (j index)
-            const T u0 = sU[kk + lk][wc + li], u1 = sU[kk + lk][wc + 16 + li];
+            const T u0 = sU[wc + li][kk + lk], u1 = sU[wc + 16 + li][kk + lk];
             const T l0 = sL[kk + lk][wr + li], l1 = sL[kk + lk][wr + 16 + li];
             acc[0][0] = mfma16(u0, l0, acc[0][0]);
             acc[0][1] = mfma16(u0, l1, acc[0][1]);
@@ -279,8 +311,25 @@ __global__ __launch_bounds__(256) void k_gemm_update(T *__restrict__ A, int n, i
             for (int v = 0; v < 4; ++v) {
                 const int gc = col0 + wc + 16 * tc + Acc<T>::row(lk, v);
                 const int gr = row0 + wr + 16 * tr + li;
-                if (gc < m && gr < m) A[(size_t)(base + gc) * n + base + gr] = acc[tc][tr][v];
+                if (gc < c1 && gr < r1) A[(size_t)gc * n + gr] = acc[tc][tr][v];
             }
+}
+
+template <typename T>
+static void gemm_update(T *A, int n, int k, int kb, int r0, int r1, int c0, int c1, hipStream_t s)
+{
+    if (r1 <= r0 || c1 <= c0 || kb <= 0) return;
+    const int tiles = ((r1 - r0 + kGT - 1) / kGT) * ((c1 - c0 + kGT - 1) / kGT);
+    const int per_xcd = (tiles + kXCD - 1) / kXCD;
+    hipLaunchKernelGGL(k_gemm_update<T>, dim3((unsigned)(per_xcd * kXCD)), dim3(256), 0, s, A, n, k, kb, r0, r1, c0,
+                       c1, per_xcd);
+}
+
+template <typename T>
+static void trsm(T *A, int n, int k, int kb, int jb, int je, hipStream_t s)
+{
+    if (je <= jb) return;
+    hipLaunchKernelGGL(k_trsm<T>, dim3((unsigned)((je - jb + 63) / 64)), dim3(256), 0, s, A, n, k, kb, jb, je);
 }
 
 // ------------------------------------------------------ triangular solves
@@ -364,21 +413,28 @@ __global__ __launch_bounds__(256) void k_permute(const TB *__restrict__ B, TX *_
 template <typename T>
 void lu_factor_launch(T *A, int n, int *ipiv, LUWork &w, hipStream_t s)
 {
-    for (int k = 0; k < n; k += kNB) {
-        const int kb = (n - k < kNB) ? n - k : kNB;
-        const unsigned gp = (unsigned)((n - k + kPB - 1) / kPB);
-        for (int c = k - 1; c < k + kb; ++c)
-            hipLaunchKernelGGL(k_panel<T>, dim3(gp), dim3(kPB), 0, s, A, n, k, kb, c, ipiv, (T *)w.pval, w.pidx,
-                               w.counter, w.info);
-        if (n - kb > 0) {
-            const unsigned gl = (unsigned)((n - kb + 255) / 256);
-            hipLaunchKernelGGL(k_laswp<T>, dim3(gl), dim3(256), 0, s, A, n, k, kb, ipiv);
+    for (int K0 = 0; K0 < n; K0 += kOuterNB) {
+        const int K1 = (n - K0 < kOuterNB) ? n : K0 + kOuterNB;
+        for (int k = K0; k < K1; k += kNB) {
+            const int kb = (K1 - k < kNB) ? K1 - k : kNB;
+            const unsigned gp = (unsigned)((n - k + kPB - 1) / kPB);
+            for (int c = k - 1; c < k + kb; ++c)
+                hipLaunchKernelGGL(k_panel<T>, dim3(gp), dim3(kPB), 0, s, A, n, k, kb, c, ipiv, (T *)w.pval, w.pidx,
+                                   w.counter, w.info);
+            if (n - kb > 0) {
+                const unsigned gl = (unsigned)((n - kb + 255) / 256);
+                hipLaunchKernelGGL(k_laswp<T>, dim3(gl), dim3(256), 0, s, A, n, k, kb, ipiv);
+            }
+            trsm(A, n, k, kb, k + kb, K1, s);
+            gemm_update(A, n, k, kb, k + kb, n, k + kb, K1, s);
         }
-        const int m = n - k - kb;
-        if (m > 0) {
-            hipLaunchKernelGGL(k_trsm<T>, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, s, A, n, k, kb);
-            const unsigned gt = (unsigned)((m + kGT - 1) / kGT);
-            hipLaunchKernelGGL(k_gemm_update<T>, dim3(gt, gt), dim3(256), 0, s, A, n, k, kb);
+        if (K1 < n) {
+            for (int b = K0; b < K1; b += kNB) {
+                const int bb = (K1 - b < kNB) ? K1 - b : kNB;
+                trsm(A, n, b, bb, K1, n, s);
+                gemm_update(A, n, b, bb, b + bb, K1, K1, n, s);
+            }
+            gemm_update(A, n, K0, K1 - K0, K1, n, K1, n, s);
         }
     }
 }

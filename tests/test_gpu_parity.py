@@ -241,7 +241,7 @@ def test_gem_eval_sampled_points(nb, gem):
 
 # ------------------------------------------------------------------- solve
 
-@pytest.mark.parametrize("n", [1, 5, 63, 64, 65, 130, 257, 777])
+@pytest.mark.parametrize("n", [1, 5, 63, 64, 65, 130, 257, 777, 1029])
 def test_lu_random(nb, n):
     rng = np.random.default_rng(n)
     A = rng.standard_normal((n, n)) + np.eye(n) * 0.5
