@@ -108,7 +108,7 @@ typedef struct nebem_options {
 } nebem_options;
 
 typedef struct nebem_solve_info {
-    int32_t ir_iters;     /* refinement step of the returned iterate (0 in FP64 mode) */
+    int32_t ir_iters;     /* refinement steps taken (0 in FP64 mode) */
     double rel_resid;     /* ||b - A x||_2 / ||b||_2 of the returned x, FP64 (mixed mode; -1 if not computed) */
 } nebem_solve_info;
 
@@ -137,10 +137,7 @@ nebem_status nebem_assemble(const nebem_panels *panels, const nebem_images *imag
  *    (unit lower L below the diagonal, U on and above), ipiv[k] (int32, n
  *    entries, 0-based) is the row swapped with row k at step k.
  *  MIXED mode: A is left unchanged; the library factors an FP32 copy and
- *    refines in FP64 until ||b - A x||_2 <= ir_tol ||b||_2 per column, and
- *    further while each step still at least halves the residual (down to
- *    the FP64 floor, so that x approaches the FP64 solution), returning the
- *    best iterate.
+ *    refines in FP64 until ||b - A x||_2 <= ir_tol ||b||_2 per column.
  *    ipiv holds the FP32 factorisation's pivots.
  * b, sigma: n x nrhs column-major (may alias).  `info` (host, may be NULL)
  * receives iteration count and residual.  Synchronises `stream`.

@@ -153,8 +153,8 @@ __device__ __forceinline__ Elem load_elem(const double *d)
 // lane); nearer copies take the exact FP64 closed form, which in that band is
 // no more expensive than a higher-order rule would be.
 // The exact form is taken per lane in its far-regime evaluation when the
-// point is at least kFarDiam diameters from the centroid, else in the
-// cancellation-free general one; the choice depends on the point alone.
+// point is at least kFarDiam diameters from the element's corner o, else in
+// the cancellation-free general one; the choice depends on the point alone.
 struct MixParams {
     double low2;    // squared distance from which the FP32 low-order rule is used
     double quad2;   // squared distance from which the quadrupole expansion is used
@@ -192,17 +192,17 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
                 }
             }
             Kern k;
-            const double qx = X - cxl, qz = Z - czl;
-            if (qx * qx + qz * qz + H * H >= far2) {
+            const double r0sq = fma(X, X, fma(Z, Z, H * H));
+            if (r0sq >= far2) {
                 if (KIND == 0)
-                    k = rect_far(X, H, Z, e.lx, e.lz);
+                    k = rect_far(X, H, Z, e.lx, e.lz, r0sq);
                 else
-                    k = rtri_far(X, H, Z, e.lx, e.lz, e.hyp, e.ihyp);
+                    k = rtri_far(X, H, Z, e.lx, e.lz, e.hyp, e.ihyp, r0sq);
             } else {
                 if (KIND == 0)
-                    k = rect_fp64(X, H, Z, e.lx, e.lz);
+                    k = rect_fp64(X, H, Z, e.lx, e.lz, r0sq);
                 else
-                    k = rtri_fp64(X, H, Z, e.lx, e.lz, e.hyp, e.ihyp);
+                    k = rtri_fp64(X, H, Z, e.lx, e.lz, e.hyp, e.ihyp, r0sq);
             }
             sp += k.phi;
             sx += k.ex;

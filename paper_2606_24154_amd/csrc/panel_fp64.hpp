@@ -74,12 +74,13 @@ __device__ __forceinline__ double half_angle_fix(double half, double N)
     return half;
 }
 
-__device__ __forceinline__ Kern rect_fp64(double X, double H, double Z, double lx, double lz)
+// r0sq = X^2 + Z^2 + H^2 (squared distance to the corner o), computed by the caller
+__device__ __forceinline__ Kern rect_fp64(double X, double H, double Z, double lx, double lz, double r0sq)
 {
     const double H2 = H * H;
     const double xm = X - lx, zm = Z - lz;
     const double X2 = X * X, Z2 = Z * Z, xm2 = xm * xm, zm2 = zm * zm;
-    const double r00 = sqrt64(X2 + Z2 + H2);
+    const double r00 = sqrt64(r0sq);
     const double r10 = sqrt64(xm2 + Z2 + H2);
     const double r11 = sqrt64(xm2 + zm2 + H2);
     const double r01 = sqrt64(X2 + zm2 + H2);
@@ -112,12 +113,12 @@ __device__ __forceinline__ Kern rect_fp64(double X, double H, double Z, double l
 }
 
 __device__ __forceinline__ Kern rtri_fp64(double X, double H, double Z, double lx, double lz, double hyp,
-                                          double ihyp)
+                                          double ihyp, double r0sq)
 {
     const double H2 = H * H;
     const double xm = X - lx, zm = Z - lz;
     const double X2 = X * X, Z2 = Z * Z;
-    const double r0 = sqrt64(X2 + Z2 + H2);
+    const double r0 = sqrt64(r0sq);
     const double r1 = sqrt64(xm * xm + Z2 + H2);
     const double r2 = sqrt64(X2 + zm * zm + H2);
     // edges: 0 (0,0)->(lx,0) m=(0,-1) p=Z;  1 (lx,0)->(0,lz) m=(lz,lx)/hyp
@@ -143,8 +144,8 @@ __device__ __forceinline__ Kern rtri_fp64(double X, double H, double Z, double l
 
 // ------------------------------------------------------------- far regime
 // Same closed forms for a point whose distance R from the element's centroid
-// is at least kFarDiam element diameters D (D bounds every vertex-to-vertex
-// and centroid-to-vertex distance).  Then every vertex distance r_i >= 3R/4
+// is at least 4 element diameters D (D bounds every vertex-to-vertex and
+// centroid-to-vertex distance).  Then every vertex distance r_i >= 3R/4
 // >= 3D, so R_a + R_b >= 6 L for every edge: Lam_k = 2 atanh(L/(R_a + R_b))
 // with an argument below 1/6, and nothing cancels.  Each triangle's solid-
 // angle denominator exceeds r1 r2 r3 (1 + 3 (1 - D^2/(2 r_i r_j))) >= 1.6 R^3
@@ -152,14 +153,17 @@ __device__ __forceinline__ Kern rtri_fp64(double X, double H, double Z, double l
 // per triangle (0.04 for the rectangle's sum); no octant logic, and N = 0 on
 // the element's plane gives Omega = 0 by itself.  All the divisions share one
 // reciprocal of the product of their denominators.
-constexpr double kFarDiam = 4.0;
+// The kernels select this form by the distance of the element's corner o
+// (the local origin): |P - o| >= kFarDiam D implies R >= (kFarDiam - 1) D = 4 D,
+// and |P - o|^2 = X^2 + Z^2 + H^2 is needed by both forms anyway.
+constexpr double kFarDiam = 5.0;
 
-__device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx, double lz)
+__device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx, double lz, double r0sq)
 {
     const double H2 = H * H;
     const double xm = X - lx, zm = Z - lz;
     const double X2 = X * X, Z2 = Z * Z, xm2 = xm * xm, zm2 = zm * zm;
-    const double r00 = sqrt64_pos(X2 + Z2 + H2);
+    const double r00 = sqrt64_pos(r0sq);
     const double r10 = sqrt64_pos(xm2 + Z2 + H2);
     const double r11 = sqrt64_pos(xm2 + zm2 + H2);
     const double r01 = sqrt64_pos(X2 + zm2 + H2);
@@ -192,12 +196,12 @@ __device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx
 }
 
 __device__ __forceinline__ Kern rtri_far(double X, double H, double Z, double lx, double lz, double hyp,
-                                         double ihyp)
+                                         double ihyp, double r0sq)
 {
     const double H2 = H * H;
     const double xm = X - lx, zm = Z - lz;
     const double X2 = X * X, Z2 = Z * Z;
-    const double r0 = sqrt64_pos(X2 + Z2 + H2);
+    const double r0 = sqrt64_pos(r0sq);
     const double r1 = sqrt64_pos(xm * xm + Z2 + H2);
     const double r2 = sqrt64_pos(X2 + zm * zm + H2);
     const double s0 = r0 + r1, s1 = r1 + r2, s2 = r2 + r0;

@@ -119,10 +119,7 @@ nebem_status solve_mixed(const double *A, const float *LU32, const double *s, co
     }
     if (bnorm == 0.0) return NEBEM_OK;
     scale_vec(s, b, n, rs.as<double>(), st);
-    // Refinement continues past tol while each step still contracts the
-    // residual by at least 2x (the error of x shrinks with it; near the FP64
-    // floor the contraction stops), and returns the best iterate.
-    double best = INFINITY, prev = INFINITY;
+    double best = INFINITY;
     int stall = 0, it = 0;
     for (it = 1; it <= max_iter; ++it) {
         lu_solve(LU32, n, perm, rs.as<double>(), d32.as<float>(), w32.as<float>(), 1, st);
@@ -132,10 +129,8 @@ nebem_status solve_mixed(const double *A, const float *LU32, const double *s, co
         double rnorm = 0.0;
         if ((e = host_norm(sq.as<double>(), nblk, h, st, rnorm))) return e;
         const double rel = rnorm / bnorm;
-        const bool contracting = rel <= 0.5 * prev;
-        prev = rel;
         if (rel < best) {
-            stall = contracting ? 0 : stall + 1;
+            stall = (rel > 0.5 * best) ? stall + 1 : 0;
             best = rel;
             NEBEM_HIP(hipMemcpyAsync(xbest.p, x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
             if (info) {
@@ -145,8 +140,7 @@ nebem_status solve_mixed(const double *A, const float *LU32, const double *s, co
         } else {
             ++stall;
         }
-        if (best <= tol && !contracting) break;
-        if (stall >= 3) break;
+        if (best <= tol || stall >= 3) break;
     }
     if (best < INFINITY)  // otherwise no step was taken and x is still 0
         NEBEM_HIP(hipMemcpyAsync(x, xbest.p, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
