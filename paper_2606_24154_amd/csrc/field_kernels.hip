@@ -352,13 +352,21 @@ void launch_eval(const double *drec, const double *sigma, int64_t n, const ImgAr
 // up to 64 points of one request against one segment of the elements of one
 // resident geometry -- and writes the segment's unscaled partial sums.  The
 // per-point arithmetic does not depend on which other items share the launch.
-template <bool MIXED>
-__global__ __launch_bounds__(64) void k_eval_items(const WorkItem *__restrict__ items,
-                                                    const ImgArgs *__restrict__ imgs, double near_factor)
+__global__ __launch_bounds__(64) void k_eval_items_fp64(const WorkItem *__restrict__ items,
+                                                       const ImgArgs *__restrict__ imgs, double near_factor)
 {
     const WorkItem &w = items[blockIdx.x];
-    eval_block<MIXED, 64>(w.drec, w.sigma, w.n, imgs[w.geom], near_factor, w.px, w.py, w.pz, w.count, 0, 1.0,
-                          w.phi, w.ex, w.ey, w.ez);
+    eval_block<false, 64>(w.drec, w.sigma, w.n, imgs[w.geom], near_factor, w.px, w.py, w.pz, w.count, 0, 1.0, w.phi,
+                          w.ex, w.ey, w.ez);
+}
+
+// three waves per SIMD, as k_eval_mixed
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_eval_items_mixed(
+    const WorkItem *__restrict__ items, const ImgArgs *__restrict__ imgs, double near_factor)
+{
+    const WorkItem &w = items[blockIdx.x];
+    eval_block<true, 64>(w.drec, w.sigma, w.n, imgs[w.geom], near_factor, w.px, w.py, w.pz, w.count, 0, 1.0, w.phi,
+                         w.ex, w.ey, w.ez);
 }
 
 void launch_eval_items(const WorkItem *items, int nitems, const ImgArgs *imgs, int mixed, double near_factor,
@@ -366,9 +374,9 @@ void launch_eval_items(const WorkItem *items, int nitems, const ImgArgs *imgs, i
 {
     if (nitems <= 0) return;
     if (mixed)
-        hipLaunchKernelGGL(k_eval_items<true>, dim3(nitems), dim3(64), 0, s, items, imgs, near_factor);
+        hipLaunchKernelGGL(k_eval_items_mixed, dim3(nitems), dim3(64), 0, s, items, imgs, near_factor);
     else
-        hipLaunchKernelGGL(k_eval_items<false>, dim3(nitems), dim3(64), 0, s, items, imgs, near_factor);
+        hipLaunchKernelGGL(k_eval_items_fp64, dim3(nitems), dim3(64), 0, s, items, imgs, near_factor);
 }
 
 // out[k][i] = k_e sum_{s < nseg} part[(s * 4 + k) * m + i], k = phi, ex, ey, ez
