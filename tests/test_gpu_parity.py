@@ -104,6 +104,41 @@ def test_single_panel_all_distances(nb, kind):
     assert worst[0] < 1e-10 and worst[1] < 1e-10, worst
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+def test_far_regime_switch_and_element_plane(nb, kind):
+    """Points around the switch between the general and the far-regime
+    evaluation (distance from the corner o of 4.5 .. 6 diameters), and points
+    in the element's plane 5 .. 50 diameters away (normal field 0 there),
+    against the oracle at the FP64 bar."""
+    rng = np.random.default_rng(60 + kind)
+    for trial in range(4):
+        Q = _rot(rng)
+        lx, lz = rng.uniform(2e-6, 40e-6, 2)
+        o = rng.uniform(-1e-3, 1e-3, 3)
+        u, w = lx * Q[:, 0], lz * Q[:, 1]
+        b = GeometryBuilder()
+        (b.rect if kind == 0 else b.right_tri)(o, u, w)
+        g = b.build("one", Images(), o - 1, o + 1)
+        D = math.hypot(lx, lz)
+        d = rng.standard_normal((2000, 3))
+        d /= np.linalg.norm(d, axis=1)[:, None]
+        pts = o + (D * rng.uniform(4.5, 6.0, 2000))[:, None] * d
+        ang = rng.uniform(0, 2 * np.pi, 500)
+        r = D * rng.uniform(5.0, 50.0, 500)
+        inplane = o + (r * np.cos(ang))[:, None] * Q[:, 0] + (r * np.sin(ang))[:, None] * Q[:, 1]
+        pts = np.vstack([pts, inplane])
+        sigma = np.array([1.0])
+        got = gpu_eval(nb, g, sigma, pts)
+        ref = oracle.eval_points(g, sigma, pts)
+        ephi = np.abs(got[:, 0] - ref[:, 0]) / np.abs(ref[:, 0])
+        eE = np.linalg.norm(got[:, 1:] - ref[:, 1:], axis=1) / np.linalg.norm(ref[:, 1:], axis=1)
+        assert ephi.max() < 1e-10 and eE.max() < 1e-10, (trial, ephi.max(), eE.max())
+        # in-plane points: the field has no component along the normal
+        n = np.cross(u, w) / np.linalg.norm(np.cross(u, w))
+        en = np.abs(got[2000:, 1:] @ n) / np.linalg.norm(got[2000:, 1:], axis=1)
+        assert en.max() < 1e-10, en.max()
+
+
 # -------------------------------------------------------- parallel plates
 
 @pytest.fixture(scope="module")
