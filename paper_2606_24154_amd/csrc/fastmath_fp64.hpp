@@ -104,13 +104,12 @@ __device__ __forceinline__ double two_atanh_poly(double t)
     return fma(t * z, horner(kLogP, z), t + t);
 }
 
-// atan(t) for |t| <= 0.04 (z <= 0.0016): Taylor series through t^13; the
-// first omitted term is below 1e-18 |t|
-constexpr double kAtanSmall[6] = {-1.0 / 3.0, 1.0 / 5.0, -1.0 / 7.0, 1.0 / 9.0, -1.0 / 11.0, 1.0 / 13.0};
+// atan(t) for |t| <= 0.039 (z <= 0.001521): 4-coefficient polynomial
+// (kAtanFar, truncation error 6e-18 relative)
 __device__ __forceinline__ double atan_small(double t)
 {
     const double z = t * t;
-    return fma(t * z, horner(kAtanSmall, z), t);
+    return fma(t * z, horner(kAtanFar, z), t);
 }
 
 // atan2(y, x) with one division: t = min/max of |x|, |y| reduced to

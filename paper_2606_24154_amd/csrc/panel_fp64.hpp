@@ -149,8 +149,8 @@ __device__ __forceinline__ Kern rtri_fp64(double X, double H, double Z, double l
 // >= 3D, so R_a + R_b >= 6 L for every edge: Lam_k = 2 atanh(L/(R_a + R_b))
 // with an argument below 1/6, and nothing cancels.  Each triangle's solid-
 // angle denominator exceeds r1 r2 r3 (1 + 3 (1 - D^2/(2 r_i r_j))) >= 1.6 R^3
-// while |N| <= R D^2/2 <= R^3/32, so every arctangent argument is below 0.02
-// per triangle (0.04 for the rectangle's sum); no octant logic, and N = 0 on
+// while |N| <= R D^2/2 <= R^3/32, so every arctangent argument is below 0.0194
+// per triangle (0.0387 for the rectangle's sum); no octant logic, and N = 0 on
 // the element's plane gives Omega = 0 by itself.  All the divisions share one
 // reciprocal of the product of their denominators.
 // The kernels select this form by the distance of the element's corner o
