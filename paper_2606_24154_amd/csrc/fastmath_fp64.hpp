@@ -96,20 +96,21 @@ __device__ __forceinline__ double log1p_ratio(double nn, double dd)
     return fma(ee, kLn2Hi, fma(ee, kLn2Lo, t));
 }
 
-// 2 atanh(t) for 0 <= t <= (sqrt2 - 1)/(sqrt2 + 1): the range of the
-// polynomial above, used directly
-__device__ __forceinline__ double two_atanh_poly(double t)
+// 2 atanh(t) = 2t + t z P(z) and atan(t) = t + t z Q(z), z = t^2, with the
+// coefficient set fitted to the range t is known to lie in (kLogP: t up to
+// (sqrt2 - 1)/(sqrt2 + 1); kLogPVF: 1/48; kAtanFar: 0.039; kAtanVF: 6.5e-4)
+template <int N>
+__device__ __forceinline__ double two_atanh_poly(double t, const double (&c)[N])
 {
     const double z = t * t;
-    return fma(t * z, horner(kLogP, z), t + t);
+    return fma(t * z, horner(c, z), t + t);
 }
 
-// atan(t) for |t| <= 0.039 (z <= 0.001521): 4-coefficient polynomial
-// (kAtanFar, truncation error 6e-18 relative)
-__device__ __forceinline__ double atan_small(double t)
+template <int N>
+__device__ __forceinline__ double atan_small(double t, const double (&c)[N])
 {
     const double z = t * t;
-    return fma(t * z, horner(kAtanFar, z), t);
+    return fma(t * z, horner(c, z), t);
 }
 
 // atan2(y, x) with one division: t = min/max of |x|, |y| reduced to

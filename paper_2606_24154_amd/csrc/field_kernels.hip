@@ -169,6 +169,7 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
     const double cxl = KIND == 0 ? 0.5 * e.lx : e.lx * (1.0 / 3.0);
     const double czl = KIND == 0 ? 0.5 * e.lz : e.lz * (1.0 / 3.0);
     const double far2 = (kFarDiam * kFarDiam) * (e.diam * e.diam);
+    const double vfar2 = (kVeryFarDiam * kVeryFarDiam) * (e.diam * e.diam);
 #pragma unroll 1
     for (int i1 = -n1; i1 <= n1; ++i1) {
         const double f1 = -(double)i1;
@@ -193,11 +194,16 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
             }
             Kern k;
             const double r0sq = fma(X, X, fma(Z, Z, H * H));
-            if (r0sq >= far2) {
+            if (r0sq >= vfar2) {
                 if (KIND == 0)
-                    k = rect_far(X, H, Z, e.lx, e.lz, r0sq);
+                    k = rect_far<true>(X, H, Z, e.lx, e.lz, r0sq);
                 else
-                    k = rtri_far(X, H, Z, e.lx, e.lz, e.hyp, e.ihyp, r0sq);
+                    k = rtri_far<true>(X, H, Z, e.lx, e.lz, e.hyp, e.ihyp, r0sq);
+            } else if (r0sq >= far2) {
+                if (KIND == 0)
+                    k = rect_far<false>(X, H, Z, e.lx, e.lz, r0sq);
+                else
+                    k = rtri_far<false>(X, H, Z, e.lx, e.lz, e.hyp, e.ihyp, r0sq);
             } else {
                 if (KIND == 0)
                     k = rect_fp64(X, H, Z, e.lx, e.lz, r0sq);

@@ -156,8 +156,27 @@ __device__ __forceinline__ Kern rtri_fp64(double X, double H, double Z, double l
 // The kernels select this form by the distance of the element's corner o
 // (the local origin): |P - o| >= kFarDiam D implies R >= (kFarDiam - 1) D = 4 D,
 // and |P - o|^2 = X^2 + Z^2 + H^2 is needed by both forms anyway.
+// Beyond kVeryFarDiam D from o (R >= 24 D, every vertex >= 24 D away) the
+// same evaluation runs with shorter polynomials fitted to the smaller
+// ranges: atanh argument <= 1/48 (4 coefficients) and arctangent argument
+// <= 2 D^2/(3.2 R^2) <= 6.5e-4 for the rectangle's sum (2 coefficients).
 constexpr double kFarDiam = 5.0;
+constexpr double kVeryFarDiam = 25.0;
 
+template <bool VF>
+struct FarPoly;
+template <>
+struct FarPoly<false> {
+    static constexpr const double (&log)[kLogPN] = kLogP;
+    static constexpr const double (&atan)[kAtanFarN] = kAtanFar;
+};
+template <>
+struct FarPoly<true> {
+    static constexpr const double (&log)[kLogPVFN] = kLogPVF;
+    static constexpr const double (&atan)[kAtanVFN] = kAtanVF;
+};
+
+template <bool VF>
 __device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx, double lz, double r0sq)
 {
     const double H2 = H * H;
@@ -182,11 +201,11 @@ __device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx
     const double inv = rcp64(ab * den);
     const double iden = ab * inv, iab = den * inv;
     const double ia = iab * b, ib = iab * a;
-    const double L0 = two_atanh_poly(lx * (ia * s1));
-    const double L1 = two_atanh_poly(lz * (ia * s0));
-    const double L2 = two_atanh_poly(lx * (ib * s3));
-    const double L3 = two_atanh_poly(lz * (ib * s2));
-    const double omega = 2.0 * atan_small(N * (D1 + D2) * iden);
+    const double L0 = two_atanh_poly(lx * (ia * s1), FarPoly<VF>::log);
+    const double L1 = two_atanh_poly(lz * (ia * s0), FarPoly<VF>::log);
+    const double L2 = two_atanh_poly(lx * (ib * s3), FarPoly<VF>::log);
+    const double L3 = two_atanh_poly(lz * (ib * s2), FarPoly<VF>::log);
+    const double omega = 2.0 * atan_small(N * (D1 + D2) * iden, FarPoly<VF>::atan);
     Kern k;
     k.phi = Z * L0 + (lx - X) * L1 + (lz - Z) * L2 + X * L3 - H * omega;
     k.ex = L1 - L3;
@@ -195,6 +214,7 @@ __device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx
     return k;
 }
 
+template <bool VF>
 __device__ __forceinline__ Kern rtri_far(double X, double H, double Z, double lx, double lz, double hyp,
                                          double ihyp, double r0sq)
 {
@@ -216,10 +236,10 @@ __device__ __forceinline__ Kern rtri_far(double X, double H, double Z, double lx
     const double inv = rcp64(b * D);
     const double iD = b * inv, ib = D * inv;
     const double ia = ib * s2;
-    const double L0 = two_atanh_poly(lx * (ia * s1));
-    const double L1 = two_atanh_poly(hyp * (ia * s0));
-    const double L2 = two_atanh_poly(lz * (ib * a));
-    const double omega = 2.0 * atan_small(N * iD);
+    const double L0 = two_atanh_poly(lx * (ia * s1), FarPoly<VF>::log);
+    const double L1 = two_atanh_poly(hyp * (ia * s0), FarPoly<VF>::log);
+    const double L2 = two_atanh_poly(lz * (ib * a), FarPoly<VF>::log);
+    const double omega = 2.0 * atan_small(N * iD, FarPoly<VF>::atan);
     const double L1h = L1 * ihyp;
     Kern k;
     k.phi = Z * L0 + P1 * L1 + X * L2 - H * omega;
