@@ -258,14 +258,14 @@ def test_spacecharge_deterministic(nb, small_gem):
 
 def test_gem_full_size_sampled(nb):
     """The benchmark's configuration (8064 elements, 121 copies, 10^6 points),
-    FP64 and mixed, checked on 24 sampled points against the oracle with a
+    FP64 and mixed, checked on 64 sampled points against the oracle with a
     seeded density."""
     g = gem_cell()
     rng = np.random.default_rng(72)
     sigma = rng.normal(0, 1e-5, g.n)
     pts = gem_eval_points(g, 1_000_000, seed=1)
     dp = nb.DevicePanels.from_geometry(g, DEV)
-    idx = rng.choice(len(pts), 24, replace=False)
+    idx = rng.choice(len(pts), 64, replace=False)
     ref = oracle.eval_points(g, sigma, pts[idx])
     for prec, tol in ((nb.FP64, 1e-10), (nb.MIXED, 1e-6)):
         got = stack(nb.eval_points(dp, dev(sigma), *cols(pts), precision=prec))
