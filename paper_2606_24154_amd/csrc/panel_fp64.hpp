@@ -152,7 +152,9 @@ __device__ __forceinline__ Kern rtri_fp64(double X, double H, double Z, double l
 // while |N| <= R D^2/2 <= R^3/32, so every arctangent argument is below 0.0194
 // per triangle (0.0387 for the rectangle's sum); no octant logic, and N = 0 on
 // the element's plane gives Omega = 0 by itself.  All the divisions share one
-// reciprocal of the product of their denominators.
+// reciprocal of the product of their denominators; its error scales every
+// Lam_k and the solid angle by the same factor, which the cancellation among
+// the edge terms does not amplify, so one Newton step suffices.
 // The kernels select this form by the distance of the element's corner o
 // (the local origin): |P - o| >= kFarDiam D implies R >= (kFarDiam - 1) D = 4 D,
 // and |P - o|^2 = X^2 + Z^2 + H^2 is needed by both forms anyway.
@@ -198,7 +200,7 @@ __device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx
     const double den = D1 * D2 - N * N;
     // one reciprocal for 1/s0 .. 1/s3 and 1/den
     const double a = s0 * s1, b = s2 * s3, ab = a * b;
-    const double inv = rcp64(ab * den);
+    const double inv = rcp64_common(ab * den);
     const double iden = ab * inv, iab = den * inv;
     const double ia = iab * b, ib = iab * a;
     const double L0 = two_atanh_poly(lx * (ia * s1), FarPoly<VF>::log);
@@ -233,7 +235,7 @@ __device__ __forceinline__ Kern rtri_far(double X, double H, double Z, double lx
     const double D = r0 * r1 * r2 + d01 * r2 + d02 * r1 + d12 * r0;
     // one reciprocal for 1/s0, 1/s1, 1/s2 and 1/D
     const double a = s0 * s1, b = a * s2;
-    const double inv = rcp64(b * D);
+    const double inv = rcp64_common(b * D);
     const double iD = b * inv, ib = D * inv;
     const double ia = ib * s2;
     const double L0 = two_atanh_poly(lx * (ia * s1), FarPoly<VF>::log);
