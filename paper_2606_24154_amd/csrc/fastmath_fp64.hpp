@@ -59,14 +59,17 @@ __device__ __forceinline__ double sqrt64(double x)
     return x > 0.0 ? g : 0.0;
 }
 
-// sqrt(x) for x > 0 (no zero test)
+// sqrt(x) for x > 0 (no zero test).  With y = rsq(x) = (1 + e)/sqrt(x):
+// g = x y refined once has error ~1.5 e^2; the final residual correction
+// (x - g^2) h then needs h = y/2 only to relative accuracy e (its error
+// multiplies a correction of size e^2), leaving ~1.5 e^3 plus rounding.
 __device__ __forceinline__ double sqrt64_pos(double x)
 {
     const double y = __builtin_amdgcn_rsq(x);
-    double g = x * y, h = 0.5 * y;
+    double g = x * y;
+    const double h = 0.5 * y;
     const double r = fma(-g, h, 0.5);
     g = fma(g, r, g);
-    h = fma(h, r, h);
     return fma(fma(-g, g, x), h, g);
 }
 
@@ -105,7 +108,7 @@ __device__ __forceinline__ double log1p_ratio(double nn, double dd)
     return fma(ee, kLn2Hi, fma(ee, kLn2Lo, t));
 }
 
-// 2 atanh(t) = 2t + t z P(z) and atan(t) = t + t z Q(z), z = t^2, with the
+// 2 atanh(t) = t (2 + z P(z)) and atan(t) = t + t z Q(z), z = t^2, with the
 // coefficient set fitted to the range t is known to lie in (kLogP: t up to
 // (sqrt2 - 1)/(sqrt2 + 1); kLogPVF: 1/48; kAtanFar: 0.039; kAtanVF: 6.5e-4)
 template <int N>
@@ -115,11 +118,32 @@ __device__ __forceinline__ double two_atanh_poly(double t, const double (&c)[N])
     return t * fma(z, horner(c, z), 2.0);  // t (2 + z P(z)), about one ulp
 }
 
+// 2 atanh(L u) / L, for a caller that needs the logarithm divided by L
 template <int N>
-__device__ __forceinline__ double atan_small(double t, const double (&c)[N])
+__device__ __forceinline__ double two_atanh_over(double u, double L, const double (&c)[N])
 {
+    const double t = L * u;
     const double z = t * t;
-    return fma(t * z, horner(c, z), t);
+    return u * fma(z, horner(c, z), 2.0);
+}
+
+// 2 atan(u/2) from u: 2 atan(t) = u + u w Q(w/4)/4 with w = u^2; the
+// coefficients of Q are rescaled by powers of 4 (exact) at compile time
+template <int N>
+__device__ __forceinline__ double two_atan_half(double u, const double (&c)[N])
+{
+    const double w = u * u;
+    double acc = c[N - 1];
+    double sc = 1.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) sc *= 0.25;
+    acc *= sc;
+#pragma unroll
+    for (int k = N - 2; k >= 0; --k) {
+        sc *= 4.0;
+        acc = fma(acc, w, c[k] * sc);
+    }
+    return fma(u * w, acc, u);
 }
 
 // atan2(y, x) with one division: t = min/max of |x|, |y| reduced to

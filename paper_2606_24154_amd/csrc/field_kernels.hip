@@ -198,12 +198,12 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
                 if (KIND == 0)
                     k = rect_far<true>(X, H, Z, e.lx, e.lz, r0sq);
                 else
-                    k = rtri_far<true>(X, H, Z, e.lx, e.lz, e.hyp, e.ihyp, r0sq);
+                    k = rtri_far<true>(X, H, Z, e.lx, e.lz, e.hyp, r0sq);
             } else if (r0sq >= far2) {
                 if (KIND == 0)
                     k = rect_far<false>(X, H, Z, e.lx, e.lz, r0sq);
                 else
-                    k = rtri_far<false>(X, H, Z, e.lx, e.lz, e.hyp, e.ihyp, r0sq);
+                    k = rtri_far<false>(X, H, Z, e.lx, e.lz, e.hyp, r0sq);
             } else {
                 if (KIND == 0)
                     k = rect_fp64(X, H, Z, e.lx, e.lz, r0sq);

@@ -189,7 +189,7 @@ __device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx
     const double r11 = sqrt64_pos(xm2 + zm2 + H2);
     const double r01 = sqrt64_pos(X2 + zm2 + H2);
     const double s0 = r00 + r10, s1 = r10 + r11, s2 = r11 + r01, s3 = r01 + r00;
-    const double N = H * lx * lz;
+    const double N2 = H * (2.0 * lx * lz);  // twice the triple product
     const double d00_10 = X * xm + Z2 + H2;
     const double d00_11 = X * xm + Z * zm + H2;
     const double d10_11 = xm2 + Z * zm + H2;
@@ -197,7 +197,7 @@ __device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx
     const double d11_01 = X * xm + zm2 + H2;
     const double D1 = r00 * r10 * r11 + d00_10 * r11 + d00_11 * r10 + d10_11 * r00;
     const double D2 = r00 * r11 * r01 + d00_11 * r01 + d00_01 * r11 + d11_01 * r00;
-    const double den = D1 * D2 - N * N;
+    const double den = fma(-0.25 * N2, N2, D1 * D2);
     // one reciprocal for 1/s0 .. 1/s3 and 1/den
     const double a = s0 * s1, b = s2 * s3, ab = a * b;
     const double inv = rcp64_common(ab * den);
@@ -207,7 +207,7 @@ __device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx
     const double L1 = two_atanh_poly(lz * (ia * s0), FarPoly<VF>::log);
     const double L2 = two_atanh_poly(lx * (ib * s3), FarPoly<VF>::log);
     const double L3 = two_atanh_poly(lz * (ib * s2), FarPoly<VF>::log);
-    const double omega = 2.0 * atan_small(N * (D1 + D2) * iden, FarPoly<VF>::atan);
+    const double omega = two_atan_half(N2 * (D1 + D2) * iden, FarPoly<VF>::atan);
     Kern k;
     k.phi = Z * L0 + (lx - X) * L1 + (lz - Z) * L2 + X * L3 - H * omega;
     k.ex = L1 - L3;
@@ -218,7 +218,7 @@ __device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx
 
 template <bool VF>
 __device__ __forceinline__ Kern rtri_far(double X, double H, double Z, double lx, double lz, double hyp,
-                                         double ihyp, double r0sq)
+                                         double r0sq)
 {
     const double H2 = H * H;
     const double xm = X - lx, zm = Z - lz;
@@ -227,8 +227,8 @@ __device__ __forceinline__ Kern rtri_far(double X, double H, double Z, double lx
     const double r1 = sqrt64_pos(xm * xm + Z2 + H2);
     const double r2 = sqrt64_pos(X2 + zm * zm + H2);
     const double s0 = r0 + r1, s1 = r1 + r2, s2 = r2 + r0;
-    const double P1 = (lx * lz - X * lz - Z * lx) * ihyp;
-    const double N = H * lx * lz;
+    const double P1n = lx * lz - X * lz - Z * lx;  // hyp times the distance to edge 1
+    const double N2 = H * (2.0 * lx * lz);  // twice the triple product
     const double d01 = X * xm + Z2 + H2;
     const double d02 = X2 + Z * zm + H2;
     const double d12 = X * xm + Z * zm + H2;
@@ -239,12 +239,11 @@ __device__ __forceinline__ Kern rtri_far(double X, double H, double Z, double lx
     const double iD = b * inv, ib = D * inv;
     const double ia = ib * s2;
     const double L0 = two_atanh_poly(lx * (ia * s1), FarPoly<VF>::log);
-    const double L1 = two_atanh_poly(hyp * (ia * s0), FarPoly<VF>::log);
+    const double L1h = two_atanh_over(ia * s0, hyp, FarPoly<VF>::log);  // Lam_1 / hyp
     const double L2 = two_atanh_poly(lz * (ib * a), FarPoly<VF>::log);
-    const double omega = 2.0 * atan_small(N * iD, FarPoly<VF>::atan);
-    const double L1h = L1 * ihyp;
+    const double omega = two_atan_half(N2 * iD, FarPoly<VF>::atan);
     Kern k;
-    k.phi = Z * L0 + P1 * L1 + X * L2 - H * omega;
+    k.phi = Z * L0 + P1n * L1h + X * L2 - H * omega;
     k.ex = lz * L1h - L2;
     k.ez = lx * L1h - L0;
     k.en = omega;
