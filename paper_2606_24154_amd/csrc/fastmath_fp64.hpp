@@ -29,9 +29,9 @@ __device__ __forceinline__ double rcp64(double d)
     return fma(r, e, r);
 }
 
-// 1/d from the hardware estimate with one Newton step (relative error about
-// 1.5e-14): for a reciprocal whose error may scale a whole set of quotients
-// by one common factor
+// 1/d from the hardware estimate with one Newton step (the estimate is good
+// to ~5e-8 relative on gfx950, the result to ~2e-15): for a reciprocal whose
+// error scales a whole set of quotients by one common factor
 __device__ __forceinline__ double rcp64_common(double d)
 {
     const double r = __builtin_amdgcn_rcp(d);
@@ -44,19 +44,6 @@ __device__ __forceinline__ double div64(double n, double d)
     const double r = rcp64(d);
     const double q = n * r;
     return fma(fma(-d, q, n), r, q);
-}
-
-// sqrt(x), x >= 0: reciprocal-square-root estimate, one coupled Newton step
-// on (sqrt, 1/(2 sqrt)) and a final residual correction
-__device__ __forceinline__ double sqrt64(double x)
-{
-    const double y = __builtin_amdgcn_rsq(x);
-    double g = x * y, h = 0.5 * y;
-    const double r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    g = fma(fma(-g, g, x), h, g);
-    return x > 0.0 ? g : 0.0;
 }
 
 // sqrt(x) for x > 0 (no zero test).  With y = rsq(x) = (1 + e)/sqrt(x):
@@ -72,6 +59,9 @@ __device__ __forceinline__ double sqrt64_pos(double x)
     g = fma(g, r, g);
     return fma(fma(-g, g, x), h, g);
 }
+
+// sqrt(x), x >= 0 (0 for x == 0, where the estimate is infinite)
+__device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? sqrt64_pos(x) : 0.0; }
 
 template <int N>
 __device__ __forceinline__ double horner(const double (&c)[N], double z)
