@@ -77,11 +77,36 @@ __device__ __forceinline__ void far_node(float px, float pz, float rc2, float rc
     a.gz = fmaf(w3, dz, a.gz);
 }
 
+// Corrections per unit area, summed in FP32 over the copies of one element
+// and added to the FP64 sums once, scaled by the area.  Each is at most a few
+// 1e-3 of its copy's monopole, so the FP32 sum over ~100 copies keeps them
+// to ~1e-8 of the element's field, below the tiers' truncation error.
+struct FarCorr {
+    float p, x, z, n;
+};
+
+// FP64 monopole A/R_c, A p/R_c^3 of one copy added to (sp, sx, sz, sn).
+// 1/R_c from the FP32 estimate fic (relative error <= 2^-23) by one Newton
+// step (error ~1.5 x 2^-46), far inside the mixed path's error budget.
+__device__ __forceinline__ void monopole_fp64(double px, double pz, double ph, double rc2, float fic, double area,
+                                              double &sp, double &sx, double &sz, double &sn)
+{
+    double ir = (double)fic;
+    ir = ir * (1.5 - 0.5 * rc2 * ir * ir);
+    const double air = area * ir;
+    const double air3 = air * ir * ir;
+    sp += air;
+    sx = fma(air3, px, sx);
+    sz = fma(air3, pz, sz);
+    sn = fma(air3, ph, sn);
+}
+
 // p = (px, pz, ph): point relative to the element centroid in the element
-// frame (FP64); rc2 = |p|^2.  Adds Phi', E' (local frame) to (sp, sx, sz, sn).
+// frame (FP64); rc2 = |p|^2.  Adds the monopole of Phi', E' (local frame) to
+// (sp, sx, sz, sn) and the quadrature correction per unit area to c.
 template <int KIND>
 __device__ __forceinline__ void far_mixed(double px, double pz, double ph, double rc2, double lx, double lz,
-                                          double area, double &sp, double &sx, double &sz, double &sn)
+                                          double area, double &sp, double &sx, double &sz, double &sn, FarCorr &c)
 {
     const float fx = (float)px, fz = (float)pz;
     const float frc2 = (float)rc2;
@@ -104,26 +129,20 @@ __device__ __forceinline__ void far_mixed(double px, double pz, double ph, doubl
             far_node(fx, fz, frc2, frc, fic, fic2, flx * (TriR3::s[k] - third), flz * (TriR3::t[k] - third),
                      TriR3::w[k], a);
     }
-    // FP64 monopole: 1/R_c from the FP32 estimate (relative error <= 2^-23)
-    // by one Newton step (error ~1.5 x 2^-46), far inside the mixed path's
-    // error budget
-    double ir = (double)fic;
-    ir = ir * (1.5 - 0.5 * rc2 * ir * ir);
-    const double air = area * ir;
-    const double air3 = air * ir * ir;
-    // corrections (FP32), promoted and added
-    const float cf = fic * a.cphi;      // sum w (1/R_k - 1/R_c)
-    const float gf = fic * a.gp;        // sum w (1/R_k^3 - 1/R_c^3)
-    sp += air + area * (double)cf;
-    sx += air3 * px + area * (double)(fx * gf - a.gx);
-    sz += air3 * pz + area * (double)(fz * gf - a.gz);
-    sn += air3 * ph + area * (double)((float)ph * gf);
+    monopole_fp64(px, pz, ph, rc2, fic, area, sp, sx, sz, sn);
+    const float cf = fic * a.cphi;  // sum w (1/R_k - 1/R_c)
+    const float gf = fic * a.gp;    // sum w (1/R_k^3 - 1/R_c^3)
+    c.p += cf;
+    c.x += fmaf(fx, gf, -a.gx);
+    c.z += fmaf(fz, gf, -a.gz);
+    c.n = fmaf((float)ph, gf, c.n);
 }
 
 // Beyond the quadrupole tier: FP64 monopole plus the FP32 quadrupole term.
 template <int KIND>
 __device__ __forceinline__ void far_quadrupole(double px, double pz, double ph, double rc2, double lx, double lz,
-                                               double area, double &sp, double &sx, double &sz, double &sn)
+                                               double area, double &sp, double &sx, double &sz, double &sn,
+                                               FarCorr &c)
 {
     const float fx = (float)px, fz = (float)pz, fh = (float)ph;
     const float frc2 = (float)rc2;
@@ -146,19 +165,12 @@ __device__ __forceinline__ void far_quadrupole(double px, double pz, double ph, 
     }
     const float t = mxx + mzz;
     const float u = fmaf(3.0f, fmaf(fx, mpx, fz * mpz), -frc2 * t);  // 3q - R^2 t
-    const float qphi = 0.5f * u * fic5;
     const float g = fmaf(2.5f * u, fic2, t);
-    const float qx = fic5 * fmaf(g, fx, -3.0f * mpx);
-    const float qz = fic5 * fmaf(g, fz, -3.0f * mpz);
-    const float qn = fic5 * (g * fh);
-    double ir = (double)fic;
-    ir = ir * (1.5 - 0.5 * rc2 * ir * ir);  // one Newton step, as in far_mixed
-    const double air = area * ir;
-    const double air3 = air * ir * ir;
-    sp += air + area * (double)qphi;
-    sx += air3 * px + area * (double)qx;
-    sz += air3 * pz + area * (double)qz;
-    sn += air3 * ph + area * (double)qn;
+    c.p = fmaf(0.5f * u, fic5, c.p);
+    c.x = fmaf(fic5, fmaf(g, fx, -3.0f * mpx), c.x);
+    c.z = fmaf(fic5, fmaf(g, fz, -3.0f * mpz), c.z);
+    c.n = fmaf(fic5, g * fh, c.n);
+    monopole_fp64(px, pz, ph, rc2, fic, area, sp, sx, sz, sn);
 }
 
 }  // namespace nebem

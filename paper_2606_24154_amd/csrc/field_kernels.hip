@@ -170,6 +170,7 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
     const double czl = KIND == 0 ? 0.5 * e.lz : e.lz * (1.0 / 3.0);
     const double far2 = (kFarDiam * kFarDiam) * (e.diam * e.diam);
     const double vfar2 = (kVeryFarDiam * kVeryFarDiam) * (e.diam * e.diam);
+    FarCorr fc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll 1
     for (int i1 = -n1; i1 <= n1; ++i1) {
         const double f1 = -(double)i1;
@@ -184,11 +185,11 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
                 const double px = X - cxl, pz = Z - czl;
                 const double rc2 = px * px + pz * pz + H * H;
                 if (rc2 >= mp.quad2) {
-                    far_quadrupole<KIND>(px, pz, H, rc2, e.lx, e.lz, e.area, sp, sx, sz, sn);
+                    far_quadrupole<KIND>(px, pz, H, rc2, e.lx, e.lz, e.area, sp, sx, sz, sn, fc);
                     continue;
                 }
                 if (rc2 >= mp.low2) {
-                    far_mixed<KIND>(px, pz, H, rc2, e.lx, e.lz, e.area, sp, sx, sz, sn);
+                    far_mixed<KIND>(px, pz, H, rc2, e.lx, e.lz, e.area, sp, sx, sz, sn, fc);
                     continue;
                 }
             }
@@ -215,6 +216,12 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
             sz += k.ez;
             sn += k.en;
         }
+    }
+    if (MIXED) {
+        sp = fma(e.area, (double)fc.p, sp);
+        sx = fma(e.area, (double)fc.x, sx);
+        sz = fma(e.area, (double)fc.z, sz);
+        sn = fma(e.area, (double)fc.n, sn);
     }
 }
 
