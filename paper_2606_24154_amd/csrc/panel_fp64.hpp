@@ -160,8 +160,15 @@ __device__ __forceinline__ Kern rtri_fp64(double X, double H, double Z, double l
 // and |P - o|^2 = X^2 + Z^2 + H^2 is needed by both forms anyway.
 // Beyond kVeryFarDiam D from o (R >= 24 D, every vertex >= 24 D away) the
 // same evaluation runs with shorter polynomials fitted to the smaller
-// ranges: atanh argument <= 1/48 (4 coefficients) and arctangent argument
+// ranges: atanh argument <= 1/48 (3 coefficients) and arctangent argument
 // <= 2 D^2/(3.2 R^2) <= 6.5e-4 for the rectangle's sum (2 coefficients).
+// Both far forms take the potential from the field components: with
+// E_x' = Lam_1 - Lam_3, E_z' = Lam_2 - Lam_0 (rectangle) the edge sum
+// Z Lam_0 + (lx - X) Lam_1 + (lz - Z) Lam_2 + X Lam_3 equals
+// lx Lam_1 + lz Lam_2 - X E_x' - Z E_z', and for the right triangle
+// Z Lam_0 + P1 Lam_1 + X Lam_2 equals lx lz Lam_1/hyp - X E_x' - Z E_z'.
+// Far away each of these terms is of the size of the potential itself
+// instead of lx or lz, and two products fewer are formed.
 constexpr double kFarDiam = 5.0;
 constexpr double kVeryFarDiam = 25.0;
 
@@ -195,8 +202,8 @@ __device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx
     const double d10_11 = xm2 + Z * zm + H2;
     const double d00_01 = X2 + Z * zm + H2;
     const double d11_01 = X * xm + zm2 + H2;
-    const double D1 = r00 * r10 * r11 + d00_10 * r11 + d00_11 * r10 + d10_11 * r00;
-    const double D2 = r00 * r11 * r01 + d00_11 * r01 + d00_01 * r11 + d11_01 * r00;
+    const double D1 = fma(fma(r00, r10, d00_10), r11, fma(d00_11, r10, d10_11 * r00));
+    const double D2 = fma(fma(r00, r11, d00_11), r01, fma(d00_01, r11, d11_01 * r00));
     const double den = fma(-0.25 * N2, N2, D1 * D2);
     // one reciprocal for 1/s0 .. 1/s3 and 1/den
     const double a = s0 * s1, b = s2 * s3, ab = a * b;
@@ -209,9 +216,9 @@ __device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx
     const double L3 = two_atanh_poly(lz * (ib * s2), FarPoly<VF>::log);
     const double omega = two_atan_half(N2 * (D1 + D2) * iden, FarPoly<VF>::atan);
     Kern k;
-    k.phi = Z * L0 + (lx - X) * L1 + (lz - Z) * L2 + X * L3 - H * omega;
     k.ex = L1 - L3;
     k.ez = L2 - L0;
+    k.phi = fma(-Z, k.ez, fma(-X, k.ex, fma(lz, L2, fma(lx, L1, -H * omega))));
     k.en = omega;
     return k;
 }
@@ -227,12 +234,12 @@ __device__ __forceinline__ Kern rtri_far(double X, double H, double Z, double lx
     const double r1 = sqrt64_pos(xm * xm + Z2 + H2);
     const double r2 = sqrt64_pos(X2 + zm * zm + H2);
     const double s0 = r0 + r1, s1 = r1 + r2, s2 = r2 + r0;
-    const double P1n = lx * lz - X * lz - Z * lx;  // hyp times the distance to edge 1
-    const double N2 = H * (2.0 * lx * lz);  // twice the triple product
+    const double lxlz = lx * lz;
+    const double N2 = H * (2.0 * lxlz);  // twice the triple product
     const double d01 = X * xm + Z2 + H2;
     const double d02 = X2 + Z * zm + H2;
     const double d12 = X * xm + Z * zm + H2;
-    const double D = r0 * r1 * r2 + d01 * r2 + d02 * r1 + d12 * r0;
+    const double D = fma(fma(r0, r1, d01), r2, fma(d02, r1, d12 * r0));
     // one reciprocal for 1/s0, 1/s1, 1/s2 and 1/D
     const double a = s0 * s1, b = a * s2;
     const double inv = rcp64_common(b * D);
@@ -243,9 +250,9 @@ __device__ __forceinline__ Kern rtri_far(double X, double H, double Z, double lx
     const double L2 = two_atanh_poly(lz * (ib * a), FarPoly<VF>::log);
     const double omega = two_atan_half(N2 * iD, FarPoly<VF>::atan);
     Kern k;
-    k.phi = Z * L0 + P1n * L1h + X * L2 - H * omega;
-    k.ex = lz * L1h - L2;
-    k.ez = lx * L1h - L0;
+    k.ex = fma(lz, L1h, -L2);
+    k.ez = fma(lx, L1h, -L0);
+    k.phi = fma(-Z, k.ez, fma(-X, k.ex, fma(lxlz, L1h, -H * omega)));
     k.en = omega;
     return k;
 }
