@@ -195,23 +195,24 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
             }
             Kern k;
             const double r0sq = fma(X, X, fma(Z, Z, H * H));
-            if (r0sq >= vfar2) {
+            if (r0sq >= vfar2) {  // far forms return the potential added to sp
                 if (KIND == 0)
-                    k = rect_far<true>(X, H, Z, e.lx, e.lz, r0sq);
+                    k = rect_far<true>(X, H, Z, e.lx, e.lz, r0sq, sp);
                 else
-                    k = rtri_far<true>(X, H, Z, e.lx, e.lz, e.hyp, r0sq);
+                    k = rtri_far<true>(X, H, Z, e.lx, e.lz, e.hyp, r0sq, sp);
             } else if (r0sq >= far2) {
                 if (KIND == 0)
-                    k = rect_far<false>(X, H, Z, e.lx, e.lz, r0sq);
+                    k = rect_far<false>(X, H, Z, e.lx, e.lz, r0sq, sp);
                 else
-                    k = rtri_far<false>(X, H, Z, e.lx, e.lz, e.hyp, r0sq);
+                    k = rtri_far<false>(X, H, Z, e.lx, e.lz, e.hyp, r0sq, sp);
             } else {
                 if (KIND == 0)
                     k = rect_fp64(X, H, Z, e.lx, e.lz, r0sq);
                 else
                     k = rtri_fp64(X, H, Z, e.lx, e.lz, e.hyp, e.ihyp, r0sq);
+                k.phi += sp;
             }
-            sp += k.phi;
+            sp = k.phi;
             sx += k.ex;
             sz += k.ez;
             sn += k.en;

@@ -185,8 +185,10 @@ struct FarPoly<true> {
     static constexpr const double (&atan)[kAtanVFN] = kAtanVF;
 };
 
+// Far forms: the potential is returned added to `acc` (the caller's running
+// sum), which saves the caller one addition per copy.
 template <bool VF>
-__device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx, double lz, double r0sq)
+__device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx, double lz, double r0sq, double acc)
 {
     const double H2 = H * H;
     const double xm = X - lx, zm = Z - lz;
@@ -218,14 +220,14 @@ __device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx
     Kern k;
     k.ex = L1 - L3;
     k.ez = L2 - L0;
-    k.phi = fma(-Z, k.ez, fma(-X, k.ex, fma(lz, L2, fma(lx, L1, -H * omega))));
+    k.phi = fma(-Z, k.ez, fma(-X, k.ex, fma(lz, L2, fma(lx, L1, fma(-H, omega, acc)))));
     k.en = omega;
     return k;
 }
 
 template <bool VF>
 __device__ __forceinline__ Kern rtri_far(double X, double H, double Z, double lx, double lz, double hyp,
-                                         double r0sq)
+                                         double r0sq, double acc)
 {
     const double H2 = H * H;
     const double xm = X - lx, zm = Z - lz;
@@ -252,7 +254,7 @@ __device__ __forceinline__ Kern rtri_far(double X, double H, double Z, double lx
     Kern k;
     k.ex = fma(lz, L1h, -L2);
     k.ez = fma(lx, L1h, -L0);
-    k.phi = fma(-Z, k.ez, fma(-X, k.ex, fma(lxlz, L1h, -H * omega)));
+    k.phi = fma(-Z, k.ez, fma(-X, k.ex, fma(lxlz, L1h, fma(-H, omega, acc))));
     k.en = omega;
     return k;
 }
