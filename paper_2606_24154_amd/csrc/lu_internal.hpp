@@ -11,11 +11,22 @@ constexpr int kOuterNB = 256;  // LU outer block width (multiple of kNB)
 // (ceil(n/256) entries), a completion counter (must start at 0; every panel
 // launch leaves it at 0) and `info` (must start at n; receives the first
 // column with a zero pivot).
+// The single-launch panel factorisation (taken when cval is not null and
+// the panel's workgroups fit on the device at once) also needs, with
+// G = ceil(n/256): cval 2 G entries of the matrix type, cidx 2 G ints, crow
+// 2 G kNB entries, trow 2 kNB entries, a barrier counter `bar` and a flag
+// `timeout`, both starting at 0; `timeout` is set if a barrier wait gave up.
 struct LUWork {
     void *pval;
     int *pidx;
     int *counter;
     int *info;
+    void *cval = nullptr;
+    int *cidx = nullptr;
+    void *crow = nullptr;
+    void *trow = nullptr;
+    unsigned *bar = nullptr;
+    int *timeout = nullptr;
 };
 
 void lu_factor(double *A, int n, int *ipiv, LUWork &w, hipStream_t s);

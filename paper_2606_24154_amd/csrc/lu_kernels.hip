@@ -11,8 +11,11 @@
 // once per outer block instead of once per panel:
 //   for each outer block [K0, K1):
 //     for each panel [k, k+kb) of it:
-//       1. panel factorisation, one launch per column: every workgroup owns
-//          256 consecutive rows; a launch eliminates column c on its rows
+//       1. panel factorisation: every workgroup owns 256 consecutive rows.
+//          Normally one cooperative launch for the whole panel, the rows kept
+//          in LDS and the columns separated by grid barriers (k_panel_fused);
+//          if the device cannot hold all of the panel's workgroups at once,
+//          one launch per column: a launch eliminates column c on its rows
 //          (scale by the pivot, rank-1 update of the rest of the panel) and
 //          then finds the largest |a| of column c+1 among its rows; the last
 //          workgroup to finish (atomic counter, no spinning) reduces the
@@ -28,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <climits>
 #include <cmath>
 
 #include "lu_internal.hpp"
@@ -35,6 +39,18 @@
 namespace nebem {
 
 constexpr int kPB = 256;  // rows per panel workgroup
+
+// Lane i's value broadcast to the wave (i uniform): v_readlane, no LDS.
+__device__ __forceinline__ double lane_bcast(double v, int i)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), i);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), i);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_bcast(float v, int i)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
+}
 
 // ------------------------------------------------------------- panel step
 // c: column eliminated by this launch (c == k - 1: none, pivot search only).
@@ -58,14 +74,28 @@ __global__ __launch_bounds__(kPB) void k_panel(T *__restrict__ A, int n, int k, 
         __syncthreads();
         const T piv = urow[0];
         if (r > c && r < n) {
+            // the row's entries in columns c .. kend-1 are loaded 32 at a time
+            // and all in flight together
             T l = A[(size_t)c * n + r];
-            l = (piv != T(0)) ? l / piv : l;
-            A[(size_t)c * n + r] = l;
-            for (int cc = c + 1; cc < kend; ++cc) {
-                T v = A[(size_t)cc * n + r];
-                v = v - l * urow[cc - c];
-                A[(size_t)cc * n + r] = v;
-                if (cc == cn) vnext = v;
+            for (int c0 = c + 1; c0 < kend; c0 += 32) {
+                T v[32];
+#pragma unroll
+                for (int t = 0; t < 32; ++t) v[t] = (c0 + t < kend) ? A[(size_t)(c0 + t) * n + r] : T(0);
+                if (c0 == c + 1) {
+                    l = (piv != T(0)) ? l / piv : l;
+                    A[(size_t)c * n + r] = l;
+                }
+#pragma unroll
+                for (int t = 0; t < 32; ++t)
+                    if (c0 + t < kend) {
+                        const T w = v[t] - l * urow[c0 + t - c];
+                        A[(size_t)(c0 + t) * n + r] = w;
+                        if (c0 + t == cn) vnext = w;
+                    }
+            }
+            if (c + 1 >= kend) {
+                l = (piv != T(0)) ? l / piv : l;
+                A[(size_t)c * n + r] = l;
             }
         }
     } else if (r < n && cn < kend) {
@@ -139,6 +169,153 @@ __global__ __launch_bounds__(kPB) void k_panel(T *__restrict__ A, int n, int k, 
     }
 }
 
+// --------------------------------------------- single-launch panel
+// The whole panel [k, k+kb) x rows [k, n) factored by one cooperative launch
+// (all G workgroups resident at once): workgroup b keeps its 256 rows of the
+// panel in LDS for all kb columns, and the columns are separated by grid
+// barriers instead of launches.  Per column c:
+//   1. each workgroup finds its candidate (largest |a_rc|, r >= c, first
+//      index among equal maxima) and publishes it with the candidate's row;
+//      the owner of row c publishes row c;
+//   2. grid barrier;
+//   3. every workgroup reduces the G candidates in the same total order, so
+//      all agree on the pivot row p, takes p's entries as the U row, swaps
+//      rows c and p if it owns either, and eliminates column c on its rows.
+// Published values are double-buffered by column parity: a slot is written
+// again two columns later, after a barrier that every reader of it has
+// passed.  Each barrier wait is bounded (kSpinLimit polls, well under a
+// second); a wait that gives up sets *timeout, and every later wait of the
+// factorisation that sees the flag returns at once, so the launches run to
+// their end and the host reports an error instead of the device hanging.
+constexpr unsigned kSpinLimit = 1u << 17;
+
+template <typename T>
+__device__ __forceinline__ void argmax_take(T &v, int &i, T v2, int i2)
+{
+    if (v2 > v || (v2 == v && i2 < i)) {
+        v = v2;
+        i = i2;
+    }
+}
+
+// (largest value, smallest index among equal) over the workgroup; every
+// thread receives the result.  sv, si: kPB/64 entries of LDS.
+template <typename T>
+__device__ __forceinline__ void block_argmax(T &v, int &i, T *sv, int *si)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const T v2 = __shfl_xor(v, off);
+        const int i2 = __shfl_xor(i, off);
+        argmax_take(v, i, v2, i2);
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        sv[threadIdx.x >> 6] = v;
+        si[threadIdx.x >> 6] = i;
+    }
+    __syncthreads();
+    v = sv[0];
+    i = si[0];
+#pragma unroll
+    for (int q = 1; q < kPB / 64; ++q) argmax_take(v, i, sv[q], si[q]);
+}
+
+// The workgroup barrier completes every wave's stores to L2 (write-through
+// L1); thread 0's agent-scope fences then write L2 back for the other dies
+// before it arrives, and invalidate the CU's caches after the wait.
+__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned target, int *timeout)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(bar, 1u);
+        unsigned polls = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(timeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            __builtin_amdgcn_s_sleep(2);
+            if (++polls == kSpinLimit) {
+                atomicExch(timeout, 1);
+                break;
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kPB) void k_panel_fused(T *__restrict__ A, int n, int k, int kb, int *__restrict__ ipiv,
+                                                     int *__restrict__ info, T *__restrict__ cval,
+                                                     int *__restrict__ cidx, T *__restrict__ crow,
+                                                     T *__restrict__ trow, unsigned *__restrict__ bar,
+                                                     int *__restrict__ timeout, unsigned base)
+{
+    __shared__ T S[kNB * kPB];  // this workgroup's rows of the panel, S[col * kPB + row]
+    __shared__ T urow[kNB];
+    __shared__ T sv[kPB / 64];
+    __shared__ int si[kPB / 64];
+    const int t = threadIdx.x, b = blockIdx.x, G = gridDim.x;
+    const int r = k + b * kPB + t;
+    const bool live = r < n;
+    for (int j0 = 0; j0 < kb; j0 += 16) {  // 16 loads in flight per thread
+        T v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = (live && j0 + u < kb) ? A[(size_t)(k + j0 + u) * n + r] : T(0);
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (j0 + u < kb) S[(j0 + u) * kPB + t] = v[u];
+    }
+    for (int j = 0; j < kb; ++j) {
+        const int c = k + j, sl = j & 1;
+        // 1. this workgroup's candidate (a NaN entry never wins)
+        const T x = fabs(S[j * kPB + t]);
+        const bool valid = live && r >= c;
+        T v = (valid && x == x) ? x : T(-1);
+        int i = valid ? r : INT_MAX;
+        block_argmax(v, i, sv, si);
+        if (t == 0) {
+            cval[sl * G + b] = v;
+            cidx[sl * G + b] = i;
+        }
+        // the candidate's row and row c, one entry per thread
+        const int il = i - k - b * kPB;  // candidate's slot in S (i valid: 0 <= il < kPB)
+        if (i != INT_MAX && t < kb) crow[((size_t)sl * G + b) * kNB + t] = S[t * kPB + il];
+        const int cl = c - k - b * kPB;
+        if (cl >= 0 && cl < kPB && t < kb) trow[sl * kNB + t] = S[t * kPB + cl];
+        // 2. every candidate published
+        grid_barrier(bar, base + (unsigned)(j + 1) * (unsigned)G, timeout);
+        // 3. pivot, row swap, elimination
+        T pv = T(-1);
+        int p = INT_MAX;
+        for (int g = t; g < G; g += kPB) argmax_take(pv, p, cval[sl * G + g], cidx[sl * G + g]);
+        block_argmax(pv, p, sv, si);
+        if (p < c || p >= n) p = c;
+        const int bw = (p - k) / kPB;
+        if (t < kb) urow[t] = (p == c) ? trow[sl * kNB + t] : crow[((size_t)sl * G + bw) * kNB + t];
+        __syncthreads();
+        if (p != c) {
+            if (r == c)
+                for (int jj = 0; jj < kb; ++jj) S[jj * kPB + t] = urow[jj];
+            else if (r == p)
+                for (int jj = 0; jj < kb; ++jj) S[jj * kPB + t] = trow[sl * kNB + jj];
+        }
+        if (b == 0 && t == 0) {
+            ipiv[c] = p;
+            if (!(pv > T(0))) atomicMin(info, c);
+        }
+        const T piv = urow[j];
+        if (live && r > c) {
+            T l = S[j * kPB + t];
+            l = (piv != T(0)) ? l / piv : l;
+            S[j * kPB + t] = l;
+            for (int jj = j + 1; jj < kb; ++jj) S[jj * kPB + t] -= l * urow[jj];
+        }
+    }
+    if (live)
+        for (int jj = 0; jj < kb; ++jj) A[(size_t)(k + jj) * n + r] = S[jj * kPB + t];
+}
+
 // Row swaps of panel [k, k+kb) applied to every column outside the panel.
 template <typename T>
 __global__ __launch_bounds__(256) void k_laswp(T *__restrict__ A, int n, int k, int kb,
@@ -159,34 +336,50 @@ __global__ __launch_bounds__(256) void k_laswp(T *__restrict__ A, int n, int k, 
 }
 
 // U = L11^-1 A[k:k+kb, j] for the columns j in [jb, je), 64 per workgroup
-// (unit lower L11 = A[k:k+kb, k:k+kb], kb <= 64).
+// (unit lower L11 = A[k:k+kb, k:k+kb], kb <= 64).  Wave w solves columns
+// 16w .. 16w+15 with lane r holding row r of each: the entry solved at step
+// i reaches the other lanes by readlane, so the waves run without barriers;
+// every subtraction comes in the order of plain forward substitution.
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsm(T *__restrict__ A, int n, int k, int kb, int jb, int je)
 {
     __shared__ T L[kNB][kNB + 1];
-    __shared__ T X[kNB][kNB + 1];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int j0 = jb + blockIdx.x * 64;
     const int ncol = min(64, je - j0);
-    for (int e = tid; e < kb * kb; e += 256) {
-        const int rr = e % kb, cc = e / kb;
-        L[rr][cc] = A[(size_t)(k + cc) * n + k + rr];
-    }
-    for (int e = tid; e < kb * ncol; e += 256) {
-        const int rr = e % kb, cc = e / kb;
-        X[rr][cc] = A[(size_t)(j0 + cc) * n + k + rr];
+    T x[16];
+    {
+        // 16 + 16 loads per thread, all issued before the first is used
+        T lv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u, rr = e & 63, cc = e >> 6;
+            lv[u] = (rr < kb && cc < kb) ? A[(size_t)(k + cc) * n + k + rr] : T(0);
+            const int xc = 16 * w + u;
+            x[u] = (lane < kb && xc < ncol) ? A[(size_t)(j0 + xc) * n + k + lane] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u;
+            L[e & 63][e >> 6] = lv[u];
+        }
     }
     __syncthreads();
+    const bool row_in = lane < kb;
     for (int i = 0; i < kb - 1; ++i) {
-        for (int e = tid; e < (kb - 1 - i) * ncol; e += 256) {
-            const int rr = i + 1 + e % (kb - 1 - i), cc = e / (kb - 1 - i);
-            X[rr][cc] -= L[rr][i] * X[i][cc];
+        const T l = L[lane][i];
+        const bool upd = row_in && lane > i;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const T xi = lane_bcast(x[q], i);
+            const T u = x[q] - l * xi;
+            x[q] = upd ? u : x[q];
         }
-        __syncthreads();
     }
-    for (int e = tid; e < kb * ncol; e += 256) {
-        const int rr = e % kb, cc = e / kb;
-        A[(size_t)(j0 + cc) * n + k + rr] = X[rr][cc];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int xc = 16 * w + q;
+        if (row_in && xc < ncol) A[(size_t)(j0 + xc) * n + k + lane] = x[q];
     }
 }
 
@@ -340,6 +533,10 @@ static void trsm(T *A, int n, int k, int kb, int jb, int je, hipStream_t s)
 // Y, and every workgroup subtracts the block's contribution from its own 256
 // rows of X on the unsolved side.  Solved rows are never written to X, so no
 // workgroup can read a half-updated diagonal block.
+// The diagonal block is solved by one wave per right-hand side: lane r holds
+// row r, and the entry solved at step i reaches the other lanes by readlane,
+// so the 64 sequential steps need no workgroup barrier.  The order of every
+// subtraction is that of plain column-oriented substitution.
 template <typename T, typename TX>
 __global__ __launch_bounds__(256) void k_trsv_step(const T *__restrict__ LU, int n, TX *__restrict__ X,
                                                    TX *__restrict__ Y, int nrhs, int b0, int bsz, int lower)
@@ -347,54 +544,106 @@ __global__ __launch_bounds__(256) void k_trsv_step(const T *__restrict__ LU, int
     __shared__ TX D[64][65];
     __shared__ TX y[64][8];
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
     for (int rc = 0; rc < nrhs; rc += 8) {
         const int nr = min(8, nrhs - rc);
         __syncthreads();
-        for (int e = tid; e < bsz * bsz; e += 256) {
-            const int rr = e % bsz, cc = e / bsz;
-            D[rr][cc] = (TX)LU[(size_t)(b0 + cc) * n + b0 + rr];
-        }
-        for (int e = tid; e < bsz * nr; e += 256) {
-            const int rr = e % bsz, q = e / bsz;
-            y[rr][q] = X[(size_t)(rc + q) * n + b0 + rr];
+        {
+            // all 16 + 2 loads of a thread issued before the first is used
+            TX dv[16], yv[2];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = tid + 256 * u, rr = e & 63, cc = e >> 6;
+                dv[u] = (rr < bsz && cc < bsz) ? (TX)LU[(size_t)(b0 + cc) * n + b0 + rr] : TX(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int e = tid + 256 * u, rr = e & 63, q = e >> 6;
+                yv[u] = (rr < bsz && q < nr) ? X[(size_t)(rc + q) * n + b0 + rr] : TX(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = tid + 256 * u;
+                D[e & 63][e >> 6] = dv[u];
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int e = tid + 256 * u;
+                y[e & 63][e >> 6] = yv[u];
+            }
         }
         __syncthreads();
-        // diagonal block: column-oriented substitution, the updates of the
-        // remaining rows of step i spread over the threads (row x rhs pairs)
-        if (lower) {
-            for (int i = 0; i < bsz - 1; ++i) {
-                for (int e = tid; e < (bsz - 1 - i) * nr; e += 256) {
-                    const int r = i + 1 + e % (bsz - 1 - i), q = e / (bsz - 1 - i);
-                    y[r][q] -= D[r][i] * y[i][q];
+        for (int q = wv; q < nr; q += 4) {
+            const bool in = lane < bsz;
+            TX v = in ? y[lane][q] : TX(0);
+            // the LDS loads do not depend on the substitution: eight of them
+            // are issued ahead of each eight steps
+            if (lower) {
+                for (int i0 = 0; i0 < bsz - 1; i0 += 8) {
+                    TX d[8];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) d[t] = D[lane][i0 + t];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const int i = i0 + t;
+                        if (i < bsz - 1) {
+                            const TX yi = lane_bcast(v, i);
+                            const TX u = v - d[t] * yi;
+                            v = (in && lane > i) ? u : v;
+                        }
+                    }
                 }
-                __syncthreads();
-            }
-        } else {
-            for (int i = bsz - 1; i >= 0; --i) {
-                if (tid < nr) y[i][tid] /= D[i][i];
-                __syncthreads();
-                for (int e = tid; e < i * nr; e += 256) {
-                    const int r = e % i, q = e / i;
-                    y[r][q] -= D[r][i] * y[i][q];
+            } else {
+                for (int i0 = ((bsz - 1) & ~7); i0 >= 0; i0 -= 8) {
+                    TX d[8], dd[8];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        d[t] = D[lane][i0 + t];
+                        dd[t] = D[(i0 + t) & 63][(i0 + t) & 63];
+                    }
+#pragma unroll
+                    for (int t = 7; t >= 0; --t) {
+                        const int i = i0 + t;
+                        if (i < bsz) {
+                            const TX yi = lane_bcast(v, i) / dd[t];
+                            const TX u = v - d[t] * yi;
+                            v = (lane == i) ? yi : ((in && lane < i) ? u : v);
+                        }
+                    }
                 }
-                __syncthreads();
             }
+            if (in) y[lane][q] = v;
         }
+        __syncthreads();
         if (blockIdx.x == 0)
             for (int e = tid; e < bsz * nr; e += 256) {
                 const int rr = e % bsz, q = e / bsz;
                 Y[(size_t)(rc + q) * n + b0 + rr] = y[rr][q];
             }
-        // update rows outside the block on the unsolved side
+        // update rows outside the block on the unsolved side; each factor
+        // entry is loaded once for all right-hand sides of the chunk
         const int lo = lower ? b0 + bsz : 0;
         const int hi = lower ? n : b0;
         const int r = lo + blockIdx.x * 256 + tid;
         if (r < hi) {
-            for (int q = 0; q < nr; ++q) {
-                TX s = X[(size_t)(rc + q) * n + r];
-                for (int j = 0; j < bsz; ++j) s -= (TX)LU[(size_t)(b0 + j) * n + r] * y[j][q];
-                X[(size_t)(rc + q) * n + r] = s;
+            TX acc[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] = q < nr ? X[(size_t)(rc + q) * n + r] : TX(0);
+            for (int j0 = 0; j0 < bsz; j0 += 16) {
+                TX l[16];  // 16 factor entries in flight at once
+#pragma unroll
+                for (int t = 0; t < 16; ++t) l[t] = (j0 + t < bsz) ? (TX)LU[(size_t)(b0 + j0 + t) * n + r] : TX(0);
+#pragma unroll
+                for (int t = 0; t < 16; ++t)
+                    if (j0 + t < bsz) {
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            if (q < nr) acc[q] -= l[t] * y[j0 + t][q];
+                    }
             }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q < nr) X[(size_t)(rc + q) * n + r] = acc[q];
         }
     }
 }
@@ -410,17 +659,49 @@ __global__ __launch_bounds__(256) void k_permute(const TB *__restrict__ B, TX *_
 }
 
 // --------------------------------------------------------------- launchers
+// Workgroups of k_panel_fused<T> the device holds at once (0 if unknown).
+template <typename T>
+static int fused_capacity()
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_panel_fused<T>, kPB, 0) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
 template <typename T>
 void lu_factor_launch(T *A, int n, int *ipiv, LUWork &w, hipStream_t s)
 {
+    const int cap = w.cval ? fused_capacity<T>() : 0;
+    unsigned base = 0;  // barrier arrivals so far (bar starts at 0)
+    bool fused_ok = cap > 0;
     for (int K0 = 0; K0 < n; K0 += kOuterNB) {
         const int K1 = (n - K0 < kOuterNB) ? n : K0 + kOuterNB;
         for (int k = K0; k < K1; k += kNB) {
             const int kb = (K1 - k < kNB) ? K1 - k : kNB;
             const unsigned gp = (unsigned)((n - k + kPB - 1) / kPB);
-            for (int c = k - 1; c < k + kb; ++c)
-                hipLaunchKernelGGL(k_panel<T>, dim3(gp), dim3(kPB), 0, s, A, n, k, kb, c, ipiv, (T *)w.pval, w.pidx,
-                                   w.counter, w.info);
+            bool done = false;
+            if (fused_ok && (int)gp <= cap) {
+                T *cval = (T *)w.cval, *crow = (T *)w.crow, *trow = (T *)w.trow;
+                int a_n = n, a_k = k, a_kb = kb;
+                void *args[] = {&A,      &a_n,  &a_k,  &a_kb,  &ipiv,      &w.info, &cval,
+                                &w.cidx, &crow, &trow, &w.bar, &w.timeout, &base};
+                if (hipLaunchCooperativeKernel((const void *)k_panel_fused<T>, dim3(gp), dim3(kPB), args, 0, s) ==
+                    hipSuccess) {
+                    base += (unsigned)kb * gp;
+                    done = true;
+                } else {
+                    (void)hipGetLastError();
+                    fused_ok = false;  // per-column launches from here on
+                }
+            }
+            if (!done)
+                for (int c = k - 1; c < k + kb; ++c)
+                    hipLaunchKernelGGL(k_panel<T>, dim3(gp), dim3(kPB), 0, s, A, n, k, kb, c, ipiv, (T *)w.pval,
+                                       w.pidx, w.counter, w.info);
             if (n - kb > 0) {
                 const unsigned gl = (unsigned)((n - kb + 255) / 256);
                 hipLaunchKernelGGL(k_laswp<T>, dim3(gl), dim3(256), 0, s, A, n, k, kb, ipiv);

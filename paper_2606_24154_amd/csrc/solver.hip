@@ -25,7 +25,7 @@ template <typename T>
 static nebem_status lu_factor_checked(T *A, int n, int *ipiv, std::vector<int> &perm, hipStream_t st)
 {
     const int nblk = (n + 255) / 256;
-    DevBuf pval, ws;
+    DevBuf pval, ws, sync;
     NEBEM_HIP(pval.alloc((size_t)nblk * sizeof(T), st));
     NEBEM_HIP(ws.alloc((size_t)(nblk + 2) * sizeof(int), st));
     LUWork w;
@@ -33,15 +33,33 @@ static nebem_status lu_factor_checked(T *A, int n, int *ipiv, std::vector<int> &
     w.pidx = ws.as<int>();
     w.counter = ws.as<int>() + nblk;
     w.info = ws.as<int>() + nblk + 1;
+    // single-launch panel scratch: bar, timeout | cidx (2 G) | cval (2 G) |
+    // trow (2 kNB) | crow (2 G kNB), each part 256-byte aligned
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_cidx = 256, o_cval = o_cidx + up(2 * (size_t)nblk * sizeof(int));
+    const size_t o_trow = o_cval + up(2 * (size_t)nblk * sizeof(T)), o_crow = o_trow + up(2 * (size_t)kNB * sizeof(T));
+    const size_t sync_bytes = o_crow + 2 * (size_t)nblk * kNB * sizeof(T);
+    NEBEM_HIP(sync.alloc(sync_bytes, st));
+    char *sb = (char *)sync.p;
+    w.bar = (unsigned *)sb;
+    w.timeout = (int *)(sb + sizeof(unsigned));
+    w.cidx = (int *)(sb + o_cidx);
+    w.cval = sb + o_cval;
+    w.trow = sb + o_trow;
+    w.crow = sb + o_crow;
     int hinfo = n;
     NEBEM_HIP(hipMemsetAsync(w.counter, 0, sizeof(int), st));
+    NEBEM_HIP(hipMemsetAsync(sb, 0, 256, st));
     NEBEM_HIP(hipMemcpyAsync(w.info, &hinfo, sizeof(int), hipMemcpyHostToDevice, st));
     lu_factor(A, n, ipiv, w, st);
     NEBEM_HIP(hipGetLastError());
     std::vector<int> hpiv(n);
+    int htimeout = 0;
     NEBEM_HIP(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, st));
+    NEBEM_HIP(hipMemcpyAsync(&htimeout, w.timeout, sizeof(int), hipMemcpyDeviceToHost, st));
     NEBEM_HIP(hipMemcpyAsync(hpiv.data(), ipiv, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, st));
     NEBEM_HIP(hipStreamSynchronize(st));
+    if (htimeout) return fail(NEBEM_EDEVICE, "solve: a panel barrier wait timed out");
     if (hinfo < n) {
         char buf[96];
         std::snprintf(buf, sizeof buf, "solve: zero pivot in column %d", hinfo);
