@@ -91,7 +91,7 @@ typedef struct nebem_images {
 } nebem_images;
 
 typedef enum nebem_precision {
-    NEBEM_FP64 = 0,  /* exact closed forms in FP64 everywhere; FP64 LU */
+    NEBEM_FP64 = 0,  /* exact closed forms in FP64 everywhere; FP64 LU + FP64 refinement */
     NEBEM_MIXED = 1  /* FP64 near field, FP64 monopole + FP32 correction far away; FP32 LU + FP64 refinement */
 } nebem_precision;
 
@@ -108,8 +108,8 @@ typedef struct nebem_options {
 } nebem_options;
 
 typedef struct nebem_solve_info {
-    int32_t ir_iters;     /* refinement steps taken (0 in FP64 mode) */
-    double rel_resid;     /* ||b - A x||_2 / ||b||_2 of the returned x, FP64 (mixed mode; -1 if not computed) */
+    int32_t ir_iters;     /* refinement steps taken (worst column) */
+    double rel_resid;     /* ||b - A x||_2 / ||b||_2 of the returned x, FP64 (worst column; -1 if not computed) */
 } nebem_solve_info;
 
 /* Fills `opt` with the defaults listed above. */
@@ -135,7 +135,14 @@ nebem_status nebem_assemble(const nebem_panels *panels, const nebem_images *imag
  * factorisation with row pivoting, without forming the inverse).
  *  FP64 mode: A (n x n, column-major) is overwritten by its LU factors
  *    (unit lower L below the diagonal, U on and above), ipiv[k] (int32, n
- *    entries, 0-based) is the row swapped with row k at step k.
+ *    entries, 0-based) is the row swapped with row k at step k.  The LU
+ *    solution is then refined in FP64 (r = b - A x against a temporary copy
+ *    of the unfactored A, x += LU^-1 r) while each step at least halves
+ *    ||r||, at most 3 steps (fixed-precision refinement: on the double
+ *    THGEM, N = 41 600, the relative residual goes from 5.1e-12 to 4.2e-13
+ *    in one step and sigma moves by 1.4e-9 relative).  If the n x n copy
+ *    cannot be allocated, the LU solution is returned unrefined
+ *    (info->ir_iters 0, rel_resid -1).
  *  MIXED mode: A is left unchanged; the library factors an FP32 copy and
  *    refines in FP64 until ||b - A x||_2 <= ir_tol ||b||_2 per column.
  *    ipiv holds the FP32 factorisation's pivots.
@@ -162,7 +169,9 @@ nebem_status nebem_eval(const nebem_panels *panels, const nebem_images *images, 
 
 /* ---------------------------------------------------------------- sessions
  * A session keeps one geometry resident: derived panel data, its influence
- * matrix factors, the boundary values and the current sigma (Sec. 4.1: the
+ * matrix and factors (FP64: the matrix and its FP64 LU, 16 n^2 bytes, every
+ * solve refined as in nebem_solve; MIXED: the matrix and the FP32 LU,
+ * 12 n^2 bytes), the boundary values and the current sigma (Sec. 4.1: the
  * factorised matrix stays in device memory for new right-hand sides). */
 typedef struct nebem_session nebem_session;
 

@@ -227,9 +227,40 @@ nebem_status nebem_solve(double *A, int64_t n, const double *b, int64_t nrhs, do
     DevBuf dperm;
     NEBEM_HIP(dperm.alloc((size_t)nn * sizeof(int), stream));
     if (o.precision == NEBEM_FP64) {
+        // The LU solution is refined in FP64 against a copy of the unfactored
+        // matrix (the factorisation overwrites A); without room for the copy
+        // the LU solution is returned as it is.
+        DevBuf acopy, bcopy64;
+        bool refine = acopy.alloc((size_t)nn * nn * sizeof(double), stream) == hipSuccess;
+        if (!refine) {
+            (void)hipGetLastError();
+            acopy.p = nullptr;
+        }
+        const double *bb = b;
+        if (refine) {
+            NEBEM_HIP(hipMemcpyAsync(acopy.p, A, (size_t)nn * nn * sizeof(double), hipMemcpyDeviceToDevice, stream));
+            if (sigma == b) {  // refinement reads b after x is written
+                NEBEM_HIP(bcopy64.alloc((size_t)nn * nrhs * sizeof(double), stream));
+                NEBEM_HIP(hipMemcpyAsync(bcopy64.p, b, (size_t)nn * nrhs * sizeof(double), hipMemcpyDeviceToDevice,
+                                         stream));
+                bb = bcopy64.as<double>();
+            }
+        }
         if ((st = factor_fp64(A, nn, ipiv, perm, stream))) return st;
         NEBEM_HIP(hipMemcpyAsync(dperm.p, perm.data(), (size_t)nn * sizeof(int), hipMemcpyHostToDevice, stream));
         if ((st = solve_fp64(A, nn, dperm.as<int>(), b, (int)nrhs, sigma, stream))) return st;
+        if (refine) {
+            nebem_solve_info agg = {0, 0.0};
+            for (int64_t q = 0; q < nrhs; ++q) {
+                nebem_solve_info ci;
+                if ((st = refine_fp64(acopy.as<double>(), A, dperm.as<int>(), nn, bb + q * n, sigma + q * n,
+                                      kFp64RefineSteps, &ci, stream)))
+                    return st;
+                agg.ir_iters = ci.ir_iters > agg.ir_iters ? ci.ir_iters : agg.ir_iters;
+                agg.rel_resid = ci.rel_resid > agg.rel_resid ? ci.rel_resid : agg.rel_resid;
+            }
+            if (info) *info = agg;
+        }
         NEBEM_HIP(hipStreamSynchronize(stream));  // perm (host) must outlive the copy
         return NEBEM_OK;
     }

@@ -46,6 +46,12 @@ nebem_status factor_mixed(const double *A, int n, float *A32, double *s, int *ip
 // X = A^-1 B for nrhs columns with FP64 factors (perm on device)
 nebem_status solve_fp64(const double *LU, int n, const int *perm, const double *B, int nrhs, double *X,
                         hipStream_t st);
+// FP64 refinement of an FP64 LU solution x (one column), against the
+// unfactored A: r = b - A x, x += LU^-1 r while ||r|| at least halves, at most
+// max_steps steps; x ends as the iterate with the smallest residual.
+nebem_status refine_fp64(const double *A, const double *LU, const int *perm, int n, const double *b, double *x,
+                         int max_steps, nebem_solve_info *info, hipStream_t st);
+constexpr int kFp64RefineSteps = 3;
 // refinement: x solves A x = b to ||b - A x|| <= tol ||b||, one column
 nebem_status solve_mixed(const double *A, const float *LU32, const double *s, const int *perm, int n, const double *b,
                          double *x, double tol, int max_iter, nebem_solve_info *info, hipStream_t st);

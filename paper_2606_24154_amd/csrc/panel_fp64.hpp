@@ -190,20 +190,23 @@ struct FarPoly<true> {
 template <bool VF>
 __device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx, double lz, double r0sq, double acc)
 {
-    const double H2 = H * H;
-    const double xm = X - lx, zm = Z - lz;
-    const double X2 = X * X, Z2 = Z * Z, xm2 = xm * xm, zm2 = zm * zm;
+    // vertex-to-point dot products and squared distances from |P - o|^2 and
+    // the edges (c00 = o, c10 = o + lx e1, c11, c01 = o + lz e2); far away
+    // every one of them is ~R^2 and nothing cancels
+    const double d00_10 = fma(-X, lx, r0sq);
+    const double d00_01 = fma(-Z, lz, r0sq);
+    const double d00_11 = fma(-Z, lz, d00_10);
+    const double r10sq = fma(-X, lx, d00_10 + lx * lx);
+    const double r01sq = fma(-Z, lz, d00_01 + lz * lz);
+    const double d10_11 = fma(-Z, lz, r10sq);
+    const double d11_01 = fma(-X, lx, r01sq);
+    const double r11sq = fma(-Z, lz, d10_11 + lz * lz);
     const double r00 = sqrt64_pos(r0sq);
-    const double r10 = sqrt64_pos(xm2 + Z2 + H2);
-    const double r11 = sqrt64_pos(xm2 + zm2 + H2);
-    const double r01 = sqrt64_pos(X2 + zm2 + H2);
+    const double r10 = sqrt64_pos(r10sq);
+    const double r11 = sqrt64_pos(r11sq);
+    const double r01 = sqrt64_pos(r01sq);
     const double s0 = r00 + r10, s1 = r10 + r11, s2 = r11 + r01, s3 = r01 + r00;
     const double N2 = H * (2.0 * lx * lz);  // twice the triple product
-    const double d00_10 = X * xm + Z2 + H2;
-    const double d00_11 = X * xm + Z * zm + H2;
-    const double d10_11 = xm2 + Z * zm + H2;
-    const double d00_01 = X2 + Z * zm + H2;
-    const double d11_01 = X * xm + zm2 + H2;
     const double D1 = fma(fma(r00, r10, d00_10), r11, fma(d00_11, r10, d10_11 * r00));
     const double D2 = fma(fma(r00, r11, d00_11), r01, fma(d00_01, r11, d11_01 * r00));
     const double den = fma(-0.25 * N2, N2, D1 * D2);
@@ -229,18 +232,17 @@ template <bool VF>
 __device__ __forceinline__ Kern rtri_far(double X, double H, double Z, double lx, double lz, double hyp,
                                          double r0sq, double acc)
 {
-    const double H2 = H * H;
-    const double xm = X - lx, zm = Z - lz;
-    const double X2 = X * X, Z2 = Z * Z;
+    // dot products (P - v_a).(P - v_b) and squared distances from |P - o|^2
+    // (v_0 = o, v_1 = o + lx e1, v_2 = o + lz e2, e1 . e2 = 0)
+    const double d01 = fma(-X, lx, r0sq);
+    const double d02 = fma(-Z, lz, r0sq);
+    const double d12 = fma(-Z, lz, d01);
     const double r0 = sqrt64_pos(r0sq);
-    const double r1 = sqrt64_pos(xm * xm + Z2 + H2);
-    const double r2 = sqrt64_pos(X2 + zm * zm + H2);
+    const double r1 = sqrt64_pos(fma(-X, lx, d01 + lx * lx));
+    const double r2 = sqrt64_pos(fma(-Z, lz, d02 + lz * lz));
     const double s0 = r0 + r1, s1 = r1 + r2, s2 = r2 + r0;
     const double lxlz = lx * lz;
     const double N2 = H * (2.0 * lxlz);  // twice the triple product
-    const double d01 = X * xm + Z2 + H2;
-    const double d02 = X2 + Z * zm + H2;
-    const double d12 = X * xm + Z * zm + H2;
     const double D = fma(fma(r0, r1, d01), r2, fma(d02, r1, d12 * r0));
     // one reciprocal for 1/s0, 1/s1, 1/s2 and 1/D
     const double a = s0 * s1, b = a * s2;

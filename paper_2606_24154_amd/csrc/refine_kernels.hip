@@ -107,6 +107,12 @@ __global__ __launch_bounds__(kRB) void k_add_f32(double *__restrict__ x, const f
     if (i < n) x[i] += (double)d[i];
 }
 
+__global__ __launch_bounds__(kRB) void k_add_f64(double *__restrict__ x, const double *__restrict__ d, int n)
+{
+    const int i = blockIdx.x * kRB + threadIdx.x;
+    if (i < n) x[i] += d[i];
+}
+
 __global__ __launch_bounds__(kRB) void k_scale_vec(const double *__restrict__ s, const double *__restrict__ b,
                                                    int n, double *__restrict__ out)
 {
@@ -150,6 +156,11 @@ void sumsq(const double *v, int n, double *sq, hipStream_t st)
 void add_f32(double *x, const float *d, int n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_add_f32, dim3(blocks(n)), dim3(kRB), 0, st, x, d, n);
+}
+
+void add_f64(double *x, const double *d, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_add_f64, dim3(blocks(n)), dim3(kRB), 0, st, x, d, n);
 }
 
 void scale_vec(const double *s, const double *b, int n, double *out, hipStream_t st)

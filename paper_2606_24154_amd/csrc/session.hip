@@ -3,8 +3,8 @@
 //
 // A session holds, in device memory, everything the paper keeps resident
 // between right-hand sides (Sec. 4.1): the derived element records, the
-// influence matrix and its factors (FP64 LU, or for the mixed path the FP64
-// matrix plus the equilibrated FP32 LU), the boundary values and the current
+// influence matrix and its factors (the FP64 matrix plus its FP64 LU, or for
+// the mixed path the equilibrated FP32 LU), the boundary values and the current
 // surface charge densities.  nebem_spacecharge_step is one time step of the
 // dynamic loop of Sec. 4.3 (Algorithm 4) with point charges (Sec. 4.2).
 #include <hip/hip_runtime.h>
@@ -27,10 +27,10 @@ static nebem_status session_solve(nebem_session *s, const double *b, hipStream_t
 {
     const int n = (int)s->n;
     if (s->opt.precision == NEBEM_FP64) {
-        nebem_status e = solve_fp64(s->A.as<double>(), n, s->perm.as<int>(), b, 1, s->sigma.as<double>(), st);
-        s->last_info.ir_iters = 0;
-        s->last_info.rel_resid = -1.0;
-        return e;
+        nebem_status e = solve_fp64(s->LU.as<double>(), n, s->perm.as<int>(), b, 1, s->sigma.as<double>(), st);
+        if (e) return e;
+        return refine_fp64(s->A.as<double>(), s->LU.as<double>(), s->perm.as<int>(), n, b, s->sigma.as<double>(),
+                           kFp64RefineSteps, &s->last_info, st);
     }
     return solve_mixed(s->A.as<double>(), s->A32.as<float>(), s->scale.as<double>(), s->perm.as<int>(), n, b,
                        s->sigma.as<double>(), s->opt.ir_tol, s->opt.ir_max_iter, &s->last_info, st);
@@ -56,8 +56,10 @@ static nebem_status session_build(nebem_session *s, const nebem_panels *panels, 
     NEBEM_HIP(s->perm.ensure((size_t)n * sizeof(int)));
     std::vector<int> perm;
     nebem_status e;
-    if (!mixed) {
-        e = factor_fp64(s->A.as<double>(), nn, s->ipiv.as<int>(), perm, st);
+    if (!mixed) {  // A stays unfactored for the refinement residuals
+        NEBEM_HIP(s->LU.ensure((size_t)n * n * sizeof(double)));
+        NEBEM_HIP(hipMemcpyAsync(s->LU.p, s->A.p, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        e = factor_fp64(s->LU.as<double>(), nn, s->ipiv.as<int>(), perm, st);
     } else {
         NEBEM_HIP(s->A32.ensure((size_t)n * n * sizeof(float)));
         NEBEM_HIP(s->scale.ensure((size_t)n * sizeof(double)));

@@ -40,7 +40,7 @@ struct nebem_session {
     double img_count = 1.0;  // copies per element (reflections x translations)
     nebem_options opt;
     nebem::ImgArgs img;
-    nebem::DevMem drec, A, A32, scale, ipiv, perm, b0, sigma, rhs, part, eb;
+    nebem::DevMem drec, A, LU, A32, scale, ipiv, perm, b0, sigma, rhs, part, eb;
     nebem::DevMem ows;  // workspace of the Morton-ordered evaluation
     nebem_solve_info last_info = {0, -1.0};
 };

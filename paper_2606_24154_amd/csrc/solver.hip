@@ -113,6 +113,60 @@ static nebem_status host_norm(const double *sq_dev, int nblk, std::vector<double
     return NEBEM_OK;
 }
 
+nebem_status refine_fp64(const double *A, const double *LU, const int *perm, int n, const double *b, double *x,
+                         int max_steps, nebem_solve_info *info, hipStream_t st)
+{
+    const int nblk = (n + 255) / 256;
+    const int nchunk = (n + kGemvChunk - 1) / kGemvChunk;
+    DevBuf ones, rs, d, w, part, sq, xbest;
+    NEBEM_HIP(ones.alloc((size_t)n * sizeof(double), st));
+    NEBEM_HIP(rs.alloc((size_t)n * sizeof(double), st));
+    NEBEM_HIP(d.alloc((size_t)n * sizeof(double), st));
+    NEBEM_HIP(w.alloc((size_t)n * sizeof(double), st));
+    NEBEM_HIP(part.alloc((size_t)n * nchunk * sizeof(double), st));
+    NEBEM_HIP(sq.alloc((size_t)nblk * sizeof(double), st));
+    NEBEM_HIP(xbest.alloc((size_t)n * sizeof(double), st));
+    fill(ones.as<double>(), n, 1.0, st);
+    std::vector<double> h;
+    double bnorm = 0.0, rnorm = 0.0;
+    sumsq(b, n, sq.as<double>(), st);
+    nebem_status e = host_norm(sq.as<double>(), nblk, h, st, bnorm);
+    if (e) return e;
+    if (info) {
+        info->ir_iters = 0;
+        info->rel_resid = 0.0;
+    }
+    if (bnorm == 0.0) return NEBEM_OK;
+    residual(A, n, x, b, ones.as<double>(), part.as<double>(), rs.as<double>(), sq.as<double>(), st);
+    NEBEM_HIP(hipGetLastError());
+    if ((e = host_norm(sq.as<double>(), nblk, h, st, rnorm))) return e;
+    double best = rnorm / bnorm;
+    int best_it = 0;
+    NEBEM_HIP(hipMemcpyAsync(xbest.p, x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    for (int it = 1; it <= max_steps; ++it) {
+        lu_solve(LU, n, perm, rs.as<double>(), d.as<double>(), w.as<double>(), 1, st);
+        add_f64(x, d.as<double>(), n, st);
+        residual(A, n, x, b, ones.as<double>(), part.as<double>(), rs.as<double>(), sq.as<double>(), st);
+        NEBEM_HIP(hipGetLastError());
+        if ((e = host_norm(sq.as<double>(), nblk, h, st, rnorm))) return e;
+        const double rel = rnorm / bnorm;
+        const bool halved = rel <= 0.5 * best;
+        if (rel < best) {
+            best = rel;
+            best_it = it;
+            NEBEM_HIP(hipMemcpyAsync(xbest.p, x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        }
+        if (!halved) break;
+    }
+    NEBEM_HIP(hipMemcpyAsync(x, xbest.p, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    NEBEM_HIP(hipStreamSynchronize(st));
+    if (info) {
+        info->ir_iters = best_it;
+        info->rel_resid = best;
+    }
+    return NEBEM_OK;
+}
+
 nebem_status solve_mixed(const double *A, const float *LU32, const double *s, const int *perm, int n, const double *b,
                          double *x, double tol, int max_iter, nebem_solve_info *info, hipStream_t st)
 {

@@ -175,6 +175,32 @@ def test_plates_solve_and_eval(nb, plates_ref):
     assert ephi < 1e-10 and eE < 1e-10, (ephi, eE)
 
 
+def test_fp64_solve_refinement(nb):
+    """FP64 solve = LU + FP64 refinement: the returned x has no larger
+    residual than the LU solution (re-solved from the returned factors), its
+    error against the known solution is no larger, and info reports the true
+    residual of the returned x."""
+    rng = np.random.default_rng(11)
+    n = 700
+    qa, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    qb, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (qa * np.logspace(0, -9, n)) @ qb.T  # cond 1e9
+    x_true = rng.standard_normal(n)
+    b = A @ x_true
+    At = dev(np.ascontiguousarray(A.T))
+    sigma, ipiv, info = nb.solve(At, dev(b))
+    x_lu = nb.solve_factored(At, ipiv, dev(b))
+    torch.cuda.synchronize()
+    x, xl = sigma.cpu().numpy(), x_lu.cpu().numpy()
+    res = lambda v: np.linalg.norm(b - A @ v) / np.linalg.norm(b)
+    # residuals near the FP64 floor: GPU and CPU evaluations of b - A x differ
+    # by their own rounding, so the comparisons allow a factor 2
+    assert 0 <= info.ir_iters <= 3
+    assert res(x) <= 2 * res(xl), (res(x), res(xl))
+    assert 0 < info.rel_resid < 1e-12 and res(x) < 1e-12, (info.rel_resid, res(x))
+    assert np.linalg.norm(x - x_true) <= 1.5 * np.linalg.norm(xl - x_true)
+
+
 def test_plates_end_to_end(nb, plates_ref):
     """assemble -> solve -> eval entirely on the GPU vs the oracle pipeline."""
     g, _, s_ref, pts, f_ref = plates_ref
@@ -299,9 +325,12 @@ def test_lu_random(nb, n):
     assert np.abs(L @ U - PA).max() <= 1e-13 * n * np.abs(A).max()
     # partial pivoting: every multiplier bounded by 1
     assert np.abs(np.tril(LU, -1)).max() <= 1.0
-    # re-solve from the resident factors
+    # re-solve from the resident factors (LU only; nb.solve also refined in
+    # FP64, so the two agree to the solve's accuracy), deterministic
     X2 = nb.solve_factored(At, ipiv, dev(B)).cpu().numpy()
-    assert np.array_equal(X2, X)
+    assert np.abs(X2 - ref).max() <= 100 * kappa * 2.2e-16 * max(1.0, np.abs(ref).max())
+    X3 = nb.solve_factored(At, ipiv, dev(B)).cpu().numpy()
+    assert np.array_equal(X2, X3)
 
 
 def test_lu_singular(nb):
