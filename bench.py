@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 # this workload, from rocprofv3 counters (64 x (ADD + MUL + TRANS + 2 FMA)
 # FP64 instructions of one evaluation launch / its interactions); see the
 # profile summaries committed under profiles/.
-FLOPS_PER_INTERACTION = 140.6
+FLOPS_PER_INTERACTION = 132.6
 # HBM bytes per evaluation launch at the default workload (FETCH_SIZE x 2 +
 # WRITE_SIZE x 1, the factors that make a plain 1 GiB copy read 1 GiB and
 # write 1 GiB); None when not measured for the current kernel.
