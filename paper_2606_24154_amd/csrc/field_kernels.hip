@@ -324,7 +324,7 @@ __device__ __forceinline__ void eval_block(const double *__restrict__ drec, cons
     }
 }
 
-// FP64: the default allocation (194 VGPRs, two waves per SIMD) keeps every
+// FP64: the default allocation (about 200 VGPRs, two waves per SIMD) keeps every
 // value in registers; a three-wave target made the allocator spill part of
 // the per-element setup to scratch (10.6 GB of HBM writes per 10^6-point
 // launch) for no measurable gain.

@@ -32,6 +32,7 @@
 
 #include <cfloat>
 #include <climits>
+#include <cstdlib>
 #include <cmath>
 
 #include "lu_internal.hpp"
@@ -672,10 +673,19 @@ static int fused_capacity()
     return per_cu * cus;
 }
 
+// NEBEM_PANEL_PER_COLUMN=1 in the environment selects the per-column panel
+// launches everywhere (the path taken when a panel's workgroups do not fit
+// on the device at once), so that tests can reach it at any size.
+static bool per_column_forced()
+{
+    const char *e = std::getenv("NEBEM_PANEL_PER_COLUMN");
+    return e && e[0] == '1';
+}
+
 template <typename T>
 void lu_factor_launch(T *A, int n, int *ipiv, LUWork &w, hipStream_t s)
 {
-    const int cap = w.cval ? fused_capacity<T>() : 0;
+    const int cap = (w.cval && !per_column_forced()) ? fused_capacity<T>() : 0;
     unsigned base = 0;  // barrier arrivals so far (bar starts at 0)
     bool fused_ok = cap > 0;
     for (int K0 = 0; K0 < n; K0 += kOuterNB) {

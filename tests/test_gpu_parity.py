@@ -333,6 +333,32 @@ def test_lu_random(nb, n):
     assert np.array_equal(X2, X3)
 
 
+@pytest.mark.parametrize("n", [65, 777])
+def test_lu_per_column_panels(nb, n, monkeypatch):
+    """The per-column panel launches (taken when a panel's workgroups do not
+    fit on the device at once) give the same factors as the single-launch
+    panels: same pivots, and L U = P A."""
+    rng = np.random.default_rng(100 + n)
+    A = rng.standard_normal((n, n)) + np.eye(n) * 0.5
+    b = rng.standard_normal(n)
+    At1 = dev(np.ascontiguousarray(A.T))
+    _, piv1, _ = nb.solve(At1, dev(b))
+    monkeypatch.setenv("NEBEM_PANEL_PER_COLUMN", "1")
+    At2 = dev(np.ascontiguousarray(A.T))
+    _, piv2, _ = nb.solve(At2, dev(b))
+    monkeypatch.delenv("NEBEM_PANEL_PER_COLUMN")
+    torch.cuda.synchronize()
+    assert np.array_equal(piv1.cpu().numpy(), piv2.cpu().numpy())
+    LU1, LU2 = At1.cpu().numpy().T, At2.cpu().numpy().T
+    assert np.abs(LU1 - LU2).max() <= 1e-12 * np.abs(LU1).max()
+    L = np.tril(LU2, -1) + np.eye(n)
+    U = np.triu(LU2)
+    PA = A.copy()
+    for k, p in enumerate(piv2.cpu().numpy()):
+        PA[[k, p]] = PA[[p, k]]
+    assert np.abs(L @ U - PA).max() <= 1e-13 * n * np.abs(A).max()
+
+
 def test_lu_singular(nb):
     n = 70
     rng = np.random.default_rng(3)
