@@ -158,6 +158,20 @@ nebem_status nebem_solve(double *A, int64_t n, const double *b, int64_t nrhs, do
 nebem_status nebem_solve_factored(const double *LU, const int32_t *ipiv, int64_t n, const double *b,
                                   int64_t nrhs, double *sigma, hipStream_t stream);
 
+/* Conditioning of the dense system.  nebem_norm1: ||A||_1 = max_j sum_i |A_ij|
+ * of the column-major n x n matrix A (device), written to *anorm (host).
+ * nebem_condest: 1-norm condition estimate anorm * est(||A^-1||_1) from the
+ * FP64 factors and pivots of nebem_solve (LAPACK gecon's estimator: Hager's
+ * method with Higham's safeguards, at most 5 pairs of solves with A and A^T
+ * plus one; a lower bound on cond_1(A), usually within a factor 3), written
+ * to *kappa1 (host).  anorm is ||A||_1 of the unfactored matrix (take it
+ * with nebem_norm1 before nebem_solve overwrites A).  Both synchronise
+ * `stream`.  EINVAL on bad sizes, NULL pointers, an invalid pivot list or a
+ * negative anorm. */
+nebem_status nebem_norm1(const double *A, int64_t n, double *anorm, hipStream_t stream);
+nebem_status nebem_condest(const double *LU, const int32_t *ipiv, int64_t n, double anorm, double *kappa1,
+                           hipStream_t stream);
+
 /* Potential and field at m points (Eqs. Potential and Field; PFAtPoint,
  * Sec. 4.1) from all panels and their copies:
  *   phi(P) = k_e sum_j sigma_j sum_copies Phi'_j(P),  E likewise with E'.
@@ -191,6 +205,10 @@ const double *nebem_session_sigma(const nebem_session *s);
  * zero elsewhere (Sec. 2.1).  `info` (host, may be NULL) as in nebem_solve.
  * Synchronises `stream`. */
 nebem_status nebem_session_solve(nebem_session *s, const double *b, nebem_solve_info *info, hipStream_t stream);
+/* cond_1 estimate of an FP64 session's matrix (as nebem_condest, from the
+ * session's matrix and factors), written to *kappa1 (host).  EINVAL for a
+ * MIXED session.  Synchronises `stream`. */
+nebem_status nebem_session_condest(nebem_session *s, double *kappa1, hipStream_t stream);
 /* phi/E at points with the session's current sigma (as nebem_eval). */
 nebem_status nebem_session_eval(nebem_session *s, const double *px, const double *py, const double *pz,
                                 int64_t m, double *phi, double *ex, double *ey, double *ez, hipStream_t stream);

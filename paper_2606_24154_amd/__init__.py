@@ -27,9 +27,11 @@ FP64 = 0
 MIXED = 1
 
 EXPORTED = (
-    "nebem_default_options", "nebem_assemble", "nebem_solve", "nebem_solve_factored", "nebem_eval",
+    "nebem_default_options", "nebem_assemble", "nebem_solve", "nebem_solve_factored", "nebem_norm1",
+    "nebem_condest", "nebem_eval",
     "nebem_session_create", "nebem_session_destroy", "nebem_session_n", "nebem_session_sigma",
-    "nebem_session_solve", "nebem_session_eval", "nebem_spacecharge_step", "nebem_last_error",
+    "nebem_session_solve", "nebem_session_condest", "nebem_session_eval", "nebem_spacecharge_step",
+    "nebem_last_error",
     "nebem_server_default_options", "nebem_server_create", "nebem_server_submit", "nebem_server_wait",
     "nebem_server_stats", "nebem_server_destroy",
 )
@@ -96,6 +98,12 @@ def _load():
     lib.nebem_solve.argtypes = [P, i64, P, i64, P, P, PO, ctypes.POINTER(SolveInfo), P]
     lib.nebem_solve_factored.argtypes = [P, P, i64, P, i64, P, P]
     lib.nebem_eval.argtypes = [PP, PI, P, P, P, P, i64, P, P, P, P, PO, P]
+    lib.nebem_norm1.argtypes = [P, i64, ctypes.POINTER(ctypes.c_double), P]
+    lib.nebem_norm1.restype = i32
+    lib.nebem_condest.argtypes = [P, P, i64, ctypes.c_double, ctypes.POINTER(ctypes.c_double), P]
+    lib.nebem_condest.restype = i32
+    lib.nebem_session_condest.argtypes = [P, ctypes.POINTER(ctypes.c_double), P]
+    lib.nebem_session_condest.restype = i32
     for name in ("nebem_assemble", "nebem_solve", "nebem_solve_factored", "nebem_eval"):
         getattr(lib, name).restype = i32
     lib.nebem_session_create.argtypes = [PP, PI, PO, P, ctypes.POINTER(P)]
@@ -238,6 +246,20 @@ def solve_factored(LU, ipiv, b, stream=None, sigma=None):
     return sigma
 
 
+def norm1(A, stream=None):
+    """||A||_1 of the column-major matrix held by A (as from `assemble`)."""
+    out = ctypes.c_double()
+    _check(lib.nebem_norm1(_ptr(A), A.shape[0], ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
+def condest(LU, ipiv, anorm, stream=None):
+    """cond_1 estimate from FP64 factors (`solve`) and ||A||_1 (`norm1`)."""
+    out = ctypes.c_double()
+    _check(lib.nebem_condest(_ptr(LU), _ptr(ipiv), LU.shape[0], float(anorm), ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
 def eval_points(dp: DevicePanels, sigma, px, py, pz, precision=FP64, stream=None, out=None, **opt):
     """(phi, ex, ey, ez) float64 tensors at the points."""
     import torch
@@ -295,6 +317,12 @@ class Session:
         if code not in (NEBEM_OK, NEBEM_ENOCONV):
             _check(code)
         return code, info
+
+    def condest(self, stream=None):
+        """cond_1 estimate of the session's matrix (FP64 sessions)."""
+        out = ctypes.c_double()
+        _check(lib.nebem_session_condest(self.handle, ctypes.byref(out), _stream(stream)))
+        return out.value
 
     def eval_points(self, px, py, pz, stream=None, out=None):
         import torch

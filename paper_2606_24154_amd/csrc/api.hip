@@ -312,4 +312,38 @@ nebem_status nebem_solve_factored(const double *LU, const int32_t *ipiv, int64_t
     return st;
 }
 
+nebem_status nebem_norm1(const double *A, int64_t n, double *anorm, hipStream_t stream)
+{
+    if (n < 0 || n > 65536 * 4) return fail(NEBEM_EINVAL, "norm1: n out of range");
+    if (!anorm || (n > 0 && !A)) return fail(NEBEM_EINVAL, "norm1: NULL argument");
+    if (n == 0) {
+        *anorm = 0.0;
+        return NEBEM_OK;
+    }
+    return norm1_fp64(A, (int)n, anorm, stream);
+}
+
+nebem_status nebem_condest(const double *LU, const int32_t *ipiv, int64_t n, double anorm, double *kappa1,
+                           hipStream_t stream)
+{
+    if (n < 0 || n > 65536 * 4) return fail(NEBEM_EINVAL, "condest: n out of range");
+    if (!kappa1 || (n > 0 && (!LU || !ipiv))) return fail(NEBEM_EINVAL, "condest: NULL argument");
+    if (!(anorm >= 0.0)) return fail(NEBEM_EINVAL, "condest: anorm must be >= 0");
+    if (n == 0) {
+        *kappa1 = 0.0;
+        return NEBEM_OK;
+    }
+    const int nn = (int)n;
+    std::vector<int> hpiv(nn), perm;
+    NEBEM_HIP(hipMemcpyAsync(hpiv.data(), ipiv, (size_t)nn * sizeof(int), hipMemcpyDeviceToHost, stream));
+    NEBEM_HIP(hipStreamSynchronize(stream));
+    for (int k = 0; k < nn; ++k)
+        if (hpiv[k] < k || hpiv[k] >= nn) return fail(NEBEM_EINVAL, "condest: ipiv is not a valid pivot list");
+    pivots_to_perm(hpiv, perm);
+    DevBuf dperm;
+    NEBEM_HIP(dperm.alloc((size_t)nn * sizeof(int), stream));
+    NEBEM_HIP(hipMemcpyAsync(dperm.p, perm.data(), (size_t)nn * sizeof(int), hipMemcpyHostToDevice, stream));
+    return condest_fp64(LU, dperm.as<int>(), nn, anorm, kappa1, stream);
+}
+
 }  // extern "C"

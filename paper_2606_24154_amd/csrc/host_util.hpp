@@ -52,6 +52,10 @@ nebem_status solve_fp64(const double *LU, int n, const int *perm, const double *
 nebem_status refine_fp64(const double *A, const double *LU, const int *perm, int n, const double *b, double *x,
                          int max_steps, nebem_solve_info *info, hipStream_t st);
 constexpr int kFp64RefineSteps = 3;
+// ||A||_1 (host result) and the 1-norm condition estimate anorm x est(||A^-1||_1)
+// from FP64 factors (Hager-Higham); both synchronise the stream.
+nebem_status norm1_fp64(const double *A, int n, double *anorm, hipStream_t st);
+nebem_status condest_fp64(const double *LU, const int *perm, int n, double anorm, double *kappa, hipStream_t st);
 // refinement: x solves A x = b to ||b - A x|| <= tol ||b||, one column
 nebem_status solve_mixed(const double *A, const float *LU32, const double *s, const int *perm, int n, const double *b,
                          double *x, double tol, int max_iter, nebem_solve_info *info, hipStream_t st);

@@ -37,5 +37,9 @@ void lu_solve(const double *LU, int n, const int *perm, const double *B, double 
               hipStream_t s);
 void lu_solve(const float *LU, int n, const int *perm, const double *B, float *X, float *W, int nrhs,
               hipStream_t s);
+// z = A^-T b with the FP64 factors of P A = L U (perm as in lu_solve); W, V:
+// n-entry workspaces.  z must not alias b, W or V.
+void lu_solve_transposed(const double *LU, int n, const int *perm, const double *b, double *z, double *W,
+                         double *V, hipStream_t s);
 
 }  // namespace nebem

@@ -649,6 +649,80 @@ __global__ __launch_bounds__(256) void k_trsv_step(const T *__restrict__ LU, int
     }
 }
 
+// Transposed solves with the same factors, one right-hand side, one launch
+// per 64-row block: lower = 1 solves U^T w = v forward (U^T lower, diagonal
+// of U), lower = 0 solves L^T v = w backward (unit diagonal).  Row r of a
+// transposed factor is column r of LU, so the block's entries of row r are
+// LU[r n + b0 .. b0 + 63], contiguous.  X is reduced in place on the
+// unsolved side and the block's solution goes to Y (as in k_trsv_step).
+__global__ __launch_bounds__(256) void k_trsv_t_step(const double *__restrict__ LU, int n, double *__restrict__ X,
+                                                     double *__restrict__ Y, int b0, int bsz, int lower)
+{
+    __shared__ double D[64][65];  // D[r][c] = (transposed factor)[b0 + r][b0 + c]
+    __shared__ double y[64];
+    const int tid = threadIdx.x;
+    {
+        double dv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u, c = e & 63, r = e >> 6;
+            dv[u] = (r < bsz && c < bsz) ? LU[(size_t)(b0 + r) * n + b0 + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u;
+            D[e >> 6][e & 63] = dv[u];
+        }
+        if (tid < 64) y[tid] = tid < bsz ? X[b0 + tid] : 0.0;
+    }
+    __syncthreads();
+    if (tid < 64) {  // one wave: lane r holds row r
+        const int lane = tid;
+        const bool in = lane < bsz;
+        double v = y[lane];
+        if (lower) {
+            for (int i = 0; i < bsz; ++i) {
+                const double yi = lane_bcast(v, i) / D[i][i];
+                const double u = v - D[lane][i] * yi;
+                v = (lane == i) ? yi : ((in && lane > i) ? u : v);
+            }
+        } else {
+            for (int i = bsz - 1; i >= 0; --i) {
+                const double yi = lane_bcast(v, i);
+                const double u = v - D[lane][i] * yi;
+                v = (in && lane < i) ? u : v;
+            }
+        }
+        if (in) y[lane] = v;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && tid < bsz) Y[b0 + tid] = y[tid];
+    const int lo = lower ? b0 + bsz : 0;
+    const int hi = lower ? n : b0;
+    const int r = lo + blockIdx.x * 256 + tid;
+    if (r < hi) {
+        double acc = X[r];
+        const double *row = LU + (size_t)r * n + b0;
+        for (int j0 = 0; j0 < bsz; j0 += 16) {
+            double l[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) l[t] = (j0 + t < bsz) ? row[j0 + t] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+                if (j0 + t < bsz) acc -= l[t] * y[j0 + t];
+        }
+        X[r] = acc;
+    }
+}
+
+// z[perm[i]] = v[i] (the inverse of the pivoting gather)
+__global__ __launch_bounds__(256) void k_unpermute(const double *__restrict__ v, double *__restrict__ z,
+                                                   const int *__restrict__ perm, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) z[perm[i]] = v[i];
+}
+
 // X[i] = B[perm[i]] (row gather for the pivoting permutation), nrhs columns
 template <typename TB, typename TX>
 __global__ __launch_bounds__(256) void k_permute(const TB *__restrict__ B, TX *__restrict__ X,
@@ -749,6 +823,27 @@ void lu_solve_launch(const T *LU, int n, const int *perm, const double *B, TX *X
         const unsigned gb = rows > 0 ? (unsigned)((rows + 255) / 256) : 1u;
         hipLaunchKernelGGL((k_trsv_step<T, TX>), dim3(gb), dim3(256), 0, s, LU, n, W, X, nrhs, b0, bsz, 0);
     }
+}
+
+void lu_solve_transposed(const double *LU, int n, const int *perm, const double *b, double *z, double *W,
+                         double *V, hipStream_t s)
+{
+    // U^T w = b: X = W (copy of b, reduced in place), solution in V
+    hipMemcpyAsync(W, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s);
+    for (int b0 = 0; b0 < n; b0 += 64) {
+        const int bsz = (n - b0 < 64) ? n - b0 : 64;
+        const int rows = n - b0 - bsz;
+        const unsigned gb = rows > 0 ? (unsigned)((rows + 255) / 256) : 1u;
+        hipLaunchKernelGGL(k_trsv_t_step, dim3(gb), dim3(256), 0, s, LU, n, W, V, b0, bsz, 1);
+    }
+    // L^T v = w: X = V, solution in W
+    const int last = ((n - 1) / 64) * 64;
+    for (int b0 = last; b0 >= 0; b0 -= 64) {
+        const int bsz = (n - b0 < 64) ? n - b0 : 64;
+        const unsigned gb = b0 > 0 ? (unsigned)((b0 + 255) / 256) : 1u;
+        hipLaunchKernelGGL(k_trsv_t_step, dim3(gb), dim3(256), 0, s, LU, n, V, W, b0, bsz, 0);
+    }
+    hipLaunchKernelGGL(k_unpermute, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, z, perm, n);
 }
 
 void lu_factor(double *A, int n, int *ipiv, LUWork &w, hipStream_t s) { lu_factor_launch<double>(A, n, ipiv, w, s); }

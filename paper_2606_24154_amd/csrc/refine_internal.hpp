@@ -18,6 +18,8 @@ void residual(const double *A, int n, const double *x, const double *b, const do
 void sumsq(const double *v, int n, double *sq, hipStream_t st);
 void add_f32(double *x, const float *d, int n, hipStream_t st);
 void add_f64(double *x, const double *d, int n, hipStream_t st);
+// cs[j] = sum_i |A_ij|, n entries
+void column_abs_sums(const double *A, int n, double *cs, hipStream_t st);
 void scale_vec(const double *s, const double *b, int n, double *out, hipStream_t st);
 void fill(double *x, int n, double v, hipStream_t st);
 

@@ -158,6 +158,29 @@ void add_f32(double *x, const float *d, int n, hipStream_t st)
     hipLaunchKernelGGL(k_add_f32, dim3(blocks(n)), dim3(kRB), 0, st, x, d, n);
 }
 
+// cs[j] = sum_i |A_ij| (column j of the column-major matrix), one workgroup
+// per column, fixed-order reduction
+__global__ __launch_bounds__(kRB) void k_colabs(const double *__restrict__ A, int n, double *__restrict__ cs)
+{
+    __shared__ double red[kRB];
+    const int j = blockIdx.x;
+    const double *col = A + (size_t)j * n;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += kRB) acc += fabs(col[i]);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int sft = kRB / 2; sft > 0; sft >>= 1) {
+        if ((int)threadIdx.x < sft) red[threadIdx.x] += red[threadIdx.x + sft];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cs[j] = red[0];
+}
+
+void column_abs_sums(const double *A, int n, double *cs, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_colabs, dim3((unsigned)n), dim3(kRB), 0, st, A, n, cs);
+}
+
 void add_f64(double *x, const double *d, int n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_add_f64, dim3(blocks(n)), dim3(kRB), 0, st, x, d, n);

@@ -153,6 +153,21 @@ nebem_status nebem_session_solve(nebem_session *s, const double *b, nebem_solve_
     return st;
 }
 
+nebem_status nebem_session_condest(nebem_session *s, double *kappa1, hipStream_t stream)
+{
+    if (!s || !kappa1) return fail(NEBEM_EINVAL, "session_condest: NULL argument");
+    if (s->opt.precision != NEBEM_FP64) return fail(NEBEM_EINVAL, "session_condest: needs an FP64 session");
+    const int n = (int)s->n;
+    if (n == 0) {
+        *kappa1 = 0.0;
+        return NEBEM_OK;
+    }
+    double anorm = 0.0;
+    nebem_status st = norm1_fp64(s->A.as<double>(), n, &anorm, stream);
+    if (st) return st;
+    return condest_fp64(s->LU.as<double>(), s->perm.as<int>(), n, anorm, kappa1, stream);
+}
+
 nebem_status nebem_session_eval(nebem_session *s, const double *px, const double *py, const double *pz, int64_t m,
                                 double *phi, double *ex, double *ey, double *ez, hipStream_t stream)
 {

@@ -359,6 +359,48 @@ def test_lu_per_column_panels(nb, n, monkeypatch):
     assert np.abs(L @ U - PA).max() <= 1e-13 * n * np.abs(A).max()
 
 
+def test_condest_exact_case_and_random(nb):
+    """cond_1 estimate: exact where the estimator's transposed step must
+    find the one large column of A^-1 (A = I - M e_i e_j^T, A^-1 =
+    I + M e_i e_j^T, i > j so that pivoting swaps rows), and a lower bound
+    within a factor 10 on random matrices with known cond_1."""
+    n, M, i0, j0 = 300, 1e6, 250, 40
+    A = np.eye(n)
+    A[i0, j0] = -M
+    At = dev(np.ascontiguousarray(A.T))
+    anorm = nb.norm1(At)
+    assert anorm == 1.0 + M
+    _, ipiv, _ = nb.solve(At, dev(np.ones(n)))
+    est = nb.condest(At, ipiv, anorm)
+    assert abs(est - (1 + M) ** 2) <= 1e-9 * (1 + M) ** 2, est
+    rng = np.random.default_rng(21)
+    for n in (70, 333):
+        qa, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        qb, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        A = (qa * np.logspace(0, -6, n)) @ qb.T
+        kappa = np.linalg.cond(A, 1)
+        At = dev(np.ascontiguousarray(A.T))
+        anorm = nb.norm1(At)
+        assert abs(anorm - np.abs(A).sum(axis=0).max()) <= 1e-12 * anorm
+        _, ipiv, _ = nb.solve(At, dev(np.ones(n)))
+        est = nb.condest(At, ipiv, anorm)
+        assert kappa / 10 <= est <= kappa * (1 + 1e-9), (est, kappa)
+
+
+def test_session_condest(nb, plates_ref):
+    g, A_ref, _, _, _ = plates_ref
+    ses = nb.Session(nb.DevicePanels.from_geometry(g, DEV), precision=nb.FP64)
+    est = ses.condest()
+    kappa = np.linalg.cond(A_ref, 1)
+    assert kappa / 10 <= est <= kappa * (1 + 1e-6), (est, kappa)
+    ses.close()
+    mixed = nb.Session(nb.DevicePanels.from_geometry(g, DEV), precision=nb.MIXED)
+    with pytest.raises(nb.NebemError) as e:
+        mixed.condest()
+    assert e.value.code == nb.NEBEM_EINVAL
+    mixed.close()
+
+
 def test_lu_singular(nb):
     n = 70
     rng = np.random.default_rng(3)
