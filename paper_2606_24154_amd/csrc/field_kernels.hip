@@ -171,6 +171,13 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
     const double far2 = (kFarDiam * kFarDiam) * (e.diam * e.diam);
     const double vfar2 = (kVeryFarDiam * kVeryFarDiam) * (e.diam * e.diam);
     FarCorr fc = {0.0f, 0.0f, 0.0f, 0.0f};
+    // MIXED: the copies are translated in centroid-relative coordinates,
+    // which the far tiers use directly; the exact tiers add the centroid
+    // offset back
+    if (MIXED) {
+        X0 -= cxl;
+        Z0 -= czl;
+    }
 #pragma unroll 1
     for (int i1 = -n1; i1 <= n1; ++i1) {
         const double f1 = -(double)i1;
@@ -178,20 +185,21 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
 #pragma unroll 1
         for (int i2 = -n2; i2 <= n2; ++i2) {
             const double f2 = -(double)i2;
-            const double X = fma(f2, bX, X1), Z = fma(f2, bZ, Z1);
+            double X = fma(f2, bX, X1), Z = fma(f2, bZ, Z1);
             double H = fma(f2, bH, H1);
             H = (self && i1 == 0 && i2 == 0) ? 0.0 : H;
             if (MIXED) {
-                const double px = X - cxl, pz = Z - czl;
-                const double rc2 = px * px + pz * pz + H * H;
+                const double rc2 = fma(X, X, fma(Z, Z, H * H));
                 if (rc2 >= mp.quad2) {
-                    far_quadrupole<KIND>(px, pz, H, rc2, e.lx, e.lz, e.area, sp, sx, sz, sn, fc);
+                    far_quadrupole<KIND>(X, Z, H, rc2, e.lx, e.lz, e.area, sp, sx, sz, sn, fc);
                     continue;
                 }
                 if (rc2 >= mp.low2) {
-                    far_mixed<KIND>(px, pz, H, rc2, e.lx, e.lz, e.area, sp, sx, sz, sn, fc);
+                    far_mixed<KIND>(X, Z, H, rc2, e.lx, e.lz, e.area, sp, sx, sz, sn, fc);
                     continue;
                 }
+                X += cxl;
+                Z += czl;
             }
             Kern k;
             const double r0sq = fma(X, X, fma(Z, Z, H * H));
