@@ -64,6 +64,10 @@ def parse():
     p.add_argument("--serve-matrix", type=int, default=0, metavar="R",
                    help="serving study instead of the step: R requests over the plates, GEM and double-THGEM "
                         "geometries, FP64 saturation measured first, then loads 0.5/0.8/0.95 in FP64 and mixed")
+    p.add_argument("--weighting", action="store_true",
+                   help="weighting fields of the GEM cell's electrodes (one column per electrode potential "
+                        "group) at the evaluation points: one several-column evaluation against one "
+                        "evaluation per column")
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     return p.parse_args()
@@ -186,6 +190,53 @@ def serve_matrix(args):
     print(json.dumps({"serve_matrix": out}), flush=True)
 
 
+def weighting_bench(args):
+    """Weighting fields (one electrode at 1 V, the others at 0) of the GEM
+    cell: multi-RHS solve, then phi/E of every column at the points, once
+    with nebem_eval_multi and once column by column; prints one JSON line."""
+    import torch
+
+    import paper_2606_24154_amd as nb
+    from synth import gem_cell, gem_eval_points
+
+    dev = torch.device("cuda:0")
+    g = gem_cell()
+    m = args.points or 1_000_000
+    val, bc = np.asarray(g.value), np.asarray(g.bc)
+    groups = np.unique(val[bc == 0])
+    B = np.stack([((bc == 0) & (val == v)).astype(float) for v in groups])
+    prec = nb.MIXED if args.precision == "mixed" else nb.FP64
+    dp = nb.DevicePanels.from_geometry(g, dev)
+    At = nb.assemble(dp)
+    sigma, _, _ = nb.solve(At, torch.from_numpy(B).to(dev))
+    del At
+    pts = gem_eval_points(g, m, seed=1)
+    pt = [torch.from_numpy(np.ascontiguousarray(pts[:, k])).to(dev) for k in range(3)]
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    nb.eval_points_multi(dp, sigma[:, :], pt[0][:4096], pt[1][:4096], pt[2][:4096], precision=prec)  # warm-up
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    multi = nb.eval_points_multi(dp, sigma, *pt, precision=prec)
+    ev[1].record(stream)
+    singles = []
+    for k in range(len(groups)):
+        singles.append(nb.eval_points(dp, sigma[k].contiguous(), *pt, precision=prec))
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    t_multi = ev[0].elapsed_time(ev[1]) * 1e-3
+    t_single = ev[1].elapsed_time(ev[2]) * 1e-3
+    same = all(torch.equal(multi[c][k], singles[k][c]) for k in range(len(groups)) for c in range(4))
+    K = len(groups)
+    inter = float(K) * m * g.n * g.images.count
+    print(json.dumps({"metric": "weighting-field evaluation", "unit": "column-interactions/s",
+                      "value": inter / t_multi, "higher_is_better": True, "n_gpus": 1, "dtype": args.precision,
+                      "config": {"workload": f"gem_cell weighting fields: N={g.n}, C={g.images.count}, M={m}, "
+                                             f"{K} electrode columns (potentials {groups.tolist()})"},
+                      "columns": K, "ms_multi": 1e3 * t_multi, "ms_column_by_column": 1e3 * t_single,
+                      "speedup": t_single / t_multi, "bitwise_equal_to_single_columns": bool(same)}), flush=True)
+
+
 def spacecharge_bench(args):
     """Config 3: GEM cell, charges ~ N(hole centre, 20 um), +-e alternating;
     each step = (re-solve every 10th step) + panel field at every charge +
@@ -238,6 +289,9 @@ def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.weighting:
+        weighting_bench(args)
         return
     if args.spacecharge:
         spacecharge_bench(args)

@@ -181,6 +181,20 @@ nebem_status nebem_eval(const nebem_panels *panels, const nebem_images *images, 
                         const double *px, const double *py, const double *pz, int64_t m, double *phi,
                         double *ex, double *ey, double *ez, const nebem_options *opt, hipStream_t stream);
 
+/* Weighting fields (Sec. 2.1: one readout at unit potential, the others at
+ * zero, one sigma per readout): phi and E at m points for nsig density
+ * columns at once.  sigma: n x nsig column-major (column k at sigma + k n);
+ * phi/ex/ey/ez: m x nsig column-major (column k at phi + k m), any of the
+ * four may be NULL.  The element copies' closed forms are evaluated once per
+ * point for up to 4 columns (larger nsig is done 4 columns at a time), so
+ * the transcendentals are shared between readouts; column k equals
+ * nebem_eval with that column bit for bit.  nsig <= 64.  Other arguments as
+ * in nebem_eval. */
+nebem_status nebem_eval_multi(const nebem_panels *panels, const nebem_images *images, const double *sigma,
+                              int64_t nsig, const double *px, const double *py, const double *pz, int64_t m,
+                              double *phi, double *ex, double *ey, double *ez, const nebem_options *opt,
+                              hipStream_t stream);
+
 /* ---------------------------------------------------------------- sessions
  * A session keeps one geometry resident: derived panel data, its influence
  * matrix and factors (FP64: the matrix and its FP64 LU, 16 n^2 bytes, every

@@ -28,7 +28,7 @@ MIXED = 1
 
 EXPORTED = (
     "nebem_default_options", "nebem_assemble", "nebem_solve", "nebem_solve_factored", "nebem_norm1",
-    "nebem_condest", "nebem_eval",
+    "nebem_condest", "nebem_eval", "nebem_eval_multi",
     "nebem_session_create", "nebem_session_destroy", "nebem_session_n", "nebem_session_sigma",
     "nebem_session_solve", "nebem_session_condest", "nebem_session_eval", "nebem_spacecharge_step",
     "nebem_last_error",
@@ -98,6 +98,8 @@ def _load():
     lib.nebem_solve.argtypes = [P, i64, P, i64, P, P, PO, ctypes.POINTER(SolveInfo), P]
     lib.nebem_solve_factored.argtypes = [P, P, i64, P, i64, P, P]
     lib.nebem_eval.argtypes = [PP, PI, P, P, P, P, i64, P, P, P, P, PO, P]
+    lib.nebem_eval_multi.argtypes = [PP, PI, P, i64, P, P, P, i64, P, P, P, P, PO, P]
+    lib.nebem_eval_multi.restype = i32
     lib.nebem_norm1.argtypes = [P, i64, ctypes.POINTER(ctypes.c_double), P]
     lib.nebem_norm1.restype = i32
     lib.nebem_condest.argtypes = [P, P, i64, ctypes.c_double, ctypes.POINTER(ctypes.c_double), P]
@@ -244,6 +246,20 @@ def solve_factored(LU, ipiv, b, stream=None, sigma=None):
         sigma = torch.empty_like(b)
     _check(lib.nebem_solve_factored(_ptr(LU), _ptr(ipiv), n, _ptr(b), nrhs, _ptr(sigma), _stream(stream)))
     return sigma
+
+
+def eval_points_multi(dp: DevicePanels, sigma, px, py, pz, precision=FP64, stream=None, **opt):
+    """Weighting fields: sigma is (nsig, n) float64 (row k = density column
+    k); returns (phi, ex, ey, ez), each (nsig, m)."""
+    import torch
+    m = px.shape[0]
+    nsig = sigma.shape[0]
+    out = [torch.empty((nsig, m), dtype=torch.float64, device=px.device) for _ in range(4)]
+    im = images_struct(dp.images)
+    o = options(precision, **opt)
+    _check(lib.nebem_eval_multi(ctypes.byref(dp.struct), ctypes.byref(im), _ptr(sigma), nsig, _ptr(px), _ptr(py),
+                                _ptr(pz), m, *(_ptr(t) for t in out), ctypes.byref(o), _stream(stream)))
+    return tuple(out)
 
 
 def norm1(A, stream=None):

@@ -185,6 +185,50 @@ nebem_status nebem_eval(const nebem_panels *panels, const nebem_images *images, 
     return NEBEM_OK;
 }
 
+nebem_status nebem_eval_multi(const nebem_panels *panels, const nebem_images *images, const double *sigma,
+                              int64_t nsig, const double *px, const double *py, const double *pz, int64_t m,
+                              double *phi, double *ex, double *ey, double *ez, const nebem_options *opt,
+                              hipStream_t stream)
+{
+    nebem_status st = check_panels(panels);
+    if (st) return st;
+    nebem_options tmp;
+    const nebem_options &o = opts_or_default(opt, tmp);
+    if ((st = check_options(o))) return st;
+    if (m < 0 || m > (int64_t)INT_MAX - 256) return fail(NEBEM_EINVAL, "eval_multi: m out of range");
+    if (nsig < 0 || nsig > 64) return fail(NEBEM_EINVAL, "eval_multi: nsig out of range (0..64)");
+    if (m == 0 || nsig == 0) return NEBEM_OK;
+    if (!px || !py || !pz) return fail(NEBEM_EINVAL, "eval_multi: NULL point array");
+    if (panels->n > 0 && !sigma) return fail(NEBEM_EINVAL, "eval_multi: NULL sigma");
+    if ((uint64_t)m * (uint64_t)nsig > (uint64_t)1 << 40) return fail(NEBEM_EINVAL, "eval_multi: m * nsig too large");
+    ImgArgs ia;
+    if ((st = make_img_args(images, &ia))) return st;
+    DevBuf drec;
+    if ((st = derive(panels, stream, drec))) return st;
+    const int mixed = o.precision == NEBEM_MIXED;
+    const int ns = (int)nsig;
+    if (eval_ordering_pays(m)) {
+        const size_t wb = ordered_eval_multi_workspace(m);
+        if (!wb) return fail(NEBEM_EDEVICE, "eval_multi: ordering workspace query failed");
+        DevBuf ws;
+        if (ws.alloc(wb, stream) != hipSuccess) return fail(NEBEM_ENOMEM, "eval_multi: ordering workspace");
+        NEBEM_HIP(launch_eval_multi_ordered(drec.as<double>(), sigma, panels->n, ns, ia, mixed, o.near_factor, px, py,
+                                            pz, m, phi, ex, ey, ez, ws.p, wb, stream));
+    } else {
+        for (int c0 = 0; c0 < ns; c0 += kMultiCols) {
+            const int k = ns - c0 < kMultiCols ? ns - c0 : kMultiCols;
+            const size_t col = (size_t)c0 * (size_t)m;
+            OutCols out = {{phi ? phi + col : nullptr, ex ? ex + col : nullptr, ey ? ey + col : nullptr,
+                            ez ? ez + col : nullptr},
+                           m};
+            launch_eval_multi(drec.as<double>(), sigma + (size_t)c0 * panels->n, panels->n, k, ia, mixed,
+                              o.near_factor, px, py, pz, m, out, stream);
+        }
+    }
+    NEBEM_HIP(hipGetLastError());
+    return NEBEM_OK;
+}
+
 nebem_status nebem_assemble(const nebem_panels *panels, const nebem_images *images, const double *cx,
                             const double *cy, const double *cz, const nebem_options *opt, double *A,
                             hipStream_t stream)

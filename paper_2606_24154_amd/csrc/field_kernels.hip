@@ -370,6 +370,115 @@ void launch_eval(const double *drec, const double *sigma, int64_t n, const ImgAr
                            pz, (int)m, phi, ex, ey, ez);
 }
 
+// ------------------------------------------------- several sigma columns
+// Weighting fields: K density columns over the same elements and points
+// (column k of sigma at sigma + k n).  Each element's copies are summed once
+// per point (the closed forms do not depend on sigma) and the K columns take
+// their own FP64 sums in the same fixed order as eval_block, so column k's
+// results equal a single-column evaluation with that column bit for bit.
+// Output (component c, column k) goes to out[c] + k * ostride (out[c] may be
+// null: that component is not stored).
+template <bool MIXED, int K>
+__device__ __forceinline__ void eval_block_multi(const double *__restrict__ drec, const double *__restrict__ sigma,
+                                                 int n, const ImgArgs &img, double near_factor,
+                                                 const double *__restrict__ px, const double *__restrict__ py,
+                                                 const double *__restrict__ pz, int m, int base_pt, OutCols out)
+{
+    __shared__ double t_rec[kTileE * R_STRIDE];
+    __shared__ double t_sig[kTileE * K];
+    const int i = base_pt + threadIdx.x;
+    const bool act = i < m;
+    const double Px = act ? px[i] : 0.0;
+    const double Py = act ? py[i] : 0.0;
+    const double Pz = act ? pz[i] : 0.0;
+    double aphi[K], aex[K], aey[K], aez[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) aphi[k] = aex[k] = aey[k] = aez[k] = 0.0;
+    for (int base = 0; base < n; base += kTileE) {
+        const int cnt = min(kTileE, n - base);
+        __syncthreads();
+        for (int q = threadIdx.x; q < cnt * R_STRIDE; q += kBlock) t_rec[q] = drec[(size_t)base * R_STRIDE + q];
+        for (int q = threadIdx.x; q < cnt * K; q += kBlock) {
+            const int pp = q / K, k = q % K;
+            t_sig[q] = sigma[(size_t)k * n + base + pp];
+        }
+        __syncthreads();
+        for (int p = 0; p < cnt; ++p) {
+            const Elem e = load_elem(t_rec + p * R_STRIDE);
+            double cp, cx, cy, cz;
+            element_copies<MIXED>(e, img, Px, Py, Pz, false, near_factor, cp, cx, cy, cz);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const double sg = uni(t_sig[p * K + k]);
+                aphi[k] = fma(sg, cp, aphi[k]);
+                aex[k] = fma(sg, cx, aex[k]);
+                aey[k] = fma(sg, cy, aey[k]);
+                aez[k] = fma(sg, cz, aez[k]);
+            }
+        }
+    }
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const size_t o = (size_t)k * out.stride + i;
+            if (out.c[0]) out.c[0][o] = kKe * aphi[k];
+            if (out.c[1]) out.c[1][o] = kKe * aex[k];
+            if (out.c[2]) out.c[2][o] = kKe * aey[k];
+            if (out.c[3]) out.c[3][o] = kKe * aez[k];
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_eval_multi_fp64(const double *__restrict__ drec,
+                                                            const double *__restrict__ sigma, int n, ImgArgs img,
+                                                            double near_factor, const double *__restrict__ px,
+                                                            const double *__restrict__ py,
+                                                            const double *__restrict__ pz, int m, OutCols out)
+{
+    eval_block_multi<false, K>(drec, sigma, n, img, near_factor, px, py, pz, m, blockIdx.x * kBlock, out);
+}
+
+// at most 256 VGPRs so that two waves share a SIMD (unbounded, K = 3 and 4
+// would take 258 and 266)
+template <int K>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_eval_multi_mixed(const double *__restrict__ drec,
+                                                             const double *__restrict__ sigma, int n, ImgArgs img,
+                                                             double near_factor, const double *__restrict__ px,
+                                                             const double *__restrict__ py,
+                                                             const double *__restrict__ pz, int m, OutCols out)
+{
+    eval_block_multi<true, K>(drec, sigma, n, img, near_factor, px, py, pz, m, blockIdx.x * kBlock, out);
+}
+
+template <int K>
+static void launch_multi_k(const double *drec, const double *sigma, int n, const ImgArgs &img, int mixed,
+                           double near_factor, const double *px, const double *py, const double *pz, int m,
+                           const OutCols &out, hipStream_t s)
+{
+    const unsigned g = (unsigned)((m + kBlock - 1) / kBlock);
+    if (mixed)
+        hipLaunchKernelGGL(k_eval_multi_mixed<K>, dim3(g), dim3(kBlock), 0, s, drec, sigma, n, img, near_factor, px,
+                           py, pz, m, out);
+    else
+        hipLaunchKernelGGL(k_eval_multi_fp64<K>, dim3(g), dim3(kBlock), 0, s, drec, sigma, n, img, near_factor, px,
+                           py, pz, m, out);
+}
+
+void launch_eval_multi(const double *drec, const double *sigma, int64_t n, int ncol, const ImgArgs &img, int mixed,
+                       double near_factor, const double *px, const double *py, const double *pz, int64_t m,
+                       const OutCols &out, hipStream_t s)
+{
+    if (m <= 0 || ncol <= 0) return;
+    const int nn = (int)n, mm = (int)m;
+    switch (ncol) {
+    case 1: launch_multi_k<1>(drec, sigma, nn, img, mixed, near_factor, px, py, pz, mm, out, s); break;
+    case 2: launch_multi_k<2>(drec, sigma, nn, img, mixed, near_factor, px, py, pz, mm, out, s); break;
+    case 3: launch_multi_k<3>(drec, sigma, nn, img, mixed, near_factor, px, py, pz, mm, out, s); break;
+    default: launch_multi_k<4>(drec, sigma, nn, img, mixed, near_factor, px, py, pz, mm, out, s); break;
+    }
+}
+
 // Continuous-batching evaluation: workgroup (one wave) b takes work item b --
 // up to 64 points of one request against one segment of the elements of one
 // resident geometry -- and writes the segment's unscaled partial sums.  The

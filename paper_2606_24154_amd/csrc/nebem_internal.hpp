@@ -81,6 +81,17 @@ void launch_prep(const nebem_panels *p, double *drec, int *bad, hipStream_t s);
 // triangles >= 48 D, never below near_factor D) use the FP64 monopole + FP32
 // correction far field, nearer ones the exact FP64 closed forms; mixed == 0:
 // the exact FP64 closed forms everywhere.
+// Output columns of a several-column evaluation: component c (phi, ex, ey,
+// ez) of column k at c[c] + k * stride; a null c[c] is not stored.
+struct OutCols {
+    double *c[4];
+    int64_t stride;
+};
+constexpr int kMultiCols = 4;  // density columns per evaluation launch
+// ncol <= kMultiCols columns of sigma (column k at sigma + k n)
+void launch_eval_multi(const double *drec, const double *sigma, int64_t n, int ncol, const ImgArgs &img, int mixed,
+                       double near_factor, const double *px, const double *py, const double *pz, int64_t m,
+                       const OutCols &out, hipStream_t s);
 void launch_eval(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
                  double near_factor, const double *px, const double *py, const double *pz, int64_t m, double *phi,
                  double *ex, double *ey, double *ez, hipStream_t s);
@@ -96,6 +107,13 @@ hipError_t launch_order_points(const double *px, const double *py, const double 
 void launch_unorder4(const double *src, const int *perm, int64_t m, double *d0, double *d1, double *d2, double *d3,
                      hipStream_t s);
 size_t ordered_eval_workspace(int64_t m);  // bytes of device workspace, 0 on error
+size_t ordered_eval_multi_workspace(int64_t m);
+// ncol columns (any count; launched kMultiCols at a time) of sigma, points
+// ordered once; outputs m x ncol column-major per component (null: skipped)
+hipError_t launch_eval_multi_ordered(const double *drec, const double *sigma, int64_t n, int ncol, const ImgArgs &img,
+                                     int mixed, double near_factor, const double *px, const double *py,
+                                     const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
+                                     void *ws, size_t ws_bytes, hipStream_t s);
 hipError_t launch_eval_ordered(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
                                double near_factor, const double *px, const double *py, const double *pz, int64_t m,
                                double *phi, double *ex, double *ey, double *ez, void *ws, size_t ws_bytes,

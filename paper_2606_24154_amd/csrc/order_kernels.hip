@@ -230,4 +230,46 @@ hipError_t launch_eval_ordered(const double *drec, const double *sigma, int64_t 
     return hipGetLastError();
 }
 
+// several-column evaluation: the sort's scratch, perm, sorted points and
+// the sorted results of one chunk of kMultiCols columns
+size_t ordered_eval_multi_workspace(int64_t m)
+{
+    const size_t w = order_points_workspace(m);
+    if (!w) return 0;
+    return w + align256(4 * (size_t)m) + align256(24 * (size_t)m) + align256(32 * kMultiCols * (size_t)m);
+}
+
+hipError_t launch_eval_multi_ordered(const double *drec, const double *sigma, int64_t n, int ncol, const ImgArgs &img,
+                                     int mixed, double near_factor, const double *px, const double *py,
+                                     const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
+                                     void *ws, size_t ws_bytes, hipStream_t s)
+{
+    if (m <= 0 || ncol <= 0) return hipSuccess;
+    const size_t w0 = order_points_workspace(m);
+    if (!w0) return hipErrorInvalidValue;
+    if (!ws || ws_bytes < ordered_eval_multi_workspace(m)) return hipErrorInvalidValue;
+    char *w = static_cast<char *>(ws);
+    int *perm = reinterpret_cast<int *>(w + w0);
+    double *sp = reinterpret_cast<double *>(w + w0 + align256(4 * (size_t)m));
+    double *so = reinterpret_cast<double *>(w + w0 + align256(4 * (size_t)m) + align256(24 * (size_t)m));
+    const size_t mm = (size_t)m;
+    hipError_t e = launch_order_points(px, py, pz, m, sp, sp + mm, sp + 2 * mm, perm, ws, w0, s);
+    if (e != hipSuccess) return e;
+    for (int c0 = 0; c0 < ncol; c0 += kMultiCols) {
+        const int k = ncol - c0 < kMultiCols ? ncol - c0 : kMultiCols;
+        // sorted results of column j of the chunk: so + 4 j m (phi, ex, ey, ez)
+        OutCols out = {{phi ? so : nullptr, ex ? so + mm : nullptr, ey ? so + 2 * mm : nullptr,
+                        ez ? so + 3 * mm : nullptr},
+                       (int64_t)(4 * mm)};
+        launch_eval_multi(drec, sigma + (size_t)c0 * n, n, k, img, mixed, near_factor, sp, sp + mm, sp + 2 * mm, m,
+                          out, s);
+        for (int j = 0; j < k; ++j) {
+            const size_t col = (size_t)(c0 + j) * mm;
+            launch_unorder4(so + 4 * (size_t)j * mm, perm, m, phi ? phi + col : nullptr, ex ? ex + col : nullptr,
+                            ey ? ey + col : nullptr, ez ? ez + col : nullptr, s);
+        }
+    }
+    return hipGetLastError();
+}
+
 }  // namespace nebem

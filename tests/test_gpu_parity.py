@@ -214,6 +214,55 @@ def test_plates_end_to_end(nb, plates_ref):
     assert ephi < 1e-10 and eE < 1e-10, (ephi, eE)
 
 
+# ------------------------------------------------------ weighting fields
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_eval_multi_equals_single_columns(nb, prec):
+    """Several density columns in one evaluation: column k equals the
+    single-column evaluation bit for bit, on the unordered (m < 4096) and
+    Morton-ordered paths, with 6 columns (a chunk of 4 and one of 2)."""
+    P = nb.FP64 if prec == "fp64" else nb.MIXED
+    rng = np.random.default_rng(31)
+    g = _mixed_geometry(rng, n=20).with_images(
+        Images(a1=np.array([1.5e-3, 0, 0]), a2=np.array([0, 1.5e-3, 0]), n1=2, n2=1))
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    nsig = 6
+    sig = rng.standard_normal((nsig, g.n)) * 1e-9
+    for m in (1000, 5000):
+        pts = uniform_points(g.box_lo, g.box_hi, m, m)
+        pt = [dev(pts[:, k]) for k in range(3)]
+        multi = nb.eval_points_multi(dp, dev(sig), *pt, precision=P)
+        for k in range(nsig):
+            single = nb.eval_points(dp, dev(sig[k]), *pt, precision=P)
+            torch.cuda.synchronize()
+            for c in range(4):
+                assert torch.equal(multi[c][k], single[c]), (m, k, c)
+
+
+def test_weighting_fields_plates(nb, plates_ref):
+    """Weighting fields of the two plates (each at 1 V with the other at 0):
+    multi-RHS solve, then both columns in one evaluation, against the
+    oracle's solve and evaluation of each column; their sum is the field of
+    both plates at 1 V."""
+    g, A_ref, _, pts, _ = plates_ref
+    top = (np.asarray(g.value) == 1.0).astype(float)
+    B = np.stack([top, 1.0 - top])
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    At = nb.assemble(dp)
+    sigma, _, _ = nb.solve(At, dev(B))
+    out = nb.eval_points_multi(dp, sigma, dev(pts[:, 0]), dev(pts[:, 1]), dev(pts[:, 2]))
+    torch.cuda.synchronize()
+    got = [np.column_stack([t[k].cpu().numpy() for t in out]) for k in range(2)]
+    for k in range(2):
+        s_ref = oracle.solve(A_ref, B[k])
+        f_ref = oracle.eval_points(g, s_ref, pts)
+        ephi, eE = rel_errors(got[k], f_ref)
+        assert ephi < 1e-10 and eE < 1e-10, (k, ephi, eE)
+    both = oracle.eval_points(g, oracle.solve(A_ref, B[0] + B[1]), pts)
+    ephi, eE = rel_errors(got[0] + got[1], both)
+    assert ephi < 1e-10 and eE < 1e-9, (ephi, eE)
+
+
 # ---------------------------------------------------- copies and mirrors
 
 def _mixed_geometry(rng, n=24, bc_mix=True):
