@@ -191,6 +191,43 @@ def solve(A, b):
     return sla.lu_solve((lu, piv), b)
 
 
+def grid_nodes(origin, step, shape) -> np.ndarray:
+    """Coordinates (nx*ny*nz, 3) of a regular grid's nodes, node (i, j, k)
+    at row i + nx (j + ny k): the FastVolume grid of Sec. 3 (a volume
+    sampled once, then interpolated)."""
+    nx, ny, nz = shape
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return np.column_stack([origin[0] + i.ravel() * step[0], origin[1] + j.ravel() * step[1],
+                            origin[2] + k.ravel() * step[2]])
+
+
+def trilinear(origin, step, shape, values, pts) -> np.ndarray:
+    """Trilinear interpolation of node values (nx*ny*nz, c), node order as in
+    `grid_nodes`, at points (m, 3): on each axis the cell index is
+    floor((x - origin)/step), limited to [0, n-2], and the weights are the
+    fractional distances to the cell's two faces.  Points outside the grid
+    (any coordinate below the first or above the last node) give NaN.
+    Plain loops over the 8 corners; the definition, not a fast path."""
+    pts = np.asarray(pts, dtype=np.float64)
+    values = np.asarray(values, dtype=np.float64)
+    nx, ny, nz = shape
+    u = (pts - np.asarray(origin)) / np.asarray(step)
+    n = np.array([nx, ny, nz])
+    inside = np.all((u >= 0) & (u <= n - 1), axis=1)
+    i0 = np.clip(np.floor(u).astype(np.int64), 0, n - 2)
+    f = u - i0
+    out = np.zeros((len(pts), values.shape[1]))
+    for dk in (0, 1):
+        for dj in (0, 1):
+            for di in (0, 1):
+                w = ((f[:, 0] if di else 1 - f[:, 0]) * (f[:, 1] if dj else 1 - f[:, 1])
+                     * (f[:, 2] if dk else 1 - f[:, 2]))
+                idx = (i0[:, 0] + di) + nx * ((i0[:, 1] + dj) + ny * (i0[:, 2] + dk))
+                out += w[:, None] * values[np.where(inside, idx, 0)]
+    out[~inside] = np.nan
+    return out
+
+
 def rhs_with_charges(geom, b0, qxyz, q, nthreads: int = 0) -> np.ndarray:
     """Boundary values with the known charges moved to the right-hand side
     (paper Sec. 4.1, RHVector with the known-charge contribution):
