@@ -195,6 +195,36 @@ nebem_status nebem_eval_multi(const nebem_panels *panels, const nebem_images *im
                               double *phi, double *ex, double *ey, double *ez, const nebem_options *opt,
                               hipStream_t stream);
 
+/* FastVolume (Sec. 3: a volume sampled once on a regular grid, then
+ * interpolated).  Grid nodes origin + (i step[0], j step[1], k step[2]),
+ * 0 <= i < n[0] etc., each n >= 2, each step > 0; node (i, j, k) has index
+ * q = i + n[0] (j + n[1] k).  Node values are interleaved: values[4 q + c]
+ * with c = 0 phi, 1 ex, 2 ey, 3 ez (device, 4 n[0] n[1] n[2] doubles,
+ * 16-byte aligned), so one interpolation gathers 8 corners x 32 bytes. */
+typedef struct nebem_grid {
+    double origin[3];
+    double step[3];
+    int32_t n[3];
+} nebem_grid;
+
+/* Fills `values` with phi and E at every grid node (one nebem_eval over the
+ * nodes, node x = origin[0] + i * step[0] with the product and the sum each
+ * rounded to FP64, likewise y, z; other arguments as in nebem_eval).
+ * n[0] n[1] n[2] <= 2^31 - 257. */
+nebem_status nebem_fastvol_build(const nebem_panels *panels, const nebem_images *images, const double *sigma,
+                                 const nebem_grid *grid, double *values, const nebem_options *opt,
+                                 hipStream_t stream);
+
+/* Trilinear interpolation of the node values at m points (px/py/pz device,
+ * m each); phi/ex/ey/ez: m outputs, any may be NULL.  On each axis the cell
+ * is floor((x - origin)/step) limited to [0, n - 2] and the weights are the
+ * fractional distances to its faces.  A point outside the grid (a
+ * coordinate below the first or above the last node, or NaN) gets NaN in
+ * every output, so the caller can evaluate it directly instead. */
+nebem_status nebem_fastvol_interp(const nebem_grid *grid, const double *values, const double *px, const double *py,
+                                  const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
+                                  hipStream_t stream);
+
 /* ---------------------------------------------------------------- sessions
  * A session keeps one geometry resident: derived panel data, its influence
  * matrix and factors (FP64: the matrix and its FP64 LU, 16 n^2 bytes, every

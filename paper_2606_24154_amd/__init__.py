@@ -28,7 +28,7 @@ MIXED = 1
 
 EXPORTED = (
     "nebem_default_options", "nebem_assemble", "nebem_solve", "nebem_solve_factored", "nebem_norm1",
-    "nebem_condest", "nebem_eval", "nebem_eval_multi",
+    "nebem_condest", "nebem_eval", "nebem_eval_multi", "nebem_fastvol_build", "nebem_fastvol_interp",
     "nebem_session_create", "nebem_session_destroy", "nebem_session_n", "nebem_session_sigma",
     "nebem_session_solve", "nebem_session_condest", "nebem_session_eval", "nebem_spacecharge_step",
     "nebem_last_error",
@@ -65,6 +65,10 @@ class Options(ctypes.Structure):
                 ("sc_resolve_every", ctypes.c_int32)]
 
 
+class GridC(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_double * 3), ("step", ctypes.c_double * 3), ("n", ctypes.c_int32 * 3)]
+
+
 class SolveInfo(ctypes.Structure):
     _fields_ = [("ir_iters", ctypes.c_int32), ("rel_resid", ctypes.c_double)]
 
@@ -98,6 +102,11 @@ def _load():
     lib.nebem_solve.argtypes = [P, i64, P, i64, P, P, PO, ctypes.POINTER(SolveInfo), P]
     lib.nebem_solve_factored.argtypes = [P, P, i64, P, i64, P, P]
     lib.nebem_eval.argtypes = [PP, PI, P, P, P, P, i64, P, P, P, P, PO, P]
+    PG = ctypes.POINTER(GridC)
+    lib.nebem_fastvol_build.argtypes = [PP, PI, P, PG, P, PO, P]
+    lib.nebem_fastvol_build.restype = i32
+    lib.nebem_fastvol_interp.argtypes = [PG, P, P, P, P, i64, P, P, P, P, P]
+    lib.nebem_fastvol_interp.restype = i32
     lib.nebem_eval_multi.argtypes = [PP, PI, P, i64, P, P, P, i64, P, P, P, P, PO, P]
     lib.nebem_eval_multi.restype = i32
     lib.nebem_norm1.argtypes = [P, i64, ctypes.POINTER(ctypes.c_double), P]
@@ -259,6 +268,36 @@ def eval_points_multi(dp: DevicePanels, sigma, px, py, pz, precision=FP64, strea
     o = options(precision, **opt)
     _check(lib.nebem_eval_multi(ctypes.byref(dp.struct), ctypes.byref(im), _ptr(sigma), nsig, _ptr(px), _ptr(py),
                                 _ptr(pz), m, *(_ptr(t) for t in out), ctypes.byref(o), _stream(stream)))
+    return tuple(out)
+
+
+def grid_struct(origin, step, shape) -> GridC:
+    g = GridC()
+    for a in range(3):
+        g.origin[a], g.step[a], g.n[a] = float(origin[a]), float(step[a]), int(shape[a])
+    return g
+
+
+def fastvol_build(dp: DevicePanels, sigma, origin, step, shape, precision=FP64, stream=None, **opt):
+    """phi/E at every node of the grid, interleaved (nx*ny*nz, 4) float64."""
+    import torch
+    g = grid_struct(origin, step, shape)
+    values = torch.empty((int(np.prod(shape)), 4), dtype=torch.float64, device=sigma.device)
+    im = images_struct(dp.images)
+    o = options(precision, **opt)
+    _check(lib.nebem_fastvol_build(ctypes.byref(dp.struct), ctypes.byref(im), _ptr(sigma), ctypes.byref(g),
+                                   _ptr(values), ctypes.byref(o), _stream(stream)))
+    return values
+
+
+def fastvol_interp(values, origin, step, shape, px, py, pz, stream=None):
+    """Trilinear interpolation of `fastvol_build` values; NaN outside."""
+    import torch
+    g = grid_struct(origin, step, shape)
+    m = px.shape[0]
+    out = [torch.empty(m, dtype=torch.float64, device=px.device) for _ in range(4)]
+    _check(lib.nebem_fastvol_interp(ctypes.byref(g), _ptr(values), _ptr(px), _ptr(py), _ptr(pz), m,
+                                    *(_ptr(t) for t in out), _stream(stream)))
     return tuple(out)
 
 

@@ -4,6 +4,7 @@
 
 #include <climits>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -225,6 +226,66 @@ nebem_status nebem_eval_multi(const nebem_panels *panels, const nebem_images *im
                               o.near_factor, px, py, pz, m, out, stream);
         }
     }
+    NEBEM_HIP(hipGetLastError());
+    return NEBEM_OK;
+}
+
+static nebem_status grid_args(const nebem_grid *grid, GridArgs &g, int64_t &nn)
+{
+    if (!grid) return fail(NEBEM_EINVAL, "fastvol: NULL grid");
+    nn = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (grid->n[a] < 2) return fail(NEBEM_EINVAL, "fastvol: fewer than 2 nodes on an axis");
+        if (!(grid->step[a] > 0.0) || !std::isfinite(grid->step[a]) || !std::isfinite(grid->origin[a]))
+            return fail(NEBEM_EINVAL, "fastvol: step must be finite and > 0, origin finite");
+        nn *= grid->n[a];
+        if (nn > (int64_t)INT_MAX - 256) return fail(NEBEM_EINVAL, "fastvol: too many nodes");
+        g.origin[a] = grid->origin[a];
+        g.step[a] = grid->step[a];
+        g.inv_step[a] = 1.0 / grid->step[a];
+        g.n[a] = grid->n[a];
+    }
+    return NEBEM_OK;
+}
+
+nebem_status nebem_fastvol_build(const nebem_panels *panels, const nebem_images *images, const double *sigma,
+                                 const nebem_grid *grid, double *values, const nebem_options *opt,
+                                 hipStream_t stream)
+{
+    GridArgs g;
+    int64_t nn = 0;
+    nebem_status st = grid_args(grid, g, nn);
+    if (st) return st;
+    if (!values) return fail(NEBEM_EINVAL, "fastvol_build: NULL values");
+    if ((uintptr_t)values % 16) return fail(NEBEM_EINVAL, "fastvol_build: values must be 16-byte aligned");
+    DevBuf tmp;
+    if (tmp.alloc((size_t)nn * 7 * sizeof(double), stream) != hipSuccess)
+        return fail(NEBEM_ENOMEM, "fastvol_build: node buffers");
+    double *t = tmp.as<double>();
+    const size_t q = (size_t)nn;
+    launch_grid_nodes(g, t, t + q, t + 2 * q, stream);
+    NEBEM_HIP(hipGetLastError());
+    if ((st = nebem_eval(panels, images, sigma, t, t + q, t + 2 * q, nn, t + 3 * q, t + 4 * q, t + 5 * q, t + 6 * q,
+                         opt, stream)))
+        return st;
+    launch_interleave4(t + 3 * q, t + 4 * q, t + 5 * q, t + 6 * q, nn, values, stream);
+    NEBEM_HIP(hipGetLastError());
+    return NEBEM_OK;
+}
+
+nebem_status nebem_fastvol_interp(const nebem_grid *grid, const double *values, const double *px, const double *py,
+                                  const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
+                                  hipStream_t stream)
+{
+    GridArgs g;
+    int64_t nn = 0;
+    nebem_status st = grid_args(grid, g, nn);
+    if (st) return st;
+    if (m < 0 || m > (int64_t)INT_MAX - 256) return fail(NEBEM_EINVAL, "fastvol_interp: m out of range");
+    if (m == 0) return NEBEM_OK;
+    if (!values || !px || !py || !pz) return fail(NEBEM_EINVAL, "fastvol_interp: NULL argument");
+    if ((uintptr_t)values % 16) return fail(NEBEM_EINVAL, "fastvol_interp: values must be 16-byte aligned");
+    launch_fastvol_interp(g, values, px, py, pz, m, phi, ex, ey, ez, stream);
     NEBEM_HIP(hipGetLastError());
     return NEBEM_OK;
 }

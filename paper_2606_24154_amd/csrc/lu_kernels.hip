@@ -862,7 +862,7 @@ void lu_solve_transposed(const double *LU, int n, const int *perm, const double 
                          double *V, hipStream_t s)
 {
     // U^T w = b: X = W (copy of b, reduced in place), solution in V
-    hipMemcpyAsync(W, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(W, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s);
     for (int b0 = 0; b0 < n; b0 += 64) {
         const int bsz = (n - b0 < 64) ? n - b0 : 64;
         const int rows = n - b0 - bsz;

@@ -81,6 +81,19 @@ void launch_prep(const nebem_panels *p, double *drec, int *bad, hipStream_t s);
 // triangles >= 48 D, never below near_factor D) use the FP64 monopole + FP32
 // correction far field, nearer ones the exact FP64 closed forms; mixed == 0:
 // the exact FP64 closed forms everywhere.
+// FastVolume grid (fastvol_kernels.hip): nodes origin + (i, j, k) * step,
+// n[0] x n[1] x n[2] of them, node values interleaved 4 per node.
+struct GridArgs {
+    double origin[3], step[3], inv_step[3];
+    int n[3];
+};
+void launch_grid_nodes(const GridArgs &g, double *px, double *py, double *pz, hipStream_t s);
+void launch_interleave4(const double *s0, const double *s1, const double *s2, const double *s3, int64_t nn,
+                        double *values, hipStream_t s);
+void launch_fastvol_interp(const GridArgs &g, const double *values, const double *px, const double *py,
+                           const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
+                           hipStream_t s);
+
 // Output columns of a several-column evaluation: component c (phi, ex, ey,
 // ez) of column k at c[c] + k * stride; a null c[c] is not stored.
 struct OutCols {

@@ -263,6 +263,55 @@ def test_weighting_fields_plates(nb, plates_ref):
     assert ephi < 1e-10 and eE < 1e-9, (ephi, eE)
 
 
+# ------------------------------------------------------------ FastVolume
+
+FV_ORIGIN, FV_STEP, FV_SHAPE = (-0.3e-3, -0.25e-3, -0.04e-3), (1e-5, 1e-5, 1e-5), (61, 51, 9)
+
+
+def test_fastvol_interp_matches_oracle(nb):
+    """Trilinear lookup of arbitrary node values against the oracle's
+    definition, inside, on the last nodes and outside (NaN)."""
+    rng = np.random.default_rng(41)
+    nn = int(np.prod(FV_SHAPE))
+    vals = rng.standard_normal((nn, 4))
+    lo = np.array(FV_ORIGIN)
+    hi = lo + (np.array(FV_SHAPE) - 1) * np.array(FV_STEP)
+    pts = rng.uniform(lo - 0.05 * (hi - lo), hi + 0.05 * (hi - lo), (3000, 3))
+    pts[:20] = oracle.grid_nodes(FV_ORIGIN, FV_STEP, FV_SHAPE)[-20:]
+    out = nb.fastvol_interp(dev(vals), FV_ORIGIN, FV_STEP, FV_SHAPE, *(dev(pts[:, k]) for k in range(3)))
+    torch.cuda.synchronize()
+    got = np.column_stack([t.cpu().numpy() for t in out])
+    ref = oracle.trilinear(FV_ORIGIN, FV_STEP, FV_SHAPE, vals, pts)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert ok.sum() > 2000 and (~ok).sum() > 100
+    assert np.abs(got[ok] - ref[ok]).max() <= 1e-14 * np.abs(vals).max()
+
+
+def test_fastvol_build_and_error_vs_direct(nb, plates_ref):
+    """Node values equal nebem_eval at the nodes bit for bit; between the
+    plates the interpolated field stays within the paper's 0.25 % of the
+    direct evaluation."""
+    g, _, s_ref, _, _ = plates_ref
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    sig = dev(s_ref)
+    vals = nb.fastvol_build(dp, sig, FV_ORIGIN, FV_STEP, FV_SHAPE)
+    nodes = oracle.grid_nodes(FV_ORIGIN, FV_STEP, FV_SHAPE)
+    direct = nb.eval_points(dp, sig, *(dev(nodes[:, k]) for k in range(3)))
+    torch.cuda.synchronize()
+    assert np.array_equal(vals.cpu().numpy(), np.column_stack([t.cpu().numpy() for t in direct]))
+    rng = np.random.default_rng(42)
+    lo = np.array(FV_ORIGIN)
+    hi = lo + (np.array(FV_SHAPE) - 1) * np.array(FV_STEP)
+    pts = rng.uniform(lo, hi, (4000, 3))
+    pt = [dev(pts[:, k]) for k in range(3)]
+    fi = np.column_stack([t.cpu().numpy() for t in nb.fastvol_interp(vals, FV_ORIGIN, FV_STEP, FV_SHAPE, *pt)])
+    fd = np.column_stack([t.cpu().numpy() for t in nb.eval_points(dp, sig, *pt)])
+    ephi = np.abs(fi[:, 0] - fd[:, 0]).max() / np.abs(fd[:, 0]).max()
+    eE = (np.linalg.norm(fi[:, 1:] - fd[:, 1:], axis=1) / np.linalg.norm(fd[:, 1:], axis=1)).max()
+    assert ephi < 2.5e-3 and eE < 2.5e-3, (ephi, eE)
+
+
 # ---------------------------------------------------- copies and mirrors
 
 def _mixed_geometry(rng, n=24, bc_mix=True):
