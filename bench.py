@@ -68,6 +68,9 @@ def parse():
                    help="weighting fields of the GEM cell's electrodes (one column per electrode potential "
                         "group) at the evaluation points: one several-column evaluation against one "
                         "evaluation per column")
+    p.add_argument("--fastvol", action="store_true",
+                   help="FastVolume on the GEM cell's drift gap: grid build (one evaluation at the nodes), "
+                        "trilinear lookups at the evaluation points, error against direct evaluation")
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     return p.parse_args()
@@ -237,6 +240,69 @@ def weighting_bench(args):
                       "speedup": t_single / t_multi, "bitwise_equal_to_single_columns": bool(same)}), flush=True)
 
 
+def fastvol_bench(args):
+    """FastVolume (Sec. 3) on the GEM cell: a 5 um grid over the centre cell's
+    bounding box in the drift gap (from 20 um above the top copper to the
+    drift plane), built by one FP64 evaluation at its nodes; then trilinear
+    lookups at 10^6 drift-gap points, timed with HIP events, and the
+    interpolation error against direct evaluation at 2*10^4 of them."""
+    import torch
+
+    import paper_2606_24154_amd as nb
+    from synth import gem_cell
+
+    dev = torch.device("cuda:0")
+    g = gem_cell()
+    ses = nb.Session(nb.DevicePanels.from_geometry(g, dev), precision=nb.FP64)
+    sigma = ses.sigma()
+    dp = nb.DevicePanels.from_geometry(g, dev)
+    z_top = float(g.o[np.asarray(g.value) == -200.0][:, 2].max())
+    h = 5e-6
+    lo = np.array([0.0, 0.0, z_top + 20e-6])
+    hi = np.array([float(g.images.a1[0] + g.images.a2[0]), float(g.images.a2[1]), float(g.box_hi[2]) - 1e-6])
+    shape = tuple(int(np.ceil((hi[a] - lo[a]) / h)) + 1 for a in range(3))
+    step = tuple((hi[a] - lo[a]) / (shape[a] - 1) for a in range(3))
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(stream)
+    vals = nb.fastvol_build(dp, sigma, lo, step, shape)
+    ev[1].record(stream)
+    m = args.points or 1_000_000
+    rng = np.random.default_rng(7)
+    pts = rng.uniform(lo, hi, (m, 3))
+    pt = [torch.from_numpy(np.ascontiguousarray(pts[:, k])).to(dev) for k in range(3)]
+    out = nb.fastvol_interp(vals, lo, step, shape, *pt)  # warm-up
+    reps = 20
+    torch.cuda.synchronize()
+    ev[2].record(stream)
+    for _ in range(reps):
+        out = nb.fastvol_interp(vals, lo, step, shape, *pt)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    t_build = ev[0].elapsed_time(ev[1]) * 1e-3
+    t_lookup = ev[2].elapsed_time(ev[3]) * 1e-3 / reps
+    ns = min(20000, m)
+    direct = nb.eval_points(dp, sigma, pt[0][:ns], pt[1][:ns], pt[2][:ns])
+    fi = np.column_stack([t[:ns].cpu().numpy() for t in out])
+    fd = np.column_stack([t.cpu().numpy() for t in direct])
+    eE = np.linalg.norm(fi[:, 1:] - fd[:, 1:], axis=1) / np.linalg.norm(fd[:, 1:], axis=1)
+    ephi = np.abs(fi[:, 0] - fd[:, 0]) / np.abs(fd[:, 0]).max()
+    q = lambda a: {k: float(np.quantile(a, f)) for k, f in (("p50", 0.5), ("p95", 0.95), ("p99", 0.99),
+                                                             ("max", 1.0))}
+    bytes_per_lookup = 24 + 32  # coordinates in, (phi, E) out; the table gathers hit L2 / the die cache
+    print(json.dumps({"metric": "FastVolume lookups", "unit": "points/s", "value": m / t_lookup,
+                      "higher_is_better": True, "n_gpus": 1, "dtype": "f64",
+                      "config": {"workload": f"gem_cell drift gap, grid {shape[0]}x{shape[1]}x{shape[2]} "
+                                             f"(step {step[0]*1e6:.2f}/{step[1]*1e6:.2f}/{step[2]*1e6:.2f} um), "
+                                             f"M={m} lookups"},
+                      "nodes": int(np.prod(shape)), "build_ms": 1e3 * t_build, "lookup_ms": 1e3 * t_lookup,
+                      "roofline": {"bound": "hbm", "achieved": bytes_per_lookup * m / t_lookup / 1e9,
+                                   "peak": 8000.0, "unit": "GB/s",
+                                   "frac": bytes_per_lookup * m / t_lookup / 8e12, "traffic": None},
+                      "rel_err_E_vs_direct": q(eE), "frac_E_within_0.25pct": float((eE <= 2.5e-3).mean()),
+                      "rel_err_phi_vs_direct_max": float(ephi.max()), "error_sample": ns}), flush=True)
+
+
 def spacecharge_bench(args):
     """Config 3: GEM cell, charges ~ N(hole centre, 20 um), +-e alternating;
     each step = (re-solve every 10th step) + panel field at every charge +
@@ -292,6 +358,9 @@ def main():
         return
     if args.weighting:
         weighting_bench(args)
+        return
+    if args.fastvol:
+        fastvol_bench(args)
         return
     if args.spacecharge:
         spacecharge_bench(args)
