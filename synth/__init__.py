@@ -13,6 +13,7 @@ from .geometry import (  # noqa: F401
     GeometryBuilder,
     parallel_plates,
     gem_cell,
+    strip_cell,
     thgem_double,
 )
 from .workloads import (  # noqa: F401

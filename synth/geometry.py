@@ -484,3 +484,31 @@ def thgem_double(k: int = 96, nr: int = 11, nrim: int = 2, nz_fr4: int = 12, nz_
     lo = np.array([0.0, 0.0, z_anode])
     hi = np.array([a1[0] + a2[0], a2[1], z_drift])
     return b.build("thgem_double", imgs, lo, hi)
+
+
+def strip_cell(pitch: float = 100e-6, n_strips: int = 4, strip_w: float = 15e-6, gap: float = 128e-6,
+               sub_u: int = 4, sub_w: int = 16, n_img: int = 5):
+    """Periodic readout-like cell for Adaptive Modelling: a pitch x pitch
+    cell (copies +-n_img along x and y) with n_strips anode strips at z = 0
+    (0 V .. alternating +-50 V) and a mesh plane at z = gap (-400 V, one
+    rectangle), each flat rectangle a primitive cut into sub_u x sub_w
+    rectangular elements.  Returns (elements, primitives, elem_prim)."""
+    eb, pb = GeometryBuilder(), GeometryBuilder()
+    emap = []
+    prims = []
+    dx = pitch / n_strips
+    for s in range(n_strips):
+        x0 = s * dx + 0.5 * (dx - strip_w)
+        prims.append(((x0, 0.0, 0.0), (strip_w, 0.0, 0.0), (0.0, pitch, 0.0), 50.0 * (-1) ** s))
+    prims.append(((0.0, 0.0, gap), (pitch, 0.0, 0.0), (0.0, pitch, 0.0), -400.0))
+    for p, (o, u, w, v) in enumerate(prims):
+        pb.rect(o, u, w, bc=CONDUCTOR, value=v)
+        for a in range(sub_u):
+            for b in range(sub_w):
+                oo = tuple(o[k] + a * u[k] / sub_u + b * w[k] / sub_w for k in range(3))
+                eb.rect(oo, tuple(c / sub_u for c in u), tuple(c / sub_w for c in w), bc=CONDUCTOR, value=v)
+                emap.append(p)
+    im = Images(a1=np.array([pitch, 0.0, 0.0]), a2=np.array([0.0, pitch, 0.0]), n1=n_img, n2=n_img)
+    box_lo, box_hi = (0.0, 0.0, 5e-6), (pitch, pitch, gap - 5e-6)
+    return (eb.build("strip_cell", im, box_lo, box_hi), pb.build("strip_cell_primitives", im, box_lo, box_hi),
+            np.asarray(emap, dtype=np.int32))
