@@ -195,6 +195,23 @@ nebem_status nebem_eval_multi(const nebem_panels *panels, const nebem_images *im
                               double *phi, double *ex, double *ey, double *ez, const nebem_options *opt,
                               hipStream_t stream);
 
+/* Adaptive Modelling (Sec. 3: far away, a periodic structure's fine charge
+ * distribution is replaced by the average density of each primitive).
+ * `prims` are the primitives the elements were cut from (flat rectangles /
+ * right triangles, same layout as `panels`; bc/value/eps are not read),
+ * elem_prim[j] (device, n entries) the primitive of element j.  Translated
+ * copies with |i1| <= prim_after and |i2| <= prim_after (with every
+ * reflection) are summed element by element exactly as in nebem_eval; every
+ * farther copy is summed primitive by primitive, each primitive with the
+ * uniform density sigma_p = sum_{j in p} sigma_j A_j / A_p (the same total
+ * charge) and the exact closed form of its own shape.  prim_after < 0: no
+ * simplification (= nebem_eval).  Other arguments as in nebem_eval.
+ * Synchronises `stream`. */
+nebem_status nebem_eval_adaptive(const nebem_panels *panels, const nebem_panels *prims, const int32_t *elem_prim,
+                                 int32_t prim_after, const nebem_images *images, const double *sigma, const double *px,
+                                 const double *py, const double *pz, int64_t m, double *phi, double *ex, double *ey,
+                                 double *ez, const nebem_options *opt, hipStream_t stream);
+
 /* FastVolume (Sec. 3: a volume sampled once on a regular grid, then
  * interpolated).  Grid nodes origin + (i step[0], j step[1], k step[2]),
  * 0 <= i < n[0] etc., each n >= 2, each step > 0; node (i, j, k) has index

@@ -28,7 +28,8 @@ MIXED = 1
 
 EXPORTED = (
     "nebem_default_options", "nebem_assemble", "nebem_solve", "nebem_solve_factored", "nebem_norm1",
-    "nebem_condest", "nebem_eval", "nebem_eval_multi", "nebem_fastvol_build", "nebem_fastvol_interp",
+    "nebem_condest", "nebem_eval", "nebem_eval_multi", "nebem_eval_adaptive", "nebem_fastvol_build",
+    "nebem_fastvol_interp",
     "nebem_session_create", "nebem_session_destroy", "nebem_session_n", "nebem_session_sigma",
     "nebem_session_solve", "nebem_session_condest", "nebem_session_eval", "nebem_spacecharge_step",
     "nebem_last_error",
@@ -102,6 +103,8 @@ def _load():
     lib.nebem_solve.argtypes = [P, i64, P, i64, P, P, PO, ctypes.POINTER(SolveInfo), P]
     lib.nebem_solve_factored.argtypes = [P, P, i64, P, i64, P, P]
     lib.nebem_eval.argtypes = [PP, PI, P, P, P, P, i64, P, P, P, P, PO, P]
+    lib.nebem_eval_adaptive.argtypes = [PP, PP, P, i32, PI, P, P, P, P, i64, P, P, P, P, PO, P]
+    lib.nebem_eval_adaptive.restype = i32
     PG = ctypes.POINTER(GridC)
     lib.nebem_fastvol_build.argtypes = [PP, PI, P, PG, P, PO, P]
     lib.nebem_fastvol_build.restype = i32
@@ -268,6 +271,22 @@ def eval_points_multi(dp: DevicePanels, sigma, px, py, pz, precision=FP64, strea
     o = options(precision, **opt)
     _check(lib.nebem_eval_multi(ctypes.byref(dp.struct), ctypes.byref(im), _ptr(sigma), nsig, _ptr(px), _ptr(py),
                                 _ptr(pz), m, *(_ptr(t) for t in out), ctypes.byref(o), _stream(stream)))
+    return tuple(out)
+
+
+def eval_points_adaptive(dp: DevicePanels, dprims: DevicePanels, elem_prim, prim_after, sigma, px, py, pz,
+                         precision=FP64, stream=None, **opt):
+    """Adaptive Modelling: copies beyond `prim_after` lattice steps summed
+    primitive by primitive with primitive-averaged densities.  elem_prim:
+    int32 device tensor (n,).  Returns (phi, ex, ey, ez)."""
+    import torch
+    m = px.shape[0]
+    out = [torch.empty(m, dtype=torch.float64, device=px.device) for _ in range(4)]
+    im = images_struct(dp.images)
+    o = options(precision, **opt)
+    _check(lib.nebem_eval_adaptive(ctypes.byref(dp.struct), ctypes.byref(dprims.struct), _ptr(elem_prim),
+                                   int(prim_after), ctypes.byref(im), _ptr(sigma), _ptr(px), _ptr(py), _ptr(pz), m,
+                                   *(_ptr(t) for t in out), ctypes.byref(o), _stream(stream)))
     return tuple(out)
 
 

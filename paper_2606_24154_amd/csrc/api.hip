@@ -33,6 +33,7 @@ nebem_status hip_fail(hipError_t e, const char *what)
 nebem_status make_img_args(const nebem_images *im, ImgArgs *o)
 {
     std::memset(o, 0, sizeof(*o));
+    o->hole = -1;
     if (!im) {
         o->nref = 1;
         o->parity[0] = 1.0;
@@ -227,6 +228,97 @@ nebem_status nebem_eval_multi(const nebem_panels *panels, const nebem_images *im
         }
     }
     NEBEM_HIP(hipGetLastError());
+    return NEBEM_OK;
+}
+
+// one evaluation pass (ordered for large batches), outputs overwritten
+static nebem_status eval_pass(const double *drec, const double *sigma, int64_t n, const ImgArgs &ia, int mixed,
+                              double near_factor, const double *px, const double *py, const double *pz, int64_t m,
+                              double *phi, double *ex, double *ey, double *ez, hipStream_t stream)
+{
+    if (eval_ordering_pays(m)) {
+        const size_t wb = ordered_eval_workspace(m);
+        if (!wb) return fail(NEBEM_EDEVICE, "eval: ordering workspace query failed");
+        DevBuf ws;
+        if (ws.alloc(wb, stream) != hipSuccess) return fail(NEBEM_ENOMEM, "eval: ordering workspace");
+        NEBEM_HIP(launch_eval_ordered(drec, sigma, n, ia, mixed, near_factor, px, py, pz, m, phi, ex, ey, ez, ws.p,
+                                      wb, stream));
+    } else {
+        launch_eval(drec, sigma, n, ia, mixed, near_factor, px, py, pz, m, phi, ex, ey, ez, stream);
+    }
+    NEBEM_HIP(hipGetLastError());
+    return NEBEM_OK;
+}
+
+nebem_status nebem_eval_adaptive(const nebem_panels *panels, const nebem_panels *prims, const int32_t *elem_prim,
+                                 int32_t prim_after, const nebem_images *images, const double *sigma, const double *px,
+                                 const double *py, const double *pz, int64_t m, double *phi, double *ex, double *ey,
+                                 double *ez, const nebem_options *opt, hipStream_t stream)
+{
+    if (prim_after < 0)
+        return nebem_eval(panels, images, sigma, px, py, pz, m, phi, ex, ey, ez, opt, stream);
+    nebem_status st = check_panels(panels);
+    if (st) return st;
+    if ((st = check_panels(prims))) return st;
+    nebem_options tmp;
+    const nebem_options &o = opts_or_default(opt, tmp);
+    if ((st = check_options(o))) return st;
+    if (m < 0 || m > (int64_t)INT_MAX - 256) return fail(NEBEM_EINVAL, "eval_adaptive: m out of range");
+    if (m == 0) return NEBEM_OK;
+    if (!px || !py || !pz) return fail(NEBEM_EINVAL, "eval_adaptive: NULL point array");
+    const int64_t n = panels->n, np = prims->n;
+    if (n > 0 && (!sigma || !elem_prim)) return fail(NEBEM_EINVAL, "eval_adaptive: NULL sigma or elem_prim");
+    ImgArgs ia;
+    if ((st = make_img_args(images, &ia))) return st;
+    const int mixed = o.precision == NEBEM_MIXED;
+    // near copies: every element, lattice |i1|, |i2| <= prim_after
+    ImgArgs near = ia;
+    near.n1 = ia.n1 < prim_after ? ia.n1 : prim_after;
+    near.n2 = ia.n2 < prim_after ? ia.n2 : prim_after;
+    DevBuf drec;
+    if ((st = derive(panels, stream, drec))) return st;
+    if (n == 0) {
+        // no elements: nothing near; the far pass below has no charge either
+        for (double *out : {phi, ex, ey, ez})
+            if (out) NEBEM_HIP(hipMemsetAsync(out, 0, (size_t)m * sizeof(double), stream));
+        return NEBEM_OK;
+    }
+    if ((st = eval_pass(drec.as<double>(), sigma, n, near, mixed, o.near_factor, px, py, pz, m, phi, ex, ey, ez,
+                        stream)))
+        return st;
+    if (prim_after >= ia.n1 && prim_after >= ia.n2) return NEBEM_OK;  // no far copies
+    if (np == 0) return fail(NEBEM_EINVAL, "eval_adaptive: no primitives");
+    // primitive-averaged densities: sigma_p = sum_{j in p} sigma_j A_j / A_p
+    DevBuf prec;
+    if ((st = derive(prims, stream, prec))) return st;
+    std::vector<double> hrec((size_t)n * R_STRIDE), hprec((size_t)np * R_STRIDE), hsig(n);
+    std::vector<int32_t> hmap(n);
+    NEBEM_HIP(hipMemcpyAsync(hrec.data(), drec.p, hrec.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    NEBEM_HIP(hipMemcpyAsync(hprec.data(), prec.p, hprec.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    NEBEM_HIP(hipMemcpyAsync(hsig.data(), sigma, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, stream));
+    NEBEM_HIP(hipMemcpyAsync(hmap.data(), elem_prim, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    NEBEM_HIP(hipStreamSynchronize(stream));
+    std::vector<double> q(np, 0.0), sbar(np);
+    for (int64_t j = 0; j < n; ++j) {
+        if (hmap[j] < 0 || hmap[j] >= np) return fail(NEBEM_EINVAL, "eval_adaptive: elem_prim out of range");
+        q[hmap[j]] += hsig[j] * hrec[(size_t)j * R_STRIDE + R_AREA];
+    }
+    for (int64_t p = 0; p < np; ++p) sbar[p] = q[p] / hprec[(size_t)p * R_STRIDE + R_AREA];
+    DevBuf dsbar, far;
+    NEBEM_HIP(dsbar.alloc((size_t)np * sizeof(double), stream));
+    NEBEM_HIP(hipMemcpyAsync(dsbar.p, sbar.data(), (size_t)np * sizeof(double), hipMemcpyHostToDevice, stream));
+    NEBEM_HIP(far.alloc((size_t)4 * m * sizeof(double), stream));
+    ImgArgs farimg = ia;
+    farimg.hole = prim_after;
+    double *f = far.as<double>();
+    const size_t mm = (size_t)m;
+    if ((st = eval_pass(prec.as<double>(), dsbar.as<double>(), np, farimg, mixed, o.near_factor, px, py, pz, m,
+                        phi ? f : nullptr, ex ? f + mm : nullptr, ey ? f + 2 * mm : nullptr, ez ? f + 3 * mm : nullptr,
+                        stream)))
+        return st;
+    launch_add4(f, m, phi, ex, ey, ez, stream);
+    NEBEM_HIP(hipGetLastError());
+    NEBEM_HIP(hipStreamSynchronize(stream));  // host vectors above must outlive the copy of sbar
     return NEBEM_OK;
 }
 

@@ -161,8 +161,8 @@ struct MixParams {
 };
 
 template <int KIND, bool MIXED>
-__device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, double X0, double Z0, double H0,
-                                                 double aX, double aZ, double aH, double bX, double bZ,
+__device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, int hole, double X0, double Z0,
+                                                 double H0, double aX, double aZ, double aH, double bX, double bZ,
                                                  double bH, bool self, const MixParams &mp, double &sp,
                                                  double &sx, double &sz, double &sn)
 {
@@ -184,6 +184,7 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
         const double X1 = fma(f1, aX, X0), Z1 = fma(f1, aZ, Z0), H1 = fma(f1, aH, H0);
 #pragma unroll 1
         for (int i2 = -n2; i2 <= n2; ++i2) {
+            if (hole >= 0 && abs(i1) <= hole && abs(i2) <= hole) continue;  // uniform: whole wave
             const double f2 = -(double)i2;
             double X = fma(f2, bX, X1), Z = fma(f2, bZ, Z1);
             double H = fma(f2, bH, H1);
@@ -268,11 +269,11 @@ __device__ __forceinline__ void element_copies(const Elem &e, const ImgArgs &img
         double sp = 0.0, sx = 0.0, sz = 0.0, sn = 0.0;
         const bool s = self && r == 0;
         if (e.kind == 0)
-            sum_translations<0, MIXED>(e, img.n1, img.n2, X0, Z0, H0, aX, aZ, aH, bX, bZ, bH, s, mp, sp, sx, sz,
-                                       sn);
+            sum_translations<0, MIXED>(e, img.n1, img.n2, img.hole, X0, Z0, H0, aX, aZ, aH, bX, bZ, bH, s, mp, sp,
+                                       sx, sz, sn);
         else
-            sum_translations<1, MIXED>(e, img.n1, img.n2, X0, Z0, H0, aX, aZ, aH, bX, bZ, bH, s, mp, sp, sx, sz,
-                                       sn);
+            sum_translations<1, MIXED>(e, img.n1, img.n2, img.hole, X0, Z0, H0, aX, aZ, aH, bX, bZ, bH, s, mp, sp,
+                                       sx, sz, sn);
         double gx = sx * e.e1x + sz * e.e2x + sn * e.e3x;
         double gy = sx * e.e1y + sz * e.e2y + sn * e.e3y;
         double gz = sx * e.e1z + sz * e.e2z + sn * e.e3z;
@@ -368,6 +369,27 @@ void launch_eval(const double *drec, const double *sigma, int64_t n, const ImgAr
     else
         hipLaunchKernelGGL(k_eval_fp64, dim3(g), dim3(kBlock), 0, s, drec, sigma, (int)n, img, near_factor, px, py,
                            pz, (int)m, phi, ex, ey, ez);
+}
+
+// out[c][i] += add[c m + i] for the non-null outputs
+__global__ __launch_bounds__(kBlock) void k_add4(const double *__restrict__ add, int m, double *__restrict__ o0,
+                                                 double *__restrict__ o1, double *__restrict__ o2,
+                                                 double *__restrict__ o3)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m) return;
+    const size_t mm = (size_t)m;
+    if (o0) o0[i] += add[i];
+    if (o1) o1[i] += add[mm + i];
+    if (o2) o2[i] += add[2 * mm + i];
+    if (o3) o3[i] += add[3 * mm + i];
+}
+
+void launch_add4(const double *add, int64_t m, double *o0, double *o1, double *o2, double *o3, hipStream_t s)
+{
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_add4, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, add, (int)m, o0, o1,
+                       o2, o3);
 }
 
 // ------------------------------------------------- several sigma columns

@@ -43,6 +43,7 @@ struct ImgArgs {
     int axes[8];
     int nref;
     int n1, n2;
+    int hole;  // >= 0: the translations with |i1| <= hole and |i2| <= hole are left out (-1: none)
 };
 
 // thread-local error text
@@ -93,6 +94,9 @@ void launch_interleave4(const double *s0, const double *s1, const double *s2, co
 void launch_fastvol_interp(const GridArgs &g, const double *values, const double *px, const double *py,
                            const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
                            hipStream_t s);
+
+// o_c[i] += add[c m + i] for each non-null o_c
+void launch_add4(const double *add, int64_t m, double *o0, double *o1, double *o2, double *o3, hipStream_t s);
 
 // Output columns of a several-column evaluation: component c (phi, ex, ey,
 // ez) of column k at c[c] + k * stride; a null c[c] is not stored.

@@ -312,6 +312,36 @@ def test_fastvol_build_and_error_vs_direct(nb, plates_ref):
     assert ephi < 2.5e-3 and eE < 2.5e-3, (ephi, eE)
 
 
+# --------------------------------------------------- Adaptive Modelling
+
+def test_adaptive_matches_oracle(nb):
+    """Adaptive Modelling against the oracle's definition for PrimAfter -1
+    .. 3 on the strip cell (copies +-3), with a reflection; PrimAfter >= 3
+    (no far copies) equals nebem_eval bit for bit."""
+    from synth import strip_cell
+    e, p, emap = strip_cell(n_img=3, sub_u=2, sub_w=8)
+    im = Images(a1=e.images.a1, a2=e.images.a2, n1=3, n2=3, mirror_mask=4,
+                mirror_pos=np.array([0.0, 0.0, -60e-6]), mirror_parity=np.array([1, 1, -1], dtype=np.int32))
+    e, p = e.with_images(im), p.with_images(im)
+    rng = np.random.default_rng(61)
+    sigma = (1.0 + 0.5 * rng.standard_normal(e.n)) * 1e-9
+    pts = uniform_points(e.box_lo, e.box_hi, 1500, 61)
+    dp, dpp = nb.DevicePanels.from_geometry(e, DEV), nb.DevicePanels.from_geometry(p, DEV)
+    demap = torch.from_numpy(emap).to(DEV)
+    pt = [dev(pts[:, k]) for k in range(3)]
+    exact = nb.eval_points(dp, dev(sigma), *pt)
+    for k in (-1, 0, 1, 2, 3):
+        out = nb.eval_points_adaptive(dp, dpp, demap, k, dev(sigma), *pt)
+        torch.cuda.synchronize()
+        got = np.column_stack([t.cpu().numpy() for t in out])
+        ref = oracle.eval_adaptive(e, p, emap, k, sigma, pts)
+        ephi, eE = rel_errors(got, ref)
+        assert ephi < 1e-10 and eE < 1e-10, (k, ephi, eE)
+        if k < 0 or k >= 3:
+            for c in range(4):
+                assert torch.equal(out[c], exact[c]), (k, c)
+
+
 # ---------------------------------------------------- copies and mirrors
 
 def _mixed_geometry(rng, n=24, bc_mix=True):
