@@ -71,6 +71,9 @@ def parse():
     p.add_argument("--fastvol", action="store_true",
                    help="FastVolume on the GEM cell's drift gap: grid build (one evaluation at the nodes), "
                         "trilinear lookups at the evaluation points, error against direct evaluation")
+    p.add_argument("--adaptive", action="store_true",
+                   help="Adaptive Modelling on a periodic strip cell: time and error against the exact sum "
+                        "for PrimAfter -1, 5, 3, 2, 1, 0")
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     return p.parse_args()
@@ -303,6 +306,54 @@ def fastvol_bench(args):
                       "rel_err_phi_vs_direct_max": float(ephi.max()), "error_sample": ns}), flush=True)
 
 
+def adaptive_bench(args):
+    """Adaptive Modelling (Sec. 3 and the paper's PrimAfter table): strip
+    cell (4 strips, each 4 primitives along its length, and a mesh plane of
+    4 x 4 primitives; every primitive cut into 4 x 16 rectangles; copies
+    +-5 x +-5), sigma from the FP64 solve, phi and E at the evaluation
+    points for PrimAfter -1 (exact), 5, 3, 2, 1, 0: time and the largest
+    error against the exact sum, pointwise relative (points with |x| >=
+    1e-3 max|x|) and relative to max|x|."""
+    import torch
+
+    import paper_2606_24154_amd as nb
+    from synth import strip_cell, uniform_points
+
+    dev = torch.device("cuda:0")
+    e, p, emap = strip_cell(sub_u=4, sub_w=16, n_img=5, split=4)
+    m = args.points or 200_000
+    ses = nb.Session(nb.DevicePanels.from_geometry(e, dev), precision=nb.FP64)
+    sigma = ses.sigma()
+    dp, dpp = nb.DevicePanels.from_geometry(e, dev), nb.DevicePanels.from_geometry(p, dev)
+    demap = torch.from_numpy(emap).to(dev)
+    pts = uniform_points(e.box_lo, e.box_hi, m, 11)
+    pt = [torch.from_numpy(np.ascontiguousarray(pts[:, k])).to(dev) for k in range(3)]
+    nb.eval_points_adaptive(dp, dpp, demap, 0, sigma, pt[0][:4096], pt[1][:4096], pt[2][:4096])  # warm-up
+    rows, ref = [], None
+    for k in (-1, 5, 3, 2, 1, 0):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = nb.eval_points_adaptive(dp, dpp, demap, k, sigma, *pt)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        got = np.column_stack([t.cpu().numpy() for t in out])
+        if ref is None:
+            ref = got
+        sel = np.abs(ref[:, 0]) >= 1e-3 * np.abs(ref[:, 0]).max()
+        en = np.linalg.norm(ref[:, 1:], axis=1)
+        selE = en >= 1e-3 * en.max()
+        ephi = float((np.abs(got[sel, 0] - ref[sel, 0]) / np.abs(ref[sel, 0])).max())
+        eE = float((np.linalg.norm(got[selE, 1:] - ref[selE, 1:], axis=1) / en[selE]).max())
+        nphi = float(np.abs(got[:, 0] - ref[:, 0]).max() / np.abs(ref[:, 0]).max())
+        nE = float(np.linalg.norm(got[:, 1:] - ref[:, 1:], axis=1).max() / en.max())
+        rows.append({"prim_after": k, "ms": 1e3 * dt, "max_rel_err_phi": ephi, "max_rel_err_E": eE,
+                     "max_err_phi_over_max_phi": nphi, "max_err_E_over_max_E": nE})
+    print(json.dumps({"metric": "Adaptive Modelling", "unit": "ms", "n_gpus": 1, "dtype": "f64",
+                      "config": {"workload": f"strip cell: N={e.n} elements in {p.n} primitives, "
+                                             f"C={e.images.count} copies, M={m} points"},
+                      "rows": rows}), flush=True)
+
+
 def spacecharge_bench(args):
     """Config 3: GEM cell, charges ~ N(hole centre, 20 um), +-e alternating;
     each step = (re-solve every 10th step) + panel field at every charge +
@@ -361,6 +412,9 @@ def main():
         return
     if args.fastvol:
         fastvol_bench(args)
+        return
+    if args.adaptive:
+        adaptive_bench(args)
         return
     if args.spacecharge:
         spacecharge_bench(args)

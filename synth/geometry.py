@@ -487,11 +487,12 @@ def thgem_double(k: int = 96, nr: int = 11, nrim: int = 2, nz_fr4: int = 12, nz_
 
 
 def strip_cell(pitch: float = 100e-6, n_strips: int = 4, strip_w: float = 15e-6, gap: float = 128e-6,
-               sub_u: int = 4, sub_w: int = 16, n_img: int = 5):
+               sub_u: int = 4, sub_w: int = 16, n_img: int = 5, split: int = 1):
     """Periodic readout-like cell for Adaptive Modelling: a pitch x pitch
     cell (copies +-n_img along x and y) with n_strips anode strips at z = 0
-    (0 V .. alternating +-50 V) and a mesh plane at z = gap (-400 V, one
-    rectangle), each flat rectangle a primitive cut into sub_u x sub_w
+    (alternating +-50 V) and a mesh plane at z = gap (-400 V).  Each strip
+    is `split` primitives along its length and the plane split x split
+    primitives; every primitive (a flat rectangle) is cut into sub_u x sub_w
     rectangular elements.  Returns (elements, primitives, elem_prim)."""
     eb, pb = GeometryBuilder(), GeometryBuilder()
     emap = []
@@ -499,8 +500,13 @@ def strip_cell(pitch: float = 100e-6, n_strips: int = 4, strip_w: float = 15e-6,
     dx = pitch / n_strips
     for s in range(n_strips):
         x0 = s * dx + 0.5 * (dx - strip_w)
-        prims.append(((x0, 0.0, 0.0), (strip_w, 0.0, 0.0), (0.0, pitch, 0.0), 50.0 * (-1) ** s))
-    prims.append(((0.0, 0.0, gap), (pitch, 0.0, 0.0), (0.0, pitch, 0.0), -400.0))
+        for t in range(split):
+            prims.append(((x0, t * pitch / split, 0.0), (strip_w, 0.0, 0.0), (0.0, pitch / split, 0.0),
+                          50.0 * (-1) ** s))
+    for a in range(split):
+        for b in range(split):
+            prims.append(((a * pitch / split, b * pitch / split, gap), (pitch / split, 0.0, 0.0),
+                          (0.0, pitch / split, 0.0), -400.0))
     for p, (o, u, w, v) in enumerate(prims):
         pb.rect(o, u, w, bc=CONDUCTOR, value=v)
         for a in range(sub_u):
