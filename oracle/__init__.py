@@ -226,6 +226,66 @@ def _inner(im, k):
     return dataclasses.replace(im, n1=min(im.n1, k), n2=min(im.n2, k))
 
 
+def voxel_lines(xyz, q, origin, step, shape):
+    """Point charges reduced to line charges (Algorithm 3): charges binned
+    into the voxels of a regular grid (voxel (i, j, k) = floor((x - origin)
+    / step) per axis, index i + nx (j + ny k); charges outside dropped);
+    every occupied voxel becomes one segment parallel to z over the voxel's
+    z extent, at the |q|-weighted mean x, y of its charges (the voxel's
+    centre if they sum to zero), carrying the voxel's total charge
+    uniformly.  Returns (lines (L, 7): ax, ay, az, bx, by, bz, lambda, in
+    increasing voxel index; number of charges outside)."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    origin, step = np.asarray(origin, dtype=np.float64), np.asarray(step, dtype=np.float64)
+    shape = np.asarray(shape)
+    ijk = np.floor((xyz - origin) / step).astype(np.int64)
+    inside = np.all((ijk >= 0) & (ijk < shape), axis=1)
+    ijk, xyz, q = ijk[inside], xyz[inside], q[inside]
+    key = ijk[:, 0] + shape[0] * (ijk[:, 1] + shape[1] * ijk[:, 2])
+    vox, inv = np.unique(key, return_inverse=True)
+    Q = np.bincount(inv, q, len(vox))
+    W = np.bincount(inv, np.abs(q), len(vox))
+    cx = np.bincount(inv, np.abs(q) * xyz[:, 0], len(vox))
+    cy = np.bincount(inv, np.abs(q) * xyz[:, 1], len(vox))
+    i = vox % shape[0]
+    j = (vox // shape[0]) % shape[1]
+    k = vox // (shape[0] * shape[1])
+    x = np.where(W > 0, cx / np.where(W > 0, W, 1), origin[0] + (i + 0.5) * step[0])
+    y = np.where(W > 0, cy / np.where(W > 0, W, 1), origin[1] + (j + 0.5) * step[1])
+    z0 = origin[2] + k * step[2]
+    lines = np.column_stack([x, y, z0, x, y, z0 + step[2], Q / step[2]])
+    return lines, int((~inside).sum())
+
+
+def line_field(lines, pts) -> np.ndarray:
+    """(phi, Ex, Ey, Ez) at the points of uniformly charged segments (A, B,
+    lambda): with t the unit direction, s_a = (a - P).t, rho the distance of
+    P from the line,
+      phi = k_e lambda (asinh(s_B / rho) - asinh(s_A / rho)),
+      E   = k_e lambda [ (s_B/r_B - s_A/r_A) (P - F) / rho^2 + (1/r_B - 1/r_A) t ],
+    F the foot of P on the line (the integral of (P - X)/|P - X|^3 along the
+    segment).  Plain loops over the segments."""
+    lines = np.asarray(lines, dtype=np.float64)
+    pts = np.asarray(pts, dtype=np.float64)
+    out = np.zeros((len(pts), 4))
+    for a0, a1, a2, b0, b1, b2, lam in lines:
+        A, B = np.array([a0, a1, a2]), np.array([b0, b1, b2])
+        L = np.linalg.norm(B - A)
+        t = (B - A) / L
+        d = pts - A
+        along = d @ t
+        perp = d - along[:, None] * t
+        rho2 = (perp * perp).sum(axis=1)
+        rho = np.sqrt(rho2)
+        sA, sB = -along, L - along
+        rA, rB = np.linalg.norm(pts - A, axis=1), np.linalg.norm(pts - B, axis=1)
+        out[:, 0] += ke() * lam * (np.arcsinh(sB / rho) - np.arcsinh(sA / rho))
+        g = (sB / rB - sA / rA) / rho2
+        out[:, 1:] += ke() * lam * (g[:, None] * perp + (1.0 / rB - 1.0 / rA)[:, None] * t)
+    return out
+
+
 def grid_nodes(origin, step, shape) -> np.ndarray:
     """Coordinates (nx*ny*nz, 3) of a regular grid's nodes, node (i, j, k)
     at row i + nx (j + ny k): the FastVolume grid of Sec. 3 (a volume
