@@ -242,6 +242,31 @@ nebem_status nebem_fastvol_interp(const nebem_grid *grid, const double *values, 
                                   const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
                                   hipStream_t stream);
 
+/* Point charges reduced to line charges (Algorithm 3, voxelisation): the
+ * charges are binned into the voxels of `vox` (voxel (i, j, k) =
+ * floor((x - origin) / step) per axis, 1 <= n, n[0] n[1] n[2] < 2^32 - 1;
+ * charges outside are dropped and counted in *outside, host, may be NULL);
+ * every occupied voxel becomes one segment parallel to z over the voxel's
+ * z extent, at the |q|-weighted mean x, y of its charges (the voxel centre
+ * if those weights sum to zero), with line density = total charge / dz.
+ * lines: 7 doubles per line (ax, ay, az, bx, by, bz, lambda), device,
+ * max_lines of them; *nlines (host) receives the number of occupied voxels,
+ * lines in increasing voxel index.  EINVAL when *nlines > max_lines
+ * (nothing written; call again with room for *nlines).  Deterministic: the
+ * charges are sorted by voxel (stable) instead of accumulated with atomics.
+ * Synchronises `stream`. */
+nebem_status nebem_voxelize_charges(const double *qx, const double *qy, const double *qz, const double *q,
+                                    int64_t nq, const nebem_grid *vox, double *lines, int64_t max_lines,
+                                    int64_t *nlines, int64_t *outside, hipStream_t stream);
+
+/* phi and E (k_e lambda times the exact segment integrals) of nlines
+ * uniformly charged segments (layout as above) at m points; outputs as in
+ * nebem_eval.  A point on a segment gets infinite phi and the principal
+ * value 0 for the field across the segment. */
+nebem_status nebem_line_field(const double *lines, int64_t nlines, const double *px, const double *py,
+                              const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
+                              hipStream_t stream);
+
 /* ---------------------------------------------------------------- sessions
  * A session keeps one geometry resident: derived panel data, its influence
  * matrix and factors (FP64: the matrix and its FP64 LU, 16 n^2 bytes, every

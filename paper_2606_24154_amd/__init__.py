@@ -29,7 +29,7 @@ MIXED = 1
 EXPORTED = (
     "nebem_default_options", "nebem_assemble", "nebem_solve", "nebem_solve_factored", "nebem_norm1",
     "nebem_condest", "nebem_eval", "nebem_eval_multi", "nebem_eval_adaptive", "nebem_fastvol_build",
-    "nebem_fastvol_interp",
+    "nebem_fastvol_interp", "nebem_voxelize_charges", "nebem_line_field",
     "nebem_session_create", "nebem_session_destroy", "nebem_session_n", "nebem_session_sigma",
     "nebem_session_solve", "nebem_session_condest", "nebem_session_eval", "nebem_spacecharge_step",
     "nebem_last_error",
@@ -106,6 +106,10 @@ def _load():
     lib.nebem_eval_adaptive.argtypes = [PP, PP, P, i32, PI, P, P, P, P, i64, P, P, P, P, PO, P]
     lib.nebem_eval_adaptive.restype = i32
     PG = ctypes.POINTER(GridC)
+    lib.nebem_voxelize_charges.argtypes = [P, P, P, P, i64, PG, P, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), P]
+    lib.nebem_voxelize_charges.restype = i32
+    lib.nebem_line_field.argtypes = [P, i64, P, P, P, i64, P, P, P, P, P]
+    lib.nebem_line_field.restype = i32
     lib.nebem_fastvol_build.argtypes = [PP, PI, P, PG, P, PO, P]
     lib.nebem_fastvol_build.restype = i32
     lib.nebem_fastvol_interp.argtypes = [PG, P, P, P, P, i64, P, P, P, P, P]
@@ -317,6 +321,32 @@ def fastvol_interp(values, origin, step, shape, px, py, pz, stream=None):
     out = [torch.empty(m, dtype=torch.float64, device=px.device) for _ in range(4)]
     _check(lib.nebem_fastvol_interp(ctypes.byref(g), _ptr(values), _ptr(px), _ptr(py), _ptr(pz), m,
                                     *(_ptr(t) for t in out), _stream(stream)))
+    return tuple(out)
+
+
+def voxelize_charges(qx, qy, qz, q, origin, step, shape, stream=None):
+    """Line charges (L, 7) from point charges (Algorithm 3) and the number
+    of charges outside the voxel grid."""
+    import torch
+    g = grid_struct(origin, step, shape)
+    nl, out = ctypes.c_int64(), ctypes.c_int64()
+    code = lib.nebem_voxelize_charges(_ptr(qx), _ptr(qy), _ptr(qz), _ptr(q), qx.shape[0], ctypes.byref(g), None, 0,
+                                      ctypes.byref(nl), ctypes.byref(out), _stream(stream))
+    if code not in (NEBEM_OK, NEBEM_EINVAL) or (code == NEBEM_EINVAL and nl.value == 0):
+        _check(code)
+    lines = torch.empty((max(nl.value, 1), 7), dtype=torch.float64, device=qx.device)
+    _check(lib.nebem_voxelize_charges(_ptr(qx), _ptr(qy), _ptr(qz), _ptr(q), qx.shape[0], ctypes.byref(g),
+                                      _ptr(lines), nl.value, ctypes.byref(nl), ctypes.byref(out), _stream(stream)))
+    return lines[:nl.value], out.value
+
+
+def line_field(lines, px, py, pz, stream=None):
+    """(phi, ex, ey, ez) of uniformly charged segments at the points."""
+    import torch
+    m = px.shape[0]
+    out = [torch.empty(m, dtype=torch.float64, device=px.device) for _ in range(4)]
+    _check(lib.nebem_line_field(_ptr(lines), lines.shape[0], _ptr(px), _ptr(py), _ptr(pz), m,
+                                *(_ptr(t) for t in out), _stream(stream)))
     return tuple(out)
 
 

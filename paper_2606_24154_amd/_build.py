@@ -11,7 +11,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libnebem.so")
 
 SOURCES = ["field_kernels.hip", "lu_kernels.hip", "refine_kernels.hip", "solver.hip", "charge_kernels.hip",
-           "fastvol_kernels.hip",
+           "fastvol_kernels.hip", "line_kernels.hip",
            "order_kernels.hip", "session.hip", "server.hip", "api.hip"]
 
 HIPCC_FLAGS = [

@@ -382,6 +382,49 @@ nebem_status nebem_fastvol_interp(const nebem_grid *grid, const double *values, 
     return NEBEM_OK;
 }
 
+nebem_status nebem_voxelize_charges(const double *qx, const double *qy, const double *qz, const double *q,
+                                    int64_t nq, const nebem_grid *vox, double *lines, int64_t max_lines,
+                                    int64_t *nlines, int64_t *outside, hipStream_t stream)
+{
+    GridArgs g;
+    int64_t nn = 0;
+    if (!nlines) return fail(NEBEM_EINVAL, "voxelize: NULL nlines");
+    *nlines = 0;
+    if (outside) *outside = 0;
+    if (!vox) return fail(NEBEM_EINVAL, "voxelize: NULL grid");
+    for (int a = 0; a < 3; ++a) {
+        if (vox->n[a] < 1) return fail(NEBEM_EINVAL, "voxelize: fewer than 1 voxel on an axis");
+        if (!(vox->step[a] > 0.0) || !std::isfinite(vox->step[a]) || !std::isfinite(vox->origin[a]))
+            return fail(NEBEM_EINVAL, "voxelize: step must be finite and > 0, origin finite");
+        g.origin[a] = vox->origin[a];
+        g.step[a] = vox->step[a];
+        g.inv_step[a] = 1.0 / vox->step[a];
+        g.n[a] = vox->n[a];
+    }
+    nn = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    if (nn >= (int64_t)0xffffffffLL) return fail(NEBEM_EINVAL, "voxelize: too many voxels (>= 2^32 - 1)");
+    if (nq < 0 || nq > (int64_t)INT_MAX - 256) return fail(NEBEM_EINVAL, "voxelize: nq out of range");
+    if (max_lines < 0) return fail(NEBEM_EINVAL, "voxelize: negative max_lines");
+    if (nq == 0) return NEBEM_OK;
+    if (!qx || !qy || !qz || !q) return fail(NEBEM_EINVAL, "voxelize: NULL charge array");
+    NEBEM_HIP(voxel_lines(qx, qy, qz, q, (int)nq, g, lines, max_lines, nlines, outside, stream));
+    if (*nlines > max_lines) return fail(NEBEM_EINVAL, "voxelize: more occupied voxels than max_lines (*nlines)");
+    return NEBEM_OK;
+}
+
+nebem_status nebem_line_field(const double *lines, int64_t nlines, const double *px, const double *py,
+                              const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
+                              hipStream_t stream)
+{
+    if (nlines < 0 || nlines > (int64_t)INT_MAX) return fail(NEBEM_EINVAL, "line_field: nlines out of range");
+    if (m < 0 || m > (int64_t)INT_MAX - 256) return fail(NEBEM_EINVAL, "line_field: m out of range");
+    if (m == 0) return NEBEM_OK;
+    if (!px || !py || !pz || (nlines > 0 && !lines)) return fail(NEBEM_EINVAL, "line_field: NULL argument");
+    launch_line_field(lines, nlines, px, py, pz, m, phi, ex, ey, ez, stream);
+    NEBEM_HIP(hipGetLastError());
+    return NEBEM_OK;
+}
+
 nebem_status nebem_assemble(const nebem_panels *panels, const nebem_images *images, const double *cx,
                             const double *cy, const double *cz, const nebem_options *opt, double *A,
                             hipStream_t stream)

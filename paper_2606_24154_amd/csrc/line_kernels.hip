@@ -1,0 +1,227 @@
+// line_kernels.hip -- point charges reduced to line charges (the paper's
+// Algorithm 3, voxelisation) and the field of uniformly charged segments.
+//
+// The reduction is deterministic: instead of atomics into voxels, the
+// charges are radix-sorted by voxel index (stable, so a voxel's charges keep
+// their input order), occupied voxels are found by comparing neighbours,
+// numbered by a prefix sum, and each line sums its voxel's charges in order.
+// Each occupied voxel gives one segment parallel to z over the voxel's z
+// extent, at the |q|-weighted mean x, y of its charges (the voxel centre if
+// that weight is zero), carrying the voxel's total charge uniformly.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+
+#include "nebem_internal.hpp"
+
+namespace nebem {
+
+constexpr int kLB = 256;
+constexpr unsigned kOutside = 0xffffffffu;
+
+__global__ __launch_bounds__(kLB) void k_voxel_keys(const double *__restrict__ qx, const double *__restrict__ qy,
+                                                    const double *__restrict__ qz, int nq, GridArgs g,
+                                                    unsigned *__restrict__ key, int *__restrict__ idx)
+{
+    const int i = blockIdx.x * kLB + threadIdx.x;
+    if (i >= nq) return;
+    const double x[3] = {qx[i], qy[i], qz[i]};
+    long long v[3];
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double u = floor((x[a] - g.origin[a]) / g.step[a]);
+        in = in && u >= 0.0 && u < (double)g.n[a];
+        v[a] = in ? (long long)u : 0;
+    }
+    key[i] = in ? (unsigned)(v[0] + (long long)g.n[0] * (v[1] + (long long)g.n[1] * v[2])) : kOutside;
+    idx[i] = i;
+}
+
+// flag[i] = 1 where an occupied voxel's run starts; nvalid = charges inside
+__global__ __launch_bounds__(kLB) void k_run_starts(const unsigned *__restrict__ key, int nq, int *__restrict__ flag,
+                                                    int *__restrict__ nvalid)
+{
+    const int i = blockIdx.x * kLB + threadIdx.x;
+    if (i >= nq) return;
+    const unsigned k = key[i];
+    flag[i] = (k != kOutside && (i == 0 || key[i - 1] != k)) ? 1 : 0;
+    if (k != kOutside && (i == nq - 1 || key[i + 1] == kOutside)) *nvalid = i + 1;
+}
+
+__global__ __launch_bounds__(kLB) void k_run_index(const int *__restrict__ flag, const int *__restrict__ pos, int nq,
+                                                   int *__restrict__ start)
+{
+    const int i = blockIdx.x * kLB + threadIdx.x;
+    if (i >= nq) return;
+    if (flag[i]) start[pos[i]] = i;
+}
+
+__global__ __launch_bounds__(kLB) void k_make_lines(const unsigned *__restrict__ key, const int *__restrict__ idx,
+                                                    const int *__restrict__ start, int nlines, int nvalid,
+                                                    const double *__restrict__ qx, const double *__restrict__ qy,
+                                                    const double *__restrict__ q, GridArgs g,
+                                                    double *__restrict__ lines)
+{
+    const int l = blockIdx.x * kLB + threadIdx.x;
+    if (l >= nlines) return;
+    const int s0 = start[l], s1 = (l + 1 < nlines) ? start[l + 1] : nvalid;
+    double Q = 0.0, W = 0.0, cx = 0.0, cy = 0.0;
+    for (int s = s0; s < s1; ++s) {
+        const int c = idx[s];
+        const double qc = q[c], w = fabs(qc);
+        Q += qc;
+        W += w;
+        cx += w * qx[c];
+        cy += w * qy[c];
+    }
+    const unsigned v = key[s0];
+    const int i = (int)(v % (unsigned)g.n[0]);
+    const int j = (int)((v / (unsigned)g.n[0]) % (unsigned)g.n[1]);
+    const int k = (int)(v / ((unsigned)g.n[0] * (unsigned)g.n[1]));
+    const double x = W > 0.0 ? cx / W : g.origin[0] + (i + 0.5) * g.step[0];
+    const double y = W > 0.0 ? cy / W : g.origin[1] + (j + 0.5) * g.step[1];
+    const double z0 = g.origin[2] + k * g.step[2];
+    double *o = lines + 7 * (size_t)l;
+    o[0] = x;
+    o[1] = y;
+    o[2] = z0;
+    o[3] = x;
+    o[4] = y;
+    o[5] = z0 + g.step[2];
+    o[6] = Q / g.step[2];
+}
+
+// phi, E of nl segments (7 doubles each: a, b, lambda) at m points, one lane
+// per point, segments through LDS; k_e applied at the end.  Potential in
+// the form ln((r_B + s_B)/(r_A + s_A)) or ln((r_A - s_A)/(r_B - s_B)),
+// whichever has no cancellation, with r + s = rho^2/(r - s) for s < 0; the
+// perpendicular field factor (s_B/r_B - s_A/r_A)/rho^2 as
+// (s_B^2 - s_A^2)/((s_B r_A + s_A r_B) r_A r_B) when P lies beyond an end
+// (s_A s_B > 0), where the plain form cancels.  A point on a segment gets
+// the principal value 0 for the perpendicular field.
+__global__ __launch_bounds__(kLB) void k_line_field(const double *__restrict__ lines, int nl,
+                                                    const double *__restrict__ px, const double *__restrict__ py,
+                                                    const double *__restrict__ pz, int m, double *__restrict__ phi,
+                                                    double *__restrict__ ex, double *__restrict__ ey,
+                                                    double *__restrict__ ez)
+{
+    __shared__ double t[kLB * 7];
+    const int i = blockIdx.x * kLB + threadIdx.x;
+    const bool act = i < m;
+    const double P0 = act ? px[i] : 0.0, P1 = act ? py[i] : 0.0, P2 = act ? pz[i] : 0.0;
+    double ap = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int base = 0; base < nl; base += kLB) {
+        const int cnt = min(kLB, nl - base);
+        __syncthreads();
+        for (int k = threadIdx.x; k < cnt * 7; k += kLB) t[k] = lines[(size_t)base * 7 + k];
+        __syncthreads();
+        for (int l = 0; l < cnt; ++l) {
+            const double *s = t + 7 * l;
+            const double d0 = s[3] - s[0], d1 = s[4] - s[1], d2 = s[5] - s[2];
+            const double L = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const double t0 = d0 / L, t1 = d1 / L, t2 = d2 / L;
+            const double q0 = P0 - s[0], q1 = P1 - s[1], q2 = P2 - s[2];
+            const double along = q0 * t0 + q1 * t1 + q2 * t2;
+            const double p0 = q0 - along * t0, p1 = q1 - along * t1, p2 = q2 - along * t2;
+            const double rho2 = p0 * p0 + p1 * p1 + p2 * p2;
+            const double sA = -along, sB = L - along;
+            const double rA = sqrt(q0 * q0 + q1 * q1 + q2 * q2);
+            const double b0 = P0 - s[3], b1 = P1 - s[4], b2 = P2 - s[5];
+            const double rB = sqrt(b0 * b0 + b1 * b1 + b2 * b2);
+            double lg;
+            if (sA + sB >= 0.0) {
+                const double den = sA >= 0.0 ? rA + sA : rho2 / (rA - sA);
+                lg = log((rB + sB) / den);
+            } else {
+                const double den = sB <= 0.0 ? rB - sB : rho2 / (rB + sB);
+                lg = log((rA - sA) / den);
+            }
+            double gp;
+            if (sA * sB > 0.0)
+                gp = (sB - sA) * (sB + sA) / ((sB * rA + sA * rB) * rA * rB);
+            else
+                gp = rho2 > 0.0 ? (sB / rB - sA / rA) / rho2 : 0.0;
+            const double gt = 1.0 / rB - 1.0 / rA;
+            const double lam = s[6];
+            ap = fma(lam, lg, ap);
+            a0 = fma(lam, fma(gp, p0, gt * t0), a0);
+            a1 = fma(lam, fma(gp, p1, gt * t1), a1);
+            a2 = fma(lam, fma(gp, p2, gt * t2), a2);
+        }
+    }
+    if (act) {
+        if (phi) phi[i] = kKe * ap;
+        if (ex) ex[i] = kKe * a0;
+        if (ey) ey[i] = kKe * a1;
+        if (ez) ez[i] = kKe * a2;
+    }
+}
+
+static size_t align256l(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// workspace: keys in/out, idx in/out, flags, positions, starts, nvalid, cub scratch
+hipError_t voxel_lines(const double *qx, const double *qy, const double *qz, const double *q, int nq,
+                       const GridArgs &g, double *lines, int64_t max_lines, int64_t *nlines, int64_t *outside,
+                       hipStream_t s)
+{
+    *nlines = 0;
+    if (outside) *outside = 0;
+    if (nq <= 0) return hipSuccess;
+    size_t sort_b = 0, scan_b = 0;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, sort_b, (unsigned *)nullptr, (unsigned *)nullptr,
+                                                      (int *)nullptr, (int *)nullptr, nq, 0, 32, s);
+    if (e != hipSuccess) return e;
+    e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_b, (int *)nullptr, (int *)nullptr, nq, s);
+    if (e != hipSuccess) return e;
+    const size_t n4 = align256l((size_t)nq * 4);
+    const size_t total = 7 * n4 + 256 + align256l(sort_b) + align256l(scan_b);
+    void *ws = nullptr;
+    if ((e = hipMallocAsync(&ws, total, s)) != hipSuccess) return e;
+    char *w = static_cast<char *>(ws);
+    unsigned *kin = reinterpret_cast<unsigned *>(w), *kout = reinterpret_cast<unsigned *>(w + n4);
+    int *iin = reinterpret_cast<int *>(w + 2 * n4), *iout = reinterpret_cast<int *>(w + 3 * n4);
+    int *flag = reinterpret_cast<int *>(w + 4 * n4), *pos = reinterpret_cast<int *>(w + 5 * n4);
+    int *start = reinterpret_cast<int *>(w + 6 * n4), *nvalid = reinterpret_cast<int *>(w + 7 * n4);
+    void *sortw = w + 7 * n4 + 256, *scanw = w + 7 * n4 + 256 + align256l(sort_b);
+    const unsigned gq = (unsigned)((nq + kLB - 1) / kLB);
+    int hv[2] = {0, 0};
+    hipLaunchKernelGGL(k_voxel_keys, dim3(gq), dim3(kLB), 0, s, qx, qy, qz, nq, g, kin, iin);
+    e = hipcub::DeviceRadixSort::SortPairs(sortw, sort_b, kin, kout, iin, iout, nq, 0, 32, s);
+    if (e == hipSuccess) e = hipMemsetAsync(nvalid, 0, sizeof(int), s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_run_starts, dim3(gq), dim3(kLB), 0, s, kout, nq, flag, nvalid);
+        e = hipcub::DeviceScan::ExclusiveSum(scanw, scan_b, flag, pos, nq, s);
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_run_index, dim3(gq), dim3(kLB), 0, s, flag, pos, nq, start);
+        // lines = pos[nq-1] + flag[nq-1]; nvalid from the device
+        int last[2];
+        e = hipMemcpyAsync(&last[0], pos + nq - 1, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&last[1], flag + nq - 1, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&hv[1], nvalid, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        hv[0] = last[0] + last[1];
+    }
+    if (e == hipSuccess) {
+        *nlines = hv[0];
+        if (outside) *outside = nq - hv[1];
+        if (hv[0] <= max_lines && hv[0] > 0 && lines)
+            hipLaunchKernelGGL(k_make_lines, dim3((unsigned)((hv[0] + kLB - 1) / kLB)), dim3(kLB), 0, s, kout, iout,
+                               start, hv[0], hv[1], qx, qy, q, g, lines);
+        e = hipGetLastError();
+    }
+    hipError_t e2 = hipFreeAsync(ws, s);
+    return e != hipSuccess ? e : e2;
+}
+
+void launch_line_field(const double *lines, int64_t nl, const double *px, const double *py, const double *pz,
+                       int64_t m, double *phi, double *ex, double *ey, double *ez, hipStream_t s)
+{
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_line_field, dim3((unsigned)((m + kLB - 1) / kLB)), dim3(kLB), 0, s, lines, (int)nl, px, py,
+                       pz, (int)m, phi, ex, ey, ez);
+}
+
+}  // namespace nebem

@@ -95,6 +95,14 @@ void launch_fastvol_interp(const GridArgs &g, const double *values, const double
                            const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
                            hipStream_t s);
 
+// Point charges -> line charges (line_kernels.hip): lines (7 doubles each)
+// written only when *nlines <= max_lines; synchronises the stream.
+hipError_t voxel_lines(const double *qx, const double *qy, const double *qz, const double *q, int nq,
+                       const GridArgs &g, double *lines, int64_t max_lines, int64_t *nlines, int64_t *outside,
+                       hipStream_t s);
+void launch_line_field(const double *lines, int64_t nl, const double *px, const double *py, const double *pz,
+                       int64_t m, double *phi, double *ex, double *ey, double *ez, hipStream_t s);
+
 // o_c[i] += add[c m + i] for each non-null o_c
 void launch_add4(const double *add, int64_t m, double *o0, double *o1, double *o2, double *o3, hipStream_t s);
 

@@ -312,6 +312,42 @@ def test_fastvol_build_and_error_vs_direct(nb, plates_ref):
     assert ephi < 2.5e-3 and eE < 2.5e-3, (ephi, eE)
 
 
+# ------------------------------------------------ point -> line charges
+
+def test_voxel_lines_match_oracle(nb):
+    """Algorithm 3's reduction against the oracle: same occupied voxels in
+    the same order, same line placement and densities, same dropped count."""
+    rng = np.random.default_rng(71)
+    n = 20000
+    xyz = rng.normal(0, 12e-6, (n, 3))
+    q = np.where(np.arange(n) % 2, 1.0, -1.0) * 1.602176634e-19
+    q[::7] *= 3.0
+    origin, step, shape = (-30e-6, -30e-6, -30e-6), (5e-6, 4e-6, 5e-6), (12, 15, 12)
+    lines, out = nb.voxelize_charges(*(dev(xyz[:, k]) for k in range(3)), dev(q), origin, step, shape)
+    ref, ref_out = oracle.voxel_lines(xyz, q, origin, step, shape)
+    got = lines.cpu().numpy()
+    assert out == ref_out and out > 0
+    assert got.shape == ref.shape
+    np.testing.assert_allclose(got[:, :6], ref[:, :6], rtol=1e-13, atol=1e-12 * 60e-6)  # z = 0 rounds either way
+    np.testing.assert_allclose(got[:, 6], ref[:, 6], rtol=0, atol=1e-12 * np.abs(ref[:, 6]).max())
+
+
+def test_line_field_matches_oracle(nb):
+    """Segment field against the oracle's closed form, at points around,
+    alongside and beyond the ends of the segments."""
+    rng = np.random.default_rng(72)
+    a = rng.uniform(-20e-6, 20e-6, (40, 3))
+    b = a + rng.normal(0, 5e-6, (40, 3))
+    lines = np.column_stack([a, b, rng.normal(0, 1e-12, 40)])
+    pts = rng.uniform(-40e-6, 40e-6, (3000, 3))
+    out = nb.line_field(dev(lines), *(dev(pts[:, k]) for k in range(3)))
+    torch.cuda.synchronize()
+    got = np.column_stack([t.cpu().numpy() for t in out])
+    ref = oracle.line_field(lines, pts)
+    ephi, eE = rel_errors(got, ref)
+    assert ephi < 1e-10 and eE < 1e-10, (ephi, eE)
+
+
 # --------------------------------------------------- Adaptive Modelling
 
 def test_adaptive_matches_oracle(nb):
