@@ -74,6 +74,9 @@ def parse():
     p.add_argument("--adaptive", action="store_true",
                    help="Adaptive Modelling on a periodic strip cell: time and error against the exact sum "
                         "for PrimAfter -1, 5, 3, 2, 1, 0")
+    p.add_argument("--voxel", action="store_true",
+                   help="point-to-line charge reduction (Algorithm 3) of the space-charge cloud: lines, "
+                        "field time at the charges, error against the point-charge field at sample points")
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     return p.parse_args()
@@ -354,6 +357,53 @@ def adaptive_bench(args):
                       "rows": rows}), flush=True)
 
 
+def voxel_bench(args):
+    """Algorithm 3 on the space-charge cloud (10^6 charges, +-e, Gaussian
+    sigma 20 um): line charges for 5 and 10 um voxels over +-100 um, the
+    lines' field at every charge (HIP events) and its error against the
+    point charges' own field at 400 points 30-60 um from the cloud centre
+    (oracle sum on the host)."""
+    import torch
+
+    import oracle
+    import paper_2606_24154_amd as nb
+    from synth import charge_cloud
+
+    dev = torch.device("cuda:0")
+    n = args.charges
+    xyz, q = charge_cloud([0.0, 0.0, 0.0], 20e-6, n, seed=3)
+    qd = [torch.from_numpy(np.ascontiguousarray(xyz[:, k])).to(dev) for k in range(3)]
+    qq = torch.from_numpy(q).to(dev)
+    rng = np.random.default_rng(5)
+    d = rng.normal(size=(400, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    pts = d * rng.uniform(30e-6, 60e-6, (400, 1))
+    ref = oracle.coulomb(pts, xyz, q)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for h in (5e-6, 10e-6):
+        nv = int(round(200e-6 / h))
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        lines, out = nb.voxelize_charges(*qd, qq, (-100e-6,) * 3, (h,) * 3, (nv,) * 3)
+        ev[1].record(stream)
+        f = nb.line_field(lines, *qd)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        pt = [torch.from_numpy(np.ascontiguousarray(pts[:, k])).to(dev) for k in range(3)]
+        got = np.column_stack([t.cpu().numpy() for t in nb.line_field(lines, *pt)])[:, 1:]
+        err = np.linalg.norm(got - ref[:, 1:], axis=1) / np.linalg.norm(ref[:, 1:], axis=1)
+        t_line = ev[1].elapsed_time(ev[2]) * 1e-3
+        rows.append({"voxel_um": h * 1e6, "lines": int(lines.shape[0]), "outside": int(out),
+                     "reduce_ms": ev[0].elapsed_time(ev[1]), "field_at_charges_ms": 1e3 * t_line,
+                     "segment_interactions_per_s": float(lines.shape[0]) * n / t_line,
+                     "E_rel_err_p50": float(np.median(err)), "E_rel_err_max": float(err.max())})
+    print(json.dumps({"metric": "point-to-line charge reduction", "unit": "ms", "n_gpus": 1, "dtype": "f64",
+                      "config": {"workload": f"{n} charges (+-e, Gaussian 20 um), voxel grids over +-100 um; "
+                                             f"E error at 400 points 30-60 um from the centre"},
+                      "rows": rows}), flush=True)
+
+
 def spacecharge_bench(args):
     """Config 3: GEM cell, charges ~ N(hole centre, 20 um), +-e alternating;
     each step = (re-solve every 10th step) + panel field at every charge +
@@ -415,6 +465,9 @@ def main():
         return
     if args.adaptive:
         adaptive_bench(args)
+        return
+    if args.voxel:
+        voxel_bench(args)
         return
     if args.spacecharge:
         spacecharge_bench(args)
