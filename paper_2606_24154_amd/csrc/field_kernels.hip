@@ -160,7 +160,7 @@ struct MixParams {
     double quad2;   // squared distance from which the quadrupole expansion is used
 };
 
-template <int KIND, bool MIXED>
+template <int KIND, bool MIXED, bool HOLE>
 __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, int hole, double X0, double Z0,
                                                  double H0, double aX, double aZ, double aH, double bX, double bZ,
                                                  double bH, bool self, const MixParams &mp, double &sp,
@@ -182,49 +182,56 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
     for (int i1 = -n1; i1 <= n1; ++i1) {
         const double f1 = -(double)i1;
         const double X1 = fma(f1, aX, X0), Z1 = fma(f1, aZ, Z0), H1 = fma(f1, aH, H0);
+        // HOLE: a row that crosses the hole runs as two ranges of i2, so the
+        // inner loop itself carries no test for it
+        const bool cut = HOLE && abs(i1) <= hole;
 #pragma unroll 1
-        for (int i2 = -n2; i2 <= n2; ++i2) {
-            if (hole >= 0 && abs(i1) <= hole && abs(i2) <= hole) continue;  // uniform: whole wave
-            const double f2 = -(double)i2;
-            double X = fma(f2, bX, X1), Z = fma(f2, bZ, Z1);
-            double H = fma(f2, bH, H1);
-            H = (self && i1 == 0 && i2 == 0) ? 0.0 : H;
-            if (MIXED) {
-                const double rc2 = fma(X, X, fma(Z, Z, H * H));
-                if (rc2 >= mp.quad2) {
-                    far_quadrupole<KIND>(X, Z, H, rc2, e.lx, e.lz, e.area, sp, sx, sz, sn, fc);
-                    continue;
+        for (int seg = 0; seg <= (int)cut; ++seg) {
+            const int i2a = seg == 0 ? -n2 : hole + 1;
+            const int i2b = (cut && seg == 0) ? -hole - 1 : n2;
+#pragma unroll 1
+            for (int i2 = i2a; i2 <= i2b; ++i2) {
+                const double f2 = -(double)i2;
+                double X = fma(f2, bX, X1), Z = fma(f2, bZ, Z1);
+                double H = fma(f2, bH, H1);
+                H = (self && i1 == 0 && i2 == 0) ? 0.0 : H;
+                if (MIXED) {
+                    const double rc2 = fma(X, X, fma(Z, Z, H * H));
+                    if (rc2 >= mp.quad2) {
+                        far_quadrupole<KIND>(X, Z, H, rc2, e.lx, e.lz, e.area, sp, sx, sz, sn, fc);
+                        continue;
+                    }
+                    if (rc2 >= mp.low2) {
+                        far_mixed<KIND>(X, Z, H, rc2, e.lx, e.lz, e.area, sp, sx, sz, sn, fc);
+                        continue;
+                    }
+                    X += cxl;
+                    Z += czl;
                 }
-                if (rc2 >= mp.low2) {
-                    far_mixed<KIND>(X, Z, H, rc2, e.lx, e.lz, e.area, sp, sx, sz, sn, fc);
-                    continue;
+                Kern k;
+                const double r0sq = fma(X, X, fma(Z, Z, H * H));
+                if (r0sq >= vfar2) {  // far forms return the potential added to sp
+                    if (KIND == 0)
+                        k = rect_far<true>(X, H, Z, e.lx, e.lz, r0sq, sp);
+                    else
+                        k = rtri_far<true>(X, H, Z, e.lx, e.lz, e.hyp, r0sq, sp);
+                } else if (r0sq >= far2) {
+                    if (KIND == 0)
+                        k = rect_far<false>(X, H, Z, e.lx, e.lz, r0sq, sp);
+                    else
+                        k = rtri_far<false>(X, H, Z, e.lx, e.lz, e.hyp, r0sq, sp);
+                } else {
+                    if (KIND == 0)
+                        k = rect_fp64(X, H, Z, e.lx, e.lz, r0sq);
+                    else
+                        k = rtri_fp64(X, H, Z, e.lx, e.lz, e.hyp, e.ihyp, r0sq);
+                    k.phi += sp;
                 }
-                X += cxl;
-                Z += czl;
+                sp = k.phi;
+                sx += k.ex;
+                sz += k.ez;
+                sn += k.en;
             }
-            Kern k;
-            const double r0sq = fma(X, X, fma(Z, Z, H * H));
-            if (r0sq >= vfar2) {  // far forms return the potential added to sp
-                if (KIND == 0)
-                    k = rect_far<true>(X, H, Z, e.lx, e.lz, r0sq, sp);
-                else
-                    k = rtri_far<true>(X, H, Z, e.lx, e.lz, e.hyp, r0sq, sp);
-            } else if (r0sq >= far2) {
-                if (KIND == 0)
-                    k = rect_far<false>(X, H, Z, e.lx, e.lz, r0sq, sp);
-                else
-                    k = rtri_far<false>(X, H, Z, e.lx, e.lz, e.hyp, r0sq, sp);
-            } else {
-                if (KIND == 0)
-                    k = rect_fp64(X, H, Z, e.lx, e.lz, r0sq);
-                else
-                    k = rtri_fp64(X, H, Z, e.lx, e.lz, e.hyp, e.ihyp, r0sq);
-                k.phi += sp;
-            }
-            sp = k.phi;
-            sx += k.ex;
-            sz += k.ez;
-            sn += k.en;
         }
     }
     if (MIXED) {
@@ -236,7 +243,7 @@ __device__ __forceinline__ void sum_translations(const Elem &e, int n1, int n2, 
 }
 
 // phi', E' (global frame) of one element with all its copies at P.
-template <bool MIXED>
+template <bool MIXED, bool HOLE = false>
 __device__ __forceinline__ void element_copies(const Elem &e, const ImgArgs &img, double Px, double Py, double Pz,
                                                bool self, double near_factor, double &ophi, double &oex,
                                                double &oey, double &oez)
@@ -269,10 +276,10 @@ __device__ __forceinline__ void element_copies(const Elem &e, const ImgArgs &img
         double sp = 0.0, sx = 0.0, sz = 0.0, sn = 0.0;
         const bool s = self && r == 0;
         if (e.kind == 0)
-            sum_translations<0, MIXED>(e, img.n1, img.n2, img.hole, X0, Z0, H0, aX, aZ, aH, bX, bZ, bH, s, mp, sp,
+            sum_translations<0, MIXED, HOLE>(e, img.n1, img.n2, img.hole, X0, Z0, H0, aX, aZ, aH, bX, bZ, bH, s, mp, sp,
                                        sx, sz, sn);
         else
-            sum_translations<1, MIXED>(e, img.n1, img.n2, img.hole, X0, Z0, H0, aX, aZ, aH, bX, bZ, bH, s, mp, sp,
+            sum_translations<1, MIXED, HOLE>(e, img.n1, img.n2, img.hole, X0, Z0, H0, aX, aZ, aH, bX, bZ, bH, s, mp, sp,
                                        sx, sz, sn);
         double gx = sx * e.e1x + sz * e.e2x + sn * e.e3x;
         double gy = sx * e.e1y + sz * e.e2y + sn * e.e3y;
@@ -292,7 +299,7 @@ __device__ __forceinline__ void element_copies(const Elem &e, const ImgArgs &img
 // One workgroup's share of an evaluation: points [base, base + BS) of the
 // m points, all n elements (records drec, densities sigma) and their copies,
 // FP64 sums per lane; outputs scaled by `scale`.
-template <bool MIXED, int BS>
+template <bool MIXED, int BS, bool HOLE = false>
 __device__ __forceinline__ void eval_block(const double *__restrict__ drec, const double *__restrict__ sigma, int n,
                                            const ImgArgs &img, double near_factor, const double *__restrict__ px,
                                            const double *__restrict__ py, const double *__restrict__ pz, int m,
@@ -317,7 +324,7 @@ __device__ __forceinline__ void eval_block(const double *__restrict__ drec, cons
         for (int p = 0; p < cnt; ++p) {
             const Elem e = load_elem(t_rec + p * R_STRIDE);
             double cp, cx, cy, cz;
-            element_copies<MIXED>(e, img, Px, Py, Pz, false, near_factor, cp, cx, cy, cz);
+            element_copies<MIXED, HOLE>(e, img, Px, Py, Pz, false, near_factor, cp, cx, cy, cz);
             const double sg = uni(t_sig[p]);
             aphi = fma(sg, cp, aphi);
             aex = fma(sg, cx, aex);
@@ -336,24 +343,27 @@ __device__ __forceinline__ void eval_block(const double *__restrict__ drec, cons
 // FP64: the default allocation (about 200 VGPRs, two waves per SIMD) keeps every
 // value in registers; a three-wave target made the allocator spill part of
 // the per-element setup to scratch (10.6 GB of HBM writes per 10^6-point
-// launch) for no measurable gain.
+// launch) for no measurable gain.  HOLE: img.hole is honoured (a separate
+// instantiation, so the plain launch carries no test for it).
+template <bool HOLE>
 __global__ __launch_bounds__(kBlock) void k_eval_fp64(
     const double *__restrict__ drec, const double *__restrict__ sigma, int n, ImgArgs img, double near_factor,
     const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz, int m,
     double *__restrict__ phi, double *__restrict__ ex, double *__restrict__ ey, double *__restrict__ ez)
 {
-    eval_block<false, kBlock>(drec, sigma, n, img, near_factor, px, py, pz, m, blockIdx.x * kBlock, kKe, phi, ex, ey,
+    eval_block<false, kBlock, HOLE>(drec, sigma, n, img, near_factor, px, py, pz, m, blockIdx.x * kBlock, kKe, phi, ex, ey,
                               ez);
 }
 
 // Mixed: three waves per SIMD (13 % faster than two): the allocator spills a
 // few values of the per-element setup, outside the per-copy loop.
+template <bool HOLE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_eval_mixed(
     const double *__restrict__ drec, const double *__restrict__ sigma, int n, ImgArgs img, double near_factor,
     const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz, int m,
     double *__restrict__ phi, double *__restrict__ ex, double *__restrict__ ey, double *__restrict__ ez)
 {
-    eval_block<true, kBlock>(drec, sigma, n, img, near_factor, px, py, pz, m, blockIdx.x * kBlock, kKe, phi, ex, ey,
+    eval_block<true, kBlock, HOLE>(drec, sigma, n, img, near_factor, px, py, pz, m, blockIdx.x * kBlock, kKe, phi, ex, ey,
                              ez);
 }
 
@@ -363,12 +373,11 @@ void launch_eval(const double *drec, const double *sigma, int64_t n, const ImgAr
 {
     if (m <= 0) return;
     const unsigned g = (unsigned)((m + kBlock - 1) / kBlock);
-    if (mixed)
-        hipLaunchKernelGGL(k_eval_mixed, dim3(g), dim3(kBlock), 0, s, drec, sigma, (int)n, img, near_factor, px, py,
-                           pz, (int)m, phi, ex, ey, ez);
-    else
-        hipLaunchKernelGGL(k_eval_fp64, dim3(g), dim3(kBlock), 0, s, drec, sigma, (int)n, img, near_factor, px, py,
-                           pz, (int)m, phi, ex, ey, ez);
+    const bool hole = img.hole >= 0;
+    auto k = mixed ? (hole ? k_eval_mixed<true> : k_eval_mixed<false>)
+                   : (hole ? k_eval_fp64<true> : k_eval_fp64<false>);
+    hipLaunchKernelGGL(k, dim3(g), dim3(kBlock), 0, s, drec, sigma, (int)n, img, near_factor, px, py, pz, (int)m, phi,
+                       ex, ey, ez);
 }
 
 // out[c][i] += add[c m + i] for the non-null outputs

@@ -43,7 +43,8 @@ struct ImgArgs {
     int axes[8];
     int nref;
     int n1, n2;
-    int hole;  // >= 0: the translations with |i1| <= hole and |i2| <= hole are left out (-1: none)
+    int hole;  // >= 0: the translations with |i1| <= hole and |i2| <= hole are left out (-1: none);
+               // honoured by launch_eval only, the other launchers take every copy
 };
 
 // thread-local error text
