@@ -262,7 +262,8 @@ nebem_status nebem_voxelize_charges(const double *qx, const double *qy, const do
 /* phi and E (k_e lambda times the exact segment integrals) of nlines
  * uniformly charged segments (layout as above) at m points; outputs as in
  * nebem_eval.  A point on a segment gets infinite phi and the principal
- * value 0 for the field across the segment. */
+ * value 0 for the field across the segment; at a segment's end the results
+ * are not finite.  A segment of zero length contributes nothing. */
 nebem_status nebem_line_field(const double *lines, int64_t nlines, const double *px, const double *py,
                               const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
                               hipStream_t stream);

@@ -13,6 +13,7 @@
 
 #include <cmath>
 
+#include "fastmath_fp64.hpp"
 #include "nebem_internal.hpp"
 
 namespace nebem {
@@ -93,21 +94,40 @@ __global__ __launch_bounds__(kLB) void k_make_lines(const unsigned *__restrict__
     o[6] = Q / g.step[2];
 }
 
+// 1/sqrt(x), x > 0: hardware estimate and two Newton steps
+__device__ __forceinline__ double rsq64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = fma(y, fma(-hx * y, y, 0.5), y);
+    return fma(y, fma(-hx * y, y, 0.5), y);
+}
+
 // phi, E of nl segments (7 doubles each: a, b, lambda) at m points, one lane
-// per point, segments through LDS; k_e applied at the end.  Potential in
-// the form ln((r_B + s_B)/(r_A + s_A)) or ln((r_A - s_A)/(r_B - s_B)),
-// whichever has no cancellation, with r + s = rho^2/(r - s) for s < 0; the
-// perpendicular field factor (s_B/r_B - s_A/r_A)/rho^2 as
-// (s_B^2 - s_A^2)/((s_B r_A + s_A r_B) r_A r_B) when P lies beyond an end
-// (s_A s_B > 0), where the plain form cancels.  A point on a segment gets
-// the principal value 0 for the perpendicular field.
+// per point; k_e applied at the end.  Each tile of segments is staged in LDS
+// as (a, unit direction t, length L, lambda), computed once per workgroup.
+//
+// With s_A = (a - P).t, s_B = s_A + L, rho the distance of P from the line
+// and r_A, r_B its distances from the ends (r^2 = rho^2 + s^2), every
+// quantity is formed without cancellation:
+//   r_B - r_A = L (s_A + s_B)/(r_A + r_B);
+//   phi/(k_e lambda) = ln((r_B + s_B)/(r_A + s_A)) = ln(1 + F/D), with
+//     F = L (r_A + r_B + |s_A + s_B|)/(r_A + r_B) and D = r_A + s_A if
+//     s_A + s_B >= 0, else (mirrored) D = r_B - s_B; a D of the form r + s
+//     with s < 0 taken as rho^2/(r - s);
+//   1/r_B - 1/r_A = -L (s_A + s_B)/((r_A + r_B) r_A r_B)  (along t);
+//   (s_B/r_B - s_A/r_A)/rho^2 (across, along P - foot) as
+//     L (s_A + s_B)/((s_B r_A + s_A r_B) r_A r_B) when P is level with or
+//     beyond an end (s_A s_B >= 0).
+// A point on a segment gets infinite phi and the principal value 0 for the
+// field across it; at an end the results are not finite.
 __global__ __launch_bounds__(kLB) void k_line_field(const double *__restrict__ lines, int nl,
                                                     const double *__restrict__ px, const double *__restrict__ py,
                                                     const double *__restrict__ pz, int m, double *__restrict__ phi,
                                                     double *__restrict__ ex, double *__restrict__ ey,
                                                     double *__restrict__ ez)
 {
-    __shared__ double t[kLB * 7];
+    __shared__ double t[kLB * 8];
     const int i = blockIdx.x * kLB + threadIdx.x;
     const bool act = i < m;
     const double P0 = act ? px[i] : 0.0, P1 = act ? py[i] : 0.0, P2 = act ? pz[i] : 0.0;
@@ -115,36 +135,51 @@ __global__ __launch_bounds__(kLB) void k_line_field(const double *__restrict__ l
     for (int base = 0; base < nl; base += kLB) {
         const int cnt = min(kLB, nl - base);
         __syncthreads();
-        for (int k = threadIdx.x; k < cnt * 7; k += kLB) t[k] = lines[(size_t)base * 7 + k];
+        if ((int)threadIdx.x < cnt) {
+            const double *g = lines + 7 * (size_t)(base + threadIdx.x);
+            const double d0 = g[3] - g[0], d1 = g[4] - g[1], d2 = g[5] - g[2];
+            const double L = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const double iL = L > 0.0 ? 1.0 / L : 0.0;  // a point segment carries no charge
+            double *o = t + 8 * threadIdx.x;
+            o[0] = g[0];
+            o[1] = g[1];
+            o[2] = g[2];
+            o[3] = L > 0.0 ? d0 * iL : 0.0;
+            o[4] = L > 0.0 ? d1 * iL : 0.0;
+            o[5] = L > 0.0 ? d2 * iL : 1.0;
+            o[6] = L;
+            o[7] = L > 0.0 ? g[6] : 0.0;
+        }
         __syncthreads();
         for (int l = 0; l < cnt; ++l) {
-            const double *s = t + 7 * l;
-            const double d0 = s[3] - s[0], d1 = s[4] - s[1], d2 = s[5] - s[2];
-            const double L = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            const double t0 = d0 / L, t1 = d1 / L, t2 = d2 / L;
+            const double *s = t + 8 * l;
             const double q0 = P0 - s[0], q1 = P1 - s[1], q2 = P2 - s[2];
-            const double along = q0 * t0 + q1 * t1 + q2 * t2;
-            const double p0 = q0 - along * t0, p1 = q1 - along * t1, p2 = q2 - along * t2;
-            const double rho2 = p0 * p0 + p1 * p1 + p2 * p2;
+            const double t0 = s[3], t1 = s[4], t2 = s[5], L = s[6], lam = s[7];
+            const double along = fma(q0, t0, fma(q1, t1, q2 * t2));
+            const double p0 = fma(-along, t0, q0), p1 = fma(-along, t1, q1), p2 = fma(-along, t2, q2);
+            const double rho2 = fma(p0, p0, fma(p1, p1, p2 * p2));
             const double sA = -along, sB = L - along;
-            const double rA = sqrt(q0 * q0 + q1 * q1 + q2 * q2);
-            const double b0 = P0 - s[3], b1 = P1 - s[4], b2 = P2 - s[5];
-            const double rB = sqrt(b0 * b0 + b1 * b1 + b2 * b2);
-            double lg;
-            if (sA + sB >= 0.0) {
-                const double den = sA >= 0.0 ? rA + sA : rho2 / (rA - sA);
-                lg = log((rB + sB) / den);
-            } else {
-                const double den = sB <= 0.0 ? rB - sB : rho2 / (rB + sB);
-                lg = log((rA - sA) / den);
-            }
-            double gp;
-            if (sA * sB > 0.0)
-                gp = (sB - sA) * (sB + sA) / ((sB * rA + sA * rB) * rA * rB);
-            else
-                gp = rho2 > 0.0 ? (sB / rB - sA / rA) / rho2 : 0.0;
-            const double gt = 1.0 / rB - 1.0 / rA;
-            const double lam = s[6];
+            const double rA2 = fma(sA, sA, rho2), rB2 = fma(sB, sB, rho2);
+            const double irA = rsq64(rA2), irB = rsq64(rB2);
+            const double rA = rA2 * irA, rB = rB2 * irB;
+            const double rs = rA + rB, ss = sA + sB;
+            // potential
+            const bool formA = ss >= 0.0;  // D built on end A, else mirrored onto end B
+            const double u = formA ? sA : -sB, v = formA ? rA : rB;
+            const bool outside = u >= 0.0;  // level with or beyond an end: s_A s_B >= 0
+            const double F = L * (rs + fabs(ss));
+            const double nn = outside ? F : F * (v - u);
+            const double dd = rs * (outside ? v + u : rho2);
+            const double lg = dd > 0.0 ? log1p_ratio(nn, dd) : __builtin_inf();
+            // field: one reciprocal serves 1/(r_A + r_B) and the across factor
+            const double c = L * ss * irA * irB;
+            double gden = outside ? fma(sB, rA, sA * rB) : rho2;
+            const bool gok = gden != 0.0;
+            gden = gok ? gden : 1.0;
+            const double R = rcp64(gden * rs);
+            const double gnum = outside ? c : fma(sB, irB, -(sA * irA));
+            const double gp = gok ? gnum * (rs * R) : 0.0;
+            const double gt = -c * (gden * R);
             ap = fma(lam, lg, ap);
             a0 = fma(lam, fma(gp, p0, gt * t0), a0);
             a1 = fma(lam, fma(gp, p1, gt * t1), a1);

@@ -348,6 +348,37 @@ def test_line_field_matches_oracle(nb):
     assert ephi < 1e-10 and eE < 1e-10, (ephi, eE)
 
 
+def test_line_field_single_segment_regimes(nb):
+    """One segment, pointwise against the oracle: far away (10 to 10^4
+    lengths), near the axis beyond either end, level with an end, and close
+    beside it -- the places where the plain forms cancel."""
+    rng = np.random.default_rng(73)
+    a = np.array([1e-6, -2e-6, 3e-6])
+    t = rng.normal(size=3)
+    t /= np.linalg.norm(t)
+    L = 5e-6
+    b = a + L * t
+    perp = np.cross(t, [0.3, 0.5, 0.8])
+    perp /= np.linalg.norm(perp)
+    mid = 0.5 * (a + b)
+    d = rng.normal(size=(400, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    far = mid + d * (L * 10 ** rng.uniform(1, 4, (400, 1)))
+    k = L * 10 ** rng.uniform(-1, 1, (200, 1))
+    axis_a = a - k * t + 1e-3 * L * perp
+    axis_b = b + k * t - 1e-3 * L * perp
+    level = a + L * 10 ** rng.uniform(-2, 1, (200, 1)) * perp
+    beside = a + rng.uniform(0.05, 0.95, (200, 1)) * L * t + L * 10 ** rng.uniform(-3, 0, (200, 1)) * perp
+    pts = np.concatenate([far, axis_a, axis_b, level, beside])
+    lines = np.concatenate([a, b, [3e-12]])[None, :]
+    out = nb.line_field(dev(lines), *(dev(pts[:, k]) for k in range(3)))
+    torch.cuda.synchronize()
+    got = np.column_stack([t.cpu().numpy() for t in out])
+    ref = oracle.line_field(lines, pts)
+    ephi, eE = rel_errors(got, ref, floor=0.0)
+    assert ephi < 1e-10 and eE < 1e-10, (ephi, eE)
+
+
 # --------------------------------------------------- Adaptive Modelling
 
 def test_adaptive_matches_oracle(nb):
