@@ -289,24 +289,18 @@ nebem_status nebem_eval_adaptive(const nebem_panels *panels, const nebem_panels 
     if (prim_after >= ia.n1 && prim_after >= ia.n2) return NEBEM_OK;  // no far copies
     if (np == 0) return fail(NEBEM_EINVAL, "eval_adaptive: no primitives");
     // primitive-averaged densities: sigma_p = sum_{j in p} sigma_j A_j / A_p
-    DevBuf prec;
+    DevBuf prec, dsbar, dbad, far;
     if ((st = derive(prims, stream, prec))) return st;
-    std::vector<double> hrec((size_t)n * R_STRIDE), hprec((size_t)np * R_STRIDE), hsig(n);
-    std::vector<int32_t> hmap(n);
-    NEBEM_HIP(hipMemcpyAsync(hrec.data(), drec.p, hrec.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
-    NEBEM_HIP(hipMemcpyAsync(hprec.data(), prec.p, hprec.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
-    NEBEM_HIP(hipMemcpyAsync(hsig.data(), sigma, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, stream));
-    NEBEM_HIP(hipMemcpyAsync(hmap.data(), elem_prim, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-    NEBEM_HIP(hipStreamSynchronize(stream));
-    std::vector<double> q(np, 0.0), sbar(np);
-    for (int64_t j = 0; j < n; ++j) {
-        if (hmap[j] < 0 || hmap[j] >= np) return fail(NEBEM_EINVAL, "eval_adaptive: elem_prim out of range");
-        q[hmap[j]] += hsig[j] * hrec[(size_t)j * R_STRIDE + R_AREA];
-    }
-    for (int64_t p = 0; p < np; ++p) sbar[p] = q[p] / hprec[(size_t)p * R_STRIDE + R_AREA];
-    DevBuf dsbar, far;
     NEBEM_HIP(dsbar.alloc((size_t)np * sizeof(double), stream));
-    NEBEM_HIP(hipMemcpyAsync(dsbar.p, sbar.data(), (size_t)np * sizeof(double), hipMemcpyHostToDevice, stream));
+    NEBEM_HIP(dbad.alloc(sizeof(int), stream));
+    NEBEM_HIP(hipMemsetAsync(dbad.p, 0, sizeof(int), stream));
+    launch_prim_density(drec.as<double>(), sigma, elem_prim, n, prec.as<double>(), np, dsbar.as<double>(),
+                        static_cast<int *>(dbad.p), stream);
+    NEBEM_HIP(hipGetLastError());
+    int hbad = 0;
+    NEBEM_HIP(hipMemcpyAsync(&hbad, dbad.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+    NEBEM_HIP(hipStreamSynchronize(stream));
+    if (hbad) return fail(NEBEM_EINVAL, "eval_adaptive: elem_prim out of range");
     NEBEM_HIP(far.alloc((size_t)4 * m * sizeof(double), stream));
     ImgArgs farimg = ia;
     farimg.hole = prim_after;
@@ -318,7 +312,7 @@ nebem_status nebem_eval_adaptive(const nebem_panels *panels, const nebem_panels 
         return st;
     launch_add4(f, m, phi, ex, ey, ez, stream);
     NEBEM_HIP(hipGetLastError());
-    NEBEM_HIP(hipStreamSynchronize(stream));  // host vectors above must outlive the copy of sbar
+    NEBEM_HIP(hipStreamSynchronize(stream));  // the scratch buffers are freed on return
     return NEBEM_OK;
 }
 

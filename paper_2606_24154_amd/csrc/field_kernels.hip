@@ -401,6 +401,37 @@ void launch_add4(const double *add, int64_t m, double *o0, double *o1, double *o
                        o2, o3);
 }
 
+// Adaptive Modelling's primitive densities: sbar[p] = (sum of sigma_j A_j
+// over the elements j with map[j] == p) / A_p, one lane per primitive,
+// elements in index order (a fixed summation order).  *bad is set when a map
+// entry is outside [0, np).
+__global__ __launch_bounds__(kBlock) void k_prim_density(const double *__restrict__ drec,
+                                                         const double *__restrict__ sigma,
+                                                         const int32_t *__restrict__ map, int n,
+                                                         const double *__restrict__ prec, int np,
+                                                         double *__restrict__ sbar, int *__restrict__ bad)
+{
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    const bool checker = p == 0;
+    double q = 0.0;
+    int oob = 0;
+    for (int j = 0; j < n; ++j) {
+        const int mj = map[j];
+        oob |= (mj < 0 || mj >= np) ? 1 : 0;
+        if (mj == p) q = fma(sigma[j], drec[(size_t)j * R_STRIDE + R_AREA], q);
+    }
+    if (checker && oob) *bad = 1;
+    if (p < np) sbar[p] = q / prec[(size_t)p * R_STRIDE + R_AREA];
+}
+
+void launch_prim_density(const double *drec, const double *sigma, const int32_t *map, int64_t n,
+                         const double *prec, int64_t np, double *sbar, int *bad, hipStream_t s)
+{
+    if (np <= 0) return;
+    hipLaunchKernelGGL(k_prim_density, dim3((unsigned)((np + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, drec, sigma,
+                       map, (int)n, prec, (int)np, sbar, bad);
+}
+
 // ------------------------------------------------- several sigma columns
 // Weighting fields: K density columns over the same elements and points
 // (column k of sigma at sigma + k n).  Each element's copies are summed once

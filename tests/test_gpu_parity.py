@@ -409,6 +409,23 @@ def test_adaptive_matches_oracle(nb):
                 assert torch.equal(out[c], exact[c]), (k, c)
 
 
+def test_adaptive_rejects_bad_primitive_map(nb):
+    """An element mapped to a primitive index outside [0, np) is refused
+    (the map is checked on the device while the densities are summed)."""
+    from synth import strip_cell
+    e, p, emap = strip_cell(n_img=2, sub_u=2, sub_w=4)
+    sigma = np.full(e.n, 1e-9)
+    pts = uniform_points(e.box_lo, e.box_hi, 64, 62)
+    dp, dpp = nb.DevicePanels.from_geometry(e, DEV), nb.DevicePanels.from_geometry(p, DEV)
+    pt = [dev(pts[:, k]) for k in range(3)]
+    for bad in (p.n, -1):
+        m = emap.copy()
+        m[e.n // 2] = bad
+        with pytest.raises(nb.NebemError) as err:
+            nb.eval_points_adaptive(dp, dpp, torch.from_numpy(m).to(DEV), 0, dev(sigma), *pt)
+        assert err.value.code == nb.NEBEM_EINVAL
+
+
 # ---------------------------------------------------- copies and mirrors
 
 def _mixed_geometry(rng, n=24, bc_mix=True):
