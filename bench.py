@@ -61,6 +61,9 @@ def parse():
                    help="instead of the default step: K steps of the dynamic space-charge loop on the GEM "
                         "cell with 10^6 charges (first step re-solves)")
     p.add_argument("--charges", type=int, default=1_000_000)
+    p.add_argument("--sc-voxel-um", type=float, default=0.0, metavar="H",
+                   help="with --spacecharge: charges reduced to line charges on H um voxels over +-100 um "
+                        "(Algorithm 3) in place of the all-pairs sum")
     p.add_argument("--serve-matrix", type=int, default=0, metavar="R",
                    help="serving study instead of the step: R requests over the plates, GEM and double-THGEM "
                         "geometries, FP64 saturation measured first, then loads 0.5/0.8/0.95 in FP64 and mixed")
@@ -422,7 +425,8 @@ def voxel_bench(args):
 def spacecharge_bench(args):
     """Config 3: GEM cell, charges ~ N(hole centre, 20 um), +-e alternating;
     each step = (re-solve every 10th step) + panel field at every charge +
-    all-pairs charge field + Euler move."""
+    all-pairs charge field (or, with --sc-voxel-um, the field of the
+    charges' line charges) + Euler move."""
     import torch
 
     import paper_2606_24154_amd as nb
@@ -445,11 +449,18 @@ def spacecharge_bench(args):
     ev[1].record(stream)
     torch.cuda.synchronize()
     t_panel = ev[0].elapsed_time(ev[1]) * 1e-3
-    times = []
+    times, nlines = [], []
+    h = args.sc_voxel_um * 1e-6
+    if h > 0:
+        nv = int(round(200e-6 / h))
+        vox = ([c - 100e-6 for c in centre], (h,) * 3, (nv,) * 3)
     for k in range(args.spacecharge):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ses.spacecharge_step(qx, qy, qz, qd, k, E=E)
+        if h > 0:
+            nlines.append(ses.spacecharge_step_lines(qx, qy, qz, qd, k, *vox, E=E)[1])
+        else:
+            ses.spacecharge_step(qx, qy, qz, qd, k, E=E)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     nq = len(q)
@@ -459,11 +470,15 @@ def spacecharge_bench(args):
     rec = {"metric": "space-charge step time", "value": 1e3 * t_plain, "unit": "ms/step",
            "higher_is_better": False, "n_gpus": 1, "steps": args.spacecharge, "dtype": args.precision,
            "config": {"workload": f"gem_cell + {nq} point charges (+-e), N={geom.n}, C={geom.images.count}, "
-                                  f"dt=1 ps, mobility 1e-4 m^2/Vs, re-solve every 10 steps"},
+                                  f"dt=1 ps, mobility 1e-4 m^2/Vs, re-solve every 10 steps"
+                                  + (f"; charges as line charges on {args.sc_voxel_um} um voxels" if h > 0 else "")},
            "step_ms": [1e3 * t for t in times], "panel_part_ms": 1e3 * t_panel,
            "panel_interactions_per_s": panel_inter / t_panel,
-           "pair_interactions_per_s": pairs / max(t_plain - t_panel, 1e-9),
            "resolve_step_ms": 1e3 * times[0]}
+    if h > 0:
+        rec["lines"] = nlines
+    else:
+        rec["pair_interactions_per_s"] = pairs / max(t_plain - t_panel, 1e-9)
     print(json.dumps(rec), flush=True)
 
 

@@ -248,7 +248,8 @@ nebem_status nebem_fastvol_interp(const nebem_grid *grid, const double *values, 
  * charges outside are dropped and counted in *outside, host, may be NULL);
  * every occupied voxel becomes one segment parallel to z over the voxel's
  * z extent, at the |q|-weighted mean x, y of its charges (the voxel centre
- * if those weights sum to zero), with line density = total charge / dz.
+ * if those weights sum to zero; a lone charge's line passes exactly through
+ * it), with line density = total charge / dz.
  * lines: 7 doubles per line (ax, ay, az, bx, by, bz, lambda), device,
  * max_lines of them; *nlines (host) receives the number of occupied voxels,
  * lines in increasing voxel index.  EINVAL when *nlines > max_lines
@@ -317,6 +318,20 @@ nebem_status nebem_session_eval(nebem_session *s, const double *px, const double
 nebem_status nebem_spacecharge_step(nebem_session *s, double *qx, double *qy, double *qz, const double *q,
                                     int64_t nq, int32_t step_index, double *ex, double *ey, double *ez,
                                     hipStream_t stream);
+
+/* The same step with the charges reduced to line charges first (Algorithm 3,
+ * the cheaper source of Sec. 4.2; voxel grid `vox` and line layout as in
+ * nebem_voxelize_charges): the lines' potential / normal field at the
+ * collocation points replaces the point charges' in step 1 and their field
+ * (nebem_line_field) the charge-charge sum in step 2.  Charges outside the
+ * grid add no field but still move.  A charge alone in its voxel lies on its
+ * own line and gets the principal value 0 of that line's field across it.
+ * *nlines (may be NULL) receives the number of lines.  The session keeps
+ * the lines (56 B per occupied voxel) and a 32 B-per-charge buffer.
+ * Synchronises `stream`. */
+nebem_status nebem_spacecharge_step_lines(nebem_session *s, double *qx, double *qy, double *qz, const double *q,
+                                          int64_t nq, int32_t step_index, const nebem_grid *vox, double *ex,
+                                          double *ey, double *ez, int64_t *nlines, hipStream_t stream);
 
 /* ----------------------------------------------------------------- serving
  * Continuous-batching evaluation service over resident sessions.  Clients

@@ -32,6 +32,7 @@ EXPORTED = (
     "nebem_fastvol_interp", "nebem_voxelize_charges", "nebem_line_field",
     "nebem_session_create", "nebem_session_destroy", "nebem_session_n", "nebem_session_sigma",
     "nebem_session_solve", "nebem_session_condest", "nebem_session_eval", "nebem_spacecharge_step",
+    "nebem_spacecharge_step_lines",
     "nebem_last_error",
     "nebem_server_default_options", "nebem_server_create", "nebem_server_submit", "nebem_server_wait",
     "nebem_server_stats", "nebem_server_destroy",
@@ -138,6 +139,9 @@ def _load():
     lib.nebem_session_eval.restype = i32
     lib.nebem_spacecharge_step.argtypes = [P, P, P, P, P, i64, i32, P, P, P, P]
     lib.nebem_spacecharge_step.restype = i32
+    lib.nebem_spacecharge_step_lines.argtypes = [P, P, P, P, P, i64, i32, ctypes.POINTER(GridC), P, P, P,
+                                                 ctypes.POINTER(i64), P]
+    lib.nebem_spacecharge_step_lines.restype = i32
     lib.nebem_server_default_options.argtypes = [ctypes.POINTER(ServerOptions)]
     lib.nebem_server_default_options.restype = None
     lib.nebem_server_create.argtypes = [ctypes.POINTER(P), i32, ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]
@@ -450,6 +454,22 @@ class Session:
         if code not in (NEBEM_OK, NEBEM_ENOCONV):
             _check(code)
         return code
+
+    def spacecharge_step_lines(self, qx, qy, qz, q, step_index, origin, step, shape, E=None, stream=None):
+        """The space-charge step with the charges reduced to line charges on
+        the voxel grid (origin, step, shape) first; returns (status, lines)."""
+        nq = qx.shape[0]
+        ex = ey = ez = None
+        if E is not None:
+            ex, ey, ez = E
+        g = grid_struct(origin, step, shape)
+        nl = ctypes.c_int64()
+        code = lib.nebem_spacecharge_step_lines(self.handle, _ptr(qx), _ptr(qy), _ptr(qz), _ptr(q), nq,
+                                                int(step_index), ctypes.byref(g), _ptr(ex), _ptr(ey), _ptr(ez),
+                                                ctypes.byref(nl), _stream(stream))
+        if code not in (NEBEM_OK, NEBEM_ENOCONV):
+            _check(code)
+        return code, nl.value
 
 
 class _DeviceArray:

@@ -135,6 +135,23 @@ void pivots_to_perm(const std::vector<int> &ipiv, std::vector<int> &perm)
     for (int k = 0; k < n; ++k) std::swap(perm[k], perm[ipiv[k]]);
 }
 
+nebem_status voxel_grid_args(const nebem_grid *vox, GridArgs &g)
+{
+    if (!vox) return fail(NEBEM_EINVAL, "voxelize: NULL grid");
+    for (int a = 0; a < 3; ++a) {
+        if (vox->n[a] < 1) return fail(NEBEM_EINVAL, "voxelize: fewer than 1 voxel on an axis");
+        if (!(vox->step[a] > 0.0) || !std::isfinite(vox->step[a]) || !std::isfinite(vox->origin[a]))
+            return fail(NEBEM_EINVAL, "voxelize: step must be finite and > 0, origin finite");
+        g.origin[a] = vox->origin[a];
+        g.step[a] = vox->step[a];
+        g.inv_step[a] = 1.0 / vox->step[a];
+        g.n[a] = vox->n[a];
+    }
+    const int64_t nn = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    if (nn >= (int64_t)0xffffffffLL) return fail(NEBEM_EINVAL, "voxelize: too many voxels (>= 2^32 - 1)");
+    return NEBEM_OK;
+}
+
 }  // namespace nebem
 
 using namespace nebem;
@@ -381,22 +398,11 @@ nebem_status nebem_voxelize_charges(const double *qx, const double *qy, const do
                                     int64_t *nlines, int64_t *outside, hipStream_t stream)
 {
     GridArgs g;
-    int64_t nn = 0;
     if (!nlines) return fail(NEBEM_EINVAL, "voxelize: NULL nlines");
     *nlines = 0;
     if (outside) *outside = 0;
-    if (!vox) return fail(NEBEM_EINVAL, "voxelize: NULL grid");
-    for (int a = 0; a < 3; ++a) {
-        if (vox->n[a] < 1) return fail(NEBEM_EINVAL, "voxelize: fewer than 1 voxel on an axis");
-        if (!(vox->step[a] > 0.0) || !std::isfinite(vox->step[a]) || !std::isfinite(vox->origin[a]))
-            return fail(NEBEM_EINVAL, "voxelize: step must be finite and > 0, origin finite");
-        g.origin[a] = vox->origin[a];
-        g.step[a] = vox->step[a];
-        g.inv_step[a] = 1.0 / vox->step[a];
-        g.n[a] = vox->n[a];
-    }
-    nn = (int64_t)g.n[0] * g.n[1] * g.n[2];
-    if (nn >= (int64_t)0xffffffffLL) return fail(NEBEM_EINVAL, "voxelize: too many voxels (>= 2^32 - 1)");
+    nebem_status st = voxel_grid_args(vox, g);
+    if (st) return st;
     if (nq < 0 || nq > (int64_t)INT_MAX - 256) return fail(NEBEM_EINVAL, "voxelize: nq out of range");
     if (max_lines < 0) return fail(NEBEM_EINVAL, "voxelize: negative max_lines");
     if (nq == 0) return NEBEM_OK;

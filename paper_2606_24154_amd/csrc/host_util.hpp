@@ -32,6 +32,9 @@ struct DevBuf {
 };
 
 nebem_status check_panels(const nebem_panels *p);
+// Validated voxel grid of the point-to-line reduction (>= 1 voxel per axis,
+// fewer than 2^32 - 1 in all)
+nebem_status voxel_grid_args(const nebem_grid *vox, GridArgs &g);
 nebem_status check_options(const nebem_options &o);
 // Derived element records (validated; synchronises the stream).
 nebem_status derive(const nebem_panels *p, hipStream_t s, DevBuf &drec);

@@ -68,21 +68,24 @@ __global__ __launch_bounds__(kLB) void k_make_lines(const unsigned *__restrict__
     const int l = blockIdx.x * kLB + threadIdx.x;
     if (l >= nlines) return;
     const int s0 = start[l], s1 = (l + 1 < nlines) ? start[l + 1] : nvalid;
+    // weighted mean taken relative to the voxel's first charge, so that the
+    // line of a lone charge passes exactly through it
+    const double x0 = qx[idx[s0]], y0 = qy[idx[s0]];
     double Q = 0.0, W = 0.0, cx = 0.0, cy = 0.0;
     for (int s = s0; s < s1; ++s) {
         const int c = idx[s];
         const double qc = q[c], w = fabs(qc);
         Q += qc;
         W += w;
-        cx += w * qx[c];
-        cy += w * qy[c];
+        cx += w * (qx[c] - x0);
+        cy += w * (qy[c] - y0);
     }
     const unsigned v = key[s0];
     const int i = (int)(v % (unsigned)g.n[0]);
     const int j = (int)((v / (unsigned)g.n[0]) % (unsigned)g.n[1]);
     const int k = (int)(v / ((unsigned)g.n[0] * (unsigned)g.n[1]));
-    const double x = W > 0.0 ? cx / W : g.origin[0] + (i + 0.5) * g.step[0];
-    const double y = W > 0.0 ? cy / W : g.origin[1] + (j + 0.5) * g.step[1];
+    const double x = W > 0.0 ? x0 + cx / W : g.origin[0] + (i + 0.5) * g.step[0];
+    const double y = W > 0.0 ? y0 + cy / W : g.origin[1] + (j + 0.5) * g.step[1];
     const double z0 = g.origin[2] + k * g.step[2];
     double *o = lines + 7 * (size_t)l;
     o[0] = x;
@@ -192,6 +195,42 @@ __global__ __launch_bounds__(kLB) void k_line_field(const double *__restrict__ l
         if (ey) ey[i] = kKe * a1;
         if (ez) ez[i] = kKe * a2;
     }
+}
+
+// collocation points (element centroids) as three arrays
+__global__ __launch_bounds__(kLB) void k_centroids(const double *__restrict__ drec, int n, double *__restrict__ cx,
+                                                   double *__restrict__ cy, double *__restrict__ cz)
+{
+    const int i = blockIdx.x * kLB + threadIdx.x;
+    if (i >= n) return;
+    const double *r = drec + (size_t)i * R_STRIDE;
+    cx[i] = r[R_CX];
+    cy[i] = r[R_CY];
+    cz[i] = r[R_CZ];
+}
+
+// b_i = b0_i - phi_i on conductor rows, b0_i - n_i . E_i on interface rows
+__global__ __launch_bounds__(kLB) void k_line_rhs_finish(const double *__restrict__ drec, int n,
+                                                         const double *__restrict__ f, const double *__restrict__ b0,
+                                                         double *__restrict__ b)
+{
+    const int i = blockIdx.x * kLB + threadIdx.x;
+    if (i >= n) return;
+    const double *r = drec + (size_t)i * R_STRIDE;
+    const double *phi = f, *ex = f + n, *ey = f + 2 * (size_t)n, *ez = f + 3 * (size_t)n;
+    const double en = fma(r[R_E3X], ex[i], fma(r[R_E3Y], ey[i], r[R_E3Z] * ez[i]));
+    b[i] = b0[i] - (r[R_BC] != 0.0 ? en : phi[i]);
+}
+
+void launch_line_rhs(const double *drec, int64_t n, const double *lines, int64_t nl, const double *b0, double *work,
+                     double *b, hipStream_t s)
+{
+    if (n <= 0) return;
+    const unsigned g = (unsigned)((n + kLB - 1) / kLB);
+    double *c = work, *f = work + 3 * (size_t)n;
+    hipLaunchKernelGGL(k_centroids, dim3(g), dim3(kLB), 0, s, drec, (int)n, c, c + n, c + 2 * n);
+    launch_line_field(lines, nl, c, c + n, c + 2 * n, n, f, f + n, f + 2 * n, f + 3 * n, s);
+    hipLaunchKernelGGL(k_line_rhs_finish, dim3(g), dim3(kLB), 0, s, drec, (int)n, f, b0, b);
 }
 
 static size_t align256l(size_t b) { return (b + 255) & ~(size_t)255; }

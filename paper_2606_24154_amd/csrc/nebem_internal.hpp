@@ -103,6 +103,10 @@ hipError_t voxel_lines(const double *qx, const double *qy, const double *qz, con
                        hipStream_t s);
 void launch_line_field(const double *lines, int64_t nl, const double *px, const double *py, const double *pz,
                        int64_t m, double *phi, double *ex, double *ey, double *ez, hipStream_t s);
+// Right-hand side with line charges at the collocation points: b = b0 - phi
+// (conductor rows) or b0 - n . E (interface rows); work: 7 n doubles
+void launch_line_rhs(const double *drec, int64_t n, const double *lines, int64_t nl, const double *b0, double *work,
+                     double *b, hipStream_t s);
 
 // o_c[i] += add[c m + i] for each non-null o_c
 void launch_add4(const double *add, int64_t m, double *o0, double *o1, double *o2, double *o3, hipStream_t s);

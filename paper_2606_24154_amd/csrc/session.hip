@@ -215,4 +215,61 @@ nebem_status nebem_spacecharge_step(nebem_session *s, double *qx, double *qy, do
     return st;
 }
 
+nebem_status nebem_spacecharge_step_lines(nebem_session *s, double *qx, double *qy, double *qz, const double *q,
+                                          int64_t nq, int32_t step_index, const nebem_grid *vox, double *ex,
+                                          double *ey, double *ez, int64_t *nlines, hipStream_t stream)
+{
+    if (nlines) *nlines = 0;
+    if (!s) return fail(NEBEM_EINVAL, "spacecharge_step_lines: NULL session");
+    if (nq < 0 || nq > (int64_t)INT32_MAX - 256) return fail(NEBEM_EINVAL, "spacecharge_step_lines: nq out of range");
+    if (step_index < 0) return fail(NEBEM_EINVAL, "spacecharge_step_lines: negative step index");
+    if (nq > 0 && (!qx || !qy || !qz || !q)) return fail(NEBEM_EINVAL, "spacecharge_step_lines: NULL charge array");
+    if ((ex == nullptr) != (ey == nullptr) || (ex == nullptr) != (ez == nullptr))
+        return fail(NEBEM_EINVAL, "spacecharge_step_lines: field arrays must be all NULL or all set");
+    GridArgs g;
+    nebem_status st = voxel_grid_args(vox, g);
+    if (st) return st;
+    const int64_t n = s->n;
+    // 1. the charges as line charges (at most one per occupied voxel)
+    int64_t nl = 0, outside = 0;
+    if (nq > 0) {
+        const int64_t nvox = (int64_t)g.n[0] * g.n[1] * g.n[2];
+        const int64_t cap = nq < nvox ? nq : nvox;
+        NEBEM_HIP(s->lines.ensure((size_t)cap * 7 * sizeof(double)));
+        NEBEM_HIP(voxel_lines(qx, qy, qz, q, (int)nq, g, s->lines.as<double>(), cap, &nl, &outside, stream));
+    }
+    if (nlines) *nlines = nl;
+    const double *lines = s->lines.as<double>();
+    // 2. re-solve with the lines' share on the right-hand side
+    if (step_index % s->opt.sc_resolve_every == 0) {
+        NEBEM_HIP(s->part.ensure((size_t)7 * n * sizeof(double)));
+        launch_line_rhs(s->drec.as<double>(), n, lines, nl, s->b0.as<double>(), s->part.as<double>(),
+                        s->rhs.as<double>(), stream);
+        NEBEM_HIP(hipGetLastError());
+        st = session_solve(s, s->rhs.as<double>(), stream);
+        if (st && st != NEBEM_ENOCONV) return st;
+    }
+    if (nq == 0) return st;
+    if (!ex) {
+        NEBEM_HIP(s->eb.ensure((size_t)3 * nq * sizeof(double)));
+        ex = s->eb.as<double>();
+        ey = ex + nq;
+        ez = ey + nq;
+    }
+    // 3. E at the charges: panels + lines, then the move
+    {
+        const nebem_status se = session_eval_points(s, qx, qy, qz, nq, nullptr, ex, ey, ez, stream);
+        if (se) return se;
+    }
+    if (nl > 0) {
+        NEBEM_HIP(s->lf.ensure((size_t)4 * nq * sizeof(double)));
+        double *t = s->lf.as<double>();
+        launch_line_field(lines, nl, qx, qy, qz, nq, nullptr, t + nq, t + 2 * nq, t + 3 * nq, stream);
+        launch_add4(t, nq, nullptr, ex, ey, ez, stream);
+    }
+    launch_euler(qx, qy, qz, q, ex, ey, ez, nq, s->opt.sc_mobility * s->opt.sc_dt, stream);
+    NEBEM_HIP(hipGetLastError());
+    return st;
+}
+
 }  // extern "C"
