@@ -65,3 +65,17 @@ def test_argument_errors_need_no_gpu(lib):
     assert b"precision" in nb.lib.nebem_last_error()
     h = ctypes.c_void_p()
     assert nb.lib.nebem_session_create(ctypes.byref(p), None, None, None, ctypes.byref(h)) == nb.NEBEM_EINVAL
+
+
+def test_line_charge_entry_points_validate_without_gpu(lib):
+    """The point-to-line entry points refuse bad arguments before any
+    device work: a NULL session, a voxel grid with an empty axis."""
+    import paper_2606_24154_amd as nb
+    n = ctypes.c_int64(5)
+    assert nb.lib.nebem_spacecharge_step_lines(None, None, None, None, None, 0, 0, None, None, None, None,
+                                               ctypes.byref(n), None) == nb.NEBEM_EINVAL
+    assert n.value == 0
+    g = nb.grid_struct((0.0, 0.0, 0.0), (1e-6, 1e-6, 1e-6), (4, 0, 4))
+    nl, out = ctypes.c_int64(), ctypes.c_int64()
+    assert nb.lib.nebem_voxelize_charges(None, None, None, None, 0, ctypes.byref(g), None, 0, ctypes.byref(nl),
+                                         ctypes.byref(out), None) == nb.NEBEM_EINVAL
