@@ -142,14 +142,15 @@ __global__ __launch_bounds__(kLB) void k_line_field(const double *__restrict__ l
             const double *g = lines + 7 * (size_t)(base + threadIdx.x);
             const double d0 = g[3] - g[0], d1 = g[4] - g[1], d2 = g[5] - g[2];
             const double L = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            const double iL = L > 0.0 ? 1.0 / L : 0.0;  // a point segment carries no charge
+            // divisions, so that an axis-parallel segment's direction is
+            // exact; a point segment carries no charge
             double *o = t + 8 * threadIdx.x;
             o[0] = g[0];
             o[1] = g[1];
             o[2] = g[2];
-            o[3] = L > 0.0 ? d0 * iL : 0.0;
-            o[4] = L > 0.0 ? d1 * iL : 0.0;
-            o[5] = L > 0.0 ? d2 * iL : 1.0;
+            o[3] = L > 0.0 ? d0 / L : 0.0;
+            o[4] = L > 0.0 ? d1 / L : 0.0;
+            o[5] = L > 0.0 ? d2 / L : 1.0;
             o[6] = L;
             o[7] = L > 0.0 ? g[6] : 0.0;
         }

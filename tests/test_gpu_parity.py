@@ -332,6 +332,27 @@ def test_voxel_lines_match_oracle(nb):
     np.testing.assert_allclose(got[:, 6], ref[:, 6], rtol=0, atol=1e-12 * np.abs(ref[:, 6]).max())
 
 
+def test_lone_charge_line_passes_through_it(nb):
+    """A charge alone in its voxel gets a line through its own x, y exactly,
+    and its field there across the line is the principal value 0."""
+    rng = np.random.default_rng(74)
+    ijk = rng.choice(10 ** 3, 200, replace=False)
+    cell = np.column_stack([ijk % 10, (ijk // 10) % 10, ijk // 100]).astype(float)
+    xyz = (cell + rng.uniform(0.05, 0.95, (200, 3))) * 7e-6 - 35e-6
+    q = rng.choice([-1.0, 1.0], 200) * 1.602176634e-19 * rng.uniform(0.5, 3.0, 200)
+    pts = [dev(np.ascontiguousarray(xyz[:, k])) for k in range(3)]
+    lines, out = nb.voxelize_charges(*pts, dev(q), (-35e-6,) * 3, (7e-6,) * 3, (10,) * 3)
+    torch.cuda.synchronize()
+    ln = lines.cpu().numpy()
+    assert out == 0 and len(ln) == 200
+    order = np.argsort(ijk)  # lines come in voxel order
+    assert np.array_equal(ln[:, 0], xyz[order, 0]) and np.array_equal(ln[:, 1], xyz[order, 1])
+    assert np.array_equal(ln[:, 3], xyz[order, 0]) and np.array_equal(ln[:, 4], xyz[order, 1])
+    f = nb.line_field(lines[:1], *(t[order[:1]] for t in pts))
+    torch.cuda.synchronize()
+    assert f[1].item() == 0.0 and f[2].item() == 0.0 and np.isinf(f[0].item())
+
+
 def test_line_field_matches_oracle(nb):
     """Segment field against the oracle's closed form, at points around,
     alongside and beyond the ends of the segments."""
