@@ -37,7 +37,7 @@ FLOPS_PER_INTERACTION = 132.6
 # HBM bytes per evaluation launch at the default workload (FETCH_SIZE x 2 +
 # WRITE_SIZE x 1, the factors that make a plain 1 GiB copy read 1 GiB and
 # write 1 GiB); None when not measured for the current kernel.
-EVAL_TRAFFIC_BYTES = 6.912e7
+EVAL_TRAFFIC_BYTES = 6.913e7
 FP64_VALU_PEAK = 78.6e12      # MI355X, FLOP/s
 HBM_PEAK = 8.0e12             # B/s
 
