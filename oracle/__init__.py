@@ -226,16 +226,21 @@ def _inner(im, k):
     return dataclasses.replace(im, n1=min(im.n1, k), n2=min(im.n2, k))
 
 
-def voxel_lines(xyz, q, origin, step, shape):
+def voxel_lines(xyz, q, origin, step, shape, placement: str = "centre"):
     """Point charges reduced to line charges (Algorithm 3): charges binned
     into the voxels of a regular grid (voxel (i, j, k) = floor((x - origin)
     / step) per axis, index i + nx (j + ny k); charges outside dropped);
     every occupied voxel becomes one segment parallel to z over the voxel's
-    z extent, at the |q|-weighted mean x, y of its charges (the voxel's
-    centre if they sum to zero), carrying the voxel's total charge
-    uniformly.  Returns (lines (L, 7): ax, ay, az, bx, by, bz, lambda, in
-    increasing voxel index; number of charges outside)."""
-    xyz = np.asarray(xyz, dtype=np.float64)
+    z extent, carrying the voxel's total charge uniformly.  The voxel record
+    of Algorithm 3 holds only the total charge and the occupancy, so by
+    default (placement "centre") the segment runs through the voxel's
+    centre in x, y; placement "weighted" puts it at the |q|-weighted mean
+    x, y of the voxel's charges instead.  Returns (lines (L, 7): ax, ay,
+    az, bx, by, bz, lambda, in increasing voxel index; number of charges
+    outside)."""
+    if placement not in ("centre", "weighted"):
+        raise ValueError(placement)
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
     q = np.asarray(q, dtype=np.float64)
     origin, step = np.asarray(origin, dtype=np.float64), np.asarray(step, dtype=np.float64)
     shape = np.asarray(shape)
@@ -245,14 +250,17 @@ def voxel_lines(xyz, q, origin, step, shape):
     key = ijk[:, 0] + shape[0] * (ijk[:, 1] + shape[1] * ijk[:, 2])
     vox, inv = np.unique(key, return_inverse=True)
     Q = np.bincount(inv, q, len(vox))
-    W = np.bincount(inv, np.abs(q), len(vox))
-    cx = np.bincount(inv, np.abs(q) * xyz[:, 0], len(vox))
-    cy = np.bincount(inv, np.abs(q) * xyz[:, 1], len(vox))
     i = vox % shape[0]
     j = (vox // shape[0]) % shape[1]
     k = vox // (shape[0] * shape[1])
-    x = np.where(W > 0, cx / np.where(W > 0, W, 1), origin[0] + (i + 0.5) * step[0])
-    y = np.where(W > 0, cy / np.where(W > 0, W, 1), origin[1] + (j + 0.5) * step[1])
+    x = origin[0] + (i + 0.5) * step[0]
+    y = origin[1] + (j + 0.5) * step[1]
+    if placement == "weighted":
+        W = np.bincount(inv, np.abs(q), len(vox))
+        cx = np.bincount(inv, np.abs(q) * xyz[:, 0], len(vox))
+        cy = np.bincount(inv, np.abs(q) * xyz[:, 1], len(vox))
+        x = np.where(W > 0, cx / np.where(W > 0, W, 1), x)
+        y = np.where(W > 0, cy / np.where(W > 0, W, 1), y)
     z0 = origin[2] + k * step[2]
     lines = np.column_stack([x, y, z0, x, y, z0 + step[2], Q / step[2]])
     return lines, int((~inside).sum())

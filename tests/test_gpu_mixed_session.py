@@ -229,7 +229,7 @@ def test_spacecharge_step_lines_matches_oracle(nb, small_gem):
     code, nl = ses.spacecharge_step_lines(qx, qy, qz, dev(q), 0, origin, step, shape, E=E)
     torch.cuda.synchronize()
     assert code == nb.NEBEM_OK
-    lines, _ = oracle.voxel_lines(xyz, q, origin, step, shape)
+    lines, _ = oracle.voxel_lines(xyz, q, origin, step, shape, placement="weighted")
     assert nl == len(lines)
     f = oracle.line_field(lines, g.centroids())
     en = np.einsum("ij,ij->i", f[:, 1:], g.normals())

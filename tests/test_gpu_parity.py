@@ -324,7 +324,7 @@ def test_voxel_lines_match_oracle(nb):
     q[::7] *= 3.0
     origin, step, shape = (-30e-6, -30e-6, -30e-6), (5e-6, 4e-6, 5e-6), (12, 15, 12)
     lines, out = nb.voxelize_charges(*(dev(xyz[:, k]) for k in range(3)), dev(q), origin, step, shape)
-    ref, ref_out = oracle.voxel_lines(xyz, q, origin, step, shape)
+    ref, ref_out = oracle.voxel_lines(xyz, q, origin, step, shape, placement="weighted")
     got = lines.cpu().numpy()
     assert out == ref_out and out > 0
     assert got.shape == ref.shape

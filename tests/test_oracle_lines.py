@@ -52,7 +52,10 @@ def test_voxel_reduction():
     assert np.allclose(lines[:, 5] - lines[:, 2], step[2], rtol=1e-12) and np.all(lines[:, 0] == lines[:, 3])
     ix = np.floor((lines[:, 0] - origin[0]) / step[0])
     assert np.all((ix >= 0) & (ix < shape[0]))
-    # a single charge alone in its voxel sits on its own x, y
+    # a lone charge: by default its line runs through the voxel centre; with
+    # the weighted placement through the charge itself
     one, _ = oracle.voxel_lines([[1e-6, 2e-6, 3e-6]], [2.0], origin, step, shape)
-    np.testing.assert_array_equal(one[0, [0, 1]], [1e-6, 2e-6])
+    np.testing.assert_allclose(one[0, [0, 1]], [2.5e-6, 2.5e-6], rtol=1e-12)
     assert one[0, 6] == 2.0 / step[2]
+    one, _ = oracle.voxel_lines([[1e-6, 2e-6, 3e-6]], [2.0], origin, step, shape, placement="weighted")
+    np.testing.assert_array_equal(one[0, [0, 1]], [1e-6, 2e-6])
