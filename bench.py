@@ -1,20 +1,25 @@
 """Benchmark: element-point interactions per second on one MI355X.
 
-Workload (default): the single-GEM unit cell -- 8064 rectangular and
+Workload (default): the staggered double thick GEM -- 41 600 rectangular and
 right-triangular elements, 121 lattice copies (+-5 along both cell vectors),
-1 000 000 evaluation points in the drift and transfer gaps -- in FP64.
-One step is the whole hot path on that input: influence-matrix assembly,
-LU factorisation and solve, then potential and field at all points.
+4 000 000 evaluation points between the anode and the drift plane -- in
+FP64.  The job is the whole hot path on that input: influence-matrix
+assembly, LU factorisation and solve with FP64 refinement, then potential
+and field at all points.  It is cut into --steps steps: step k evaluates
+the k-th slice of the points, step 0 also assembles and solves, so the
+timed region holds the job exactly once.
 
-value = (assembly + evaluation interactions per step) / step time, where an
-interaction is one (observation point, element copy) pair.
+value = (assembly + evaluation interactions of the job) / timed seconds,
+where an interaction is one (observation point, element copy) pair.
 
 Prints one JSON line.  Extra keys: per-stage times, the evaluation kernel's
-roofline (FP64 vector ALU bound), the CPU oracle timed on this host's cores
-on a bounded sample of the same evaluation, the mixed-precision step on the
-same input (rate, speedup, largest relative difference from the FP64
-results), and a bounded serving replay (continuous batching over resident
-sessions, Poisson arrivals) with p50/p99 request latency.
+roofline (FP64 vector ALU bound, against the closed forms' algorithmic
+operation count), the CPU oracle timed on this host's cores on a bounded
+sample of the same evaluation, the mixed-precision job on the same input
+(rate, speedup, largest relative difference from the FP64 results), and a
+bounded serving replay (continuous batching over resident sessions of the
+plates, the GEM cell and this workload, Poisson arrivals) with p50/p99
+request latency.
 """
 from __future__ import annotations
 
@@ -29,15 +34,18 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP64 floating-point operations per interaction of the evaluation kernel on
-# this workload, from rocprofv3 counters (64 x (ADD + MUL + TRANS + 2 FMA)
-# FP64 instructions of one evaluation launch / its interactions); see the
-# profile summaries committed under profiles/.
-FLOPS_PER_INTERACTION = 132.6
-# HBM bytes per evaluation launch at the default workload (FETCH_SIZE x 2 +
-# WRITE_SIZE x 1, the factors that make a plain 1 GiB copy read 1 GiB and
-# write 1 GiB); None when not measured for the current kernel.
-EVAL_TRAFFIC_BYTES = 6.913e7
+# Algorithmic FLOP per interaction of the closed forms (a transcendental or a
+# division counted as one operation): rectangle ~110 arithmetic + 4 sqrt +
+# 4 log + 2 atan + 4 div; right triangle ~90 + 3 + 3 + 1 + 3.
+ALG_FLOPS_RECT = 124.0
+ALG_FLOPS_TRI = 100.0
+# Counter figures of the FP64 evaluation kernel per workload, from the
+# rocprofv3 runs summarised under profiles/ (FP64 FLOP per interaction =
+# 64 x (ADD + MUL + TRANS + 2 FMA) FP64 instructions / interactions; HBM
+# bytes per launch = FETCH_SIZE x 2 + WRITE_SIZE, the factors that make a
+# plain 1 GiB copy read 1 GiB and write 1 GiB), valid for launches of
+# points_per_launch points with the kernels as committed with them.
+COUNTER_CALIBRATION = {}
 FP64_VALU_PEAK = 78.6e12      # MI355X, FLOP/s
 HBM_PEAK = 8.0e12             # B/s
 
@@ -45,13 +53,16 @@ HBM_PEAK = 8.0e12             # B/s
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=2)
-    p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", choices=["gem", "thgem", "plates"], default="gem",
-                   help="gem: single-GEM cell (default, the headline figure); thgem: staggered double "
-                        "THGEM, 41 600 elements; plates: 512-element parallel plates")
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--workload", choices=["gem", "thgem", "plates"], default="thgem",
+                   help="thgem: staggered double THGEM, 41 600 elements, 4*10^6 points (default, the headline "
+                        "figure); gem: single-GEM cell, 8064 elements, 10^6 points; plates: 512-element "
+                        "parallel plates")
     p.add_argument("--points", type=int, default=None, help="evaluation points (default per workload)")
-    p.add_argument("--cpu-sample", type=int, default=256, help="points in the oracle's timed sample")
+    p.add_argument("--cpu-sample", type=int, default=48,
+                   help="points in the oracle's timed sample on all host threads (at most 16)")
+    p.add_argument("--cpu-sample-1t", type=int, default=3, help="points in the oracle's one-thread timed sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison step")
@@ -96,17 +107,37 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_read": x.numel() * 8, "copy_probe_bytes_written": y.numel() * 8}))
 
 
-def cpu_baseline(geom, pts, sigma, n_sample):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(geom, pts, sigma, n_sample, n_sample_1t):
+    """The oracle's evaluation timed on this host: on up to 16 threads (the
+    host share of one GPU) over the first n_sample points, and on one thread
+    over the next n_sample_1t points."""
     import oracle
-    threads = min(16, os.cpu_count() or 1)
-    sample = pts[:n_sample]
+    threads = min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1))
+    per_pt = geom.n * geom.images.count
     t0 = time.perf_counter()
-    oracle.eval_points(geom, sigma, sample, nthreads=threads)
+    oracle.eval_points(geom, sigma, pts[:n_sample], nthreads=threads)
     dt = time.perf_counter() - t0
-    inter = n_sample * geom.n * geom.images.count
-    return {"value": inter / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
-            "sample": f"evaluation at the first {n_sample} of the benchmark's points "
-                      f"({inter:.3e} interactions, {dt:.1f} s)"}
+    t0 = time.perf_counter()
+    oracle.eval_points(geom, sigma, pts[n_sample:n_sample + n_sample_1t], nthreads=1)
+    dt1 = time.perf_counter() - t0
+    return {"value": n_sample * per_pt / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+            "sample": f"evaluation at the first {n_sample} of the benchmark's points ({n_sample * per_pt:.3e} "
+                      f"interactions, {dt:.1f} s on {threads} threads); one thread: the next {n_sample_1t} "
+                      f"points ({n_sample_1t * per_pt:.3e} interactions, {dt1:.1f} s)",
+            "value_1_thread": n_sample_1t * per_pt / dt1, "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "cpu_model": _cpu_model()}
 
 
 def rel_diff(a, b, floor=1e-3):
@@ -509,6 +540,16 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU sharding is not built "
                                    "(--gpus must be 1)"}))
         sys.exit(2)
+    headline(args)
+
+
+def headline(args):
+    """The default bench line: the whole job of one workload (assembly, LU
+    solve with refinement, evaluation at all M points) cut into `steps`
+    steps -- step k evaluates the k-th of `steps` equal slices of the points,
+    and step 0 also assembles and solves -- so that the timed region holds
+    the job exactly once.  value = (N^2 C + M N C) interactions / timed
+    seconds.  Warm-up steps run steps 0 .. warmup-1 of the same job."""
     import torch
 
     import paper_2606_24154_amd as nb
@@ -516,6 +557,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    t_setup = time.perf_counter()
     if args.workload == "gem":
         geom = gem_cell()
         M = args.points or 1_000_000
@@ -529,6 +571,7 @@ def main():
         M = args.points or 4096
         pts = uniform_points(geom.box_lo, geom.box_hi, M, 0)
     n, C = geom.n, geom.images.count
+    K = max(1, args.steps)
     dp = nb.DevicePanels.from_geometry(geom, dev)
     px, py, pz = (torch.from_numpy(np.ascontiguousarray(pts[:, k])).to(dev) for k in range(3))
     b = torch.from_numpy(geom.rhs()).to(dev)
@@ -536,110 +579,145 @@ def main():
     ipiv = torch.empty(n, dtype=torch.int32, device=dev)
     sigma = torch.empty(n, dtype=torch.float64, device=dev)
     out = tuple(torch.empty(M, dtype=torch.float64, device=dev) for _ in range(4))
+    bounds = np.linspace(0, M, K + 1).round().astype(np.int64)
     stream = torch.cuda.current_stream()
-
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    stage = {"assemble": [], "solve": [], "eval": []}
-
     prec = nb.MIXED if args.precision == "mixed" else nb.FP64
     info = {}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    log(f"{geom.name}: N={n}, C={C}, M={M}, {K} steps; set-up {time.perf_counter() - t_setup:.1f} s")
 
-    def step():
+    def step(k):
+        """step k of the job; returns (assemble ms, solve ms, eval ms, points)"""
+        i0, i1 = int(bounds[k]), int(bounds[k + 1])
         ev[0].record(stream)
-        nb.assemble(dp, A=A, precision=prec)
-        ev[1].record(stream)
-        _, _, si = nb.solve(A, b, sigma=sigma, ipiv=ipiv, precision=prec)
-        info["ir_iters"], info["rel_resid"] = si.ir_iters, si.rel_resid
+        if k == 0:
+            nb.assemble(dp, A=A, precision=prec)
+            ev[1].record(stream)
+            _, _, si = nb.solve(A, b, sigma=sigma, ipiv=ipiv, precision=prec)
+            info["ir_iters"], info["rel_resid"] = si.ir_iters, si.rel_resid
+        else:
+            ev[1].record(stream)
         ev[2].record(stream)
-        nb.eval_points(dp, sigma, px, py, pz, out=out, precision=prec)
+        if i1 > i0:
+            nb.eval_points(dp, sigma, px[i0:i1], py[i0:i1], pz[i0:i1], out=tuple(o[i0:i1] for o in out),
+                           precision=prec)
         ev[3].record(stream)
-
-    def progress(tag):
-        print(f"[bench] {tag}: assemble {ev[0].elapsed_time(ev[1]):.1f} ms, solve "
-              f"{ev[1].elapsed_time(ev[2]):.1f} ms, eval {ev[2].elapsed_time(ev[3]):.1f} ms",
-              file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        return (ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3]), i1 - i0)
 
     for w in range(args.warmup):
-        step()
-        torch.cuda.synchronize()
-        progress(f"warmup {w}")
+        t = step(w % K)
+        log(f"warmup {w}: assemble {t[0]:.1f} ms, solve {t[1]:.1f} ms, eval {t[2]:.1f} ms ({t[3]} points)")
+    stages = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        step()
-        torch.cuda.synchronize()
-        stage["assemble"].append(ev[0].elapsed_time(ev[1]))
-        stage["solve"].append(ev[1].elapsed_time(ev[2]))
-        stage["eval"].append(ev[2].elapsed_time(ev[3]))
-        progress(f"step {k}")
+    for k in range(K):
+        t = step(k)
+        stages.append(t)
+        log(f"step {k}: assemble {t[0]:.1f} ms, solve {t[1]:.1f} ms, eval {t[2]:.1f} ms ({t[3]} points)")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms_step = 1e3 * dt / args.steps
     inter_asm = n * n * C
     inter_eval = M * n * C
-    value = (inter_asm + inter_eval) / (dt / args.steps)
-    ms = {k: float(np.mean(v)) for k, v in stage.items()}
-    eval_rate = inter_eval / (ms["eval"] * 1e-3)
+    value = (inter_asm + inter_eval) / dt
+    t_asm, t_solve = stages[0][0], stages[0][1]
+    t_eval = sum(t[2] for t in stages)
+    eval_rate = inter_eval / (t_eval * 1e-3)
 
     roof = None
-    if FLOPS_PER_INTERACTION is not None and prec == nb.FP64 and args.workload == "gem":
-        ach = FLOPS_PER_INTERACTION * inter_eval / (ms["eval"] * 1e-3)
+    if prec == nb.FP64:
+        # algorithmic FLOP per interaction: the closed forms' operation counts,
+        # a transcendental or division counted as one operation, over this
+        # geometry's mix of rectangles and right triangles
+        kind = np.asarray(geom.kind)
+        n_rect, n_tri = int((kind == 0).sum()), int((kind == 1).sum())
+        f_alg = (n_rect * ALG_FLOPS_RECT + n_tri * ALG_FLOPS_TRI) / n
+        # average over the evaluation launches (one per step; their points
+        # differ by at most one), HIP events on the launching stream
+        per_launch_ms = t_eval / K
+        per_launch_inter = inter_eval / K
+        ach = f_alg * per_launch_inter / (per_launch_ms * 1e-3)
+        cal = COUNTER_CALIBRATION.get(args.workload)
         roof = {"bound": "alu", "kernel": "k_eval_fp64", "achieved": ach / 1e12, "peak": FP64_VALU_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK,
-                "traffic": EVAL_TRAFFIC_BYTES if (M == 1_000_000 and args.workload == "gem") else None,
-                "flops_per_interaction": FLOPS_PER_INTERACTION}
+                "traffic": cal["traffic_bytes"] if (cal and cal["points_per_launch"] == round(M / K)) else None,
+                "flops_per_interaction": f_alg, "flops_per_interaction_kind": "algorithmic",
+                "elements": {"rectangles": n_rect, "right_triangles": n_tri},
+                "launches": K, "avg_launch_ms": per_launch_ms, "interactions_per_launch": per_launch_inter}
+        if cal:
+            roof["counter_flops_per_interaction"] = cal["flops_per_interaction"]
+            roof["counter_frac"] = cal["flops_per_interaction"] * eval_rate / FP64_VALU_PEAK
 
     mixed = None
     if not args.no_mixed and prec == nb.FP64:
         torch.cuda.synchronize()
         ref = [t.cpu().numpy() for t in out]
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         t1 = time.perf_counter()
+        e[0].record(stream)
         nb.assemble(dp, A=A, precision=nb.MIXED)
+        e[1].record(stream)
         _, _, si = nb.solve(A, b, sigma=sigma, ipiv=ipiv, precision=nb.MIXED)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
+        e[2].record(stream)
         nb.eval_points(dp, sigma, px, py, pz, out=out, precision=nb.MIXED)
-        e1.record(stream)
+        e[3].record(stream)
         torch.cuda.synchronize()
         dt_m = time.perf_counter() - t1
         got = [t.cpu().numpy() for t in out]
         ephi, eE = rel_diff(got, ref)
-        print(f"[bench] mixed step: {1e3 * dt_m:.1f} ms", file=sys.stderr, flush=True)
-        mixed = {"value": (inter_asm + inter_eval) / dt_m, "ms_per_step": 1e3 * dt_m,
-                 "eval_interactions_per_s": inter_eval / (e0.elapsed_time(e1) * 1e-3),
-                 "speedup_vs_fp64": ms_step / (1e3 * dt_m), "ir_iters": si.ir_iters,
+        log(f"mixed job: {1e3 * dt_m:.1f} ms (assemble {e[0].elapsed_time(e[1]):.1f}, solve "
+            f"{e[1].elapsed_time(e[2]):.1f}, eval {e[2].elapsed_time(e[3]):.1f} ms)")
+        mixed = {"value": (inter_asm + inter_eval) / dt_m, "job_ms": 1e3 * dt_m,
+                 "stages_ms": {"assemble": e[0].elapsed_time(e[1]), "solve": e[1].elapsed_time(e[2]),
+                               "eval": e[2].elapsed_time(e[3])},
+                 "eval_interactions_per_s": inter_eval / (e[2].elapsed_time(e[3]) * 1e-3),
+                 "speedup_vs_fp64": dt / dt_m, "ir_iters": si.ir_iters,
                  "rel_resid": si.rel_resid, "max_rel_diff_vs_fp64": {"phi": ephi, "E": eE}}
+    del A
+    torch.cuda.empty_cache()
 
     serve = None
-    if args.serve_requests > 0 and prec == nb.FP64 and args.workload == "gem":
-        from synth import parallel_plates
-        geoms = [parallel_plates(), geom]
+    if args.serve_requests > 0 and prec == nb.FP64:
+        geoms = [parallel_plates(), gem_cell(), geom] if args.workload == "thgem" else [parallel_plates(), geom]
         serve = {}
         for name, pr in (("fp64", nb.FP64), ("mixed", nb.MIXED)):
+            t1 = time.perf_counter()
             ses = [nb.Session(nb.DevicePanels.from_geometry(g, dev), precision=pr) for g in geoms]
+            log(f"serve {name}: {len(ses)} sessions ready in {time.perf_counter() - t1:.1f} s")
             serve[name] = serve_replay(nb, geoms, ses, args.serve_requests, args.serve_load, eval_rate)
+            log(f"serve {name}: p50 {serve[name]['p50_ms']:.0f} ms, p99 {serve[name]['p99_ms']:.0f} ms")
             for x in ses:
                 x.close()
+            del ses
+            torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu:
         # timing only: a seeded density, not the GPU's solution
         s_host = np.random.default_rng(7).normal(0.0, 1e-5, n)
-        cpu = cpu_baseline(geom, pts, s_host, args.cpu_sample)
+        cpu = cpu_baseline(geom, pts, s_host, args.cpu_sample, args.cpu_sample_1t)
+        log(f"oracle: {cpu['value']:.3e} interactions/s on {cpu['cores']} threads, "
+            f"{cpu['value_1_thread']:.3e} on 1")
 
     rec = {
         "metric": "elem-point interactions/s (FP64 vs mixed @1e-6 rel); p50/p99 serve latency",
-        "value": value, "unit": "interactions/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "value": value, "unit": "interactions/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / K, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if prec == nb.FP64 else "f64+f32", "data": "synthetic",
-        "config": {"workload": f"{geom.name}: N={n} elements, C={C} copies, M={M} points; "
-                               f"assemble + LU solve + evaluate, {args.precision}",
+        "config": {"workload": f"{geom.name}: N={n} elements, C={C} copies, M={M} points; assemble + LU solve "
+                               f"(+ refinement) + evaluate, {args.precision}; the job cut into {K} steps "
+                               f"(step k evaluates slice k of the points, step 0 also assembles and solves)",
                    "elements": n, "copies": C, "points": M},
-        "stages_ms": ms, "eval_interactions_per_s": eval_rate, "solve_info": info,
+        "job_s": dt, "stages_ms": {"assemble": t_asm, "solve": t_solve, "eval_total": t_eval},
+        "eval_interactions_per_s": eval_rate, "solve_info": info,
         "roofline": roof, "cpu_baseline": cpu, "mixed": mixed, "serve": serve,
     }
     print(json.dumps(rec), flush=True)
+    # release device memory before the interpreter tears down
+    del out, px, py, pz, b, ipiv, sigma, dp
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
 
 
 if __name__ == "__main__":

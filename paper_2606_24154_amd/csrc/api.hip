@@ -152,6 +152,22 @@ nebem_status voxel_grid_args(const nebem_grid *vox, GridArgs &g)
     return NEBEM_OK;
 }
 
+// one evaluation through the driver, with a stream-ordered workspace of
+// the driver's preferred size; outputs overwritten
+nebem_status eval_with_workspace(const double *drec, const double *sigma, int64_t n, int ncol, const ImgArgs &ia,
+                                 int mixed, double near_factor, const double *px, const double *py, const double *pz,
+                                 int64_t m, double *phi, double *ex, double *ey, double *ez, hipStream_t stream,
+                                 const char *what)
+{
+    const size_t wb = eval_workspace(n, ia, m, ncol);
+    DevBuf ws;
+    if (wb && ws.alloc(wb, stream) != hipSuccess)
+        return fail(NEBEM_ENOMEM, std::string(what) + ": evaluation workspace");
+    NEBEM_HIP(run_eval(drec, sigma, n, ncol, ia, mixed, near_factor, px, py, pz, m, phi, ex, ey, ez, ws.p, wb,
+                       stream));
+    return NEBEM_OK;
+}
+
 }  // namespace nebem
 
 using namespace nebem;
@@ -189,19 +205,8 @@ nebem_status nebem_eval(const nebem_panels *panels, const nebem_images *images, 
     if ((st = make_img_args(images, &ia))) return st;
     DevBuf drec;
     if ((st = derive(panels, stream, drec))) return st;
-    if (eval_ordering_pays(m)) {
-        const size_t wb = ordered_eval_workspace(m);
-        if (!wb) return fail(NEBEM_EDEVICE, "eval: ordering workspace query failed");
-        DevBuf ws;
-        if (ws.alloc(wb, stream) != hipSuccess) return fail(NEBEM_ENOMEM, "eval: ordering workspace");
-        NEBEM_HIP(launch_eval_ordered(drec.as<double>(), sigma, panels->n, ia, o.precision == NEBEM_MIXED,
-                                      o.near_factor, px, py, pz, m, phi, ex, ey, ez, ws.p, wb, stream));
-    } else {
-        launch_eval(drec.as<double>(), sigma, panels->n, ia, o.precision == NEBEM_MIXED, o.near_factor, px, py, pz,
-                    m, phi, ex, ey, ez, stream);
-    }
-    NEBEM_HIP(hipGetLastError());
-    return NEBEM_OK;
+    return eval_with_workspace(drec.as<double>(), sigma, panels->n, 1, ia, o.precision == NEBEM_MIXED,
+                               o.near_factor, px, py, pz, m, phi, ex, ey, ez, stream, "eval");
 }
 
 nebem_status nebem_eval_multi(const nebem_panels *panels, const nebem_images *images, const double *sigma,
@@ -224,47 +229,8 @@ nebem_status nebem_eval_multi(const nebem_panels *panels, const nebem_images *im
     if ((st = make_img_args(images, &ia))) return st;
     DevBuf drec;
     if ((st = derive(panels, stream, drec))) return st;
-    const int mixed = o.precision == NEBEM_MIXED;
-    const int ns = (int)nsig;
-    if (eval_ordering_pays(m)) {
-        const size_t wb = ordered_eval_multi_workspace(m);
-        if (!wb) return fail(NEBEM_EDEVICE, "eval_multi: ordering workspace query failed");
-        DevBuf ws;
-        if (ws.alloc(wb, stream) != hipSuccess) return fail(NEBEM_ENOMEM, "eval_multi: ordering workspace");
-        NEBEM_HIP(launch_eval_multi_ordered(drec.as<double>(), sigma, panels->n, ns, ia, mixed, o.near_factor, px, py,
-                                            pz, m, phi, ex, ey, ez, ws.p, wb, stream));
-    } else {
-        for (int c0 = 0; c0 < ns; c0 += kMultiCols) {
-            const int k = ns - c0 < kMultiCols ? ns - c0 : kMultiCols;
-            const size_t col = (size_t)c0 * (size_t)m;
-            OutCols out = {{phi ? phi + col : nullptr, ex ? ex + col : nullptr, ey ? ey + col : nullptr,
-                            ez ? ez + col : nullptr},
-                           m};
-            launch_eval_multi(drec.as<double>(), sigma + (size_t)c0 * panels->n, panels->n, k, ia, mixed,
-                              o.near_factor, px, py, pz, m, out, stream);
-        }
-    }
-    NEBEM_HIP(hipGetLastError());
-    return NEBEM_OK;
-}
-
-// one evaluation pass (ordered for large batches), outputs overwritten
-static nebem_status eval_pass(const double *drec, const double *sigma, int64_t n, const ImgArgs &ia, int mixed,
-                              double near_factor, const double *px, const double *py, const double *pz, int64_t m,
-                              double *phi, double *ex, double *ey, double *ez, hipStream_t stream)
-{
-    if (eval_ordering_pays(m)) {
-        const size_t wb = ordered_eval_workspace(m);
-        if (!wb) return fail(NEBEM_EDEVICE, "eval: ordering workspace query failed");
-        DevBuf ws;
-        if (ws.alloc(wb, stream) != hipSuccess) return fail(NEBEM_ENOMEM, "eval: ordering workspace");
-        NEBEM_HIP(launch_eval_ordered(drec, sigma, n, ia, mixed, near_factor, px, py, pz, m, phi, ex, ey, ez, ws.p,
-                                      wb, stream));
-    } else {
-        launch_eval(drec, sigma, n, ia, mixed, near_factor, px, py, pz, m, phi, ex, ey, ez, stream);
-    }
-    NEBEM_HIP(hipGetLastError());
-    return NEBEM_OK;
+    return eval_with_workspace(drec.as<double>(), sigma, panels->n, (int)nsig, ia, o.precision == NEBEM_MIXED,
+                               o.near_factor, px, py, pz, m, phi, ex, ey, ez, stream, "eval_multi");
 }
 
 nebem_status nebem_eval_adaptive(const nebem_panels *panels, const nebem_panels *prims, const int32_t *elem_prim,
@@ -300,8 +266,8 @@ nebem_status nebem_eval_adaptive(const nebem_panels *panels, const nebem_panels 
             if (out) NEBEM_HIP(hipMemsetAsync(out, 0, (size_t)m * sizeof(double), stream));
         return NEBEM_OK;
     }
-    if ((st = eval_pass(drec.as<double>(), sigma, n, near, mixed, o.near_factor, px, py, pz, m, phi, ex, ey, ez,
-                        stream)))
+    if ((st = eval_with_workspace(drec.as<double>(), sigma, n, 1, near, mixed, o.near_factor, px, py, pz, m, phi, ex,
+                                  ey, ez, stream, "eval_adaptive")))
         return st;
     if (prim_after >= ia.n1 && prim_after >= ia.n2) return NEBEM_OK;  // no far copies
     if (np == 0) return fail(NEBEM_EINVAL, "eval_adaptive: no primitives");
@@ -323,9 +289,9 @@ nebem_status nebem_eval_adaptive(const nebem_panels *panels, const nebem_panels 
     farimg.hole = prim_after;
     double *f = far.as<double>();
     const size_t mm = (size_t)m;
-    if ((st = eval_pass(prec.as<double>(), dsbar.as<double>(), np, farimg, mixed, o.near_factor, px, py, pz, m,
-                        phi ? f : nullptr, ex ? f + mm : nullptr, ey ? f + 2 * mm : nullptr, ez ? f + 3 * mm : nullptr,
-                        stream)))
+    if ((st = eval_with_workspace(prec.as<double>(), dsbar.as<double>(), np, 1, farimg, mixed, o.near_factor, px, py,
+                                  pz, m, phi ? f : nullptr, ex ? f + mm : nullptr, ey ? f + 2 * mm : nullptr,
+                                  ez ? f + 3 * mm : nullptr, stream, "eval_adaptive")))
         return st;
     launch_add4(f, m, phi, ex, ey, ez, stream);
     NEBEM_HIP(hipGetLastError());

@@ -340,44 +340,88 @@ __device__ __forceinline__ void eval_block(const double *__restrict__ drec, cons
     }
 }
 
+// Element segments.  Every evaluation path (stateless, session, ordered,
+// several-column, serving) splits a geometry's elements into the same
+// contiguous segments of about kSegWork interactions per point, evaluates
+// each (point, segment) pair as an independent unit and adds the segments'
+// partial sums in segment order.  The plan depends on the element count and
+// the copies only, so a point's result does not depend on how many other
+// points share its launch; and a launch of a few hundred thousand points
+// over tens of thousands of elements still has ~10^5 workgroups, so its last
+// round of waves is a small share of it (one workgroup per 256 points over
+// all elements would leave a 200 000-point launch at 1.5 rounds).
+int64_t img_copies(const ImgArgs &img)
+{
+    int64_t t = (int64_t)(2 * img.n1 + 1) * (2 * img.n2 + 1);
+    if (img.hole >= 0) {
+        const int64_t h1 = img.hole < img.n1 ? img.hole : img.n1;
+        const int64_t h2 = img.hole < img.n2 ? img.hole : img.n2;
+        t -= (2 * h1 + 1) * (2 * h2 + 1);
+    }
+    return (int64_t)img.nref * t;
+}
+
+SegPlan seg_plan(int64_t n, const ImgArgs &img)
+{
+    SegPlan p = {1, (int)(n > 0 ? n : 1)};
+    if (n <= 0) return p;
+    const double per_pt = (double)n * (double)img_copies(img);
+    int nseg = (int)(per_pt / kSegWork + 0.5);
+    nseg = nseg < 1 ? 1 : (nseg > kMaxSeg ? kMaxSeg : nseg);
+    if (nseg > n) nseg = (int)n;
+    p.segsz = (int)((n + nseg - 1) / nseg);
+    p.nseg = (int)((n + p.segsz - 1) / p.segsz);
+    return p;
+}
+
 // FP64: the default allocation (about 200 VGPRs, two waves per SIMD) keeps every
 // value in registers; a three-wave target made the allocator spill part of
 // the per-element setup to scratch (10.6 GB of HBM writes per 10^6-point
 // launch) for no measurable gain.  HOLE: img.hole is honoured (a separate
 // instantiation, so the plain launch carries no test for it).
+// Grid: x over blocks of kBlock points, y over element segments of segsz
+// elements; segment y writes its sums (times `scale`) at outputs + y * seg_stride.
 template <bool HOLE>
 __global__ __launch_bounds__(kBlock) void k_eval_fp64(
-    const double *__restrict__ drec, const double *__restrict__ sigma, int n, ImgArgs img, double near_factor,
-    const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz, int m,
-    double *__restrict__ phi, double *__restrict__ ex, double *__restrict__ ey, double *__restrict__ ez)
+    const double *__restrict__ drec, const double *__restrict__ sigma, int n, int segsz, ImgArgs img,
+    double near_factor, const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz,
+    int m, double scale, double *__restrict__ phi, double *__restrict__ ex, double *__restrict__ ey,
+    double *__restrict__ ez, int64_t seg_stride)
 {
-    eval_block<false, kBlock, HOLE>(drec, sigma, n, img, near_factor, px, py, pz, m, blockIdx.x * kBlock, kKe, phi, ex, ey,
-                              ez);
+    const int e0 = blockIdx.y * segsz;
+    const size_t so = (size_t)blockIdx.y * (size_t)seg_stride;
+    eval_block<false, kBlock, HOLE>(drec + (size_t)e0 * R_STRIDE, sigma + e0, min(segsz, n - e0), img, near_factor,
+                                    px, py, pz, m, blockIdx.x * kBlock, scale, phi ? phi + so : nullptr,
+                                    ex ? ex + so : nullptr, ey ? ey + so : nullptr, ez ? ez + so : nullptr);
 }
 
 // Mixed: three waves per SIMD (13 % faster than two): the allocator spills a
 // few values of the per-element setup, outside the per-copy loop.
 template <bool HOLE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_eval_mixed(
-    const double *__restrict__ drec, const double *__restrict__ sigma, int n, ImgArgs img, double near_factor,
-    const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz, int m,
-    double *__restrict__ phi, double *__restrict__ ex, double *__restrict__ ey, double *__restrict__ ez)
+    const double *__restrict__ drec, const double *__restrict__ sigma, int n, int segsz, ImgArgs img,
+    double near_factor, const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz,
+    int m, double scale, double *__restrict__ phi, double *__restrict__ ex, double *__restrict__ ey,
+    double *__restrict__ ez, int64_t seg_stride)
 {
-    eval_block<true, kBlock, HOLE>(drec, sigma, n, img, near_factor, px, py, pz, m, blockIdx.x * kBlock, kKe, phi, ex, ey,
-                             ez);
+    const int e0 = blockIdx.y * segsz;
+    const size_t so = (size_t)blockIdx.y * (size_t)seg_stride;
+    eval_block<true, kBlock, HOLE>(drec + (size_t)e0 * R_STRIDE, sigma + e0, min(segsz, n - e0), img, near_factor,
+                                   px, py, pz, m, blockIdx.x * kBlock, scale, phi ? phi + so : nullptr,
+                                   ex ? ex + so : nullptr, ey ? ey + so : nullptr, ez ? ez + so : nullptr);
 }
 
-void launch_eval(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
-                 double near_factor, const double *px, const double *py, const double *pz, int64_t m, double *phi,
-                 double *ex, double *ey, double *ez, hipStream_t s)
+void launch_eval_seg(const double *drec, const double *sigma, int64_t n, const SegPlan &sp, const ImgArgs &img,
+                     int mixed, double near_factor, const double *px, const double *py, const double *pz, int64_t m,
+                     double scale, double *phi, double *ex, double *ey, double *ez, int64_t seg_stride, hipStream_t s)
 {
-    if (m <= 0) return;
-    const unsigned g = (unsigned)((m + kBlock - 1) / kBlock);
+    if (m <= 0 || n <= 0) return;
+    const dim3 g((unsigned)((m + kBlock - 1) / kBlock), (unsigned)sp.nseg);
     const bool hole = img.hole >= 0;
     auto k = mixed ? (hole ? k_eval_mixed<true> : k_eval_mixed<false>)
                    : (hole ? k_eval_fp64<true> : k_eval_fp64<false>);
-    hipLaunchKernelGGL(k, dim3(g), dim3(kBlock), 0, s, drec, sigma, (int)n, img, near_factor, px, py, pz, (int)m, phi,
-                       ex, ey, ez);
+    hipLaunchKernelGGL(k, g, dim3(kBlock), 0, s, drec, sigma, (int)n, sp.segsz, img, near_factor, px, py, pz, (int)m,
+                       scale, phi, ex, ey, ez, seg_stride);
 }
 
 // out[c][i] += add[c m + i] for the non-null outputs
@@ -442,9 +486,10 @@ void launch_prim_density(const double *drec, const double *sigma, const int32_t 
 // null: that component is not stored).
 template <bool MIXED, int K>
 __device__ __forceinline__ void eval_block_multi(const double *__restrict__ drec, const double *__restrict__ sigma,
-                                                 int n, const ImgArgs &img, double near_factor,
+                                                 int n, int64_t sig_stride, const ImgArgs &img, double near_factor,
                                                  const double *__restrict__ px, const double *__restrict__ py,
-                                                 const double *__restrict__ pz, int m, int base_pt, OutCols out)
+                                                 const double *__restrict__ pz, int m, int base_pt, double scale,
+                                                 OutCols out)
 {
     __shared__ double t_rec[kTileE * R_STRIDE];
     __shared__ double t_sig[kTileE * K];
@@ -462,7 +507,7 @@ __device__ __forceinline__ void eval_block_multi(const double *__restrict__ drec
         for (int q = threadIdx.x; q < cnt * R_STRIDE; q += kBlock) t_rec[q] = drec[(size_t)base * R_STRIDE + q];
         for (int q = threadIdx.x; q < cnt * K; q += kBlock) {
             const int pp = q / K, k = q % K;
-            t_sig[q] = sigma[(size_t)k * n + base + pp];
+            t_sig[q] = sigma[(size_t)k * sig_stride + base + pp];
         }
         __syncthreads();
         for (int p = 0; p < cnt; ++p) {
@@ -483,61 +528,92 @@ __device__ __forceinline__ void eval_block_multi(const double *__restrict__ drec
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const size_t o = (size_t)k * out.stride + i;
-            if (out.c[0]) out.c[0][o] = kKe * aphi[k];
-            if (out.c[1]) out.c[1][o] = kKe * aex[k];
-            if (out.c[2]) out.c[2][o] = kKe * aey[k];
-            if (out.c[3]) out.c[3][o] = kKe * aez[k];
+            if (out.c[0]) out.c[0][o] = scale * aphi[k];
+            if (out.c[1]) out.c[1][o] = scale * aex[k];
+            if (out.c[2]) out.c[2][o] = scale * aey[k];
+            if (out.c[3]) out.c[3][o] = scale * aez[k];
         }
     }
 }
 
+// outputs of segment `seg`: every stored component moved by seg * seg_stride
+__device__ __forceinline__ OutCols seg_out(OutCols o, int seg, int64_t seg_stride)
+{
+    const size_t so = (size_t)seg * (size_t)seg_stride;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) o.c[c] = o.c[c] ? o.c[c] + so : nullptr;
+    return o;
+}
+
+// grid as k_eval_fp64: x over point blocks, y over element segments
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_eval_multi_fp64(const double *__restrict__ drec,
-                                                            const double *__restrict__ sigma, int n, ImgArgs img,
+                                                            const double *__restrict__ sigma, int n,
+                                                            int64_t sig_stride, int segsz, ImgArgs img,
                                                             double near_factor, const double *__restrict__ px,
                                                             const double *__restrict__ py,
-                                                            const double *__restrict__ pz, int m, OutCols out)
+                                                            const double *__restrict__ pz, int m, double scale,
+                                                            OutCols out, int64_t seg_stride)
 {
-    eval_block_multi<false, K>(drec, sigma, n, img, near_factor, px, py, pz, m, blockIdx.x * kBlock, out);
+    const int e0 = blockIdx.y * segsz;
+    eval_block_multi<false, K>(drec + (size_t)e0 * R_STRIDE, sigma + e0, min(segsz, n - e0), sig_stride, img,
+                               near_factor, px, py, pz, m, blockIdx.x * kBlock, scale,
+                               seg_out(out, blockIdx.y, seg_stride));
 }
 
 // at most 256 VGPRs so that two waves share a SIMD (unbounded, K = 3 and 4
 // would take 258 and 266)
 template <int K>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_eval_multi_mixed(const double *__restrict__ drec,
-                                                             const double *__restrict__ sigma, int n, ImgArgs img,
-                                                             double near_factor, const double *__restrict__ px,
-                                                             const double *__restrict__ py,
-                                                             const double *__restrict__ pz, int m, OutCols out)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_eval_multi_mixed(
+    const double *__restrict__ drec, const double *__restrict__ sigma, int n, int64_t sig_stride, int segsz,
+    ImgArgs img, double near_factor, const double *__restrict__ px, const double *__restrict__ py,
+    const double *__restrict__ pz, int m, double scale, OutCols out, int64_t seg_stride)
 {
-    eval_block_multi<true, K>(drec, sigma, n, img, near_factor, px, py, pz, m, blockIdx.x * kBlock, out);
+    const int e0 = blockIdx.y * segsz;
+    eval_block_multi<true, K>(drec + (size_t)e0 * R_STRIDE, sigma + e0, min(segsz, n - e0), sig_stride, img,
+                              near_factor, px, py, pz, m, blockIdx.x * kBlock, scale,
+                              seg_out(out, blockIdx.y, seg_stride));
 }
 
 template <int K>
-static void launch_multi_k(const double *drec, const double *sigma, int n, const ImgArgs &img, int mixed,
-                           double near_factor, const double *px, const double *py, const double *pz, int m,
-                           const OutCols &out, hipStream_t s)
+static void launch_multi_k(const double *drec, const double *sigma, int n, int64_t sig_stride, const SegPlan &sp,
+                           const ImgArgs &img, int mixed, double near_factor, const double *px, const double *py,
+                           const double *pz, int m, double scale, const OutCols &out, int64_t seg_stride,
+                           hipStream_t s)
 {
-    const unsigned g = (unsigned)((m + kBlock - 1) / kBlock);
+    const dim3 g((unsigned)((m + kBlock - 1) / kBlock), (unsigned)sp.nseg);
     if (mixed)
-        hipLaunchKernelGGL(k_eval_multi_mixed<K>, dim3(g), dim3(kBlock), 0, s, drec, sigma, n, img, near_factor, px,
-                           py, pz, m, out);
+        hipLaunchKernelGGL(k_eval_multi_mixed<K>, g, dim3(kBlock), 0, s, drec, sigma, n, sig_stride, sp.segsz, img,
+                           near_factor, px, py, pz, m, scale, out, seg_stride);
     else
-        hipLaunchKernelGGL(k_eval_multi_fp64<K>, dim3(g), dim3(kBlock), 0, s, drec, sigma, n, img, near_factor, px,
-                           py, pz, m, out);
+        hipLaunchKernelGGL(k_eval_multi_fp64<K>, g, dim3(kBlock), 0, s, drec, sigma, n, sig_stride, sp.segsz, img,
+                           near_factor, px, py, pz, m, scale, out, seg_stride);
 }
 
-void launch_eval_multi(const double *drec, const double *sigma, int64_t n, int ncol, const ImgArgs &img, int mixed,
-                       double near_factor, const double *px, const double *py, const double *pz, int64_t m,
-                       const OutCols &out, hipStream_t s)
+void launch_eval_multi_seg(const double *drec, const double *sigma, int64_t n, int64_t sig_stride, int ncol,
+                           const SegPlan &sp, const ImgArgs &img, int mixed, double near_factor, const double *px,
+                           const double *py, const double *pz, int64_t m, double scale, const OutCols &out,
+                           int64_t seg_stride, hipStream_t s)
 {
-    if (m <= 0 || ncol <= 0) return;
+    if (m <= 0 || ncol <= 0 || n <= 0) return;
     const int nn = (int)n, mm = (int)m;
     switch (ncol) {
-    case 1: launch_multi_k<1>(drec, sigma, nn, img, mixed, near_factor, px, py, pz, mm, out, s); break;
-    case 2: launch_multi_k<2>(drec, sigma, nn, img, mixed, near_factor, px, py, pz, mm, out, s); break;
-    case 3: launch_multi_k<3>(drec, sigma, nn, img, mixed, near_factor, px, py, pz, mm, out, s); break;
-    default: launch_multi_k<4>(drec, sigma, nn, img, mixed, near_factor, px, py, pz, mm, out, s); break;
+    case 1:
+        launch_multi_k<1>(drec, sigma, nn, sig_stride, sp, img, mixed, near_factor, px, py, pz, mm, scale, out,
+                          seg_stride, s);
+        break;
+    case 2:
+        launch_multi_k<2>(drec, sigma, nn, sig_stride, sp, img, mixed, near_factor, px, py, pz, mm, scale, out,
+                          seg_stride, s);
+        break;
+    case 3:
+        launch_multi_k<3>(drec, sigma, nn, sig_stride, sp, img, mixed, near_factor, px, py, pz, mm, scale, out,
+                          seg_stride, s);
+        break;
+    default:
+        launch_multi_k<4>(drec, sigma, nn, sig_stride, sp, img, mixed, near_factor, px, py, pz, mm, scale, out,
+                          seg_stride, s);
+        break;
     }
 }
 
@@ -572,24 +648,30 @@ void launch_eval_items(const WorkItem *items, int nitems, const ImgArgs *imgs, i
         hipLaunchKernelGGL(k_eval_items_fp64, dim3(nitems), dim3(64), 0, s, items, imgs, near_factor);
 }
 
-// out[k][i] = k_e sum_{s < nseg} part[(s * 4 + k) * m + i], k = phi, ex, ey, ez
-__global__ __launch_bounds__(kBlock) void k_reduce_segments(const double *__restrict__ part, int nseg, int m,
-                                                             double *__restrict__ out)
+// Segment partial sums -> results: for column k < ncol and component c,
+// out.c[c][k * out.stride + i] = k_e (0 + sum over s = 0 .. nseg-1, in that
+// order, of part[s * seg_stride + (4 k + c) m + i]); null components skipped.
+__global__ __launch_bounds__(kBlock) void k_reduce_segments(const double *__restrict__ part, int nseg, int ncol,
+                                                             int m, int64_t seg_stride, OutCols out)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= m) return;
-    for (int k = 0; k < 4; ++k) {
-        double acc = 0.0;
-        for (int s = 0; s < nseg; ++s) acc += part[((size_t)s * 4 + k) * m + i];
-        out[(size_t)k * m + i] = kKe * acc;
-    }
+    for (int k = 0; k < ncol; ++k)
+        for (int c = 0; c < 4; ++c) {
+            if (!out.c[c]) continue;
+            const double *p = part + (size_t)(4 * k + c) * m + i;
+            double acc = 0.0;
+            for (int s = 0; s < nseg; ++s) acc += p[(size_t)s * (size_t)seg_stride];
+            out.c[c][(size_t)k * out.stride + i] = kKe * acc;
+        }
 }
 
-void launch_reduce_segments(const double *part, int nseg, int64_t m, double *out, hipStream_t s)
+void launch_reduce_segments(const double *part, int nseg, int ncol, int64_t m, int64_t seg_stride,
+                            const OutCols &out, hipStream_t s)
 {
     if (m <= 0) return;
     hipLaunchKernelGGL(k_reduce_segments, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, part, nseg,
-                       (int)m, out);
+                       ncol, (int)m, seg_stride, out);
 }
 
 // ---------------------------------------------------------------- assembly

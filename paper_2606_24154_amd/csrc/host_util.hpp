@@ -38,6 +38,11 @@ nebem_status voxel_grid_args(const nebem_grid *vox, GridArgs &g);
 nebem_status check_options(const nebem_options &o);
 // Derived element records (validated; synchronises the stream).
 nebem_status derive(const nebem_panels *p, hipStream_t s, DevBuf &drec);
+// run_eval with a stream-ordered workspace of its preferred size (api.hip)
+nebem_status eval_with_workspace(const double *drec, const double *sigma, int64_t n, int ncol, const ImgArgs &ia,
+                                 int mixed, double near_factor, const double *px, const double *py, const double *pz,
+                                 int64_t m, double *phi, double *ex, double *ey, double *ez, hipStream_t stream,
+                                 const char *what);
 void pivots_to_perm(const std::vector<int> &ipiv, std::vector<int> &perm);
 
 // Dense solve drivers (solver.hip).  FP64: A is factored in place.

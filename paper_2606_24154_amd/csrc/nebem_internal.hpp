@@ -79,10 +79,6 @@ struct WorkItem {
 // bad_count[1] = first invalid index (or n).  bad_count must be zeroed/set
 // to {0, n} by the caller.
 void launch_prep(const nebem_panels *p, double *drec, int *bad, hipStream_t s);
-// mixed != 0: copies beyond the far-field tiers (rectangles >= 24 D,
-// triangles >= 48 D, never below near_factor D) use the FP64 monopole + FP32
-// correction far field, nearer ones the exact FP64 closed forms; mixed == 0:
-// the exact FP64 closed forms everywhere.
 // FastVolume grid (fastvol_kernels.hip): nodes origin + (i, j, k) * step,
 // n[0] x n[1] x n[2] of them, node values interleaved 4 per node.
 struct GridArgs {
@@ -122,15 +118,37 @@ struct OutCols {
     int64_t stride;
 };
 constexpr int kMultiCols = 4;  // density columns per evaluation launch
-// ncol <= kMultiCols columns of sigma (column k at sigma + k n)
-void launch_eval_multi(const double *drec, const double *sigma, int64_t n, int ncol, const ImgArgs &img, int mixed,
-                       double near_factor, const double *px, const double *py, const double *pz, int64_t m,
-                       const OutCols &out, hipStream_t s);
-void launch_eval(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
-                 double near_factor, const double *px, const double *py, const double *pz, int64_t m, double *phi,
-                 double *ex, double *ey, double *ez, hipStream_t s);
-// ---- evaluation in Morton order of the points (order_kernels.hip); the
-// results are bit-identical to launch_eval's, in the caller's order.
+
+// Element segments of an evaluation (field_kernels.hip): nseg contiguous
+// ranges of segsz elements (the last may be shorter), about kSegWork
+// interactions per point each; a function of the element count and copies
+// only, shared by every evaluation path and the server.
+constexpr double kSegWork = 1.2e5;
+constexpr int kMaxSeg = 64;
+struct SegPlan {
+    int nseg, segsz;
+};
+int64_t img_copies(const ImgArgs &img);  // copies per element (reflections x translations, minus any hole)
+SegPlan seg_plan(int64_t n, const ImgArgs &img);
+// In the evaluation launchers, mixed != 0: copies beyond the far-field tiers
+// (rectangles >= 24 D, triangles >= 48 D, never below near_factor D) use the
+// FP64 monopole + FP32 correction far field, nearer ones the exact FP64
+// closed forms; mixed == 0: the exact FP64 closed forms everywhere.
+// One launch over all segments: segment y's sums (times `scale`) go to the
+// outputs + y * seg_stride (nseg == 1, scale k_e: the final results).
+void launch_eval_seg(const double *drec, const double *sigma, int64_t n, const SegPlan &sp, const ImgArgs &img,
+                     int mixed, double near_factor, const double *px, const double *py, const double *pz, int64_t m,
+                     double scale, double *phi, double *ex, double *ey, double *ez, int64_t seg_stride, hipStream_t s);
+// ncol <= kMultiCols columns of sigma (column k at sigma + k sig_stride)
+void launch_eval_multi_seg(const double *drec, const double *sigma, int64_t n, int64_t sig_stride, int ncol,
+                           const SegPlan &sp, const ImgArgs &img, int mixed, double near_factor, const double *px,
+                           const double *py, const double *pz, int64_t m, double scale, const OutCols &out,
+                           int64_t seg_stride, hipStream_t s);
+// out.c[c][k stride + i] = k_e * (0 + sum_s part[s seg_stride + (4k + c) m + i]), in segment order
+void launch_reduce_segments(const double *part, int nseg, int ncol, int64_t m, int64_t seg_stride,
+                            const OutCols &out, hipStream_t s);
+
+// ---- Morton order of points (order_kernels.hip)
 bool eval_ordering_pays(int64_t m);
 // Morton order of m points: s{x,y,z}[k] = p{x,y,z}[perm[k]]; ws of
 // order_points_workspace(m) bytes (0 on error)
@@ -140,23 +158,25 @@ hipError_t launch_order_points(const double *px, const double *py, const double 
 // d_j[perm[k]] = src[j * m + k] for each non-null d_j (j = 0..3)
 void launch_unorder4(const double *src, const int *perm, int64_t m, double *d0, double *d1, double *d2, double *d3,
                      hipStream_t s);
-size_t ordered_eval_workspace(int64_t m);  // bytes of device workspace, 0 on error
-size_t ordered_eval_multi_workspace(int64_t m);
-// ncol columns (any count; launched kMultiCols at a time) of sigma, points
-// ordered once; outputs m x ncol column-major per component (null: skipped)
-hipError_t launch_eval_multi_ordered(const double *drec, const double *sigma, int64_t n, int ncol, const ImgArgs &img,
-                                     int mixed, double near_factor, const double *px, const double *py,
-                                     const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
-                                     void *ws, size_t ws_bytes, hipStream_t s);
-hipError_t launch_eval_ordered(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
-                               double near_factor, const double *px, const double *py, const double *pz, int64_t m,
-                               double *phi, double *ex, double *ey, double *ez, void *ws, size_t ws_bytes,
-                               hipStream_t s);
+
+// ---- the evaluation driver (order_kernels.hip), used by every evaluation
+// entry point: ncol density columns (column k at sigma + k n), outputs m x
+// ncol column-major per component (null: not stored).  Points are taken in
+// chunks whose workspace fits ws_bytes; chunks of >= 4096 points are
+// evaluated in Morton order; every element segment of a chunk is one grid
+// row, and the segments' partial sums are reduced in segment order.  No
+// result bit depends on the chunking, the ordering or the other points.
+// eval_workspace: the workspace that lets the driver take its preferred
+// chunk (0 when none is needed).
+size_t eval_workspace(int64_t n, const ImgArgs &img, int64_t m, int ncol);
+// smallest workspace with which run_eval accepts the call
+size_t eval_workspace_min(int64_t n, const ImgArgs &img, int64_t m, int ncol);
+hipError_t run_eval(const double *drec, const double *sigma, int64_t n, int ncol, const ImgArgs &img, int mixed,
+                    double near_factor, const double *px, const double *py, const double *pz, int64_t m, double *phi,
+                    double *ex, double *ey, double *ez, void *ws, size_t ws_bytes, hipStream_t s);
 // items/imgs in device memory; one 64-lane workgroup per item
 void launch_eval_items(const WorkItem *items, int nitems, const ImgArgs *imgs, int mixed, double near_factor,
                        hipStream_t s);
-// out (4 x m) = k_e * sum over nseg segments of part (nseg x 4 x m), fixed order
-void launch_reduce_segments(const double *part, int nseg, int64_t m, double *out, hipStream_t s);
 // A (n x n col-major), exact closed forms.  cx/cy/cz may be null (centroids).
 void launch_assemble(const double *drec, int64_t n, const ImgArgs &img, const double *cx, const double *cy,
                      const double *cz, double *A, hipStream_t s);

@@ -13,8 +13,9 @@
 // caller's order.
 #include <hip/hip_runtime.h>
 
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
+#include <algorithm>
 #include <cmath>
 
 #include "nebem_internal.hpp"
@@ -127,18 +128,17 @@ __global__ __launch_bounds__(kOB) void k_scatter4(const double *__restrict__ src
 namespace {
 // scratch of one sort: keys (in/out), identity indices, partial boxes, sort temp
 struct SortLayout {
-    size_t keys_in, keys_out, idx_in, part, cub, total;
-    size_t cub_bytes;
+    size_t keys_in, keys_out, idx_in, part, sort, total;
+    size_t sort_bytes;
 };
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 hipError_t sort_layout(int64_t m, SortLayout &L)
 {
-    size_t cub_bytes = 0;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, cub_bytes, (const unsigned *)nullptr,
-                                                      (unsigned *)nullptr, (const int *)nullptr, (int *)nullptr,
-                                                      (int)m, 0, 30);
+    size_t sort_bytes = 0;
+    hipError_t e = rocprim::radix_sort_pairs(nullptr, sort_bytes, (const unsigned *)nullptr, (unsigned *)nullptr,
+                                             (const int *)nullptr, (int *)nullptr, (int)m, 0u, 30u);
     if (e != hipSuccess) return e;
     size_t off = 0;
     auto take = [&](size_t b) {
@@ -150,8 +150,8 @@ hipError_t sort_layout(int64_t m, SortLayout &L)
     L.keys_out = take(4 * (size_t)m);
     L.idx_in = take(4 * (size_t)m);
     L.part = take(sizeof(double) * 6 * kBoxParts);
-    L.cub = take(cub_bytes);
-    L.cub_bytes = cub_bytes;
+    L.sort = take(sort_bytes);
+    L.sort_bytes = sort_bytes;
     L.total = off;
     return hipSuccess;
 }
@@ -184,8 +184,8 @@ hipError_t launch_order_points(const double *px, const double *py, const double 
     const int nparts = (int)std::min<int64_t>(kBoxParts, g);
     hipLaunchKernelGGL(k_bbox_part, dim3(nparts), dim3(kOB), 0, s, px, py, pz, mi, part);
     hipLaunchKernelGGL(k_keys, dim3(g), dim3(kOB), 0, s, px, py, pz, mi, part, nparts, keys_in, idx_in);
-    size_t cub_bytes = L.cub_bytes;
-    e = hipcub::DeviceRadixSort::SortPairs(w + L.cub, cub_bytes, keys_in, keys_out, idx_in, perm, mi, 0, 30, s);
+    size_t sort_bytes = L.sort_bytes;
+    e = rocprim::radix_sort_pairs(w + L.sort, sort_bytes, keys_in, keys_out, idx_in, perm, mi, 0u, 30u, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gather3, dim3(g), dim3(kOB), 0, s, px, py, pz, perm, mi, sx, sy, sz);
     return hipGetLastError();
@@ -199,74 +199,178 @@ void launch_unorder4(const double *src, const int *perm, int64_t m, double *d0, 
                        d2, d3);
 }
 
-// evaluation workspace: the sort's scratch, then perm, sorted points and
-// sorted results
-size_t ordered_eval_workspace(int64_t m)
+// ------------------------------------------------------- evaluation driver
+namespace {
+constexpr size_t kPartBudget = size_t(256) << 20;  // preferred bytes of segment partial sums per chunk
+
+struct EvalShape {
+    SegPlan sp;
+    int kc;           // columns per launch
+    size_t part_pp;   // partial-sum bytes per point (0: one segment, no partials)
+};
+
+EvalShape eval_shape(int64_t n, const ImgArgs &img, int ncol)
 {
-    const size_t w = order_points_workspace(m);
-    if (!w) return 0;
-    return w + align256(4 * (size_t)m) + align256(24 * (size_t)m) + align256(32 * (size_t)m);
+    EvalShape sh;
+    sh.sp = seg_plan(n, img);
+    sh.kc = ncol < kMultiCols ? ncol : kMultiCols;
+    sh.part_pp = sh.sp.nseg > 1 ? (size_t)32 * sh.kc * sh.sp.nseg : 0;
+    return sh;
 }
 
-hipError_t launch_eval_ordered(const double *drec, const double *sigma, int64_t n, const ImgArgs &img, int mixed,
-                               double near_factor, const double *px, const double *py, const double *pz, int64_t m,
-                               double *phi, double *ex, double *ey, double *ez, void *ws, size_t ws_bytes,
-                               hipStream_t s)
+// workspace layout of one chunk of c points: [sort scratch | perm | sorted
+// points | sorted results (kc columns)] when ordered, then the partial sums
+struct ChunkLayout {
+    bool ordered;
+    size_t sort_ws, perm, pts, res, part, total;
+};
+
+bool chunk_layout(const EvalShape &sh, int64_t c, ChunkLayout &L)
 {
-    if (m <= 0) return hipSuccess;
-    const size_t w0 = order_points_workspace(m);
-    if (!w0) return hipErrorInvalidValue;
-    if (!ws || ws_bytes < ordered_eval_workspace(m)) return hipErrorInvalidValue;
-    char *w = static_cast<char *>(ws);
-    int *perm = reinterpret_cast<int *>(w + w0);
-    double *sp = reinterpret_cast<double *>(w + w0 + align256(4 * (size_t)m));
-    double *so = reinterpret_cast<double *>(w + w0 + align256(4 * (size_t)m) + align256(24 * (size_t)m));
-    const size_t mm = (size_t)m;
-    hipError_t e = launch_order_points(px, py, pz, m, sp, sp + mm, sp + 2 * mm, perm, ws, w0, s);
-    if (e != hipSuccess) return e;
-    launch_eval(drec, sigma, n, img, mixed, near_factor, sp, sp + mm, sp + 2 * mm, m, phi ? so : nullptr,
-                ex ? so + mm : nullptr, ey ? so + 2 * mm : nullptr, ez ? so + 3 * mm : nullptr, s);
-    launch_unorder4(so, perm, m, phi, ex, ey, ez, s);
-    return hipGetLastError();
+    L.ordered = eval_ordering_pays(c);
+    size_t off = 0;
+    L.sort_ws = L.perm = L.pts = L.res = 0;
+    if (L.ordered) {
+        const size_t w = order_points_workspace(c);
+        if (!w) return false;
+        L.sort_ws = w;
+        off = w;
+        L.perm = off;
+        off += align256(4 * (size_t)c);
+        L.pts = off;
+        off += align256(24 * (size_t)c);
+        L.res = off;
+        off += align256(32 * (size_t)sh.kc * (size_t)c);
+    }
+    L.part = off;
+    off += align256(sh.part_pp * (size_t)c);
+    L.total = off;
+    return true;
 }
 
-// several-column evaluation: the sort's scratch, perm, sorted points and
-// the sorted results of one chunk of kMultiCols columns
-size_t ordered_eval_multi_workspace(int64_t m)
+int64_t preferred_chunk(const EvalShape &sh, int64_t m)
 {
-    const size_t w = order_points_workspace(m);
-    if (!w) return 0;
-    return w + align256(4 * (size_t)m) + align256(24 * (size_t)m) + align256(32 * kMultiCols * (size_t)m);
+    int64_t c = m;
+    if (sh.part_pp) {
+        const int64_t lim = (int64_t)(kPartBudget / sh.part_pp) & ~(int64_t)255;
+        c = std::min<int64_t>(m, std::max<int64_t>(lim, 256));
+    }
+    return c;
 }
 
-hipError_t launch_eval_multi_ordered(const double *drec, const double *sigma, int64_t n, int ncol, const ImgArgs &img,
-                                     int mixed, double near_factor, const double *px, const double *py,
-                                     const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
-                                     void *ws, size_t ws_bytes, hipStream_t s)
+// one chunk of c points (unsorted input px.., outputs o.c[comp] + col * ostride)
+void eval_chunk(const double *drec, const double *sigma, int64_t n, int ncol, const EvalShape &sh,
+                const ImgArgs &img, int mixed, double near_factor, const double *px, const double *py,
+                const double *pz, int64_t c, const OutCols &o, double *part, hipStream_t s)
 {
-    if (m <= 0 || ncol <= 0) return hipSuccess;
-    const size_t w0 = order_points_workspace(m);
-    if (!w0) return hipErrorInvalidValue;
-    if (!ws || ws_bytes < ordered_eval_multi_workspace(m)) return hipErrorInvalidValue;
-    char *w = static_cast<char *>(ws);
-    int *perm = reinterpret_cast<int *>(w + w0);
-    double *sp = reinterpret_cast<double *>(w + w0 + align256(4 * (size_t)m));
-    double *so = reinterpret_cast<double *>(w + w0 + align256(4 * (size_t)m) + align256(24 * (size_t)m));
-    const size_t mm = (size_t)m;
-    hipError_t e = launch_order_points(px, py, pz, m, sp, sp + mm, sp + 2 * mm, perm, ws, w0, s);
-    if (e != hipSuccess) return e;
     for (int c0 = 0; c0 < ncol; c0 += kMultiCols) {
         const int k = ncol - c0 < kMultiCols ? ncol - c0 : kMultiCols;
-        // sorted results of column j of the chunk: so + 4 j m (phi, ex, ey, ez)
-        OutCols out = {{phi ? so : nullptr, ex ? so + mm : nullptr, ey ? so + 2 * mm : nullptr,
-                        ez ? so + 3 * mm : nullptr},
-                       (int64_t)(4 * mm)};
-        launch_eval_multi(drec, sigma + (size_t)c0 * n, n, k, img, mixed, near_factor, sp, sp + mm, sp + 2 * mm, m,
-                          out, s);
-        for (int j = 0; j < k; ++j) {
-            const size_t col = (size_t)(c0 + j) * mm;
-            launch_unorder4(so + 4 * (size_t)j * mm, perm, m, phi ? phi + col : nullptr, ex ? ex + col : nullptr,
-                            ey ? ey + col : nullptr, ez ? ez + col : nullptr, s);
+        const double *sg = sigma + (size_t)c0 * n;
+        OutCols oc = o;
+        for (int q = 0; q < 4; ++q) oc.c[q] = o.c[q] ? o.c[q] + (size_t)c0 * o.stride : nullptr;
+        if (sh.sp.nseg == 1) {
+            if (ncol == 1)
+                launch_eval_seg(drec, sg, n, sh.sp, img, mixed, near_factor, px, py, pz, c, kKe, oc.c[0], oc.c[1],
+                                oc.c[2], oc.c[3], 0, s);
+            else
+                launch_eval_multi_seg(drec, sg, n, n, k, sh.sp, img, mixed, near_factor, px, py, pz, c, kKe, oc, 0,
+                                      s);
+            continue;
+        }
+        // partials: column j, component q of segment y at part + y * 4 k c + (4 j + q) c
+        const size_t cc = (size_t)c;
+        OutCols pc = {{o.c[0] ? part : nullptr, o.c[1] ? part + cc : nullptr, o.c[2] ? part + 2 * cc : nullptr,
+                       o.c[3] ? part + 3 * cc : nullptr},
+                      (int64_t)(4 * cc)};
+        const int64_t seg_stride = (int64_t)(4 * (size_t)k * cc);
+        if (ncol == 1)
+            launch_eval_seg(drec, sg, n, sh.sp, img, mixed, near_factor, px, py, pz, c, 1.0, pc.c[0], pc.c[1], pc.c[2],
+                            pc.c[3], seg_stride, s);
+        else
+            launch_eval_multi_seg(drec, sg, n, n, k, sh.sp, img, mixed, near_factor, px, py, pz, c, 1.0, pc,
+                                  seg_stride, s);
+        launch_reduce_segments(part, sh.sp.nseg, k, c, seg_stride, oc, s);
+    }
+}
+}  // namespace
+
+size_t eval_workspace(int64_t n, const ImgArgs &img, int64_t m, int ncol)
+{
+    if (m <= 0 || ncol <= 0 || n <= 0) return 0;
+    const EvalShape sh = eval_shape(n, img, ncol);
+    ChunkLayout L;
+    if (!chunk_layout(sh, preferred_chunk(sh, m), L)) return 0;
+    return L.total;
+}
+
+size_t eval_workspace_min(int64_t n, const ImgArgs &img, int64_t m, int ncol)
+{
+    if (m <= 0 || ncol <= 0 || n <= 0) return 0;
+    const EvalShape sh = eval_shape(n, img, ncol);
+    ChunkLayout L;
+    if (!chunk_layout(sh, std::min<int64_t>(m, 256), L)) return 0;
+    return L.total;
+}
+
+hipError_t run_eval(const double *drec, const double *sigma, int64_t n, int ncol, const ImgArgs &img, int mixed,
+                    double near_factor, const double *px, const double *py, const double *pz, int64_t m, double *phi,
+                    double *ex, double *ey, double *ez, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    if (m <= 0 || ncol <= 0) return hipSuccess;
+    const size_t mm = (size_t)m;
+    if (n <= 0) {  // no elements: zero fields
+        for (double *o : {phi, ex, ey, ez})
+            if (o) {
+                hipError_t e = hipMemsetAsync(o, 0, mm * (size_t)ncol * sizeof(double), s);
+                if (e != hipSuccess) return e;
+            }
+        return hipSuccess;
+    }
+    const EvalShape sh = eval_shape(n, img, ncol);
+    // the largest chunk (up to the preferred one) whose workspace fits
+    int64_t c = preferred_chunk(sh, m);
+    ChunkLayout L;
+    for (;;) {
+        if (!chunk_layout(sh, c, L)) return hipErrorInvalidValue;
+        if (L.total <= ws_bytes || (L.total == 0)) break;
+        if (c <= 256) return hipErrorInvalidValue;
+        c = std::max<int64_t>(256, (c / 2) & ~(int64_t)255);
+    }
+    if (L.total > 0 && !ws) return hipErrorInvalidValue;
+    char *w = static_cast<char *>(ws);
+    double *part = sh.part_pp ? reinterpret_cast<double *>(w + L.part) : nullptr;
+    for (int64_t p0 = 0; p0 < m; p0 += c) {
+        const int64_t cnt = std::min<int64_t>(c, m - p0);
+        ChunkLayout Lc;
+        if (!chunk_layout(sh, cnt, Lc) || Lc.total > ws_bytes) return hipErrorInvalidValue;
+        if (!Lc.ordered) {
+            OutCols o = {{phi ? phi + p0 : nullptr, ex ? ex + p0 : nullptr, ey ? ey + p0 : nullptr,
+                          ez ? ez + p0 : nullptr},
+                         m};
+            eval_chunk(drec, sigma, n, ncol, sh, img, mixed, near_factor, px + p0, py + p0, pz + p0, cnt, o, part, s);
+            continue;
+        }
+        const size_t cc = (size_t)cnt;
+        int *perm = reinterpret_cast<int *>(w + Lc.perm);
+        double *sp = reinterpret_cast<double *>(w + Lc.pts);
+        double *so = reinterpret_cast<double *>(w + Lc.res);
+        double *pc = sh.part_pp ? reinterpret_cast<double *>(w + Lc.part) : nullptr;
+        hipError_t e = launch_order_points(px + p0, py + p0, pz + p0, cnt, sp, sp + cc, sp + 2 * cc, perm, ws,
+                                           Lc.sort_ws, s);
+        if (e != hipSuccess) return e;
+        for (int c0 = 0; c0 < ncol; c0 += kMultiCols) {
+            const int k = ncol - c0 < kMultiCols ? ncol - c0 : kMultiCols;
+            // sorted results of column j of this column block: so + 4 j cnt (phi, ex, ey, ez)
+            OutCols o = {{phi ? so : nullptr, ex ? so + cc : nullptr, ey ? so + 2 * cc : nullptr,
+                          ez ? so + 3 * cc : nullptr},
+                         (int64_t)(4 * cc)};
+            eval_chunk(drec, sigma + (size_t)c0 * n, n, k, sh, img, mixed, near_factor, sp, sp + cc, sp + 2 * cc,
+                       cnt, o, pc, s);
+            for (int j = 0; j < k; ++j) {
+                const size_t col = (size_t)(c0 + j) * mm + (size_t)p0;
+                launch_unorder4(so + 4 * (size_t)j * cc, perm, cnt, phi ? phi + col : nullptr,
+                                ex ? ex + col : nullptr, ey ? ey + col : nullptr, ez ? ez + col : nullptr, s);
+            }
         }
     }
     return hipGetLastError();

@@ -45,9 +45,6 @@
 
 namespace nebem {
 
-constexpr double kSegWork = 1.2e5;  // interactions per point per element segment
-constexpr int kMaxSeg = 64;
-
 static double now_s()
 {
     using namespace std::chrono;
@@ -285,7 +282,8 @@ static void worker_main(nebem_server *s)
         // submission order
         for (Request *r : done)
             if (r->status == NEBEM_OK) {
-                launch_reduce_segments(stage(s, r, 8), r->nseg, r->m, stage(s, r, 3), s->stream);
+                const OutCols out = {{stage(s, r, 3), stage(s, r, 4), stage(s, r, 5), stage(s, r, 6)}, r->m};
+                launch_reduce_segments(stage(s, r, 8), r->nseg, 1, r->m, 4 * r->m, out, s->stream);
                 if (r->ordered)
                     launch_unorder4(stage(s, r, 3), reinterpret_cast<const int *>(stage(s, r, 7)), r->m,
                                     stage(s, r, 8), stage(s, r, 9), stage(s, r, 10), stage(s, r, 11), s->stream);
@@ -356,13 +354,11 @@ nebem_status nebem_server_create(nebem_session *const *sessions, int32_t nsessio
     for (int k = 0; k < nsessions; ++k) {
         s->geoms.push_back(sessions[k]);
         s->geom_n.push_back(sessions[k]->n);
-        const double per_pt = (double)sessions[k]->n * sessions[k]->img_count;
-        int nseg = (int)(per_pt / kSegWork + 0.5);
-        nseg = nseg < 1 ? 1 : (nseg > kMaxSeg ? kMaxSeg : nseg);
-        if (nseg > sessions[k]->n) nseg = (int)sessions[k]->n;
-        const int segsz = (int)((sessions[k]->n + nseg - 1) / nseg);
-        s->geom_segsz.push_back(segsz);
-        s->geom_nseg.push_back((int)((sessions[k]->n + segsz - 1) / segsz));
+        // the segments every evaluation path uses, so that served results equal
+        // a session evaluation's bit for bit
+        const SegPlan sp = seg_plan(sessions[k]->n, sessions[k]->img);
+        s->geom_segsz.push_back(sp.segsz);
+        s->geom_nseg.push_back(sp.nseg);
     }
     auto bail = [&](hipError_t e, const char *what) {
         nebem_status st = hip_fail(e, what);

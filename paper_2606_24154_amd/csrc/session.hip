@@ -78,23 +78,16 @@ static nebem_status session_build(nebem_session *s, const nebem_panels *panels, 
     return e;
 }
 
-// Evaluation over the resident geometry; large batches go through the
-// Morton-ordered path with the session's own workspace.
+// Evaluation over the resident geometry through the evaluation driver, with
+// the session's own workspace (grown to the driver's preferred size).
 static nebem_status session_eval_points(nebem_session *s, const double *px, const double *py, const double *pz,
                                         int64_t m, double *phi, double *ex, double *ey, double *ez, hipStream_t st)
 {
     const int mixed = s->opt.precision == NEBEM_MIXED;
-    if (eval_ordering_pays(m)) {
-        const size_t wb = ordered_eval_workspace(m);
-        if (!wb) return fail(NEBEM_EDEVICE, "session eval: ordering workspace query failed");
-        NEBEM_HIP(s->ows.ensure(wb));
-        NEBEM_HIP(launch_eval_ordered(s->drec.as<double>(), s->sigma.as<double>(), s->n, s->img, mixed,
-                                      s->opt.near_factor, px, py, pz, m, phi, ex, ey, ez, s->ows.p, s->ows.bytes, st));
-    } else {
-        launch_eval(s->drec.as<double>(), s->sigma.as<double>(), s->n, s->img, mixed, s->opt.near_factor, px, py, pz,
-                    m, phi, ex, ey, ez, st);
-    }
-    NEBEM_HIP(hipGetLastError());
+    const size_t wb = eval_workspace(s->n, s->img, m, 1);
+    if (wb) NEBEM_HIP(s->ows.ensure(wb));
+    NEBEM_HIP(run_eval(s->drec.as<double>(), s->sigma.as<double>(), s->n, 1, s->img, mixed, s->opt.near_factor, px,
+                       py, pz, m, phi, ex, ey, ez, s->ows.p, s->ows.bytes, st));
     return NEBEM_OK;
 }
 
