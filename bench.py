@@ -75,6 +75,8 @@ def parse():
     p.add_argument("--sc-voxel-um", type=float, default=0.0, metavar="H",
                    help="with --spacecharge: charges reduced to line charges on H um voxels over +-100 um "
                         "(Algorithm 3) in place of the all-pairs sum")
+    p.add_argument("--sc-placement", choices=["centre", "weighted"], default="centre",
+                   help="with --sc-voxel-um: line placement in each voxel")
     p.add_argument("--serve-matrix", type=int, default=0, metavar="R",
                    help="serving study instead of the step: R requests over the plates, GEM and double-THGEM "
                         "geometries, FP64 saturation measured first, then loads 0.5/0.8/0.95 in FP64 and mixed")
@@ -395,13 +397,12 @@ def voxel_bench(args):
     """Algorithm 3 on an avalanche-like cloud of 10^6 charges: +e ions and
     -e electrons, each a Gaussian of sigma 20 um, their centres 20 um apart
     along z (an interleaved neutral cloud has no coarse structure for lines
-    to keep); line charges for 5 and 10 um voxels over +-100 um, the lines'
-    field at every charge (HIP events) and its error against the point
-    charges' own field (oracle sum on the host) at 400 points 40-80 um from
-    the centre, inside the cloud, and at 200 points 120-200 um out, beyond
-    the voxel grid.  Inside, the error is largest at points within a small
-    fraction of a voxel of a line, where the segment's 1/rho field stands in
-    for charges spread over the voxel."""
+    to keep); line charges on 5 and 10 um voxels over +-100 um, both line
+    placements.  Per row: the reduction, the lines' field at every charge
+    (HIP events), and the error of the charges' own field at 400 sampled
+    charges against the exact point-charge sum (oracle on the host), for
+    the lines alone and for the field with the 27 voxels around each charge
+    taken as point charges."""
     import torch
 
     import oracle
@@ -416,40 +417,45 @@ def voxel_bench(args):
     q = np.concatenate([np.full(n // 2, 1.602176634e-19), np.full(n - n // 2, -1.602176634e-19)])
     qd = [torch.from_numpy(np.ascontiguousarray(xyz[:, k])).to(dev) for k in range(3)]
     qq = torch.from_numpy(q).to(dev)
-    rng = np.random.default_rng(5)
-    d = rng.normal(size=(400, 3))
-    d /= np.linalg.norm(d, axis=1)[:, None]
-    pts = d * rng.uniform(40e-6, 80e-6, (400, 1))
-    d = rng.normal(size=(200, 3))
-    d /= np.linalg.norm(d, axis=1)[:, None]
-    pts = np.concatenate([pts, d * rng.uniform(120e-6, 200e-6, (200, 1))])
-    ref = oracle.coulomb(pts, xyz, q)
+    sample = np.random.default_rng(5).choice(n, 400, replace=False)
+    ref = oracle.coulomb(xyz[sample], xyz, q, sample)[:, 1:]
+    refn = np.linalg.norm(ref, axis=1)
     stream = torch.cuda.current_stream()
+    stats = lambda e: {"p50": float(np.median(e)), "p90": float(np.quantile(e, 0.9)), "max": float(e.max())}
     rows = []
     for h in (5e-6, 10e-6):
         nv = int(round(200e-6 / h))
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        ev[0].record(stream)
-        lines, out = nb.voxelize_charges(*qd, qq, (-100e-6,) * 3, (h,) * 3, (nv,) * 3)
-        ev[1].record(stream)
-        f = nb.line_field(lines, *qd)
-        ev[2].record(stream)
-        torch.cuda.synchronize()
-        pt = [torch.from_numpy(np.ascontiguousarray(pts[:, k])).to(dev) for k in range(3)]
-        got = np.column_stack([t.cpu().numpy() for t in nb.line_field(lines, *pt)])[:, 1:]
-        err = np.linalg.norm(got - ref[:, 1:], axis=1) / np.linalg.norm(ref[:, 1:], axis=1)
-        ins, outs = err[:400], err[400:]
-        t_line = ev[1].elapsed_time(ev[2]) * 1e-3
-        rows.append({"voxel_um": h * 1e6, "lines": int(lines.shape[0]), "outside": int(out),
-                     "reduce_ms": ev[0].elapsed_time(ev[1]), "field_at_charges_ms": 1e3 * t_line,
-                     "segment_interactions_per_s": float(lines.shape[0]) * n / t_line,
-                     "E_rel_err_inside": {"p50": float(np.median(ins)), "p90": float(np.quantile(ins, 0.9)),
-                                          "max": float(ins.max())},
-                     "E_rel_err_outside": {"p50": float(np.median(outs)), "max": float(outs.max())}})
+        grid = ((-100e-6,) * 3, (h,) * 3, (nv,) * 3)
+        for placement in ("centre", "weighted"):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            ev[0].record(stream)
+            lines, out = nb.voxelize_charges(*qd, qq, *grid, placement=placement)
+            ev[1].record(stream)
+            f = nb.line_field(lines, *qd)
+            ev[2].record(stream)
+            E, nl = nb.charge_field_lines(*qd, qq, *grid, placement=placement)
+            ev[3].record(stream)
+            torch.cuda.synchronize()
+            plain = np.column_stack([t.cpu().numpy() for t in f[1:]])[sample]
+            near = np.column_stack([t.cpu().numpy() for t in E])[sample]
+            with np.errstate(invalid="ignore"):
+                e_plain = np.linalg.norm(plain - ref, axis=1) / refn
+            e_near = np.linalg.norm(near - ref, axis=1) / refn
+            rows.append({"voxel_um": h * 1e6, "placement": placement, "lines": int(lines.shape[0]),
+                         "outside": int(out), "reduce_ms": ev[0].elapsed_time(ev[1]),
+                         "lines_field_at_charges_ms": ev[1].elapsed_time(ev[2]),
+                         "near_exact_field_at_charges_ms": ev[2].elapsed_time(ev[3]),
+                         "segment_interactions_per_s": float(lines.shape[0]) * n / (ev[1].elapsed_time(ev[2]) * 1e-3),
+                         "E_rel_err_lines_only": stats(np.nan_to_num(e_plain, nan=np.inf)),
+                         "E_rel_err_near_exact": stats(e_near)})
+            print(f"[voxel] {h * 1e6:.0f} um {placement}: {rows[-1]['lines']} lines, near-exact field "
+                  f"{rows[-1]['near_exact_field_at_charges_ms']:.1f} ms, E err p50 "
+                  f"{rows[-1]['E_rel_err_near_exact']['p50']:.2e} (lines only "
+                  f"{rows[-1]['E_rel_err_lines_only']['p50']:.2e})", file=sys.stderr, flush=True)
     print(json.dumps({"metric": "point-to-line charge reduction", "unit": "ms", "n_gpus": 1, "dtype": "f64",
                       "config": {"workload": f"{n} charges (+e and -e Gaussians of 20 um, centres 20 um apart), "
-                                             f"voxel grids over +-100 um; E error at 400 points 40-80 um "
-                                             f"and 200 points 120-200 um from the centre"},
+                                             f"voxel grids over +-100 um; the charges' own field at 400 sampled "
+                                             f"charges against the exact point sum"},
                       "rows": rows}), flush=True)
 
 
@@ -489,7 +495,7 @@ def spacecharge_bench(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if h > 0:
-            nlines.append(ses.spacecharge_step_lines(qx, qy, qz, qd, k, *vox, E=E)[1])
+            nlines.append(ses.spacecharge_step_lines(qx, qy, qz, qd, k, *vox, E=E, placement=args.sc_placement)[1])
         else:
             ses.spacecharge_step(qx, qy, qz, qd, k, E=E)
         torch.cuda.synchronize()

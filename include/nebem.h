@@ -247,18 +247,37 @@ nebem_status nebem_fastvol_interp(const nebem_grid *grid, const double *values, 
  * floor((x - origin) / step) per axis, 1 <= n, n[0] n[1] n[2] < 2^32 - 1;
  * charges outside are dropped and counted in *outside, host, may be NULL);
  * every occupied voxel becomes one segment parallel to z over the voxel's
- * z extent, at the |q|-weighted mean x, y of its charges (the voxel centre
- * if those weights sum to zero; a lone charge's line passes exactly through
- * it), with line density = total charge / dz.
+ * z extent, with line density = total charge / dz, placed in x, y by
+ * `placement`: NEBEM_LINE_CENTRE through the voxel's centre (Algorithm 3's
+ * voxel record holds only the total charge and the occupancy), or
+ * NEBEM_LINE_WEIGHTED at the |q|-weighted mean x, y of its charges (the
+ * centre if those weights sum to zero; a lone charge's line then passes
+ * exactly through it); any other value is EINVAL.
  * lines: 7 doubles per line (ax, ay, az, bx, by, bz, lambda), device,
  * max_lines of them; *nlines (host) receives the number of occupied voxels,
  * lines in increasing voxel index.  EINVAL when *nlines > max_lines
  * (nothing written; call again with room for *nlines).  Deterministic: the
  * charges are sorted by voxel (stable) instead of accumulated with atomics.
- * Synchronises `stream`. */
+ * Allocates a stream-ordered workspace of ~36 B per charge; synchronises
+ * `stream`. */
+enum { NEBEM_LINE_CENTRE = 0, NEBEM_LINE_WEIGHTED = 1 };
 nebem_status nebem_voxelize_charges(const double *qx, const double *qy, const double *qz, const double *q,
-                                    int64_t nq, const nebem_grid *vox, double *lines, int64_t max_lines,
-                                    int64_t *nlines, int64_t *outside, hipStream_t stream);
+                                    int64_t nq, const nebem_grid *vox, int32_t placement, double *lines,
+                                    int64_t max_lines, int64_t *nlines, int64_t *outside, hipStream_t stream);
+
+/* The charges' own field at every charge with the charges reduced to line
+ * charges (Algorithm 3 as the source of the space-charge field, Sec. 4.2):
+ * at a charge in voxel (i, j, k), the lines of all voxels outside
+ * (i +- 1, j +- 1, k +- 1) plus the charges of those 27 voxels one by one
+ * (k_e q (x - x_j)/|x - x_j|^3, FP32 per pair with FP64 sums of up to 64
+ * pairs, coincident charges skipped), so no charge feels the line that
+ * contains it; a charge outside the grid feels every line.  ex/ey/ez
+ * (device, nq each) are overwritten; *nlines (may be NULL) receives the
+ * number of lines.  Grid, placement and workspace as in
+ * nebem_voxelize_charges; synchronises `stream`. */
+nebem_status nebem_charge_field_lines(const double *qx, const double *qy, const double *qz, const double *q,
+                                      int64_t nq, const nebem_grid *vox, int32_t placement, double *ex, double *ey,
+                                      double *ez, int64_t *nlines, hipStream_t stream);
 
 /* phi and E (k_e lambda times the exact segment integrals) of nlines
  * uniformly charged segments (layout as above) at m points; outputs as in
@@ -320,18 +339,18 @@ nebem_status nebem_spacecharge_step(nebem_session *s, double *qx, double *qy, do
                                     hipStream_t stream);
 
 /* The same step with the charges reduced to line charges first (Algorithm 3,
- * the cheaper source of Sec. 4.2; voxel grid `vox` and line layout as in
- * nebem_voxelize_charges): the lines' potential / normal field at the
- * collocation points replaces the point charges' in step 1 and their field
- * (nebem_line_field) the charge-charge sum in step 2.  Charges outside the
- * grid add no field but still move.  A charge alone in its voxel lies on its
- * own line and gets the principal value 0 of that line's field across it.
+ * the cheaper source of Sec. 4.2; voxel grid `vox`, `placement` and line
+ * layout as in nebem_voxelize_charges): the lines' potential / normal field
+ * at the collocation points replaces the point charges' in step 1, and the
+ * charges' own field at every charge is that of nebem_charge_field_lines
+ * (far voxels as lines, the 27 voxels around the charge as point charges)
+ * in step 2.  Charges outside the grid add no field but still move.
  * *nlines (may be NULL) receives the number of lines.  The session keeps
- * the lines (56 B per occupied voxel) and a 32 B-per-charge buffer.
- * Synchronises `stream`. */
+ * the lines (56 B per occupied voxel), a 32 B-per-charge buffer and the
+ * reduction's workspace.  Synchronises `stream`. */
 nebem_status nebem_spacecharge_step_lines(nebem_session *s, double *qx, double *qy, double *qz, const double *q,
-                                          int64_t nq, int32_t step_index, const nebem_grid *vox, double *ex,
-                                          double *ey, double *ez, int64_t *nlines, hipStream_t stream);
+                                          int64_t nq, int32_t step_index, const nebem_grid *vox, int32_t placement,
+                                          double *ex, double *ey, double *ez, int64_t *nlines, hipStream_t stream);
 
 /* ----------------------------------------------------------------- serving
  * Continuous-batching evaluation service over resident sessions.  Clients

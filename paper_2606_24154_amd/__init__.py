@@ -32,7 +32,7 @@ EXPORTED = (
     "nebem_fastvol_interp", "nebem_voxelize_charges", "nebem_line_field",
     "nebem_session_create", "nebem_session_destroy", "nebem_session_n", "nebem_session_sigma",
     "nebem_session_solve", "nebem_session_condest", "nebem_session_eval", "nebem_spacecharge_step",
-    "nebem_spacecharge_step_lines",
+    "nebem_spacecharge_step_lines", "nebem_charge_field_lines",
     "nebem_last_error",
     "nebem_server_default_options", "nebem_server_create", "nebem_server_submit", "nebem_server_wait",
     "nebem_server_stats", "nebem_server_destroy",
@@ -107,7 +107,8 @@ def _load():
     lib.nebem_eval_adaptive.argtypes = [PP, PP, P, i32, PI, P, P, P, P, i64, P, P, P, P, PO, P]
     lib.nebem_eval_adaptive.restype = i32
     PG = ctypes.POINTER(GridC)
-    lib.nebem_voxelize_charges.argtypes = [P, P, P, P, i64, PG, P, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), P]
+    lib.nebem_voxelize_charges.argtypes = [P, P, P, P, i64, PG, i32, P, i64, ctypes.POINTER(i64),
+                                           ctypes.POINTER(i64), P]
     lib.nebem_voxelize_charges.restype = i32
     lib.nebem_line_field.argtypes = [P, i64, P, P, P, i64, P, P, P, P, P]
     lib.nebem_line_field.restype = i32
@@ -139,7 +140,9 @@ def _load():
     lib.nebem_session_eval.restype = i32
     lib.nebem_spacecharge_step.argtypes = [P, P, P, P, P, i64, i32, P, P, P, P]
     lib.nebem_spacecharge_step.restype = i32
-    lib.nebem_spacecharge_step_lines.argtypes = [P, P, P, P, P, i64, i32, ctypes.POINTER(GridC), P, P, P,
+    lib.nebem_charge_field_lines.argtypes = [P, P, P, P, i64, PG, i32, P, P, P, ctypes.POINTER(i64), P]
+    lib.nebem_charge_field_lines.restype = i32
+    lib.nebem_spacecharge_step_lines.argtypes = [P, P, P, P, P, i64, i32, ctypes.POINTER(GridC), i32, P, P, P,
                                                  ctypes.POINTER(i64), P]
     lib.nebem_spacecharge_step_lines.restype = i32
     lib.nebem_server_default_options.argtypes = [ctypes.POINTER(ServerOptions)]
@@ -328,20 +331,41 @@ def fastvol_interp(values, origin, step, shape, px, py, pz, stream=None):
     return tuple(out)
 
 
-def voxelize_charges(qx, qy, qz, q, origin, step, shape, stream=None):
+LINE_CENTRE, LINE_WEIGHTED = 0, 1
+_PLACEMENT = {"centre": LINE_CENTRE, "weighted": LINE_WEIGHTED}
+
+
+def voxelize_charges(qx, qy, qz, q, origin, step, shape, placement="centre", stream=None):
     """Line charges (L, 7) from point charges (Algorithm 3) and the number
-    of charges outside the voxel grid."""
+    of charges outside the voxel grid; placement "centre" (through the voxel
+    centre) or "weighted" (at the |q|-weighted mean x, y)."""
     import torch
     g = grid_struct(origin, step, shape)
+    pl = _PLACEMENT[placement]
     nl, out = ctypes.c_int64(), ctypes.c_int64()
-    code = lib.nebem_voxelize_charges(_ptr(qx), _ptr(qy), _ptr(qz), _ptr(q), qx.shape[0], ctypes.byref(g), None, 0,
-                                      ctypes.byref(nl), ctypes.byref(out), _stream(stream))
+    code = lib.nebem_voxelize_charges(_ptr(qx), _ptr(qy), _ptr(qz), _ptr(q), qx.shape[0], ctypes.byref(g), pl, None,
+                                      0, ctypes.byref(nl), ctypes.byref(out), _stream(stream))
     if code not in (NEBEM_OK, NEBEM_EINVAL) or (code == NEBEM_EINVAL and nl.value == 0):
         _check(code)
     lines = torch.empty((max(nl.value, 1), 7), dtype=torch.float64, device=qx.device)
-    _check(lib.nebem_voxelize_charges(_ptr(qx), _ptr(qy), _ptr(qz), _ptr(q), qx.shape[0], ctypes.byref(g),
+    _check(lib.nebem_voxelize_charges(_ptr(qx), _ptr(qy), _ptr(qz), _ptr(q), qx.shape[0], ctypes.byref(g), pl,
                                       _ptr(lines), nl.value, ctypes.byref(nl), ctypes.byref(out), _stream(stream)))
     return lines[:nl.value], out.value
+
+
+def charge_field_lines(qx, qy, qz, q, origin, step, shape, placement="centre", stream=None):
+    """The charges' own field at every charge with far voxels as line
+    charges and the 27 voxels around each charge as point charges; returns
+    ((ex, ey, ez), number of lines)."""
+    import torch
+    g = grid_struct(origin, step, shape)
+    n = qx.shape[0]
+    out = [torch.empty(n, dtype=torch.float64, device=qx.device) for _ in range(3)]
+    nl = ctypes.c_int64()
+    _check(lib.nebem_charge_field_lines(_ptr(qx), _ptr(qy), _ptr(qz), _ptr(q), n, ctypes.byref(g),
+                                        _PLACEMENT[placement], *(_ptr(t) for t in out), ctypes.byref(nl),
+                                        _stream(stream)))
+    return tuple(out), nl.value
 
 
 def line_field(lines, px, py, pz, stream=None):
@@ -455,7 +479,8 @@ class Session:
             _check(code)
         return code
 
-    def spacecharge_step_lines(self, qx, qy, qz, q, step_index, origin, step, shape, E=None, stream=None):
+    def spacecharge_step_lines(self, qx, qy, qz, q, step_index, origin, step, shape, E=None, placement="centre",
+                               stream=None):
         """The space-charge step with the charges reduced to line charges on
         the voxel grid (origin, step, shape) first; returns (status, lines)."""
         nq = qx.shape[0]
@@ -465,7 +490,8 @@ class Session:
         g = grid_struct(origin, step, shape)
         nl = ctypes.c_int64()
         code = lib.nebem_spacecharge_step_lines(self.handle, _ptr(qx), _ptr(qy), _ptr(qz), _ptr(q), nq,
-                                                int(step_index), ctypes.byref(g), _ptr(ex), _ptr(ey), _ptr(ez),
+                                                int(step_index), ctypes.byref(g), _PLACEMENT[placement],
+                                                _ptr(ex), _ptr(ey), _ptr(ez),
                                                 ctypes.byref(nl), _stream(stream))
         if code not in (NEBEM_OK, NEBEM_ENOCONV):
             _check(code)

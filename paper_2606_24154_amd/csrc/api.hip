@@ -360,8 +360,8 @@ nebem_status nebem_fastvol_interp(const nebem_grid *grid, const double *values, 
 }
 
 nebem_status nebem_voxelize_charges(const double *qx, const double *qy, const double *qz, const double *q,
-                                    int64_t nq, const nebem_grid *vox, double *lines, int64_t max_lines,
-                                    int64_t *nlines, int64_t *outside, hipStream_t stream)
+                                    int64_t nq, const nebem_grid *vox, int32_t placement, double *lines,
+                                    int64_t max_lines, int64_t *nlines, int64_t *outside, hipStream_t stream)
 {
     GridArgs g;
     if (!nlines) return fail(NEBEM_EINVAL, "voxelize: NULL nlines");
@@ -369,12 +369,48 @@ nebem_status nebem_voxelize_charges(const double *qx, const double *qy, const do
     if (outside) *outside = 0;
     nebem_status st = voxel_grid_args(vox, g);
     if (st) return st;
+    if (placement != NEBEM_LINE_CENTRE && placement != NEBEM_LINE_WEIGHTED)
+        return fail(NEBEM_EINVAL, "voxelize: unknown line placement");
     if (nq < 0 || nq > (int64_t)INT_MAX - 256) return fail(NEBEM_EINVAL, "voxelize: nq out of range");
     if (max_lines < 0) return fail(NEBEM_EINVAL, "voxelize: negative max_lines");
     if (nq == 0) return NEBEM_OK;
     if (!qx || !qy || !qz || !q) return fail(NEBEM_EINVAL, "voxelize: NULL charge array");
-    NEBEM_HIP(voxel_lines(qx, qy, qz, q, (int)nq, g, lines, max_lines, nlines, outside, stream));
+    const size_t wb = voxel_workspace((int)nq);
+    DevBuf ws;
+    if (!wb || ws.alloc(wb, stream) != hipSuccess) return fail(NEBEM_ENOMEM, "voxelize: workspace");
+    NEBEM_HIP(voxel_lines(qx, qy, qz, q, (int)nq, g, placement == NEBEM_LINE_WEIGHTED, lines, max_lines, nlines,
+                          outside, ws.p, wb, stream));
     if (*nlines > max_lines) return fail(NEBEM_EINVAL, "voxelize: more occupied voxels than max_lines (*nlines)");
+    return NEBEM_OK;
+}
+
+nebem_status nebem_charge_field_lines(const double *qx, const double *qy, const double *qz, const double *q,
+                                      int64_t nq, const nebem_grid *vox, int32_t placement, double *ex, double *ey,
+                                      double *ez, int64_t *nlines, hipStream_t stream)
+{
+    if (nlines) *nlines = 0;
+    GridArgs g;
+    nebem_status st = voxel_grid_args(vox, g);
+    if (st) return st;
+    if (placement != NEBEM_LINE_CENTRE && placement != NEBEM_LINE_WEIGHTED)
+        return fail(NEBEM_EINVAL, "charge_field_lines: unknown line placement");
+    if (nq < 0 || nq > (int64_t)INT_MAX - 256) return fail(NEBEM_EINVAL, "charge_field_lines: nq out of range");
+    if (nq == 0) return NEBEM_OK;
+    if (!qx || !qy || !qz || !q || !ex || !ey || !ez)
+        return fail(NEBEM_EINVAL, "charge_field_lines: NULL argument");
+    const int64_t nvox = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    const int64_t cap = nq < nvox ? nq : nvox;
+    const size_t wb = voxel_workspace((int)nq);
+    DevBuf ws, lines;
+    if (!wb || ws.alloc(wb, stream) != hipSuccess ||
+        lines.alloc((size_t)cap * 7 * sizeof(double), stream) != hipSuccess)
+        return fail(NEBEM_ENOMEM, "charge_field_lines: workspace");
+    int64_t nl = 0;
+    NEBEM_HIP(voxel_lines(qx, qy, qz, q, (int)nq, g, placement == NEBEM_LINE_WEIGHTED, lines.as<double>(), cap, &nl,
+                          nullptr, ws.p, wb, stream));
+    launch_line_field_at_charges(lines.as<double>(), nl, ws.p, g, qx, qy, qz, q, (int)nq, ex, ey, ez, stream);
+    NEBEM_HIP(hipGetLastError());
+    if (nlines) *nlines = nl;
     return NEBEM_OK;
 }
 

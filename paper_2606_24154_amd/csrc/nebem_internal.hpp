@@ -92,11 +92,29 @@ void launch_fastvol_interp(const GridArgs &g, const double *values, const double
                            const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
                            hipStream_t s);
 
-// Point charges -> line charges (line_kernels.hip): lines (7 doubles each)
-// written only when *nlines <= max_lines; synchronises the stream.
+// Point charges -> line charges (line_kernels.hip).  Workspace layout of
+// one reduction (byte offsets); after voxel_lines it holds the charges
+// sorted by voxel (kout keys, iout charge indices), the runs' starts, the
+// count of charges inside the grid (nvalid, device int) and, at `flag`, the
+// lines' voxel keys.
+struct VoxelLayout {
+    size_t kin, kout, iin, iout, flag, pos, start, nvalid, sortw, sort_bytes, scanw, scan_bytes, total;
+};
+bool voxel_layout(int nq, VoxelLayout &L);
+size_t voxel_workspace(int nq);  // 0 on error
+// lines (7 doubles each) written only when *nlines <= max_lines; weighted:
+// lines at the |q|-weighted mean x, y of their charges, else through the
+// voxel centre; synchronises the stream.
 hipError_t voxel_lines(const double *qx, const double *qy, const double *qz, const double *q, int nq,
-                       const GridArgs &g, double *lines, int64_t max_lines, int64_t *nlines, int64_t *outside,
-                       hipStream_t s);
+                       const GridArgs &g, int weighted, double *lines, int64_t max_lines, int64_t *nlines,
+                       int64_t *outside, void *ws, size_t ws_bytes, hipStream_t s);
+// Field of the charges at themselves from their lines (ws as left by
+// voxel_lines with these charges and lines): the lines of every voxel except
+// the charge's own and the 26 around it, plus those voxels' charges one by
+// one; written to ex/ey/ez.
+void launch_line_field_at_charges(const double *lines, int64_t nl, const void *ws, const GridArgs &g,
+                                  const double *qx, const double *qy, const double *qz, const double *q, int nq,
+                                  double *ex, double *ey, double *ez, hipStream_t s);
 void launch_line_field(const double *lines, int64_t nl, const double *px, const double *py, const double *pz,
                        int64_t m, double *phi, double *ex, double *ey, double *ez, hipStream_t s);
 // Right-hand side with line charges at the collocation points: b = b0 - phi

@@ -209,8 +209,8 @@ nebem_status nebem_spacecharge_step(nebem_session *s, double *qx, double *qy, do
 }
 
 nebem_status nebem_spacecharge_step_lines(nebem_session *s, double *qx, double *qy, double *qz, const double *q,
-                                          int64_t nq, int32_t step_index, const nebem_grid *vox, double *ex,
-                                          double *ey, double *ez, int64_t *nlines, hipStream_t stream)
+                                          int64_t nq, int32_t step_index, const nebem_grid *vox, int32_t placement,
+                                          double *ex, double *ey, double *ez, int64_t *nlines, hipStream_t stream)
 {
     if (nlines) *nlines = 0;
     if (!s) return fail(NEBEM_EINVAL, "spacecharge_step_lines: NULL session");
@@ -219,17 +219,24 @@ nebem_status nebem_spacecharge_step_lines(nebem_session *s, double *qx, double *
     if (nq > 0 && (!qx || !qy || !qz || !q)) return fail(NEBEM_EINVAL, "spacecharge_step_lines: NULL charge array");
     if ((ex == nullptr) != (ey == nullptr) || (ex == nullptr) != (ez == nullptr))
         return fail(NEBEM_EINVAL, "spacecharge_step_lines: field arrays must be all NULL or all set");
+    if (placement != NEBEM_LINE_CENTRE && placement != NEBEM_LINE_WEIGHTED)
+        return fail(NEBEM_EINVAL, "spacecharge_step_lines: unknown line placement");
     GridArgs g;
     nebem_status st = voxel_grid_args(vox, g);
     if (st) return st;
     const int64_t n = s->n;
-    // 1. the charges as line charges (at most one per occupied voxel)
+    // 1. the charges as line charges (at most one per occupied voxel); the
+    // workspace keeps the charges sorted by voxel for step 3
     int64_t nl = 0, outside = 0;
     if (nq > 0) {
         const int64_t nvox = (int64_t)g.n[0] * g.n[1] * g.n[2];
         const int64_t cap = nq < nvox ? nq : nvox;
+        const size_t wb = voxel_workspace((int)nq);
+        if (!wb) return fail(NEBEM_EDEVICE, "spacecharge_step_lines: workspace query failed");
+        NEBEM_HIP(s->vws.ensure(wb));
         NEBEM_HIP(s->lines.ensure((size_t)cap * 7 * sizeof(double)));
-        NEBEM_HIP(voxel_lines(qx, qy, qz, q, (int)nq, g, s->lines.as<double>(), cap, &nl, &outside, stream));
+        NEBEM_HIP(voxel_lines(qx, qy, qz, q, (int)nq, g, placement == NEBEM_LINE_WEIGHTED, s->lines.as<double>(),
+                              cap, &nl, &outside, s->vws.p, s->vws.bytes, stream));
     }
     if (nlines) *nlines = nl;
     const double *lines = s->lines.as<double>();
@@ -249,17 +256,16 @@ nebem_status nebem_spacecharge_step_lines(nebem_session *s, double *qx, double *
         ey = ex + nq;
         ez = ey + nq;
     }
-    // 3. E at the charges: panels + lines, then the move
+    // 3. E at the charges: panels + far lines + near charges, then the move
     {
         const nebem_status se = session_eval_points(s, qx, qy, qz, nq, nullptr, ex, ey, ez, stream);
         if (se) return se;
     }
-    if (nl > 0) {
-        NEBEM_HIP(s->lf.ensure((size_t)4 * nq * sizeof(double)));
-        double *t = s->lf.as<double>();
-        launch_line_field(lines, nl, qx, qy, qz, nq, nullptr, t + nq, t + 2 * nq, t + 3 * nq, stream);
-        launch_add4(t, nq, nullptr, ex, ey, ez, stream);
-    }
+    NEBEM_HIP(s->lf.ensure((size_t)4 * nq * sizeof(double)));
+    double *t = s->lf.as<double>();
+    launch_line_field_at_charges(lines, nl, s->vws.p, g, qx, qy, qz, q, (int)nq, t + nq, t + 2 * nq, t + 3 * nq,
+                                 stream);
+    launch_add4(t, nq, nullptr, ex, ey, ez, stream);
     launch_euler(qx, qy, qz, q, ex, ey, ez, nq, s->opt.sc_mobility * s->opt.sc_dt, stream);
     NEBEM_HIP(hipGetLastError());
     return st;

@@ -41,7 +41,7 @@ struct nebem_session {
     nebem_options opt;
     nebem::ImgArgs img;
     nebem::DevMem drec, A, LU, A32, scale, ipiv, perm, b0, sigma, rhs, part, eb;
-    nebem::DevMem lines, lf;  // line charges and their field at the charges (line-charge steps)
+    nebem::DevMem lines, lf, vws;  // line charges, their field at the charges, the reduction's workspace
     nebem::DevMem ows;  // workspace of the Morton-ordered evaluation
     nebem_solve_info last_info = {0, -1.0};
 };

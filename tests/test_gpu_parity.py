@@ -314,7 +314,8 @@ def test_fastvol_build_and_error_vs_direct(nb, plates_ref):
 
 # ------------------------------------------------ point -> line charges
 
-def test_voxel_lines_match_oracle(nb):
+@pytest.mark.parametrize("placement", ["centre", "weighted"])
+def test_voxel_lines_match_oracle(nb, placement):
     """Algorithm 3's reduction against the oracle: same occupied voxels in
     the same order, same line placement and densities, same dropped count."""
     rng = np.random.default_rng(71)
@@ -323,13 +324,37 @@ def test_voxel_lines_match_oracle(nb):
     q = np.where(np.arange(n) % 2, 1.0, -1.0) * 1.602176634e-19
     q[::7] *= 3.0
     origin, step, shape = (-30e-6, -30e-6, -30e-6), (5e-6, 4e-6, 5e-6), (12, 15, 12)
-    lines, out = nb.voxelize_charges(*(dev(xyz[:, k]) for k in range(3)), dev(q), origin, step, shape)
-    ref, ref_out = oracle.voxel_lines(xyz, q, origin, step, shape, placement="weighted")
+    lines, out = nb.voxelize_charges(*(dev(xyz[:, k]) for k in range(3)), dev(q), origin, step, shape,
+                                     placement=placement)
+    ref, ref_out = oracle.voxel_lines(xyz, q, origin, step, shape, placement=placement)
     got = lines.cpu().numpy()
     assert out == ref_out and out > 0
     assert got.shape == ref.shape
     np.testing.assert_allclose(got[:, :6], ref[:, :6], rtol=1e-13, atol=1e-12 * 60e-6)  # z = 0 rounds either way
     np.testing.assert_allclose(got[:, 6], ref[:, 6], rtol=0, atol=1e-12 * np.abs(ref[:, 6]).max())
+
+
+@pytest.mark.parametrize("placement", ["centre", "weighted"])
+def test_charge_field_lines_matches_oracle(nb, placement):
+    """The charges' own field with far voxels as lines and the 27 voxels
+    around each charge as point charges, against the oracle's definition;
+    FP32 pair terms with FP64 sums: error bound 1e-6 of the sum of the
+    terms' magnitudes.  Some charges outside the grid."""
+    rng = np.random.default_rng(77)
+    n = 3000
+    xyz = rng.normal(0, 15e-6, (n, 3))
+    q = np.where(np.arange(n) % 2, 1.0, -1.0) * 1.602176634e-19 * rng.uniform(0.5, 2.0, n)
+    origin, step, shape = (-40e-6, -36e-6, -40e-6), (5e-6, 6e-6, 5e-6), (16, 12, 16)
+    E, nl = nb.charge_field_lines(*(dev(xyz[:, k]) for k in range(3)), dev(q), origin, step, shape,
+                                  placement=placement)
+    torch.cuda.synchronize()
+    ref, S = oracle.charge_field_lines(xyz, q, origin, step, shape, placement)
+    lines, nout = oracle.voxel_lines(xyz, q, origin, step, shape, placement)
+    assert nl == len(lines) and nout > 0
+    got = np.column_stack([t.cpu().numpy() for t in E])
+    assert np.isfinite(got).all()
+    err = np.linalg.norm(got - ref, axis=1) / S
+    assert err.max() < 1e-6, err.max()
 
 
 def test_lone_charge_line_passes_through_it(nb):
@@ -341,7 +366,7 @@ def test_lone_charge_line_passes_through_it(nb):
     xyz = (cell + rng.uniform(0.05, 0.95, (200, 3))) * 7e-6 - 35e-6
     q = rng.choice([-1.0, 1.0], 200) * 1.602176634e-19 * rng.uniform(0.5, 3.0, 200)
     pts = [dev(np.ascontiguousarray(xyz[:, k])) for k in range(3)]
-    lines, out = nb.voxelize_charges(*pts, dev(q), (-35e-6,) * 3, (7e-6,) * 3, (10,) * 3)
+    lines, out = nb.voxelize_charges(*pts, dev(q), (-35e-6,) * 3, (7e-6,) * 3, (10,) * 3, placement="weighted")
     torch.cuda.synchronize()
     ln = lines.cpu().numpy()
     assert out == 0 and len(ln) == 200

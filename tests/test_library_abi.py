@@ -72,10 +72,16 @@ def test_line_charge_entry_points_validate_without_gpu(lib):
     device work: a NULL session, a voxel grid with an empty axis."""
     import paper_2606_24154_amd as nb
     n = ctypes.c_int64(5)
-    assert nb.lib.nebem_spacecharge_step_lines(None, None, None, None, None, 0, 0, None, None, None, None,
+    assert nb.lib.nebem_spacecharge_step_lines(None, None, None, None, None, 0, 0, None, 0, None, None, None,
                                                ctypes.byref(n), None) == nb.NEBEM_EINVAL
     assert n.value == 0
     g = nb.grid_struct((0.0, 0.0, 0.0), (1e-6, 1e-6, 1e-6), (4, 0, 4))
     nl, out = ctypes.c_int64(), ctypes.c_int64()
-    assert nb.lib.nebem_voxelize_charges(None, None, None, None, 0, ctypes.byref(g), None, 0, ctypes.byref(nl),
+    assert nb.lib.nebem_voxelize_charges(None, None, None, None, 0, ctypes.byref(g), 0, None, 0, ctypes.byref(nl),
                                          ctypes.byref(out), None) == nb.NEBEM_EINVAL
+    # an unknown line placement
+    g = nb.grid_struct((0.0, 0.0, 0.0), (1e-6, 1e-6, 1e-6), (4, 4, 4))
+    assert nb.lib.nebem_voxelize_charges(None, None, None, None, 0, ctypes.byref(g), 2, None, 0, ctypes.byref(nl),
+                                         ctypes.byref(out), None) == nb.NEBEM_EINVAL
+    assert nb.lib.nebem_charge_field_lines(None, None, None, None, 0, ctypes.byref(g), 5, None, None, None,
+                                           ctypes.byref(nl), None) == nb.NEBEM_EINVAL

@@ -59,3 +59,49 @@ def test_voxel_reduction():
     assert one[0, 6] == 2.0 / step[2]
     one, _ = oracle.voxel_lines([[1e-6, 2e-6, 3e-6]], [2.0], origin, step, shape, placement="weighted")
     np.testing.assert_array_equal(one[0, [0, 1]], [1e-6, 2e-6])
+
+
+def _cloud(n, centre, sigma, seed):
+    rng = np.random.default_rng(seed)
+    xyz = np.asarray(centre) + rng.normal(0, sigma, (n, 3))
+    q = np.where(np.arange(n) % 2, 1.0, -1.0) * 1.602176634e-19 * rng.uniform(0.5, 2.0, n)
+    return xyz, q
+
+
+def test_charge_field_lines_all_near_is_the_point_sum():
+    """On a 2 x 2 x 2 grid every voxel is a neighbour of every other, so no
+    line is used: the field is the plain sum over the other charges."""
+    xyz, q = _cloud(300, [0, 0, 0], 4e-6, 2)
+    origin, step, shape = (-20e-6,) * 3, (20e-6,) * 3, (2, 2, 2)
+    assert np.all(np.abs(xyz) < 20e-6)
+    E, S = oracle.charge_field_lines(xyz, q, origin, step, shape)
+    ref = oracle.coulomb(xyz, xyz, q, np.arange(len(q)))[:, 1:]
+    np.testing.assert_allclose(E, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    assert np.all(S >= np.linalg.norm(ref, axis=1) * (1 - 1e-12))
+
+
+def test_charge_field_lines_far_cluster_as_lines():
+    """Two clusters, each within two neighbouring voxels and five voxels
+    from the other: a charge of one feels its own cluster charge by charge
+    and the other cluster through that cluster's lines only; a charge
+    outside the grid feels every line."""
+    a, qa = _cloud(200, [-15e-6, 2.5e-6, 2.5e-6], 0.6e-6, 3)
+    b, qb = _cloud(200, [20e-6, 2.5e-6, 2.5e-6], 0.6e-6, 4)
+    origin, step, shape = (-25e-6, -5e-6, -5e-6), (5e-6, 5e-6, 5e-6), (10, 2, 2)
+    xyz, q = np.vstack([a, b]), np.concatenate([qa, qb])
+    # cluster a within x voxels 1..2, cluster b within 8..9
+    ia = np.floor((a[:, 0] - origin[0]) / step[0])
+    ib = np.floor((b[:, 0] - origin[0]) / step[0])
+    assert ia.min() >= 1 and ia.max() <= 2 and ib.min() >= 8 and ib.max() <= 9
+    assert np.all(np.abs(xyz[:, 1:] - 2.5e-6) < 7.5e-6)
+    for placement in ("centre", "weighted"):
+        E, _ = oracle.charge_field_lines(xyz, q, origin, step, shape, placement)
+        lb, _ = oracle.voxel_lines(b, qb, origin, step, shape, placement)
+        ref = oracle.coulomb(a, a, qa, np.arange(len(qa)))[:, 1:] + oracle.line_field(lb, a)[:, 1:]
+        np.testing.assert_allclose(E[:len(a)], ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+    # a charge outside the grid
+    out = np.array([[0.0, 40e-6, 0.0]])
+    E, _ = oracle.charge_field_lines(np.vstack([xyz, out]), np.concatenate([q, [1.6e-19]]), origin, step, shape)
+    lines, nout = oracle.voxel_lines(xyz, q, origin, step, shape)
+    ref = oracle.line_field(lines, out)[0, 1:]
+    np.testing.assert_allclose(E[-1], ref, rtol=1e-12, atol=0)
