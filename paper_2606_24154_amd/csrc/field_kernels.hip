@@ -638,6 +638,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
                          w.ex, w.ey, w.ez);
 }
 
+int eval_items_slots(int mixed)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 1;
+    const hipError_t e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eval_items_mixed, 64, 0)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eval_items_fp64, 64, 0);
+    return (e == hipSuccess && per_cu > 0) ? cus * per_cu : 1;
+}
+
 void launch_eval_items(const WorkItem *items, int nitems, const ImgArgs *imgs, int mixed, double near_factor,
                        hipStream_t s)
 {

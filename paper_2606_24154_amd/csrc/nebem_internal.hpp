@@ -192,6 +192,9 @@ size_t eval_workspace_min(int64_t n, const ImgArgs &img, int64_t m, int ncol);
 hipError_t run_eval(const double *drec, const double *sigma, int64_t n, int ncol, const ImgArgs &img, int mixed,
                     double near_factor, const double *px, const double *py, const double *pz, int64_t m, double *phi,
                     double *ex, double *ey, double *ez, void *ws, size_t ws_bytes, hipStream_t s);
+// work items (one wave each) the device holds at once: CUs x resident
+// workgroups of the items kernel per CU (1 when the query fails)
+int eval_items_slots(int mixed);
 // items/imgs in device memory; one 64-lane workgroup per item
 void launch_eval_items(const WorkItem *items, int nitems, const ImgArgs *imgs, int mixed, double near_factor,
                        hipStream_t s);

@@ -131,6 +131,7 @@ struct nebem_server {
     void *sort_ws = nullptr;                // scratch of the point sort (grown on demand)
     size_t sort_ws_bytes = 0;
     int items_cap = 0;
+    int round_items = 1;  // work items (waves) the device runs at once
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<nebem::Request *> queue;
@@ -218,11 +219,15 @@ static void worker_main(nebem_server *s)
                 r->status = NEBEM_EDEVICE;
             }
         }
-        // build the work list: round-robin, one item per request per round
+        // build the work list: round-robin, one item per request per round,
+        // until the iteration's budget is used and the list fills whole
+        // rounds of the device's work-item slots (an item is one wave, and a
+        // launch whose last round is part-filled leaves CUs idle at its end)
         int nitems = 0;
         double budget = s->opt.batch_interactions;
         bool progress = true;
-        while (progress && budget > 0.0 && nitems < s->items_cap) {
+        auto more = [&] { return budget > 0.0 || nitems % s->round_items != 0; };
+        while (progress && more() && nitems < s->items_cap) {
             progress = false;
             for (Request *r : act) {
                 if (r->status != NEBEM_OK || r->next >= r->nitems || nitems >= s->items_cap) continue;
@@ -253,7 +258,7 @@ static void worker_main(nebem_server *s)
                 budget -= work;
                 s->interactions_done += work;
                 progress = true;
-                if (budget <= 0.0) break;
+                if (!more()) break;
             }
         }
         const double t0 = now_s();
@@ -378,6 +383,8 @@ nebem_status nebem_server_create(nebem_session *const *sessions, int32_t nsessio
     if ((e = hipMemcpy(s->imgs_dev, imgs.data(), sizeof(ImgArgs) * nsessions, hipMemcpyHostToDevice)) != hipSuccess)
         return bail(e, "hipMemcpy(images)");
     s->items_cap = o.max_items;
+    s->round_items = eval_items_slots(mixed);
+    if (s->round_items < 1 || s->round_items > s->items_cap) s->round_items = 1;
     if ((e = hipMalloc((void **)&s->items_dev, sizeof(WorkItem) * s->items_cap)) != hipSuccess)
         return bail(e, "hipMalloc(work list)");
     if ((e = hipHostMalloc((void **)&s->items_host, sizeof(WorkItem) * s->items_cap, hipHostMallocDefault)) !=
