@@ -320,6 +320,21 @@ nebem_status nebem_session_condest(nebem_session *s, double *kappa1, hipStream_t
 nebem_status nebem_session_eval(nebem_session *s, const double *px, const double *py, const double *pz,
                                 int64_t m, double *phi, double *ex, double *ey, double *ez, hipStream_t stream);
 
+/* nebem_session_eval for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same results, bit for bit, with no allocation.  The
+ * evaluation's workspace (element-segment partial sums, the Morton sort of
+ * the points) lives in a fixed 64 MiB scratch array in device memory, one
+ * per GPU, that the library holds until the process ends; points are taken
+ * in chunks that fit it.  Every call on a GPU uses that GPU's one scratch:
+ * calls that overlap on one GPU (other host threads, other streams) race
+ * and must be serialised by the caller.  EINVAL when even a 256-point chunk
+ * of this session's evaluation would not fit (more element segments than
+ * the scratch allows) or m is out of range. */
+nebem_status nebem_session_eval_noalloc(nebem_session *s, const double *px, const double *py, const double *pz,
+                                        int64_t m, double *phi, double *ex, double *ey, double *ez,
+                                        hipStream_t stream);
+
 /* One step of the dynamic space-charge loop (Sec. 4.3, Algorithm 4; point
  * charges, Sec. 4.2 and Algorithm 2), in place on nq charges:
  *  1. if step_index % sc_resolve_every == 0: right-hand side b_i = V_i -

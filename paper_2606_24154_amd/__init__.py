@@ -31,7 +31,8 @@ EXPORTED = (
     "nebem_condest", "nebem_eval", "nebem_eval_multi", "nebem_eval_adaptive", "nebem_fastvol_build",
     "nebem_fastvol_interp", "nebem_voxelize_charges", "nebem_line_field",
     "nebem_session_create", "nebem_session_destroy", "nebem_session_n", "nebem_session_sigma",
-    "nebem_session_solve", "nebem_session_condest", "nebem_session_eval", "nebem_spacecharge_step",
+    "nebem_session_solve", "nebem_session_condest", "nebem_session_eval", "nebem_session_eval_noalloc",
+    "nebem_spacecharge_step",
     "nebem_spacecharge_step_lines", "nebem_charge_field_lines",
     "nebem_last_error",
     "nebem_server_default_options", "nebem_server_create", "nebem_server_submit", "nebem_server_wait",
@@ -138,6 +139,8 @@ def _load():
     lib.nebem_session_solve.restype = i32
     lib.nebem_session_eval.argtypes = [P, P, P, P, i64, P, P, P, P, P]
     lib.nebem_session_eval.restype = i32
+    lib.nebem_session_eval_noalloc.argtypes = [P, P, P, P, i64, P, P, P, P, P]
+    lib.nebem_session_eval_noalloc.restype = i32
     lib.nebem_spacecharge_step.argtypes = [P, P, P, P, P, i64, i32, P, P, P, P]
     lib.nebem_spacecharge_step.restype = i32
     lib.nebem_charge_field_lines.argtypes = [P, P, P, P, i64, PG, i32, P, P, P, ctypes.POINTER(i64), P]
@@ -464,6 +467,14 @@ class Session:
         phi, ex, ey, ez = out
         _check(lib.nebem_session_eval(self.handle, _ptr(px), _ptr(py), _ptr(pz), m, _ptr(phi), _ptr(ex),
                                       _ptr(ey), _ptr(ez), _stream(stream)))
+        return out
+
+    def eval_points_noalloc(self, px, py, pz, out, stream=None):
+        """eval_points into caller-allocated outputs, with no device
+        allocation by the library (its fixed scratch instead)."""
+        phi, ex, ey, ez = out
+        _check(lib.nebem_session_eval_noalloc(self.handle, _ptr(px), _ptr(py), _ptr(pz), px.shape[0], _ptr(phi),
+                                              _ptr(ex), _ptr(ey), _ptr(ez), _stream(stream)))
         return out
 
     def spacecharge_step(self, qx, qy, qz, q, step_index, E=None, stream=None):

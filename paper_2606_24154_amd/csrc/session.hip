@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -91,6 +93,34 @@ static nebem_status session_eval_points(nebem_session *s, const double *px, cons
     return NEBEM_OK;
 }
 
+// ---- allocation-free evaluation
+// Scratch of nebem_session_eval_noalloc: a file-scope device array, one
+// copy per GPU the library runs on, held until the process ends.  Host code
+// never passes the array's name to a kernel or a copy (on the host it is a
+// stand-in, not a device address): each device's address is taken once with
+// hipGetSymbolAddress, with that device current, and kept.
+constexpr size_t kNoAllocScratch = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void *> g_scratch_ptr;
+
+static nebem_status scratch_address(void **out)
+{
+    int dev = 0;
+    NEBEM_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+        it = g_scratch_ptr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return NEBEM_OK;
+}
+
 }  // namespace nebem
 
 extern "C" {
@@ -169,6 +199,28 @@ nebem_status nebem_session_eval(nebem_session *s, const double *px, const double
     if (m == 0) return NEBEM_OK;
     if (!px || !py || !pz) return fail(NEBEM_EINVAL, "session_eval: NULL point array");
     return session_eval_points(s, px, py, pz, m, phi, ex, ey, ez, stream);
+}
+
+nebem_status nebem_session_eval_noalloc(nebem_session *s, const double *px, const double *py, const double *pz,
+                                        int64_t m, double *phi, double *ex, double *ey, double *ez,
+                                        hipStream_t stream)
+{
+    if (!s) return fail(NEBEM_EINVAL, "session_eval_noalloc: NULL session");
+    if (m < 0 || m > (int64_t)INT32_MAX - 256) return fail(NEBEM_EINVAL, "session_eval_noalloc: m out of range");
+    if (m == 0) return NEBEM_OK;
+    if (!px || !py || !pz) return fail(NEBEM_EINVAL, "session_eval_noalloc: NULL point array");
+    if (eval_workspace_min(s->n, s->img, m, 1) > kNoAllocScratch)
+        return fail(NEBEM_EINVAL, "session_eval_noalloc: the evaluation needs more than the " +
+                                      std::to_string(kNoAllocScratch >> 20) + " MiB scratch");
+    void *ws = nullptr;
+    nebem_status st = scratch_address(&ws);
+    if (st) return st;
+    // the driver takes point chunks whose workspace fits the scratch; its
+    // results do not depend on the chunking
+    NEBEM_HIP(run_eval(s->drec.as<double>(), s->sigma.as<double>(), s->n, 1, s->img,
+                       s->opt.precision == NEBEM_MIXED, s->opt.near_factor, px, py, pz, m, phi, ex, ey, ez, ws,
+                       kNoAllocScratch, stream));
+    return NEBEM_OK;
 }
 
 nebem_status nebem_spacecharge_step(nebem_session *s, double *qx, double *qy, double *qz, const double *q, int64_t nq,
