@@ -80,6 +80,11 @@ def parse():
     p.add_argument("--serve-matrix", type=int, default=0, metavar="R",
                    help="serving study instead of the step: R requests over the plates, GEM and double-THGEM "
                         "geometries, FP64 saturation measured first, then loads 0.5/0.8/0.95 in FP64 and mixed")
+    p.add_argument("--serve-warmup", type=int, default=50, help="serving study: warm-up requests per run")
+    p.add_argument("--serve-modes", default="fp64,mixed", help="serving study: precisions, comma-separated")
+    p.add_argument("--serve-loads", default="0.5,0.8,0.95", help="serving study: loads to run (of 0.5, 0.8, 0.95)")
+    p.add_argument("--serve-sat", type=float, default=None,
+                   help="serving study: FP64 saturation rate (interactions/s) instead of measuring it")
     p.add_argument("--weighting", action="store_true",
                    help="weighting fields of the GEM cell's electrodes (one column per electrode potential "
                         "group) at the evaluation points: one several-column evaluation against one "
@@ -181,9 +186,12 @@ def serve_replay(nb, geoms, sessions, n_req, load, eval_rate, seed=4):
 def serve_matrix(args):
     """Serving over three resident geometries (plates, GEM cell, double
     THGEM), geometry uniform, sizes log-uniform in [64, 262144]: the FP64
-    saturation rate is measured by submitting every request at once; then
-    Poisson arrivals at 0.5 / 0.8 / 0.95 of it (the same absolute rates for
-    both precisions).  Prints one JSON line."""
+    saturation rate is measured by submitting every request at once (or
+    taken from --serve-sat); then Poisson arrivals at 0.5 / 0.8 / 0.95 of it
+    (the same absolute rates for both precisions, seed 4 + the rate's
+    index), each run --serve-warmup requests followed by R measured ones
+    (latency statistics over the measured requests only).  Prints one JSON
+    line."""
     import torch
 
     import paper_2606_24154_amd as nb
@@ -193,6 +201,9 @@ def serve_matrix(args):
     dev = torch.device("cuda:0")
     geoms = [parallel_plates(), gem_cell(), thgem_double()]
     n_req = args.serve_matrix
+    n_warm = args.serve_warmup
+    modes = [m for m in args.serve_modes.split(",") if m]
+    loads = [float(x) for x in args.serve_loads.split(",") if x]
 
     def make_points(g, n, sd):
         return uniform_points(geoms[g].box_lo, geoms[g].box_hi, n, sd)
@@ -200,37 +211,55 @@ def serve_matrix(args):
     def log(msg):
         print(f"[serve] {msg}", file=sys.stderr, flush=True)
 
-    burst = [(0.0, g, n, sd) for (_, g, n, sd) in serve_requests(n_req, 1.0, 3, seed=4)]
-    work = sum(n * geoms[g].n * geoms[g].images.count for (_, g, n, _) in burst)
-    out = {"requests": n_req, "geometries": [g.name for g in geoms],
-           "mean_interactions_per_request": work / n_req}
-    for name, pr in (("fp64", nb.FP64), ("mixed", nb.MIXED)):
+    def stats(run, skip):
+        lat = run["latency_s"][skip:]
+        return {"p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                "max_ms": 1e3 * float(lat.max()), "mean_ms": 1e3 * float(lat.mean()), "measured": int(lat.size)}
+
+    out = {"requests": n_req, "warmup_requests": n_warm, "geometries": [g.name for g in geoms]}
+    sat = args.serve_sat
+    for name in modes:
+        pr = nb.FP64 if name == "fp64" else nb.MIXED
         t0 = time.perf_counter()
         ses = [nb.Session(nb.DevicePanels.from_geometry(g, dev), precision=pr) for g in geoms]
         log(f"{name}: sessions ready in {time.perf_counter() - t0:.1f} s")
         res = {}
-        if name == "fp64":
+        if sat is None:
+            burst = [(0.0, g, n, sd) for (_, g, n, sd) in serve_requests(n_req, 1.0, 3, seed=4)]
+            work = sum(n * geoms[g].n * geoms[g].images.count for (_, g, n, _) in burst)
             srv = nb.Server(ses)
             run = replay(srv, burst, make_points)
             srv.close()
             sat = work / run["span_s"]
             out["saturation_interactions_per_s"] = sat
             out["saturation_requests_per_s"] = n_req / run["span_s"]
-            log(f"fp64 saturation: {sat:.3e} interactions/s over {run['span_s']:.1f} s")
-        for load in (0.5, 0.8, 0.95):
+            out["mean_interactions_per_request"] = work / n_req
+            log(f"{name} saturation: {sat:.3e} interactions/s over {run['span_s']:.1f} s")
+        else:
+            burst = serve_requests(n_req, 1.0, 3, seed=4)
+            work = sum(n * geoms[g].n * geoms[g].images.count for (_, g, n, _) in burst)
+            out["saturation_interactions_per_s"] = sat
+            out["saturation_requests_per_s"] = sat / (work / n_req)
+            out["mean_interactions_per_request"] = work / n_req
+        for ri, load in enumerate((0.5, 0.8, 0.95)):
+            if load not in loads:
+                continue
             rate = load * out["saturation_requests_per_s"]
-            reqs = serve_requests(n_req, rate, 3, seed=4)
+            reqs = serve_requests(n_warm + n_req, rate, 3, seed=4 + ri)
             srv = nb.Server(ses)
             run = replay(srv, reqs, make_points)
             c = srv.counters()
             srv.close()
-            res[str(load)] = {"arrival_rate_hz": rate, "p50_ms": 1e3 * run["p50_s"], "p99_ms": 1e3 * run["p99_s"],
-                              "max_ms": 1e3 * float(run["latency_s"].max()),
-                              "points_per_s": run["points_per_s"], "interactions_per_s": c.interactions / run["span_s"],
-                              "launches": int(c.launches), "errors": len(run["errors"])}
-            log(f"{name} load {load}: p50 {res[str(load)]['p50_ms']:.0f} ms, p99 {res[str(load)]['p99_ms']:.0f} ms")
+            st = stats(run, n_warm)
+            res[str(load)] = {"arrival_rate_hz": rate, **st, "points_per_s": run["points_per_s"],
+                              "interactions_per_s": c.interactions / run["span_s"], "launches": int(c.launches),
+                              "errors": len(run["errors"])}
+            log(f"{name} load {load}: p50 {st['p50_ms']:.0f} ms, p99 {st['p99_ms']:.0f} ms "
+                f"({st['measured']} requests)")
         for x in ses:
             x.close()
+        del ses
+        torch.cuda.empty_cache()
         out[name] = res
     print(json.dumps({"serve_matrix": out}), flush=True)
 
@@ -283,11 +312,14 @@ def weighting_bench(args):
 
 
 def fastvol_bench(args):
-    """FastVolume (Sec. 3) on the GEM cell: a 5 um grid over the centre cell's
-    bounding box in the drift gap (from 20 um above the top copper to the
-    drift plane), built by one FP64 evaluation at its nodes; then trilinear
-    lookups at 10^6 drift-gap points, timed with HIP events, and the
-    interpolation error against direct evaluation at 2*10^4 of them."""
+    """FastVolume (Sec. 3) on the GEM cell's drift gap, from 20 um above the
+    top copper to the drift plane, over the centre cell's bounding box:
+    a regular 5 um grid, and a graded grid of about as many nodes (2.5 um in
+    x and y; in z 1 um at the foil, growing by 5 % per node up to 40 um) --
+    each built by one FP64 evaluation at its nodes.  Trilinear lookups at
+    10^6 drift-gap points (HIP events); interpolation error against direct
+    evaluation at 2*10^4 of them and at 2*10^4 points in the 100 um above
+    the grid's foil side, where the hole's field varies fastest."""
     import torch
 
     import paper_2606_24154_amd as nb
@@ -299,50 +331,87 @@ def fastvol_bench(args):
     sigma = ses.sigma()
     dp = nb.DevicePanels.from_geometry(g, dev)
     z_top = float(g.o[np.asarray(g.value) == -200.0][:, 2].max())
-    h = 5e-6
     lo = np.array([0.0, 0.0, z_top + 20e-6])
     hi = np.array([float(g.images.a1[0] + g.images.a2[0]), float(g.images.a2[1]), float(g.box_hi[2]) - 1e-6])
-    shape = tuple(int(np.ceil((hi[a] - lo[a]) / h)) + 1 for a in range(3))
-    step = tuple((hi[a] - lo[a]) / (shape[a] - 1) for a in range(3))
-    stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    ev[0].record(stream)
-    vals = nb.fastvol_build(dp, sigma, lo, step, shape)
-    ev[1].record(stream)
     m = args.points or 1_000_000
     rng = np.random.default_rng(7)
     pts = rng.uniform(lo, hi, (m, 3))
+    near = rng.uniform(lo, [hi[0], hi[1], lo[2] + 100e-6], (20000, 3))
     pt = [torch.from_numpy(np.ascontiguousarray(pts[:, k])).to(dev) for k in range(3)]
-    out = nb.fastvol_interp(vals, lo, step, shape, *pt)  # warm-up
-    reps = 20
-    torch.cuda.synchronize()
-    ev[2].record(stream)
-    for _ in range(reps):
-        out = nb.fastvol_interp(vals, lo, step, shape, *pt)
-    ev[3].record(stream)
-    torch.cuda.synchronize()
-    t_build = ev[0].elapsed_time(ev[1]) * 1e-3
-    t_lookup = ev[2].elapsed_time(ev[3]) * 1e-3 / reps
+    ptn = [torch.from_numpy(np.ascontiguousarray(near[:, k])).to(dev) for k in range(3)]
     ns = min(20000, m)
-    direct = nb.eval_points(dp, sigma, pt[0][:ns], pt[1][:ns], pt[2][:ns])
-    fi = np.column_stack([t[:ns].cpu().numpy() for t in out])
-    fd = np.column_stack([t.cpu().numpy() for t in direct])
-    eE = np.linalg.norm(fi[:, 1:] - fd[:, 1:], axis=1) / np.linalg.norm(fd[:, 1:], axis=1)
-    ephi = np.abs(fi[:, 0] - fd[:, 0]) / np.abs(fd[:, 0]).max()
+    direct = np.column_stack([t.cpu().numpy() for t in nb.eval_points(dp, sigma, *(p[:ns] for p in pt))])
+    direct_n = np.column_stack([t.cpu().numpy() for t in nb.eval_points(dp, sigma, *ptn)])
+    stream = torch.cuda.current_stream()
     q = lambda a: {k: float(np.quantile(a, f)) for k, f in (("p50", 0.5), ("p95", 0.95), ("p99", 0.99),
                                                              ("max", 1.0))}
+
+    def errors(fi, fd):
+        eE = np.linalg.norm(fi[:, 1:] - fd[:, 1:], axis=1) / np.linalg.norm(fd[:, 1:], axis=1)
+        return {"E_rel": q(eE), "frac_E_within_0.25pct": float((eE <= 2.5e-3).mean()),
+                "phi_err_over_max_phi": float((np.abs(fi[:, 0] - fd[:, 0]) / np.abs(fd[:, 0]).max()).max())}
+
+    def graded_axis(a0, a1, h0, growth, hmax):
+        x = [a0]
+        h = h0
+        while x[-1] + h < a1:
+            x.append(x[-1] + h)
+            h = min(h * growth, hmax)
+        if a1 - x[-1] < 0.3 * h and len(x) > 1:
+            x[-1] = a1
+        else:
+            x.append(a1)
+        return np.array(x)
+
+    h = 5e-6
+    shape = tuple(int(np.ceil((hi[a] - lo[a]) / h)) + 1 for a in range(3))
+    step = tuple((hi[a] - lo[a]) / (shape[a] - 1) for a in range(3))
+    axes = (np.linspace(lo[0], hi[0], int(np.ceil((hi[0] - lo[0]) / 2.5e-6)) + 1),
+            np.linspace(lo[1], hi[1], int(np.ceil((hi[1] - lo[1]) / 2.5e-6)) + 1),
+            graded_axis(lo[2], hi[2], 1e-6, 1.05, 40e-6))
+    axd = [torch.from_numpy(a).to(dev) for a in axes]
+    rows = {}
+    for name in ("regular", "graded"):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        if name == "regular":
+            vals = nb.fastvol_build(dp, sigma, lo, step, shape)
+            look = lambda p: nb.fastvol_interp(vals, lo, step, shape, *p)
+            nodes, desc = int(np.prod(shape)), f"{shape[0]}x{shape[1]}x{shape[2]}, step {h * 1e6:.1f} um"
+        else:
+            vals = nb.fastvol_build_axes(dp, sigma, *axd)
+            look = lambda p: nb.fastvol_interp_axes(vals, *axd, *p)
+            nodes = int(np.prod([len(a) for a in axes]))
+            desc = (f"{len(axes[0])}x{len(axes[1])}x{len(axes[2])}, 2.5 um in x, y; z 1 um at the foil "
+                    f"growing 5 %/node to 40 um")
+        ev[1].record(stream)
+        out = look(pt)  # warm-up
+        reps = 20
+        torch.cuda.synchronize()
+        ev[2].record(stream)
+        for _ in range(reps):
+            out = look(pt)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        t_lookup = ev[2].elapsed_time(ev[3]) * 1e-3 / reps
+        fi = np.column_stack([t[:ns].cpu().numpy() for t in out])
+        fin = np.column_stack([t.cpu().numpy() for t in look(ptn)])
+        rows[name] = {"grid": desc, "nodes": nodes, "build_ms": ev[0].elapsed_time(ev[1]),
+                      "lookup_ms": 1e3 * t_lookup, "lookups_per_s": m / t_lookup,
+                      "drift_gap": errors(fi, direct), "above_foil_100um": errors(fin, direct_n)}
+        print(f"[fastvol] {name}: {nodes} nodes, lookup {1e3 * t_lookup:.3f} ms, E err max "
+              f"{rows[name]['drift_gap']['E_rel']['max']:.2e} (above the foil "
+              f"{rows[name]['above_foil_100um']['E_rel']['max']:.2e})", file=sys.stderr, flush=True)
+    r = rows["regular"]
     bytes_per_lookup = 24 + 32  # coordinates in, (phi, E) out; the table gathers hit L2 / the die cache
-    print(json.dumps({"metric": "FastVolume lookups", "unit": "points/s", "value": m / t_lookup,
+    print(json.dumps({"metric": "FastVolume lookups", "unit": "points/s", "value": r["lookups_per_s"],
                       "higher_is_better": True, "n_gpus": 1, "dtype": "f64",
-                      "config": {"workload": f"gem_cell drift gap, grid {shape[0]}x{shape[1]}x{shape[2]} "
-                                             f"(step {step[0]*1e6:.2f}/{step[1]*1e6:.2f}/{step[2]*1e6:.2f} um), "
-                                             f"M={m} lookups"},
-                      "nodes": int(np.prod(shape)), "build_ms": 1e3 * t_build, "lookup_ms": 1e3 * t_lookup,
-                      "roofline": {"bound": "hbm", "achieved": bytes_per_lookup * m / t_lookup / 1e9,
+                      "config": {"workload": f"gem_cell drift gap, M={m} lookups, errors at {ns} drift-gap "
+                                             f"points and 20000 points in the 100 um above the foil side"},
+                      "roofline": {"bound": "hbm", "achieved": bytes_per_lookup * m / (r["lookup_ms"] * 1e-3) / 1e9,
                                    "peak": 8000.0, "unit": "GB/s",
-                                   "frac": bytes_per_lookup * m / t_lookup / 8e12, "traffic": None},
-                      "rel_err_E_vs_direct": q(eE), "frac_E_within_0.25pct": float((eE <= 2.5e-3).mean()),
-                      "rel_err_phi_vs_direct_max": float(ephi.max()), "error_sample": ns}), flush=True)
+                                   "frac": bytes_per_lookup * m / (r["lookup_ms"] * 1e-3) / 8e12, "traffic": None},
+                      "grids": rows}), flush=True)
 
 
 def adaptive_bench(args):

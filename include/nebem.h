@@ -104,7 +104,10 @@ typedef struct nebem_options {
     int32_t ir_max_iter;   /* mixed solve: refinement steps (30) */
     double sc_dt;          /* space charge: time step, s (1e-12) */
     double sc_mobility;    /* space charge: |v| = mobility |E|, m^2/(V s) (1e-4) */
-    int32_t sc_resolve_every; /* space charge: re-solve sigma every k steps (10) */
+    int32_t sc_resolve_every; /* space charge: re-solve sigma every k steps (10), when sc_threshold < 0 */
+    double sc_threshold;   /* space charge (Algorithm 4's SpChTh): >= 0: re-solve at a step when the
+                              charges' magnitude sum_i |q_i| exceeds it, C, checked every step; < 0
+                              (default -1): the fixed schedule sc_resolve_every */
 } nebem_options;
 
 typedef struct nebem_solve_info {
@@ -242,6 +245,33 @@ nebem_status nebem_fastvol_interp(const nebem_grid *grid, const double *values, 
                                   const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
                                   hipStream_t stream);
 
+/* Graded FastVolume grid: node (i, j, k) at (x[i], y[j], z[k]), each axis
+ * a strictly increasing array of finite coordinates (device memory, caller
+ * owned, n >= 2 per axis, n[0] n[1] n[2] <= 2^31 - 257), so that nodes can
+ * be dense where the field varies fast (near electrodes and holes) and
+ * sparse elsewhere.  Node index and value layout as for nebem_grid. */
+typedef struct nebem_axes {
+    const double *x, *y, *z;
+    int32_t n[3];
+} nebem_axes;
+
+/* phi and E at every node of a graded grid (one nebem_eval over the nodes);
+ * EINVAL if an axis is not strictly increasing and finite (checked on the
+ * device before the evaluation; synchronises `stream`). */
+nebem_status nebem_fastvol_build_axes(const nebem_panels *panels, const nebem_images *images, const double *sigma,
+                                      const nebem_axes *grid, double *values, const nebem_options *opt,
+                                      hipStream_t stream);
+
+/* Trilinear interpolation on a graded grid: per axis the cell is the last
+ * node at or below the coordinate (binary search; the last cell for the
+ * last node), the weights the fractional position in it; points outside
+ * [first node, last node] on any axis get NaN.  Axes as given to the build
+ * (not re-checked here: with axes that are not increasing the results are
+ * meaningless but every read stays inside the arrays). */
+nebem_status nebem_fastvol_interp_axes(const nebem_axes *grid, const double *values, const double *px,
+                                       const double *py, const double *pz, int64_t m, double *phi, double *ex,
+                                       double *ey, double *ez, hipStream_t stream);
+
 /* Point charges reduced to line charges (Algorithm 3, voxelisation): the
  * charges are binned into the voxels of `vox` (voxel (i, j, k) =
  * floor((x - origin) / step) per axis, 1 <= n, n[0] n[1] n[2] < 2^32 - 1;
@@ -335,9 +365,23 @@ nebem_status nebem_session_eval_noalloc(nebem_session *s, const double *px, cons
                                         int64_t m, double *phi, double *ex, double *ey, double *ez,
                                         hipStream_t stream);
 
+/* FastVolume map kept by the session (Algorithm 4's CreateFastVolPF): with
+ * exactly one of `grid` (regular) or `axes` (graded) given, the session
+ * fills `values` (device, caller owned, 4 doubles per node as in
+ * nebem_fastvol_build, 16-byte aligned, kept alive by the caller, as are
+ * graded axes) with phi and E at the nodes now, and again after every
+ * re-solve of a space-charge step, then with the panels' field plus the
+ * charges' own field at the nodes (the point charges, or the lines of a
+ * nebem_spacecharge_step_lines step) at the step's start-of-step
+ * positions.  Both NULL: the map is detached (values no longer written).
+ * Synchronises `stream`. */
+nebem_status nebem_session_fastvol(nebem_session *s, const nebem_grid *grid, const nebem_axes *axes, double *values,
+                                   hipStream_t stream);
+
 /* One step of the dynamic space-charge loop (Sec. 4.3, Algorithm 4; point
  * charges, Sec. 4.2 and Algorithm 2), in place on nq charges:
- *  1. if step_index % sc_resolve_every == 0: right-hand side b_i = V_i -
+ *  1. if a re-solve is due (step_index % sc_resolve_every == 0, or with
+ *     sc_threshold >= 0 when sum_i |q_i| > sc_threshold): right-hand side b_i = V_i -
  *     phi_q(c_i) on conductor rows, -n_i . E_q(c_i) on dielectric rows
  *     (RHVector with known charges), then sigma = A^-1 b from the resident
  *     factors;

@@ -62,7 +62,7 @@ def _load():
     lib.oracle_assemble.argtypes = [i64, P, P, P, P, P, P, P, ctypes.POINTER(_Images), P, P, ctypes.c_int]
     lib.oracle_assemble_rows.argtypes = [i64, P, P, P, P, P, P, P, ctypes.POINTER(_Images), P, i64, P, P,
                                          ctypes.c_int]
-    lib.oracle_coulomb.argtypes = [i64, P, P, i64, P, P, P, ctypes.c_int]
+    lib.oracle_coulomb.argtypes = [i64, P, P, i64, P, P, P, P, ctypes.c_int]
     lib.oracle_ke.restype = ctypes.c_double
     lib.oracle_eps0.restype = ctypes.c_double
     lib.oracle_max_threads.restype = ctypes.c_int
@@ -170,16 +170,20 @@ def assemble_rows(geom, rows, colloc=None, nthreads: int = 0) -> np.ndarray:
     return out
 
 
-def coulomb(targets, sources, q, self_index=None, nthreads: int = 0) -> np.ndarray:
-    """(phi, E) [nt, 4] of point charges at targets, skipping self pairs."""
+def coulomb(targets, sources, q, self_index=None, nthreads: int = 0, with_abs: bool = False):
+    """(phi, E) [nt, 4] of point charges at targets, skipping self pairs and
+    coincident charges; with_abs: also the sum of the field terms'
+    magnitudes, k_e sum_j |q_j| / r_j^2 [nt] (the scale of a
+    condition-normalised error)."""
     lib = _load()
     t = _f64(targets, (-1, 3))
     s = _f64(sources, (-1, 3))
     qq = _f64(q)
     si = None if self_index is None else np.ascontiguousarray(self_index, dtype=np.int64)
     out = np.zeros((t.shape[0], 4))
-    lib.oracle_coulomb(t.shape[0], _p(t), _p(si), s.shape[0], _p(s), _p(qq), _p(out), int(nthreads))
-    return out
+    ab = np.zeros(t.shape[0]) if with_abs else None
+    lib.oracle_coulomb(t.shape[0], _p(t), _p(si), s.shape[0], _p(s), _p(qq), _p(out), _p(ab), int(nthreads))
+    return (out, ab) if with_abs else out
 
 
 def solve(A, b):
@@ -189,6 +193,21 @@ def solve(A, b):
     import scipy.linalg as sla
     lu, piv = sla.lu_factor(A)
     return sla.lu_solve((lu, piv), b)
+
+
+def solve_refined(A, b, steps: int = 2):
+    """`solve` followed by `steps` rounds of iterative refinement in FP64
+    (r = b - A sigma, sigma += A^-1 r with the same LU factors): the same
+    definition, sigma solving A sigma = b, with the LU solution's residual
+    (which an ill-conditioned collocation matrix makes large: 7e-11 relative
+    on the 8064-element GEM cell) brought down to the rounding of the
+    residual product itself."""
+    import scipy.linalg as sla
+    lu, piv = sla.lu_factor(A)
+    x = sla.lu_solve((lu, piv), b)
+    for _ in range(steps):
+        x = x + sla.lu_solve((lu, piv), b - A @ x)
+    return x
 
 
 def primitive_density(elems, prims, elem_prim, sigma) -> np.ndarray:
@@ -372,6 +391,44 @@ def trilinear(origin, step, shape, values, pts) -> np.ndarray:
     return out
 
 
+def axes_nodes(axes) -> np.ndarray:
+    """Nodes (nx*ny*nz, 3) of a graded grid given by three strictly
+    increasing coordinate lists, node (i, j, k) at row i + nx (j + ny k)."""
+    x, y, z = (np.asarray(a, dtype=np.float64) for a in axes)
+    k, j, i = np.meshgrid(np.arange(len(z)), np.arange(len(y)), np.arange(len(x)), indexing="ij")
+    return np.column_stack([x[i.ravel()], y[j.ravel()], z[k.ravel()]])
+
+
+def trilinear_axes(axes, values, pts) -> np.ndarray:
+    """Trilinear interpolation on a graded grid (FastVolume with nodes dense
+    where the field varies fast): on each axis the cell is the last node at
+    or below the coordinate (the last cell for the last node), the weight
+    the fractional position (x - a_i) / (a_{i+1} - a_i); outside
+    [first node, last node] on any axis: NaN.  Plain loops over the 8
+    corners."""
+    ax = [np.asarray(a, dtype=np.float64) for a in axes]
+    pts = np.asarray(pts, dtype=np.float64)
+    values = np.asarray(values, dtype=np.float64)
+    n = [len(a) for a in ax]
+    i0, f = [], []
+    inside = np.ones(len(pts), dtype=bool)
+    for d in range(3):
+        a, x = ax[d], pts[:, d]
+        inside &= (x >= a[0]) & (x <= a[-1])
+        i = np.clip(np.searchsorted(a, x, side="right") - 1, 0, n[d] - 2)
+        i0.append(i)
+        f.append((x - a[i]) / (a[i + 1] - a[i]))
+    out = np.zeros((len(pts), values.shape[1]))
+    for dk in (0, 1):
+        for dj in (0, 1):
+            for di in (0, 1):
+                w = ((f[0] if di else 1 - f[0]) * (f[1] if dj else 1 - f[1]) * (f[2] if dk else 1 - f[2]))
+                idx = (i0[0] + di) + n[0] * ((i0[1] + dj) + n[1] * (i0[2] + dk))
+                out += w[:, None] * values[np.where(inside, idx, 0)]
+    out[~inside] = np.nan
+    return out
+
+
 def rhs_with_charges(geom, b0, qxyz, q, nthreads: int = 0) -> np.ndarray:
     """Boundary values with the known charges moved to the right-hand side
     (paper Sec. 4.1, RHVector with the known-charge contribution):
@@ -388,20 +445,27 @@ class SpaceChargeParams:
     dt: float = 1e-12          # s
     mobility: float = 1e-4     # m^2 / (V s), same for both signs
     resolve_every: int = 10
+    threshold: float = -1.0    # >= 0: Algorithm 4's SpChTh on sum |q| instead of the schedule
 
 
 def spacecharge_step(geom, A, b0, sigma, qxyz, q, step_index, params: SpaceChargeParams,
                      nthreads: int = 0):
     """One step of the dynamic space-charge loop (paper Algorithm 4 with a
     fixed drift model in place of the avalanche transport):
-      1. if step_index % resolve_every == 0: re-solve sigma with the charges
-         on the right-hand side;
+      1. if a re-solve is due -- step_index % resolve_every == 0, or with
+         threshold >= 0 (Algorithm 4's SpChTh) when the charges' magnitude
+         sum |q| exceeds the threshold -- re-solve sigma with the charges on
+         the right-hand side;
       2. E at every charge = panel part (all copies) + point-charge part
          (all other charges, no copies);
       3. every charge moves by sign(q) * mobility * E * dt (all fields from
          the start-of-step positions).
     Returns (new positions, sigma, E at the charges)."""
-    if step_index % params.resolve_every == 0:
+    if params.threshold >= 0.0:
+        due = float(np.abs(q).sum()) > params.threshold
+    else:
+        due = step_index % params.resolve_every == 0
+    if due:
         b = rhs_with_charges(geom, b0, qxyz, q, nthreads)
         sigma = solve(A, b)
     ep = eval_points(geom, sigma, qxyz, nthreads)[:, 1:]

@@ -423,7 +423,7 @@ void oracle_assemble(int64_t n, const int32_t *kind, const double *o, const doub
  * the target's own index (self[t] = j, or -1) and any source at distance 0.
  * out[nt][4]. */
 void oracle_coulomb(int64_t nt, const double *tgt, const int64_t *self, int64_t ns, const double *src,
-                    const double *q, double *out, int nthreads)
+                    const double *q, double *out, double *absum, int nthreads)
 {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -431,6 +431,7 @@ void oracle_coulomb(int64_t nt, const double *tgt, const int64_t *self, int64_t 
 #endif
     for (int64_t t = 0; t < nt; ++t) {
         acc_t a[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+        acc_t m = {0, 0};
         int64_t me = self ? self[t] : -1;
         for (int64_t j = 0; j < ns; ++j) {
             if (j == me) continue;
@@ -444,8 +445,10 @@ void oracle_coulomb(int64_t nt, const double *tgt, const int64_t *self, int64_t 
             acc_add(&a[1], q[j] * r[0] * inv3);
             acc_add(&a[2], q[j] * r[1] * inv3);
             acc_add(&a[3], q[j] * r[2] * inv3);
+            acc_add(&m, fabs(q[j]) / r2);
         }
         for (int k = 0; k < 4; ++k) out[4 * t + k] = KE * acc_get(&a[k]);
+        if (absum) absum[t] = KE * acc_get(&m);
     }
 }
 

@@ -29,9 +29,10 @@ MIXED = 1
 EXPORTED = (
     "nebem_default_options", "nebem_assemble", "nebem_solve", "nebem_solve_factored", "nebem_norm1",
     "nebem_condest", "nebem_eval", "nebem_eval_multi", "nebem_eval_adaptive", "nebem_fastvol_build",
-    "nebem_fastvol_interp", "nebem_voxelize_charges", "nebem_line_field",
+    "nebem_fastvol_interp", "nebem_fastvol_build_axes", "nebem_fastvol_interp_axes",
+    "nebem_voxelize_charges", "nebem_line_field",
     "nebem_session_create", "nebem_session_destroy", "nebem_session_n", "nebem_session_sigma",
-    "nebem_session_solve", "nebem_session_condest", "nebem_session_eval", "nebem_session_eval_noalloc",
+    "nebem_session_solve", "nebem_session_condest", "nebem_session_eval", "nebem_session_eval_noalloc", "nebem_session_fastvol",
     "nebem_spacecharge_step",
     "nebem_spacecharge_step_lines", "nebem_charge_field_lines",
     "nebem_last_error",
@@ -65,11 +66,15 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("near_factor", ctypes.c_double),
                 ("ir_tol", ctypes.c_double), ("ir_max_iter", ctypes.c_int32),
                 ("sc_dt", ctypes.c_double), ("sc_mobility", ctypes.c_double),
-                ("sc_resolve_every", ctypes.c_int32)]
+                ("sc_resolve_every", ctypes.c_int32), ("sc_threshold", ctypes.c_double)]
 
 
 class GridC(ctypes.Structure):
     _fields_ = [("origin", ctypes.c_double * 3), ("step", ctypes.c_double * 3), ("n", ctypes.c_int32 * 3)]
+
+
+class AxesC(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p), ("n", ctypes.c_int32 * 3)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -108,6 +113,11 @@ def _load():
     lib.nebem_eval_adaptive.argtypes = [PP, PP, P, i32, PI, P, P, P, P, i64, P, P, P, P, PO, P]
     lib.nebem_eval_adaptive.restype = i32
     PG = ctypes.POINTER(GridC)
+    PA = ctypes.POINTER(AxesC)
+    lib.nebem_fastvol_build_axes.argtypes = [PP, PI, P, PA, P, PO, P]
+    lib.nebem_fastvol_build_axes.restype = i32
+    lib.nebem_fastvol_interp_axes.argtypes = [PA, P, P, P, P, i64, P, P, P, P, P]
+    lib.nebem_fastvol_interp_axes.restype = i32
     lib.nebem_voxelize_charges.argtypes = [P, P, P, P, i64, PG, i32, P, i64, ctypes.POINTER(i64),
                                            ctypes.POINTER(i64), P]
     lib.nebem_voxelize_charges.restype = i32
@@ -139,6 +149,8 @@ def _load():
     lib.nebem_session_solve.restype = i32
     lib.nebem_session_eval.argtypes = [P, P, P, P, i64, P, P, P, P, P]
     lib.nebem_session_eval.restype = i32
+    lib.nebem_session_fastvol.argtypes = [P, PG, PA, P, P]
+    lib.nebem_session_fastvol.restype = i32
     lib.nebem_session_eval_noalloc.argtypes = [P, P, P, P, i64, P, P, P, P, P]
     lib.nebem_session_eval_noalloc.restype = i32
     lib.nebem_spacecharge_step.argtypes = [P, P, P, P, P, i64, i32, P, P, P, P]
@@ -334,6 +346,37 @@ def fastvol_interp(values, origin, step, shape, px, py, pz, stream=None):
     return tuple(out)
 
 
+def axes_struct(ax, ay, az) -> AxesC:
+    """Graded grid from three strictly increasing float64 device tensors."""
+    g = AxesC()
+    g.x, g.y, g.z = _ptr(ax), _ptr(ay), _ptr(az)
+    g.n[:] = [int(ax.shape[0]), int(ay.shape[0]), int(az.shape[0])]
+    return g
+
+
+def fastvol_build_axes(dp: DevicePanels, sigma, ax, ay, az, precision=FP64, stream=None, **opt):
+    """phi/E at every node of a graded grid, interleaved (nx*ny*nz, 4) float64."""
+    import torch
+    g = axes_struct(ax, ay, az)
+    nn = ax.shape[0] * ay.shape[0] * az.shape[0]
+    vals = torch.empty((nn, 4), dtype=torch.float64, device=ax.device)
+    im = images_struct(dp.images)
+    o = options(precision, **opt)
+    _check(lib.nebem_fastvol_build_axes(ctypes.byref(dp.struct), ctypes.byref(im), _ptr(sigma), ctypes.byref(g),
+                                        _ptr(vals), ctypes.byref(o), _stream(stream)))
+    return vals
+
+
+def fastvol_interp_axes(values, ax, ay, az, px, py, pz, stream=None):
+    import torch
+    g = axes_struct(ax, ay, az)
+    m = px.shape[0]
+    out = [torch.empty(m, dtype=torch.float64, device=px.device) for _ in range(4)]
+    _check(lib.nebem_fastvol_interp_axes(ctypes.byref(g), _ptr(values), _ptr(px), _ptr(py), _ptr(pz), m,
+                                         *(_ptr(t) for t in out), _stream(stream)))
+    return tuple(out)
+
+
 LINE_CENTRE, LINE_WEIGHTED = 0, 1
 _PLACEMENT = {"centre": LINE_CENTRE, "weighted": LINE_WEIGHTED}
 
@@ -417,6 +460,7 @@ class Session:
     def __init__(self, dp: DevicePanels, precision=FP64, stream=None, **opt):
         self.dp = dp
         self.n = dp.n
+        self.device = dp.tensors["ox"].device
         self.options = options(precision, **opt)
         self.precision = precision
         im = images_struct(dp.images)
@@ -468,6 +512,29 @@ class Session:
         _check(lib.nebem_session_eval(self.handle, _ptr(px), _ptr(py), _ptr(pz), m, _ptr(phi), _ptr(ex),
                                       _ptr(ey), _ptr(ez), _stream(stream)))
         return out
+
+    def fastvol(self, values=None, grid=None, axes=None, stream=None):
+        """Attach a FastVolume map that the session fills now and after
+        every space-charge re-solve: grid = (origin, step, shape) or axes =
+        (ax, ay, az) device tensors; values: (nodes, 4) float64 device
+        tensor (allocated when None).  No grid and no axes: detach."""
+        import torch
+        if grid is None and axes is None:
+            _check(lib.nebem_session_fastvol(self.handle, None, None, None, _stream(stream)))
+            return None
+        if grid is not None:
+            g, nn = grid_struct(*grid), int(np.prod(grid[2]))
+            a = None
+        else:
+            g, a = None, axes_struct(*axes)
+            nn = int(axes[0].shape[0] * axes[1].shape[0] * axes[2].shape[0])
+            self._fv_axes = axes  # kept alive while attached
+        if values is None:
+            values = torch.empty((nn, 4), dtype=torch.float64, device=self.device)
+        _check(lib.nebem_session_fastvol(self.handle, ctypes.byref(g) if g is not None else None,
+                                         ctypes.byref(a) if a is not None else None, _ptr(values),
+                                         _stream(stream)))
+        return values
 
     def eval_points_noalloc(self, px, py, pz, out, stream=None):
         """eval_points into caller-allocated outputs, with no device

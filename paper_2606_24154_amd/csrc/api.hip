@@ -184,6 +184,7 @@ void nebem_default_options(nebem_options *o)
     o->sc_dt = 1e-12;
     o->sc_mobility = 1e-4;
     o->sc_resolve_every = 10;
+    o->sc_threshold = -1.0;
 }
 
 const char *nebem_last_error(void) { return g_err.c_str(); }
@@ -355,6 +356,73 @@ nebem_status nebem_fastvol_interp(const nebem_grid *grid, const double *values, 
     if (!values || !px || !py || !pz) return fail(NEBEM_EINVAL, "fastvol_interp: NULL argument");
     if ((uintptr_t)values % 16) return fail(NEBEM_EINVAL, "fastvol_interp: values must be 16-byte aligned");
     launch_fastvol_interp(g, values, px, py, pz, m, phi, ex, ey, ez, stream);
+    NEBEM_HIP(hipGetLastError());
+    return NEBEM_OK;
+}
+
+static nebem_status axes_args(const nebem_axes *grid, AxesArgs &g, int64_t &nn)
+{
+    if (!grid) return fail(NEBEM_EINVAL, "fastvol_axes: NULL grid");
+    if (!grid->x || !grid->y || !grid->z) return fail(NEBEM_EINVAL, "fastvol_axes: NULL axis");
+    g.ax[0] = grid->x;
+    g.ax[1] = grid->y;
+    g.ax[2] = grid->z;
+    nn = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (grid->n[a] < 2) return fail(NEBEM_EINVAL, "fastvol_axes: fewer than 2 nodes on an axis");
+        g.n[a] = grid->n[a];
+        nn *= grid->n[a];
+        if (nn > (int64_t)INT_MAX - 256) return fail(NEBEM_EINVAL, "fastvol_axes: too many nodes");
+    }
+    return NEBEM_OK;
+}
+
+nebem_status nebem_fastvol_build_axes(const nebem_panels *panels, const nebem_images *images, const double *sigma,
+                                      const nebem_axes *grid, double *values, const nebem_options *opt,
+                                      hipStream_t stream)
+{
+    AxesArgs g;
+    int64_t nn = 0;
+    nebem_status st = axes_args(grid, g, nn);
+    if (st) return st;
+    if (!values) return fail(NEBEM_EINVAL, "fastvol_build_axes: NULL values");
+    if ((uintptr_t)values % 16) return fail(NEBEM_EINVAL, "fastvol_build_axes: values must be 16-byte aligned");
+    DevBuf tmp, dbad;
+    if (tmp.alloc((size_t)nn * 7 * sizeof(double), stream) != hipSuccess ||
+        dbad.alloc(sizeof(int), stream) != hipSuccess)
+        return fail(NEBEM_ENOMEM, "fastvol_build_axes: node buffers");
+    NEBEM_HIP(hipMemsetAsync(dbad.p, 0, sizeof(int), stream));
+    launch_axes_check(g, static_cast<int *>(dbad.p), stream);
+    NEBEM_HIP(hipGetLastError());
+    int hbad = 0;
+    NEBEM_HIP(hipMemcpyAsync(&hbad, dbad.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+    NEBEM_HIP(hipStreamSynchronize(stream));
+    if (hbad) return fail(NEBEM_EINVAL, "fastvol_build_axes: an axis is not strictly increasing and finite");
+    double *t = tmp.as<double>();
+    const size_t q = (size_t)nn;
+    launch_axes_nodes(g, t, t + q, t + 2 * q, stream);
+    NEBEM_HIP(hipGetLastError());
+    if ((st = nebem_eval(panels, images, sigma, t, t + q, t + 2 * q, nn, t + 3 * q, t + 4 * q, t + 5 * q, t + 6 * q,
+                         opt, stream)))
+        return st;
+    launch_interleave4(t + 3 * q, t + 4 * q, t + 5 * q, t + 6 * q, nn, values, stream);
+    NEBEM_HIP(hipGetLastError());
+    return NEBEM_OK;
+}
+
+nebem_status nebem_fastvol_interp_axes(const nebem_axes *grid, const double *values, const double *px,
+                                       const double *py, const double *pz, int64_t m, double *phi, double *ex,
+                                       double *ey, double *ez, hipStream_t stream)
+{
+    AxesArgs g;
+    int64_t nn = 0;
+    nebem_status st = axes_args(grid, g, nn);
+    if (st) return st;
+    if (m < 0 || m > (int64_t)INT_MAX - 256) return fail(NEBEM_EINVAL, "fastvol_interp_axes: m out of range");
+    if (m == 0) return NEBEM_OK;
+    if (!values || !px || !py || !pz) return fail(NEBEM_EINVAL, "fastvol_interp_axes: NULL argument");
+    if ((uintptr_t)values % 16) return fail(NEBEM_EINVAL, "fastvol_interp_axes: values must be 16-byte aligned");
+    launch_fastvol_interp_axes(g, values, px, py, pz, m, phi, ex, ey, ez, stream);
     NEBEM_HIP(hipGetLastError());
     return NEBEM_OK;
 }

@@ -11,10 +11,24 @@
 // lanes of a workgroup, and every target's sum has a fixed order -- no atomics,
 // run-to-run identical results.
 //
-// Precision (pair sums): the position difference is formed in FP64 and the
-// pair term in FP32; each run of 64 sources is summed in FP32 and then added
-// to FP64 accumulators.
+// Pair sums at the charges (k_coulomb_sorted): the charges are first put in
+// Morton order of their bounding box, so that the 256 targets of a
+// workgroup and the 256 sources of an LDS tile each sit in a small region.
+// Each workgroup takes the first of its targets as the origin, and both its
+// targets and every source it stages are held as FP32 offsets from that
+// origin in micrometres (the FP64 subtraction and the rounding happen once
+// per staged value, not per pair).  A pair then costs 3 FP32 subtractions
+// for the difference, 3 FMAs for r^2 (seeded with 1e-24 um^2, far below any
+// resolvable distance, which keeps 1/r^3 finite for a charge and itself,
+// whose difference is exactly zero), one reciprocal square root, 3
+// multiplications and 3 FMAs: 13 VALU instructions.  The rounding of an
+// offset is relative to its size -- about the pair distance plus the
+// extent of a Morton block -- so the pair term's error stays a few 1e-7 of
+// the largest term near the origin; each run of 64 sources is summed in
+// FP32 and then added to FP64 accumulators.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "charge_internal.hpp"
 #include "nebem_internal.hpp"
@@ -24,48 +38,49 @@ namespace nebem {
 constexpr int kCB = 256;   // lanes per workgroup = sources per LDS tile
 constexpr int kRun = 64;   // sources per FP32 partial sum
 
-// E at every charge from all other charges (added to ex/ey/ez, scaled by k_e)
-__global__ __launch_bounds__(kCB) void k_coulomb_self(const double *__restrict__ qx, const double *__restrict__ qy,
-                                                      const double *__restrict__ qz, const double *__restrict__ q,
-                                                      int nq, double *__restrict__ ex, double *__restrict__ ey,
-                                                      double *__restrict__ ez)
+static inline unsigned blocks(int64_t n) { return (unsigned)((n + kCB - 1) / kCB); }
+
+constexpr double kUm = 1e6;          // metres -> micrometres for the FP32 offsets
+constexpr float kSeedR2 = 1e-24f;    // um^2, keeps 1/r^3 finite at r = 0
+
+// E at every charge from all other charges, over charges in Morton order
+// (positions sx/sy/sz, charges sq, all sorted); written to the sorted
+// outputs ox/oy/oz, scaled by k_e.
+__global__ __launch_bounds__(kCB) void k_coulomb_sorted(const double *__restrict__ sx, const double *__restrict__ sy,
+                                                        const double *__restrict__ sz, const double *__restrict__ sq,
+                                                        int nq, double *__restrict__ ox, double *__restrict__ oy,
+                                                        double *__restrict__ oz)
 {
-    __shared__ double sx[kCB], sy[kCB], sz[kCB];
-    __shared__ float sq[kCB];
-    const int i = blockIdx.x * kCB + threadIdx.x;
+    __shared__ float4 src[kCB];
+    const int b0 = blockIdx.x * kCB;
+    const double cx = sx[b0], cy = sy[b0], cz = sz[b0];  // the block's origin
+    const int i = b0 + threadIdx.x;
     const bool act = i < nq;
-    const double xi = act ? qx[i] : 0.0, yi = act ? qy[i] : 0.0, zi = act ? qz[i] : 0.0;
+    const float tx = act ? (float)((sx[i] - cx) * kUm) : 0.0f;
+    const float ty = act ? (float)((sy[i] - cy) * kUm) : 0.0f;
+    const float tz = act ? (float)((sz[i] - cz) * kUm) : 0.0f;
     double ax = 0.0, ay = 0.0, az = 0.0;
     for (int base = 0; base < nq; base += kCB) {
         __syncthreads();
         const int j = base + threadIdx.x;
-        if (j < nq) {
-            sx[threadIdx.x] = qx[j];
-            sy[threadIdx.x] = qy[j];
-            sz[threadIdx.x] = qz[j];
-            sq[threadIdx.x] = (float)q[j];
-        } else {  // padding: zero charge
-            sx[threadIdx.x] = 0.0;
-            sy[threadIdx.x] = 0.0;
-            sz[threadIdx.x] = 0.0;
-            sq[threadIdx.x] = 0.0f;
-        }
+        // padding: a zero charge at the origin
+        src[threadIdx.x] = j < nq ? make_float4((float)((sx[j] - cx) * kUm), (float)((sy[j] - cy) * kUm),
+                                                (float)((sz[j] - cz) * kUm), (float)sq[j])
+                                  : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         __syncthreads();
 #pragma unroll 1
         for (int r0 = 0; r0 < kCB; r0 += kRun) {
             float fx = 0.0f, fy = 0.0f, fz = 0.0f;
 #pragma unroll 8
             for (int k = r0; k < r0 + kRun; ++k) {
-                const float dx = (float)(xi - sx[k]);
-                const float dy = (float)(yi - sy[k]);
-                const float dz = (float)(zi - sz[k]);
-                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                // the target itself and coincident charges contribute nothing
-                const float ir = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
-                const float s = sq[k] * (ir * ir * ir);
-                fx = fmaf(s, dx, fx);
-                fy = fmaf(s, dy, fy);
-                fz = fmaf(s, dz, fz);
+                const float4 c = src[k];
+                const float dx = tx - c.x, dy = ty - c.y, dz = tz - c.z;
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, kSeedR2)));
+                const float ir = __builtin_amdgcn_rsqf(r2);
+                const float w = (c.w * ir) * (ir * ir);
+                fx = fmaf(w, dx, fx);
+                fy = fmaf(w, dy, fy);
+                fz = fmaf(w, dz, fz);
             }
             ax += (double)fx;
             ay += (double)fy;
@@ -73,10 +88,105 @@ __global__ __launch_bounds__(kCB) void k_coulomb_self(const double *__restrict__
         }
     }
     if (act) {
-        ex[i] += kKe * ax;
-        ey[i] += kKe * ay;
-        ez[i] += kKe * az;
+        // um offsets: q dx / r^3 in C / um^2 -> x 1e12 for C / m^2
+        const double sc = kKe * kUm * kUm;
+        ox[i] = sc * ax;
+        oy[i] = sc * ay;
+        oz[i] = sc * az;
     }
+}
+
+// e_c[perm[k]] += src[c nq + k]
+__global__ __launch_bounds__(kCB) void k_scatter_add3(const double *__restrict__ src, const int *__restrict__ perm,
+                                                      int nq, double *__restrict__ ex, double *__restrict__ ey,
+                                                      double *__restrict__ ez)
+{
+    const int k = blockIdx.x * kCB + threadIdx.x;
+    if (k >= nq) return;
+    const int i = perm[k];
+    const size_t n = (size_t)nq;
+    ex[i] += src[k];
+    ey[i] += src[n + k];
+    ez[i] += src[2 * n + k];
+}
+
+__global__ __launch_bounds__(kCB) void k_gather1(const double *__restrict__ v, const int *__restrict__ perm, int nq,
+                                                 double *__restrict__ out)
+{
+    const int k = blockIdx.x * kCB + threadIdx.x;
+    if (k < nq) out[k] = v[perm[k]];
+}
+
+// phi and E of point charges (sources) at arbitrary points (targets),
+// added to phi/ex/ey/ez (any may be null): one lane per target, sources
+// through LDS; the difference in FP64, the pair term in FP32, runs of 64
+// sources summed in FP32 then added to FP64.  Coincident points add nothing.
+__global__ __launch_bounds__(kCB) void k_point_field(const double *__restrict__ tx, const double *__restrict__ ty,
+                                                     const double *__restrict__ tz, int m,
+                                                     const double *__restrict__ qx, const double *__restrict__ qy,
+                                                     const double *__restrict__ qz, const double *__restrict__ q,
+                                                     int nq, double *__restrict__ phi, double *__restrict__ ex,
+                                                     double *__restrict__ ey, double *__restrict__ ez)
+{
+    __shared__ double sx[kCB], sy[kCB], sz[kCB];
+    __shared__ float sq[kCB];
+    const int i = blockIdx.x * kCB + threadIdx.x;
+    const bool act = i < m;
+    const double xi = act ? tx[i] : 0.0, yi = act ? ty[i] : 0.0, zi = act ? tz[i] : 0.0;
+    double ap = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+    for (int base = 0; base < nq; base += kCB) {
+        __syncthreads();
+        const int j = base + threadIdx.x;
+        sx[threadIdx.x] = j < nq ? qx[j] : 0.0;
+        sy[threadIdx.x] = j < nq ? qy[j] : 0.0;
+        sz[threadIdx.x] = j < nq ? qz[j] : 0.0;
+        sq[threadIdx.x] = j < nq ? (float)q[j] : 0.0f;
+        __syncthreads();
+#pragma unroll 1
+        for (int r0 = 0; r0 < kCB; r0 += kRun) {
+            float fp = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
+#pragma unroll 8
+            for (int k = r0; k < r0 + kRun; ++k) {
+                const float dx = (float)(xi - sx[k]);
+                const float dy = (float)(yi - sy[k]);
+                const float dz = (float)(zi - sz[k]);
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const float ir = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+                const float w = sq[k] * ir;
+                fp += w;
+                const float w3 = w * (ir * ir);
+                fx = fmaf(w3, dx, fx);
+                fy = fmaf(w3, dy, fy);
+                fz = fmaf(w3, dz, fz);
+            }
+            ap += (double)fp;
+            ax += (double)fx;
+            ay += (double)fy;
+            az += (double)fz;
+        }
+    }
+    if (act) {
+        if (phi) phi[i] += kKe * ap;
+        if (ex) ex[i] += kKe * ax;
+        if (ey) ey[i] += kKe * ay;
+        if (ez) ez[i] += kKe * az;
+    }
+}
+
+// part[b] = sum of |q| over a strided share of the charges (b < gridDim.x),
+// reduced in a fixed order within the block
+__global__ __launch_bounds__(kCB) void k_abs_sum(const double *__restrict__ q, int nq, double *__restrict__ part)
+{
+    __shared__ double red[kCB];
+    double a = 0.0;
+    for (int i = blockIdx.x * kCB + threadIdx.x; i < nq; i += gridDim.x * kCB) a += fabs(q[i]);
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = kCB / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
 // Right-hand side with the known charges (RHVector with the charges' share,
@@ -162,13 +272,54 @@ __global__ __launch_bounds__(kCB) void k_boundary_values(const int *__restrict__
     if (i < n) b0[i] = bc[i] == 0 ? (value ? value[i] : 0.0) : 0.0;
 }
 
-static inline unsigned blocks(int64_t n) { return (unsigned)((n + kCB - 1) / kCB); }
 
-void launch_coulomb_self(const double *qx, const double *qy, const double *qz, const double *q, int64_t nq, double *ex,
-                         double *ey, double *ez, hipStream_t s)
+static size_t align256c(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t coulomb_workspace(int64_t nq)
 {
-    if (nq <= 0) return;
-    hipLaunchKernelGGL(k_coulomb_self, dim3(blocks(nq)), dim3(kCB), 0, s, qx, qy, qz, q, (int)nq, ex, ey, ez);
+    if (nq <= 0) return 0;
+    const size_t w = order_points_workspace(nq);
+    if (!w) return 0;
+    const size_t n = (size_t)nq;
+    return w + align256c(4 * n) + align256c(24 * n) + align256c(8 * n) + align256c(24 * n);
+}
+
+hipError_t launch_coulomb(const double *qx, const double *qy, const double *qz, const double *q, int64_t nq,
+                          double *ex, double *ey, double *ez, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    if (nq <= 0) return hipSuccess;
+    const size_t w0 = order_points_workspace(nq);
+    if (!w0 || !ws || ws_bytes < coulomb_workspace(nq)) return hipErrorInvalidValue;
+    const size_t n = (size_t)nq;
+    char *w = static_cast<char *>(ws);
+    int *perm = reinterpret_cast<int *>(w + w0);
+    double *sp = reinterpret_cast<double *>(w + w0 + align256c(4 * n));
+    double *sq = reinterpret_cast<double *>(w + w0 + align256c(4 * n) + align256c(24 * n));
+    double *se = reinterpret_cast<double *>(w + w0 + align256c(4 * n) + align256c(24 * n) + align256c(8 * n));
+    hipError_t e = launch_order_points(qx, qy, qz, nq, sp, sp + n, sp + 2 * n, perm, ws, w0, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gather1, dim3(blocks(nq)), dim3(kCB), 0, s, q, perm, (int)nq, sq);
+    hipLaunchKernelGGL(k_coulomb_sorted, dim3(blocks(nq)), dim3(kCB), 0, s, sp, sp + n, sp + 2 * n, sq, (int)nq, se,
+                       se + n, se + 2 * n);
+    hipLaunchKernelGGL(k_scatter_add3, dim3(blocks(nq)), dim3(kCB), 0, s, se, perm, (int)nq, ex, ey, ez);
+    return hipGetLastError();
+}
+
+void launch_point_field(const double *tx, const double *ty, const double *tz, int64_t m, const double *qx,
+                        const double *qy, const double *qz, const double *q, int64_t nq, double *phi, double *ex,
+                        double *ey, double *ez, hipStream_t s)
+{
+    if (m <= 0 || nq <= 0) return;
+    hipLaunchKernelGGL(k_point_field, dim3(blocks(m)), dim3(kCB), 0, s, tx, ty, tz, (int)m, qx, qy, qz, q, (int)nq,
+                       phi, ex, ey, ez);
+}
+
+int launch_abs_sum(const double *q, int64_t nq, double *part, hipStream_t s)
+{
+    if (nq <= 0) return 0;
+    const int nb = (int)std::min<int64_t>(kAbsParts, (nq + kCB - 1) / kCB);
+    hipLaunchKernelGGL(k_abs_sum, dim3(nb), dim3(kCB), 0, s, q, (int)nq, part);
+    return nb;
 }
 
 int charge_rhs_chunks(int64_t n, int64_t nq)

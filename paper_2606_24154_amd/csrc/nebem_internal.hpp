@@ -86,6 +86,18 @@ struct GridArgs {
     int n[3];
 };
 void launch_grid_nodes(const GridArgs &g, double *px, double *py, double *pz, hipStream_t s);
+// Graded FastVolume grid: node (i, j, k) at (ax[0][i], ax[1][j], ax[2][k]),
+// each axis strictly increasing (device arrays), same node order and value
+// interleaving as the regular grid.
+struct AxesArgs {
+    const double *ax[3];
+    int n[3];
+};
+void launch_axes_nodes(const AxesArgs &g, double *px, double *py, double *pz, hipStream_t s);
+void launch_axes_check(const AxesArgs &g, int *bad, hipStream_t s);  // bad[0] = 1 on a bad axis
+void launch_fastvol_interp_axes(const AxesArgs &g, const double *values, const double *px, const double *py,
+                                const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
+                                hipStream_t s);
 void launch_interleave4(const double *s0, const double *s1, const double *s2, const double *s3, int64_t nn,
                         double *values, hipStream_t s);
 void launch_fastvol_interp(const GridArgs &g, const double *values, const double *px, const double *py,

@@ -9,6 +9,7 @@
 // dynamic loop of Sec. 4.3 (Algorithm 4) with point charges (Sec. 4.2).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -93,6 +94,62 @@ static nebem_status session_eval_points(nebem_session *s, const double *px, cons
     return NEBEM_OK;
 }
 
+// Algorithm 4's UpdateFields decision: the fixed schedule, or with
+// sc_threshold >= 0 the charges' magnitude sum |q| against the threshold
+// (partial sums on the device, added on the host in index order).
+static nebem_status resolve_due(nebem_session *s, int step, const double *q, int64_t nq, hipStream_t st, bool &due)
+{
+    if (s->opt.sc_threshold < 0.0) {
+        due = step % s->opt.sc_resolve_every == 0;
+        return NEBEM_OK;
+    }
+    double total = 0.0;
+    if (nq > 0) {
+        NEBEM_HIP(s->absq.ensure(kAbsParts * sizeof(double)));
+        const int np = launch_abs_sum(q, nq, s->absq.as<double>(), st);
+        NEBEM_HIP(hipGetLastError());
+        double h[kAbsParts];
+        NEBEM_HIP(hipMemcpyAsync(h, s->absq.p, np * sizeof(double), hipMemcpyDeviceToHost, st));
+        NEBEM_HIP(hipStreamSynchronize(st));
+        for (int k = 0; k < np; ++k) total += h[k];
+    }
+    due = total > s->opt.sc_threshold;
+    return NEBEM_OK;
+}
+
+// The session's FastVolume map (Algorithm 4's CreateFastVolPF): panels with
+// the current sigma at every node, plus the charges' own field (point
+// charges, or lines when `lines` is set), interleaved into the caller's
+// buffer.
+static nebem_status refresh_fastvol(nebem_session *s, const double *qx, const double *qy, const double *qz,
+                                    const double *q, int64_t nq, const double *lines, int64_t nl, hipStream_t st)
+{
+    if (!s->fv_kind) return NEBEM_OK;
+    const size_t nn = (size_t)s->fv_nodes;
+    NEBEM_HIP(s->fv_tmp.ensure(7 * nn * sizeof(double)));
+    double *t = s->fv_tmp.as<double>();
+    if (s->fv_kind == 1)
+        launch_grid_nodes(s->fv_grid, t, t + nn, t + 2 * nn, st);
+    else
+        launch_axes_nodes(s->fv_axes, t, t + nn, t + 2 * nn, st);
+    NEBEM_HIP(hipGetLastError());
+    nebem_status e = session_eval_points(s, t, t + nn, t + 2 * nn, (int64_t)nn, t + 3 * nn, t + 4 * nn, t + 5 * nn,
+                                         t + 6 * nn, st);
+    if (e) return e;
+    if (lines && nl > 0) {
+        NEBEM_HIP(s->lf.ensure(4 * nn * sizeof(double)));
+        double *f = s->lf.as<double>();
+        launch_line_field(lines, nl, t, t + nn, t + 2 * nn, (int64_t)nn, f, f + nn, f + 2 * nn, f + 3 * nn, st);
+        launch_add4(f, (int64_t)nn, t + 3 * nn, t + 4 * nn, t + 5 * nn, t + 6 * nn, st);
+    } else if (!lines && nq > 0) {
+        launch_point_field(t, t + nn, t + 2 * nn, (int64_t)nn, qx, qy, qz, q, nq, t + 3 * nn, t + 4 * nn, t + 5 * nn,
+                           t + 6 * nn, st);
+    }
+    launch_interleave4(t + 3 * nn, t + 4 * nn, t + 5 * nn, t + 6 * nn, (int64_t)nn, s->fv_values, st);
+    NEBEM_HIP(hipGetLastError());
+    return NEBEM_OK;
+}
+
 // ---- allocation-free evaluation
 // Scratch of nebem_session_eval_noalloc: a file-scope device array, one
 // copy per GPU the library runs on, held until the process ends.  Host code
@@ -140,7 +197,7 @@ nebem_status nebem_session_create(const nebem_panels *panels, const nebem_images
     else
         nebem_default_options(&o);
     if ((st = check_options(o))) return st;
-    if (o.sc_resolve_every < 1 || !(o.sc_dt >= 0.0) || !(o.sc_mobility >= 0.0))
+    if (o.sc_resolve_every < 1 || !(o.sc_dt >= 0.0) || !(o.sc_mobility >= 0.0) || !std::isfinite(o.sc_threshold))
         return fail(NEBEM_EINVAL, "session_create: bad space-charge options");
     nebem_session *s = new (std::nothrow) nebem_session;
     if (!s) return fail(NEBEM_ENOMEM, "session_create: host allocation failed");
@@ -201,6 +258,69 @@ nebem_status nebem_session_eval(nebem_session *s, const double *px, const double
     return session_eval_points(s, px, py, pz, m, phi, ex, ey, ez, stream);
 }
 
+nebem_status nebem_session_fastvol(nebem_session *s, const nebem_grid *grid, const nebem_axes *axes, double *values,
+                                   hipStream_t stream)
+{
+    if (!s) return fail(NEBEM_EINVAL, "session_fastvol: NULL session");
+    if (!grid && !axes) {
+        s->fv_kind = 0;
+        s->fv_values = nullptr;
+        return NEBEM_OK;
+    }
+    if (grid && axes) return fail(NEBEM_EINVAL, "session_fastvol: give a regular grid or graded axes, not both");
+    if (!values) return fail(NEBEM_EINVAL, "session_fastvol: NULL values");
+    if ((uintptr_t)values % 16) return fail(NEBEM_EINVAL, "session_fastvol: values must be 16-byte aligned");
+    int64_t nn = 1;
+    if (grid) {
+        GridArgs g;
+        for (int a = 0; a < 3; ++a) {
+            if (grid->n[a] < 2 || !(grid->step[a] > 0.0) || !std::isfinite(grid->step[a]) ||
+                !std::isfinite(grid->origin[a]))
+                return fail(NEBEM_EINVAL, "session_fastvol: bad regular grid");
+            g.origin[a] = grid->origin[a];
+            g.step[a] = grid->step[a];
+            g.inv_step[a] = 1.0 / grid->step[a];
+            g.n[a] = grid->n[a];
+            nn *= grid->n[a];
+            if (nn > (int64_t)INT32_MAX - 256) return fail(NEBEM_EINVAL, "session_fastvol: too many nodes");
+        }
+        s->fv_grid = g;
+        s->fv_kind = 1;
+    } else {
+        AxesArgs g;
+        if (!axes->x || !axes->y || !axes->z) return fail(NEBEM_EINVAL, "session_fastvol: NULL axis");
+        g.ax[0] = axes->x;
+        g.ax[1] = axes->y;
+        g.ax[2] = axes->z;
+        for (int a = 0; a < 3; ++a) {
+            if (axes->n[a] < 2) return fail(NEBEM_EINVAL, "session_fastvol: fewer than 2 nodes on an axis");
+            g.n[a] = axes->n[a];
+            nn *= axes->n[a];
+            if (nn > (int64_t)INT32_MAX - 256) return fail(NEBEM_EINVAL, "session_fastvol: too many nodes");
+        }
+        NEBEM_HIP(s->absq.ensure(kAbsParts * sizeof(double)));
+        int *bad = reinterpret_cast<int *>(s->absq.p);
+        NEBEM_HIP(hipMemsetAsync(bad, 0, sizeof(int), stream));
+        launch_axes_check(g, bad, stream);
+        NEBEM_HIP(hipGetLastError());
+        int hbad = 0;
+        NEBEM_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream));
+        NEBEM_HIP(hipStreamSynchronize(stream));
+        if (hbad) return fail(NEBEM_EINVAL, "session_fastvol: an axis is not strictly increasing and finite");
+        s->fv_axes = g;
+        s->fv_kind = 2;
+    }
+    s->fv_values = values;
+    s->fv_nodes = nn;
+    nebem_status st = refresh_fastvol(s, nullptr, nullptr, nullptr, nullptr, 0, nullptr, 0, stream);
+    if (st) {
+        s->fv_kind = 0;
+        return st;
+    }
+    NEBEM_HIP(hipStreamSynchronize(stream));
+    return NEBEM_OK;
+}
+
 nebem_status nebem_session_eval_noalloc(nebem_session *s, const double *px, const double *py, const double *pz,
                                         int64_t m, double *phi, double *ex, double *ey, double *ez,
                                         hipStream_t stream)
@@ -234,7 +354,9 @@ nebem_status nebem_spacecharge_step(nebem_session *s, double *qx, double *qy, do
         return fail(NEBEM_EINVAL, "spacecharge_step: field arrays must be all NULL or all set");
     const int64_t n = s->n;
     nebem_status st = NEBEM_OK;
-    if (step_index % s->opt.sc_resolve_every == 0) {
+    bool due = false;
+    if ((st = resolve_due(s, step_index, q, nq, stream, due))) return st;
+    if (due) {
         const int nchunk = charge_rhs_chunks(n, nq);
         NEBEM_HIP(s->part.ensure((size_t)nchunk * n * sizeof(double)));
         launch_charge_rhs(s->drec.as<double>(), n, qx, qy, qz, q, nq, s->b0.as<double>(), s->part.as<double>(), nchunk,
@@ -242,6 +364,8 @@ nebem_status nebem_spacecharge_step(nebem_session *s, double *qx, double *qy, do
         NEBEM_HIP(hipGetLastError());
         st = session_solve(s, s->rhs.as<double>(), stream);
         if (st && st != NEBEM_ENOCONV) return st;
+        const nebem_status sf = refresh_fastvol(s, qx, qy, qz, q, nq, nullptr, 0, stream);
+        if (sf) return sf;
     }
     if (nq == 0) return st;
     if (!ex) {
@@ -254,7 +378,12 @@ nebem_status nebem_spacecharge_step(nebem_session *s, double *qx, double *qy, do
         const nebem_status se = session_eval_points(s, qx, qy, qz, nq, nullptr, ex, ey, ez, stream);
         if (se) return se;
     }
-    launch_coulomb_self(qx, qy, qz, q, nq, ex, ey, ez, stream);
+    {
+        const size_t wb = coulomb_workspace(nq);
+        if (!wb) return fail(NEBEM_EDEVICE, "spacecharge_step: workspace query failed");
+        NEBEM_HIP(s->cws.ensure(wb));
+        NEBEM_HIP(launch_coulomb(qx, qy, qz, q, nq, ex, ey, ez, s->cws.p, s->cws.bytes, stream));
+    }
     launch_euler(qx, qy, qz, q, ex, ey, ez, nq, s->opt.sc_mobility * s->opt.sc_dt, stream);
     NEBEM_HIP(hipGetLastError());
     return st;
@@ -293,13 +422,17 @@ nebem_status nebem_spacecharge_step_lines(nebem_session *s, double *qx, double *
     if (nlines) *nlines = nl;
     const double *lines = s->lines.as<double>();
     // 2. re-solve with the lines' share on the right-hand side
-    if (step_index % s->opt.sc_resolve_every == 0) {
+    bool due = false;
+    if ((st = resolve_due(s, step_index, q, nq, stream, due))) return st;
+    if (due) {
         NEBEM_HIP(s->part.ensure((size_t)7 * n * sizeof(double)));
         launch_line_rhs(s->drec.as<double>(), n, lines, nl, s->b0.as<double>(), s->part.as<double>(),
                         s->rhs.as<double>(), stream);
         NEBEM_HIP(hipGetLastError());
         st = session_solve(s, s->rhs.as<double>(), stream);
         if (st && st != NEBEM_ENOCONV) return st;
+        const nebem_status sf = refresh_fastvol(s, qx, qy, qz, q, nq, lines, nl, stream);
+        if (sf) return sf;
     }
     if (nq == 0) return st;
     if (!ex) {

@@ -43,5 +43,14 @@ struct nebem_session {
     nebem::DevMem drec, A, LU, A32, scale, ipiv, perm, b0, sigma, rhs, part, eb;
     nebem::DevMem lines, lf, vws;  // line charges, their field at the charges, the reduction's workspace
     nebem::DevMem ows;  // workspace of the Morton-ordered evaluation
+    nebem::DevMem cws;  // workspace of the charge-pair sums (Morton order of the charges)
     nebem_solve_info last_info = {0, -1.0};
+    // FastVolume map regenerated after every space-charge re-solve
+    int fv_kind = 0;  // 0 none, 1 regular grid, 2 graded axes
+    nebem::GridArgs fv_grid = {};
+    nebem::AxesArgs fv_axes = {};
+    double *fv_values = nullptr;  // caller's buffer, 4 doubles per node
+    int64_t fv_nodes = 0;
+    nebem::DevMem fv_tmp;  // nodes (3) and field (4) columns
+    nebem::DevMem absq;    // partial sums of |q| (threshold rule)
 };

@@ -6,14 +6,16 @@ GPU path.  Run from the repository root:
     python tests/golden/make_golden.py traj      # ~25 min on 8 threads
 
 gem:  the single-GEM cell (8064 elements, copies +-5): the oracle's full
-      influence matrix (Eq. Matrix), its LU solution sigma, and phi, E at
-      256 of the cell's seeded evaluation points (Eqs. Potential/Field).
+      influence matrix (Eq. Matrix), its solution sigma (LU with two steps
+      of FP64 refinement), and phi, E at 256 of the cell's seeded
+      evaluation points (Eqs. Potential/Field).
 traj: the reduced space-charge trajectory: the same cell with copies +-1,
       4096 charges (+-e alternating) from the seeded 20 um Gaussian at the
       hole centre, 20 steps of the dynamic loop (Algorithm 4 with point
       charges, Algorithm 2's sum; re-solve at steps 0 and 10, dt = 1 ps,
-      mobility 1e-4 m^2/Vs): positions and the field at the charges after
-      every step, and sigma after each re-solve.
+      mobility 1e-4 m^2/Vs): for 1024 sampled charges, positions and the
+      field at the charges after steps 0, 9, 10 and 19 (around each
+      re-solve and at the end), and sigma after each re-solve.
 """
 import os
 import sys
@@ -31,6 +33,8 @@ from synth import charge_cloud, gem_cell, gem_eval_points  # noqa: E402
 GEM_POINTS = 256
 TRAJ_CHARGES = 4096
 TRAJ_STEPS = 20
+TRAJ_KEEP_STEPS = (0, 9, 10, 19)
+TRAJ_SAMPLE = 1024
 
 
 def log(msg):
@@ -43,7 +47,7 @@ def make_gem():
     A = oracle.assemble(g)
     log(f"gem: assembly {g.n} x {g.n} x {g.images.count} copies in {time.time() - t0:.0f} s")
     b = g.rhs()
-    sigma = oracle.solve(A, b)
+    sigma = oracle.solve_refined(A, b)
     resid = np.linalg.norm(A @ sigma - b) / np.linalg.norm(b)
     pts = gem_eval_points(g, 1_000_000, seed=1)
     idx = np.random.default_rng(11).choice(len(pts), GEM_POINTS, replace=False)
@@ -75,8 +79,11 @@ def make_traj():
         if k % params.resolve_every == 0:
             sig.append(sigma)
         log(f"traj: step {k} in {time.time() - t0:.0f} s")
-    np.savez(os.path.join(HERE, "gem_cell_trajectory.npz"), start=xyz, q=q, positions=np.stack(pos),
-             fields=np.stack(E), sigma=np.stack(sig), dt=params.dt, mobility=params.mobility,
+    keep = np.array(TRAJ_KEEP_STEPS)
+    sample = np.sort(np.random.default_rng(17).choice(TRAJ_CHARGES, TRAJ_SAMPLE, replace=False))
+    np.savez(os.path.join(HERE, "gem_cell_trajectory.npz"), steps=keep, sample=sample,
+             positions=np.stack(pos)[keep][:, sample], fields=np.stack(E)[keep][:, sample], sigma=np.stack(sig),
+             n_steps=TRAJ_STEPS, n_charges=TRAJ_CHARGES, dt=params.dt, mobility=params.mobility,
              resolve_every=params.resolve_every)
 
 

@@ -284,6 +284,74 @@ def test_spacecharge_newton_third_law_and_resolve_schedule(nb, small_gem):
     ses.close()
 
 
+def test_spacecharge_threshold_rule(nb, small_gem):
+    """Algorithm 4's SpChTh: with sc_threshold >= 0 sigma is re-solved at a
+    step exactly when the charges' magnitude sum |q| exceeds it."""
+    g = small_gem[0]
+    xyz, q = _charges(g, 3000, 17)
+    qabs = np.abs(q).sum()
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    for thr, resolves in ((2.0 * qabs, False), (0.5 * qabs, True)):
+        ses = nb.Session(dp, precision=nb.FP64, sc_threshold=thr)
+        s0 = ses.sigma().cpu().numpy()
+        qx, qy, qz = cols(xyz)
+        for k in (0, 1):  # the schedule would re-solve at step 0 only; the rule at both or neither
+            before = ses.sigma().cpu().numpy()
+            ses.spacecharge_step(qx, qy, qz, dev(q), k)
+            torch.cuda.synchronize()
+            after = ses.sigma().cpu().numpy()
+            assert (not np.array_equal(before, after)) == resolves, (thr, k)
+        if not resolves:
+            assert np.array_equal(ses.sigma().cpu().numpy(), s0)
+        ses.close()
+
+
+@pytest.mark.parametrize("lines", [False, True])
+def test_spacecharge_fastvol_regenerated(nb, small_gem, lines):
+    """Algorithm 4's CreateFastVolPF: a FastVolume map attached to the
+    session holds the panels' field now, and after a re-solve the panels'
+    field with the new sigma plus the charges' own field (point charges or
+    their lines) at the start-of-step positions."""
+    g = small_gem[0]
+    xyz, q = _charges(g, 2000, 18)
+    c0 = np.array([0.5 * (g.images.a1[0] + g.images.a2[0]), 0.5 * g.images.a2[1], 0.0])
+    origin, step, shape = tuple(c0 + np.array([-60e-6, -60e-6, 40e-6])), (10e-6, 12e-6, 15e-6), (13, 11, 9)
+    vox = (tuple(c0 - 60e-6), (10e-6,) * 3, (12,) * 3)
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    ses = nb.Session(dp, precision=nb.FP64)
+    vals = ses.fastvol(grid=(origin, step, shape))
+    torch.cuda.synchronize()
+    nodes = oracle.grid_nodes(origin, step, shape)
+    direct = stack(ses.eval_points(*cols(nodes)))
+    assert np.array_equal(vals.cpu().numpy(), direct)
+    qx, qy, qz = cols(xyz)
+    if lines:
+        ses.spacecharge_step_lines(qx, qy, qz, dev(q), 0, *vox)
+    else:
+        ses.spacecharge_step(qx, qy, qz, dev(q), 0)
+    torch.cuda.synchronize()
+    got = vals.cpu().numpy()
+    panels = stack(ses.eval_points(*cols(nodes)))  # the new sigma
+    assert not np.array_equal(panels, direct)
+    if lines:
+        ln, _ = oracle.voxel_lines(xyz, q, *vox)
+        ref = oracle.line_field(ln, nodes)
+        tol = 1e-10
+        scale = np.abs(ref).max(axis=0)
+    else:
+        ref, S = oracle.coulomb(nodes, xyz, q, with_abs=True)
+        tol = 1e-6
+        scale = np.column_stack([S * 0 + np.abs(ref[:, 0]).max(), S, S, S])
+    charge_part = got - panels
+    assert np.all(np.abs(charge_part - ref) <= tol * (scale + np.abs(panels).max(axis=0) * 1e-6)), \
+        np.max(np.abs(charge_part - ref) / (scale + 1e-300))
+    ses.fastvol()  # detach
+    ses.spacecharge_step(qx, qy, qz, dev(q), 10 if not lines else 10)
+    torch.cuda.synchronize()
+    assert np.array_equal(vals.cpu().numpy(), got)
+    ses.close()
+
+
 def test_spacecharge_deterministic(nb, small_gem):
     g = small_gem[0]
     xyz, q = _charges(g, 5000, 15)

@@ -312,6 +312,54 @@ def test_fastvol_build_and_error_vs_direct(nb, plates_ref):
     assert ephi < 2.5e-3 and eE < 2.5e-3, (ephi, eE)
 
 
+FV_AXES = (np.array([-0.5e-3, -0.3e-3, -0.2e-3, -0.15e-3, -0.12e-3, 0.0, 0.1e-3, 0.35e-3, 0.5e-3]),
+           np.array([-0.5e-3, -0.45e-3, -0.1e-3, 0.2e-3, 0.22e-3, 0.5e-3]),
+           np.array([-0.09e-3, -0.085e-3, -0.07e-3, -0.03e-3, 0.02e-3, 0.06e-3, 0.08e-3, 0.089e-3]))
+
+
+def test_fastvol_axes_interp_matches_oracle(nb):
+    """Trilinear lookup on a graded grid (uneven node spacing per axis) of
+    arbitrary node values against the oracle's definition, inside, on the
+    last nodes, exactly on inner nodes and outside (NaN)."""
+    rng = np.random.default_rng(43)
+    nn = int(np.prod([len(a) for a in FV_AXES]))
+    vals = rng.standard_normal((nn, 4))
+    lo = np.array([a[0] for a in FV_AXES])
+    hi = np.array([a[-1] for a in FV_AXES])
+    pts = rng.uniform(lo - 0.05 * (hi - lo), hi + 0.05 * (hi - lo), (3000, 3))
+    nodes = oracle.axes_nodes(FV_AXES)
+    pts[:20] = nodes[-20:]
+    pts[20:60] = nodes[rng.choice(nn, 40, replace=False)]
+    ax = [dev(a) for a in FV_AXES]
+    out = nb.fastvol_interp_axes(dev(vals), *ax, *(dev(pts[:, k]) for k in range(3)))
+    torch.cuda.synchronize()
+    got = np.column_stack([t.cpu().numpy() for t in out])
+    ref = oracle.trilinear_axes(FV_AXES, vals, pts)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert ok.sum() > 2000 and (~ok).sum() > 100
+    assert np.abs(got[ok] - ref[ok]).max() <= 1e-14 * np.abs(vals).max()
+
+
+def test_fastvol_axes_build_and_validation(nb, plates_ref):
+    """Graded-grid node values equal nebem_eval at the nodes bit for bit; an
+    axis that is not strictly increasing is refused."""
+    g, _, s_ref, _, _ = plates_ref
+    dp = nb.DevicePanels.from_geometry(g, DEV)
+    sig = dev(s_ref)
+    ax = [dev(a) for a in FV_AXES]
+    vals = nb.fastvol_build_axes(dp, sig, *ax)
+    nodes = oracle.axes_nodes(FV_AXES)
+    direct = nb.eval_points(dp, sig, *(dev(nodes[:, k]) for k in range(3)))
+    torch.cuda.synchronize()
+    assert np.array_equal(vals.cpu().numpy(), np.column_stack([t.cpu().numpy() for t in direct]))
+    bad = FV_AXES[2].copy()
+    bad[3] = bad[2]
+    with pytest.raises(nb.NebemError) as e:
+        nb.fastvol_build_axes(dp, sig, ax[0], ax[1], dev(bad))
+    assert e.value.code == nb.NEBEM_EINVAL
+
+
 # ------------------------------------------------ point -> line charges
 
 @pytest.mark.parametrize("placement", ["centre", "weighted"])

@@ -117,3 +117,22 @@ def test_voxel_placement_mixed_sign_voxel(oracle_lib):
         assert 0.0 <= x < step[0] and 0.0 <= y < step[1]
         assert (lines[0, 2], lines[0, 5]) == (0.0, step[2])
         assert lines[0, 6] * step[2] == pytest.approx(E, rel=1e-12)
+
+
+def test_spacecharge_threshold_rule(oracle_lib):
+    """Algorithm 4's SpChTh: with a threshold the re-solve happens exactly
+    when the charges' magnitude sum |q| exceeds it -- a neutral +-e pair
+    counts 2e, not 0 -- and the fixed schedule is not consulted."""
+    g = parallel_plates(n=6)
+    A = oracle.assemble(g)
+    b0 = g.rhs()
+    s0 = oracle.solve(A, b0)
+    x = np.array([[0.1e-3, 0.0, 0.02e-3], [-0.1e-3, 0.05e-3, -0.03e-3]])
+    q = np.array([E, -E])
+    for thr, due in ((1.5 * E, True), (2.5 * E, False)):
+        p = oracle.SpaceChargeParams(threshold=thr, resolve_every=1)
+        _, sigma, _ = oracle.spacecharge_step(g, A, b0, s0, x, q, 0, p)
+        assert (not np.array_equal(sigma, s0)) == due
+        p = oracle.SpaceChargeParams(threshold=thr, resolve_every=10)
+        _, sigma, _ = oracle.spacecharge_step(g, A, b0, s0, x, q, 3, p)  # off-schedule step
+        assert (not np.array_equal(sigma, s0)) == due

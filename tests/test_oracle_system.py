@@ -246,3 +246,22 @@ def test_point_charges(oracle_lib):
     tgt = rng.standard_normal((20, 3)) * 1e-4
     f = oracle.coulomb(tgt, pair, qp)
     assert np.abs(f).max() <= 1e-14 * ke * 1.6e-19 * 50 / 1e-8
+
+
+def test_refined_solve_residual_and_agreement():
+    """Iterative refinement keeps the solution of the same system and brings
+    an ill-conditioned system's residual down to rounding."""
+    rng = np.random.default_rng(12)
+    n = 300
+    U_, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    V_, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    A = (U_ * np.logspace(0, -9, n)) @ V_.T  # condition number 1e9
+    x_true = rng.normal(size=n)
+    b = A @ x_true
+    x0 = oracle.solve(A, b)
+    x1 = oracle.solve_refined(A, b)
+    r0 = np.linalg.norm(b - A @ x0)
+    r1 = np.linalg.norm(b - A @ x1)
+    assert r1 <= r0 and r1 <= 1e-15 * np.linalg.norm(A, 2) * np.linalg.norm(x1) * n
+    # both within the conditioning bound of the true solution
+    assert np.linalg.norm(x1 - x_true) <= 1e9 * 1e-13 * np.linalg.norm(x_true)
