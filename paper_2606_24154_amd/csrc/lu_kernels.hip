@@ -552,134 +552,6 @@ static void gemm_update(T *A, int n, int k, int kb, int r0, int r1, int c0, int 
                        c1, per_xcd);
 }
 
-// The outer trailing update (K = one outer block, 256): C -= L21 U12 with
-// larger tiles and a software pipeline.  Workgroup tile kBR rows x kBC
-// columns, four waves each 64 rows x 32 columns (4 x 2 MFMA tiles: six
-// operand loads from LDS per eight MFMAs, against four per four in
-// k_gemm_update).  K in chunks of BigK<T>::kc (16 FP64 / 32 FP32 values,
-// the same bytes); LDS holds two chunks: while the matrix cores work on
-// one, the next chunk's global loads are in flight into registers and are
-// stored into the other buffer afterwards -- one barrier per chunk.
-// Operand layouts, result layout, MFMA transposition and the XCD-grouped
-// tile order as in k_gemm_update.
-constexpr int kBR = 128, kBC = 64;
-template <typename T>
-struct BigK;
-template <>
-struct BigK<double> {
-    static constexpr int kc = 16, upad = 2;
-};
-template <>
-struct BigK<float> {
-    static constexpr int kc = 32, upad = 4;
-};
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_big(T *__restrict__ A, int n, int k, int kb, int r0, int r1, int c0,
-                                                  int c1, int per_xcd)
-{
-    typedef typename Acc<T>::type V4;
-    constexpr int KC = BigK<T>::kc;
-    __shared__ T sL[2][KC][kBR + 16];              // sL[buf][kk][row] = -L21
-    __shared__ T sU[2][kBC][KC + BigK<T>::upad];  // sU[buf][col][kk] =  U12
-    const int nt_r = (r1 - r0 + kBR - 1) / kBR, nt_c = (c1 - c0 + kBC - 1) / kBC;
-    const int lin = (int)(blockIdx.x % kXCD) * per_xcd + (int)(blockIdx.x / kXCD);
-    if (lin >= nt_r * nt_c) return;  // whole workgroup: padding of the last die's range
-    const int gsz = kGroupR * nt_c;
-    const int first = (lin / gsz) * kGroupR;
-    const int rows_in = min(kGroupR, nt_r - first);
-    const int within = lin % gsz;
-    const int row0 = r0 + (first + within % rows_in) * kBR;
-    const int col0 = c0 + (within / rows_in) * kBC;
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int wr = (wave & 1) * 64, wc = (wave >> 1) * 32;  // wave's 64 x 32 sub-tile
-    const int li = lane & 15, lk = lane >> 4;
-    V4 acc[2][4];
-#pragma unroll
-    for (int tc = 0; tc < 2; ++tc)
-#pragma unroll
-        for (int tr = 0; tr < 4; ++tr)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int gc = col0 + wc + 16 * tc + Acc<T>::row(lk, v);
-                const int gr = row0 + wr + 16 * tr + li;
-                acc[tc][tr][v] = (gc < c1 && gr < r1) ? A[(size_t)gc * n + gr] : T(0);
-            }
-    constexpr int kPL = KC * kBR / 256, kPU = KC * kBC / 256;  // staged values per thread
-    T pl[kPL], pu[kPU];
-    auto fetch = [&](int k0) {
-#pragma unroll
-        for (int u = 0; u < kPL; ++u) {
-            const int e = tid + 256 * u;
-            const int rr = e % kBR, kl = e / kBR;
-            const int gr = row0 + rr, gk = k0 + kl;
-            pl[u] = (gr < r1 && gk < kb) ? -A[(size_t)(k + gk) * n + gr] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < kPU; ++u) {
-            const int e = tid + 256 * u;
-            const int ku = e % KC, cc = e / KC;
-            const int gc = col0 + cc, gk = k0 + ku;
-            pu[u] = (gc < c1 && gk < kb) ? A[(size_t)gc * n + k + gk] : T(0);
-        }
-    };
-    auto store = [&](int b) {
-#pragma unroll
-        for (int u = 0; u < kPL; ++u) {
-            const int e = tid + 256 * u;
-            sL[b][e / kBR][e % kBR] = pl[u];
-        }
-#pragma unroll
-        for (int u = 0; u < kPU; ++u) {
-            const int e = tid + 256 * u;
-            sU[b][e / KC][e % KC] = pu[u];
-        }
-    };
-    const int nch = (kb + KC - 1) / KC;
-    fetch(0);
-    store(0);
-    __syncthreads();
-    for (int c = 0; c < nch; ++c) {
-        const int b = c & 1;
-        if (c + 1 < nch) fetch((c + 1) * KC);
-#pragma unroll
-        for (int kk = 0; kk < KC; kk += 4) {
-            T u[2], l[4];
-#pragma unroll
-            for (int tc = 0; tc < 2; ++tc) u[tc] = sU[b][wc + 16 * tc + li][kk + lk];
-#pragma unroll
-            for (int tr = 0; tr < 4; ++tr) l[tr] = sL[b][kk + lk][wr + 16 * tr + li];
-#pragma unroll
-            for (int tc = 0; tc < 2; ++tc)
-#pragma unroll
-                for (int tr = 0; tr < 4; ++tr) acc[tc][tr] = mfma16(u[tc], l[tr], acc[tc][tr]);
-        }
-        if (c + 1 < nch) store(b ^ 1);
-        __syncthreads();
-    }
-#pragma unroll
-    for (int tc = 0; tc < 2; ++tc)
-#pragma unroll
-        for (int tr = 0; tr < 4; ++tr)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int gc = col0 + wc + 16 * tc + Acc<T>::row(lk, v);
-                const int gr = row0 + wr + 16 * tr + li;
-                if (gc < c1 && gr < r1) A[(size_t)gc * n + gr] = acc[tc][tr][v];
-            }
-}
-
-template <typename T>
-static void gemm_big(T *A, int n, int k, int kb, int r0, int r1, int c0, int c1, hipStream_t s)
-{
-    if (r1 <= r0 || c1 <= c0 || kb <= 0) return;
-    const int tiles = ((r1 - r0 + kBR - 1) / kBR) * ((c1 - c0 + kBC - 1) / kBC);
-    const int per_xcd = (tiles + kXCD - 1) / kXCD;
-    hipLaunchKernelGGL(k_gemm_big<T>, dim3((unsigned)(per_xcd * kXCD)), dim3(256), 0, s, A, n, k, kb, r0, r1, c0, c1,
-                       per_xcd);
-}
-
 template <typename T>
 static void trsm(T *A, int n, int k, int kb, int jb, int je, hipStream_t s)
 {
@@ -960,7 +832,7 @@ void lu_factor_launch(T *A, int n, int *ipiv, LUWork &w, hipStream_t s)
                 trsm(A, n, b, bb, K1, n, s);
                 gemm_update(A, n, b, bb, b + bb, K1, K1, n, s);
             }
-            gemm_big(A, n, K0, K1 - K0, K1, n, K1, n, s);
+            gemm_update(A, n, K0, K1 - K0, K1, n, K1, n, s);
         }
     }
 }

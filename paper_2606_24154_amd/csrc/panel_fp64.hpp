@@ -201,10 +201,10 @@ __device__ __forceinline__ Kern rect_far(double X, double H, double Z, double lx
     const double d10_11 = fma(-Z, lz, r10sq);
     const double d11_01 = fma(-X, lx, r01sq);
     const double r11sq = fma(-Z, lz, d10_11 + lz * lz);
-    const double r00 = sqrt64_pos(r0sq);
-    const double r10 = sqrt64_pos(r10sq);
-    const double r11 = sqrt64_pos(r11sq);
-    const double r01 = sqrt64_pos(r01sq);
+    const double r00 = sqrt64_far(r0sq);
+    const double r10 = sqrt64_far(r10sq);
+    const double r11 = sqrt64_far(r11sq);
+    const double r01 = sqrt64_far(r01sq);
     const double s0 = r00 + r10, s1 = r10 + r11, s2 = r11 + r01, s3 = r01 + r00;
     const double N2 = H * (2.0 * lx * lz);  // twice the triple product
     const double D1 = fma(fma(r00, r10, d00_10), r11, fma(d00_11, r10, d10_11 * r00));
@@ -237,9 +237,9 @@ __device__ __forceinline__ Kern rtri_far(double X, double H, double Z, double lx
     const double d01 = fma(-X, lx, r0sq);
     const double d02 = fma(-Z, lz, r0sq);
     const double d12 = fma(-Z, lz, d01);
-    const double r0 = sqrt64_pos(r0sq);
-    const double r1 = sqrt64_pos(fma(-X, lx, d01 + lx * lx));
-    const double r2 = sqrt64_pos(fma(-Z, lz, d02 + lz * lz));
+    const double r0 = sqrt64_far(r0sq);
+    const double r1 = sqrt64_far(fma(-X, lx, d01 + lx * lx));
+    const double r2 = sqrt64_far(fma(-Z, lz, d02 + lz * lz));
     const double s0 = r0 + r1, s1 = r1 + r2, s2 = r2 + r0;
     const double lxlz = lx * lz;
     const double N2 = H * (2.0 * lxlz);  // twice the triple product
