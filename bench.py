@@ -44,8 +44,25 @@ ALG_FLOPS_TRI = 100.0
 # 64 x (ADD + MUL + TRANS + 2 FMA) FP64 instructions / interactions; HBM
 # bytes per launch = FETCH_SIZE x 2 + WRITE_SIZE, the factors that make a
 # plain 1 GiB copy read 1 GiB and write 1 GiB), valid for launches of
-# points_per_launch points with the kernels as committed with them.
-COUNTER_CALIBRATION = {}
+# points_per_launch points and only while the evaluation kernel's sources
+# hash to source_sha16 (otherwise the counter figures are not reported).
+COUNTER_CALIBRATION = {
+    # profiles/eval_fp64_thgem_200k.md: one 2e5-point launch, 1.00672e12 interactions
+    "thgem": {"flops_per_interaction": 122.21, "valu_per_interaction": 88.60, "traffic_bytes": 537092096,
+              "points_per_launch": 200000, "source_sha16": "74d163b174faf977"},
+}
+EVAL_SOURCES = ("field_kernels.hip", "panel_fp64.hpp", "fastmath_fp64.hpp", "poly_coeffs.hpp", "farfield_mixed.hpp",
+                "order_kernels.hip", "nebem_internal.hpp")
+
+
+def eval_source_sha16():
+    """sha256 (first 16 hex digits) of the evaluation kernel's sources"""
+    import hashlib
+    h = hashlib.sha256()
+    for name in EVAL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2606_24154_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 FP64_VALU_PEAK = 78.6e12      # MI355X, FLOP/s
 HBM_PEAK = 8.0e12             # B/s
 
@@ -211,10 +228,20 @@ def serve_matrix(args):
     def log(msg):
         print(f"[serve] {msg}", file=sys.stderr, flush=True)
 
-    def stats(run, skip):
+    def progress(k, n):
+        if k % 50 == 0 or k == n:
+            log(f"  {k}/{n} requests done")
+
+    def stats(run, reqs, skip, sat):
         lat = run["latency_s"][skip:]
+        # slowdown: latency over the request's own time on an otherwise idle
+        # device at the saturation rate (its interactions / that rate)
+        own = np.array([n * geoms[g].n * geoms[g].images.count for (_, g, n, _) in reqs[skip:]]) / sat
+        sd = lat / own
         return {"p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
-                "max_ms": 1e3 * float(lat.max()), "mean_ms": 1e3 * float(lat.mean()), "measured": int(lat.size)}
+                "max_ms": 1e3 * float(lat.max()), "mean_ms": 1e3 * float(lat.mean()), "measured": int(lat.size),
+                "slowdown_p50": float(np.percentile(sd, 50)), "slowdown_p99": float(np.percentile(sd, 99)),
+                "own_time_p99_ms": 1e3 * float(np.percentile(own, 99))}
 
     out = {"requests": n_req, "warmup_requests": n_warm, "geometries": [g.name for g in geoms]}
     sat = args.serve_sat
@@ -228,7 +255,7 @@ def serve_matrix(args):
             burst = [(0.0, g, n, sd) for (_, g, n, sd) in serve_requests(n_req, 1.0, 3, seed=4)]
             work = sum(n * geoms[g].n * geoms[g].images.count for (_, g, n, _) in burst)
             srv = nb.Server(ses)
-            run = replay(srv, burst, make_points)
+            run = replay(srv, burst, make_points, progress)
             srv.close()
             sat = work / run["span_s"]
             out["saturation_interactions_per_s"] = sat
@@ -247,15 +274,17 @@ def serve_matrix(args):
             rate = load * out["saturation_requests_per_s"]
             reqs = serve_requests(n_warm + n_req, rate, 3, seed=4 + ri)
             srv = nb.Server(ses)
-            run = replay(srv, reqs, make_points)
+            run = replay(srv, reqs, make_points, progress)
             c = srv.counters()
             srv.close()
-            st = stats(run, n_warm)
+            st = stats(run, reqs, n_warm, out["saturation_interactions_per_s"])
             res[str(load)] = {"arrival_rate_hz": rate, **st, "points_per_s": run["points_per_s"],
                               "interactions_per_s": c.interactions / run["span_s"], "launches": int(c.launches),
                               "errors": len(run["errors"])}
-            log(f"{name} load {load}: p50 {st['p50_ms']:.0f} ms, p99 {st['p99_ms']:.0f} ms "
-                f"({st['measured']} requests)")
+            log(f"{name} load {load}: p50 {st['p50_ms']:.0f} ms, p99 {st['p99_ms']:.0f} ms, slowdown p50 "
+                f"{st['slowdown_p50']:.2f} p99 {st['slowdown_p99']:.1f} ({st['measured']} requests)")
+            # each (precision, load) row as soon as it is measured
+            print(json.dumps({"serve_matrix_row": {"precision": name, "load": load, **res[str(load)]}}), flush=True)
         for x in ses:
             x.close()
         del ses
@@ -314,8 +343,10 @@ def weighting_bench(args):
 def fastvol_bench(args):
     """FastVolume (Sec. 3) on the GEM cell's drift gap, from 20 um above the
     top copper to the drift plane, over the centre cell's bounding box:
-    a regular 5 um grid, and a graded grid of about as many nodes (2.5 um in
-    x and y; in z 1 um at the foil, growing by 5 % per node up to 40 um) --
+    a regular 5 um grid, and a graded grid (x, y: uniform 2 um -- the cell's
+    box holds parts of the neighbouring holes, so no band of one axis is
+    away from every hole; z: 1 um at the foil and at the drift plane,
+    growing by 5 % per node up to 40 um in between) --
     each built by one FP64 evaluation at its nodes.  Trilinear lookups at
     10^6 drift-gap points (HIP events); interpolation error against direct
     evaluation at 2*10^4 of them and at 2*10^4 points in the 100 um above
@@ -346,29 +377,32 @@ def fastvol_bench(args):
     q = lambda a: {k: float(np.quantile(a, f)) for k, f in (("p50", 0.5), ("p95", 0.95), ("p99", 0.99),
                                                              ("max", 1.0))}
 
-    def errors(fi, fd):
+    def errors(fi, fd, p):
         eE = np.linalg.norm(fi[:, 1:] - fd[:, 1:], axis=1) / np.linalg.norm(fd[:, 1:], axis=1)
+        w = int(np.argmax(eE))
         return {"E_rel": q(eE), "frac_E_within_0.25pct": float((eE <= 2.5e-3).mean()),
-                "phi_err_over_max_phi": float((np.abs(fi[:, 0] - fd[:, 0]) / np.abs(fd[:, 0]).max()).max())}
+                "phi_err_over_max_phi": float((np.abs(fi[:, 0] - fd[:, 0]) / np.abs(fd[:, 0]).max()).max()),
+                "worst_point_um": [float(1e6 * v) for v in p[w]], "worst_abs_E": float(np.linalg.norm(fd[w, 1:]))}
 
     def graded_axis(a0, a1, h0, growth, hmax):
-        x = [a0]
+        """nodes from a0 to a1 spaced h0 at both ends, growing by `growth`
+        per node towards the middle, at most hmax"""
+        lo_side, hi_side = [a0], [a1]
         h = h0
-        while x[-1] + h < a1:
-            x.append(x[-1] + h)
+        while hi_side[-1] - lo_side[-1] > 2.0 * h:
+            lo_side.append(lo_side[-1] + h)
+            hi_side.append(hi_side[-1] - h)
             h = min(h * growth, hmax)
-        if a1 - x[-1] < 0.3 * h and len(x) > 1:
-            x[-1] = a1
-        else:
-            x.append(a1)
-        return np.array(x)
+        if hi_side[-1] - lo_side[-1] > h:
+            lo_side.append(0.5 * (lo_side[-1] + hi_side[-1]))
+        return np.array(lo_side + hi_side[::-1])
 
     h = 5e-6
     shape = tuple(int(np.ceil((hi[a] - lo[a]) / h)) + 1 for a in range(3))
     step = tuple((hi[a] - lo[a]) / (shape[a] - 1) for a in range(3))
-    axes = (np.linspace(lo[0], hi[0], int(np.ceil((hi[0] - lo[0]) / 2.5e-6)) + 1),
-            np.linspace(lo[1], hi[1], int(np.ceil((hi[1] - lo[1]) / 2.5e-6)) + 1),
-            graded_axis(lo[2], hi[2], 1e-6, 1.05, 40e-6))
+    hxy = 2e-6
+    axes = tuple(np.linspace(lo[a], hi[a], int(np.ceil((hi[a] - lo[a]) / hxy)) + 1) for a in range(2)) + \
+        (graded_axis(lo[2], hi[2], 1e-6, 1.05, 40e-6),)
     axd = [torch.from_numpy(a).to(dev) for a in axes]
     rows = {}
     for name in ("regular", "graded"):
@@ -382,8 +416,8 @@ def fastvol_bench(args):
             vals = nb.fastvol_build_axes(dp, sigma, *axd)
             look = lambda p: nb.fastvol_interp_axes(vals, *axd, *p)
             nodes = int(np.prod([len(a) for a in axes]))
-            desc = (f"{len(axes[0])}x{len(axes[1])}x{len(axes[2])}, 2.5 um in x, y; z 1 um at the foil "
-                    f"growing 5 %/node to 40 um")
+            desc = (f"{len(axes[0])}x{len(axes[1])}x{len(axes[2])}; x, y uniform {hxy * 1e6:.0f} um; z 1 um at "
+                    f"the foil and at the drift plane, growing 5 %/node to 40 um in between")
         ev[1].record(stream)
         out = look(pt)  # warm-up
         reps = 20
@@ -398,7 +432,7 @@ def fastvol_bench(args):
         fin = np.column_stack([t.cpu().numpy() for t in look(ptn)])
         rows[name] = {"grid": desc, "nodes": nodes, "build_ms": ev[0].elapsed_time(ev[1]),
                       "lookup_ms": 1e3 * t_lookup, "lookups_per_s": m / t_lookup,
-                      "drift_gap": errors(fi, direct), "above_foil_100um": errors(fin, direct_n)}
+                      "drift_gap": errors(fi, direct, pts[:ns]), "above_foil_100um": errors(fin, direct_n, near)}
         print(f"[fastvol] {name}: {nodes} nodes, lookup {1e3 * t_lookup:.3f} ms, E err max "
               f"{rows[name]['drift_gap']['E_rel']['max']:.2e} (above the foil "
               f"{rows[name]['above_foil_100um']['E_rel']['max']:.2e})", file=sys.stderr, flush=True)
@@ -714,12 +748,16 @@ def headline(args):
         per_launch_inter = inter_eval / K
         ach = f_alg * per_launch_inter / (per_launch_ms * 1e-3)
         cal = COUNTER_CALIBRATION.get(args.workload)
+        sha = eval_source_sha16()
+        if cal and cal.get("source_sha16") != sha:
+            cal = None  # the kernel changed since the counters were taken
         roof = {"bound": "alu", "kernel": "k_eval_fp64", "achieved": ach / 1e12, "peak": FP64_VALU_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK,
                 "traffic": cal["traffic_bytes"] if (cal and cal["points_per_launch"] == round(M / K)) else None,
                 "flops_per_interaction": f_alg, "flops_per_interaction_kind": "algorithmic",
                 "elements": {"rectangles": n_rect, "right_triangles": n_tri},
-                "launches": K, "avg_launch_ms": per_launch_ms, "interactions_per_launch": per_launch_inter}
+                "launches": K, "avg_launch_ms": per_launch_ms, "interactions_per_launch": per_launch_inter,
+                "eval_source_sha16": sha}
         if cal:
             roof["counter_flops_per_interaction"] = cal["flops_per_interaction"]
             roof["counter_frac"] = cal["flops_per_interaction"] * eval_rate / FP64_VALU_PEAK

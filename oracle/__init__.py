@@ -455,7 +455,9 @@ def spacecharge_step(geom, A, b0, sigma, qxyz, q, step_index, params: SpaceCharg
       1. if a re-solve is due -- step_index % resolve_every == 0, or with
          threshold >= 0 (Algorithm 4's SpChTh) when the charges' magnitude
          sum |q| exceeds the threshold -- re-solve sigma with the charges on
-         the right-hand side;
+         the right-hand side (LU with FP64 refinement: the unrefined
+         solution's residual moves the field by ~1e-6 relative at the
+         weak-field points of a GEM cell);
       2. E at every charge = panel part (all copies) + point-charge part
          (all other charges, no copies);
       3. every charge moves by sign(q) * mobility * E * dt (all fields from
@@ -467,7 +469,7 @@ def spacecharge_step(geom, A, b0, sigma, qxyz, q, step_index, params: SpaceCharg
         due = step_index % params.resolve_every == 0
     if due:
         b = rhs_with_charges(geom, b0, qxyz, q, nthreads)
-        sigma = solve(A, b)
+        sigma = solve_refined(A, b)
     ep = eval_points(geom, sigma, qxyz, nthreads)[:, 1:]
     ec = coulomb(qxyz, qxyz, q, np.arange(qxyz.shape[0]), nthreads)[:, 1:]
     E = ep + ec

@@ -273,14 +273,15 @@ nebem_status nebem_eval_adaptive(const nebem_panels *panels, const nebem_panels 
     if (prim_after >= ia.n1 && prim_after >= ia.n2) return NEBEM_OK;  // no far copies
     if (np == 0) return fail(NEBEM_EINVAL, "eval_adaptive: no primitives");
     // primitive-averaged densities: sigma_p = sum_{j in p} sigma_j A_j / A_p
-    DevBuf prec, dsbar, dbad, far;
+    DevBuf prec, dsbar, dbad, far, pws;
     if ((st = derive(prims, stream, prec))) return st;
     NEBEM_HIP(dsbar.alloc((size_t)np * sizeof(double), stream));
     NEBEM_HIP(dbad.alloc(sizeof(int), stream));
     NEBEM_HIP(hipMemsetAsync(dbad.p, 0, sizeof(int), stream));
-    launch_prim_density(drec.as<double>(), sigma, elem_prim, n, prec.as<double>(), np, dsbar.as<double>(),
-                        static_cast<int *>(dbad.p), stream);
-    NEBEM_HIP(hipGetLastError());
+    const size_t pwb = prim_density_workspace(n);
+    if (!pwb || pws.alloc(pwb, stream) != hipSuccess) return fail(NEBEM_ENOMEM, "eval_adaptive: workspace");
+    NEBEM_HIP(launch_prim_density(drec.as<double>(), sigma, elem_prim, n, prec.as<double>(), np, dsbar.as<double>(),
+                                  static_cast<int *>(dbad.p), pws.p, pwb, stream));
     int hbad = 0;
     NEBEM_HIP(hipMemcpyAsync(&hbad, dbad.p, sizeof(int), hipMemcpyDeviceToHost, stream));
     NEBEM_HIP(hipStreamSynchronize(stream));

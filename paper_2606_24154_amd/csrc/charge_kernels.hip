@@ -13,19 +13,24 @@
 //
 // Pair sums at the charges (k_coulomb_sorted): the charges are first put in
 // Morton order of their bounding box, so that the 256 targets of a
-// workgroup and the 256 sources of an LDS tile each sit in a small region.
-// Each workgroup takes the first of its targets as the origin, and both its
-// targets and every source it stages are held as FP32 offsets from that
-// origin in micrometres (the FP64 subtraction and the rounding happen once
-// per staged value, not per pair).  A pair then costs 3 FP32 subtractions
-// for the difference, 3 FMAs for r^2 (seeded with 1e-24 um^2, far below any
-// resolvable distance, which keeps 1/r^3 finite for a charge and itself,
-// whose difference is exactly zero), one reciprocal square root, 3
-// multiplications and 3 FMAs: 13 VALU instructions.  The rounding of an
-// offset is relative to its size -- about the pair distance plus the
-// extent of a Morton block -- so the pair term's error stays a few 1e-7 of
-// the largest term near the origin; each run of 64 sources is summed in
-// FP32 and then added to FP64 accumulators.
+// workgroup and the 256 sources of an LDS tile each sit in a small box (the
+// boxes of all 256-charge tiles are computed once per step).  A source tile
+// whose box is farther from the workgroup's box than twice the larger box's
+// diagonal is far: its sources are staged as FP32 offsets in micrometres from
+// the workgroup's first target, as are the targets (one FP64 subtraction
+// and rounding per staged value, not per pair), and a pair costs 3 FP32
+// subtractions, 3 FMAs for r^2 (seeded with 1e-24 um^2, far below any
+// resolvable distance, which keeps 1/r^3 finite), one reciprocal square
+// root, 3 multiplications and 3 FMAs: 13 VALU instructions.  An offset's
+// rounding is relative to its size, at most about the pair distance plus
+// three box diagonals, so in a far tile the difference keeps ~1.5e-7 of the
+// pair distance.  The few near tiles (the workgroup's own and its spatial
+// neighbours: under 1 % of the pairs for a 10^6-charge cloud) take the
+// difference in FP64 and round it once, so close pairs -- whose terms can
+// dominate a charge's field -- keep the FP32 pair term's own accuracy.
+// Runs of 64 sources are summed in FP32 (eight interleaved sums of 8 in the
+// far tiles, where Morton-adjacent terms add coherently) and then added to
+// FP64 accumulators.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,48 +48,124 @@ static inline unsigned blocks(int64_t n) { return (unsigned)((n + kCB - 1) / kCB
 constexpr double kUm = 1e6;          // metres -> micrometres for the FP32 offsets
 constexpr float kSeedR2 = 1e-24f;    // um^2, keeps 1/r^3 finite at r = 0
 
+// box[6 t .. 6 t + 5] = (min x, y, z, max x, y, z) of sorted charges
+// [256 t, 256 t + 256)
+__global__ __launch_bounds__(kCB) void k_tile_boxes(const double *__restrict__ sx, const double *__restrict__ sy,
+                                                    const double *__restrict__ sz, int nq, double *__restrict__ box)
+{
+    __shared__ double red[6][kCB];
+    const int i = blockIdx.x * kCB + threadIdx.x;
+    const bool act = i < nq;
+    const double v[3] = {act ? sx[i] : sx[blockIdx.x * kCB], act ? sy[i] : sy[blockIdx.x * kCB],
+                         act ? sz[i] : sz[blockIdx.x * kCB]};
+    for (int k = 0; k < 3; ++k) {
+        red[k][threadIdx.x] = v[k];
+        red[3 + k][threadIdx.x] = v[k];
+    }
+    __syncthreads();
+    for (int h = kCB / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 6; ++k)
+                red[k][threadIdx.x] = k < 3 ? fmin(red[k][threadIdx.x], red[k][threadIdx.x + h])
+                                            : fmax(red[k][threadIdx.x], red[k][threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) box[6 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
 // E at every charge from all other charges, over charges in Morton order
-// (positions sx/sy/sz, charges sq, all sorted); written to the sorted
-// outputs ox/oy/oz, scaled by k_e.
+// (positions sx/sy/sz, charges sq, all sorted; tile boxes from
+// k_tile_boxes); written to the sorted outputs ox/oy/oz, scaled by k_e.
 __global__ __launch_bounds__(kCB) void k_coulomb_sorted(const double *__restrict__ sx, const double *__restrict__ sy,
                                                         const double *__restrict__ sz, const double *__restrict__ sq,
-                                                        int nq, double *__restrict__ ox, double *__restrict__ oy,
+                                                        const double *__restrict__ box, int nq,
+                                                        double *__restrict__ ox, double *__restrict__ oy,
                                                         double *__restrict__ oz)
 {
     __shared__ float4 src[kCB];
+    __shared__ double nx[kCB], ny[kCB], nz[kCB];
     const int b0 = blockIdx.x * kCB;
     const double cx = sx[b0], cy = sy[b0], cz = sz[b0];  // the block's origin
+    const double *mb = box + 6 * (size_t)blockIdx.x;
+    const double m0 = mb[0], m1 = mb[1], m2 = mb[2], m3 = mb[3], m4 = mb[4], m5 = mb[5];
+    const double mdiag2 = (m3 - m0) * (m3 - m0) + (m4 - m1) * (m4 - m1) + (m5 - m2) * (m5 - m2);
     const int i = b0 + threadIdx.x;
     const bool act = i < nq;
-    const float tx = act ? (float)((sx[i] - cx) * kUm) : 0.0f;
-    const float ty = act ? (float)((sy[i] - cy) * kUm) : 0.0f;
-    const float tz = act ? (float)((sz[i] - cz) * kUm) : 0.0f;
+    const double xi = act ? sx[i] : cx, yi = act ? sy[i] : cy, zi = act ? sz[i] : cz;
+    const float tx = (float)((xi - cx) * kUm);
+    const float ty = (float)((yi - cy) * kUm);
+    const float tz = (float)((zi - cz) * kUm);
     double ax = 0.0, ay = 0.0, az = 0.0;
     for (int base = 0; base < nq; base += kCB) {
+        const double *tb = box + 6 * (size_t)(base / kCB);
+        const double gx = fmax(0.0, fmax(tb[0] - m3, m0 - tb[3]));
+        const double gy = fmax(0.0, fmax(tb[1] - m4, m1 - tb[4]));
+        const double gz = fmax(0.0, fmax(tb[2] - m5, m2 - tb[5]));
+        const double tdiag2 = (tb[3] - tb[0]) * (tb[3] - tb[0]) + (tb[4] - tb[1]) * (tb[4] - tb[1]) +
+                              (tb[5] - tb[2]) * (tb[5] - tb[2]);
+        const bool near = gx * gx + gy * gy + gz * gz < 4.0 * fmax(mdiag2, tdiag2);  // uniform
         __syncthreads();
         const int j = base + threadIdx.x;
-        // padding: a zero charge at the origin
-        src[threadIdx.x] = j < nq ? make_float4((float)((sx[j] - cx) * kUm), (float)((sy[j] - cy) * kUm),
-                                                (float)((sz[j] - cz) * kUm), (float)sq[j])
-                                  : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (near) {
+            // padding: a zero charge at the target block's origin
+            nx[threadIdx.x] = j < nq ? sx[j] : cx;
+            ny[threadIdx.x] = j < nq ? sy[j] : cy;
+            nz[threadIdx.x] = j < nq ? sz[j] : cz;
+            src[threadIdx.x] = make_float4(0.0f, 0.0f, 0.0f, j < nq ? (float)sq[j] : 0.0f);
+        } else {
+            src[threadIdx.x] = j < nq ? make_float4((float)((sx[j] - cx) * kUm), (float)((sy[j] - cy) * kUm),
+                                                    (float)((sz[j] - cz) * kUm), (float)sq[j])
+                                      : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
         __syncthreads();
+        if (near) {
+#pragma unroll 1
+            for (int r0 = 0; r0 < kCB; r0 += kRun) {
+                float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+#pragma unroll 8
+                for (int k = r0; k < r0 + kRun; ++k) {
+                    const float dx = (float)((xi - nx[k]) * kUm);
+                    const float dy = (float)((yi - ny[k]) * kUm);
+                    const float dz = (float)((zi - nz[k]) * kUm);
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    // the target itself and coincident charges add nothing
+                    const float ir = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+                    const float w = (src[k].w * ir) * (ir * ir);
+                    fx = fmaf(w, dx, fx);
+                    fy = fmaf(w, dy, fy);
+                    fz = fmaf(w, dz, fz);
+                }
+                ax += (double)fx;
+                ay += (double)fy;
+                az += (double)fz;
+            }
+            continue;
+        }
 #pragma unroll 1
         for (int r0 = 0; r0 < kCB; r0 += kRun) {
-            float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-#pragma unroll 8
-            for (int k = r0; k < r0 + kRun; ++k) {
-                const float4 c = src[k];
-                const float dx = tx - c.x, dy = ty - c.y, dz = tz - c.z;
-                const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, kSeedR2)));
-                const float ir = __builtin_amdgcn_rsqf(r2);
-                const float w = (c.w * ir) * (ir * ir);
-                fx = fmaf(w, dx, fx);
-                fy = fmaf(w, dy, fy);
-                fz = fmaf(w, dz, fz);
+            float fx[8], fy[8], fz[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) fx[u] = fy[u] = fz[u] = 0.0f;
+#pragma unroll 1
+            for (int g = r0; g < r0 + kRun; g += 8) {
+                float4 cs[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) cs[u] = src[g + u];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const float4 c = cs[u];
+                    const float dx = tx - c.x, dy = ty - c.y, dz = tz - c.z;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, kSeedR2)));
+                    const float ir = __builtin_amdgcn_rsqf(r2);
+                    const float w = (c.w * ir) * (ir * ir);
+                    fx[u] = fmaf(w, dx, fx[u]);
+                    fy[u] = fmaf(w, dy, fy[u]);
+                    fz[u] = fmaf(w, dz, fz[u]);
+                }
             }
-            ax += (double)fx;
-            ay += (double)fy;
-            az += (double)fz;
+            ax += (double)(((fx[0] + fx[1]) + (fx[2] + fx[3])) + ((fx[4] + fx[5]) + (fx[6] + fx[7])));
+            ay += (double)(((fy[0] + fy[1]) + (fy[2] + fy[3])) + ((fy[4] + fy[5]) + (fy[6] + fy[7])));
+            az += (double)(((fz[0] + fz[1]) + (fz[2] + fz[3])) + ((fz[4] + fz[5]) + (fz[6] + fz[7])));
         }
     }
     if (act) {
@@ -281,7 +362,8 @@ size_t coulomb_workspace(int64_t nq)
     const size_t w = order_points_workspace(nq);
     if (!w) return 0;
     const size_t n = (size_t)nq;
-    return w + align256c(4 * n) + align256c(24 * n) + align256c(8 * n) + align256c(24 * n);
+    return w + align256c(4 * n) + align256c(24 * n) + align256c(8 * n) + align256c(24 * n) +
+           align256c(48 * (size_t)blocks(nq));
 }
 
 hipError_t launch_coulomb(const double *qx, const double *qy, const double *qz, const double *q, int64_t nq,
@@ -296,11 +378,14 @@ hipError_t launch_coulomb(const double *qx, const double *qy, const double *qz, 
     double *sp = reinterpret_cast<double *>(w + w0 + align256c(4 * n));
     double *sq = reinterpret_cast<double *>(w + w0 + align256c(4 * n) + align256c(24 * n));
     double *se = reinterpret_cast<double *>(w + w0 + align256c(4 * n) + align256c(24 * n) + align256c(8 * n));
+    double *bx = reinterpret_cast<double *>(w + w0 + align256c(4 * n) + align256c(24 * n) + align256c(8 * n) +
+                                            align256c(24 * n));
     hipError_t e = launch_order_points(qx, qy, qz, nq, sp, sp + n, sp + 2 * n, perm, ws, w0, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gather1, dim3(blocks(nq)), dim3(kCB), 0, s, q, perm, (int)nq, sq);
-    hipLaunchKernelGGL(k_coulomb_sorted, dim3(blocks(nq)), dim3(kCB), 0, s, sp, sp + n, sp + 2 * n, sq, (int)nq, se,
-                       se + n, se + 2 * n);
+    hipLaunchKernelGGL(k_tile_boxes, dim3(blocks(nq)), dim3(kCB), 0, s, sp, sp + n, sp + 2 * n, (int)nq, bx);
+    hipLaunchKernelGGL(k_coulomb_sorted, dim3(blocks(nq)), dim3(kCB), 0, s, sp, sp + n, sp + 2 * n, sq, bx, (int)nq,
+                       se, se + n, se + 2 * n);
     hipLaunchKernelGGL(k_scatter_add3, dim3(blocks(nq)), dim3(kCB), 0, s, se, perm, (int)nq, ex, ey, ez);
     return hipGetLastError();
 }

@@ -15,6 +15,8 @@
 // arrives in.
 #include <hip/hip_runtime.h>
 
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include <cmath>
 
 #include "nebem_internal.hpp"
@@ -445,35 +447,86 @@ void launch_add4(const double *add, int64_t m, double *o0, double *o1, double *o
                        o2, o3);
 }
 
-// Adaptive Modelling's primitive densities: sbar[p] = (sum of sigma_j A_j
-// over the elements j with map[j] == p) / A_p, one lane per primitive,
-// elements in index order (a fixed summation order).  *bad is set when a map
-// entry is outside [0, np).
-__global__ __launch_bounds__(kBlock) void k_prim_density(const double *__restrict__ drec,
-                                                         const double *__restrict__ sigma,
-                                                         const int32_t *__restrict__ map, int n,
-                                                         const double *__restrict__ prec, int np,
-                                                         double *__restrict__ sbar, int *__restrict__ bad)
+// Primitive-averaged densities (Adaptive Modelling): sbar[p] = (sum of
+// sigma_j A_j over the elements j with map[j] == p, in element order) / A_p.
+// The elements are first sorted by primitive (stable radix sort of
+// (map[j], j)); then one lane per primitive finds its run by binary search
+// and sums it in order -- O(n log n) work instead of every lane scanning all
+// n elements, the same sums bit for bit.  *bad is set when a map entry is
+// outside [0, np) (such an element is sorted past every primitive).
+__global__ __launch_bounds__(kBlock) void k_prim_keys(const int32_t *__restrict__ map, int n, int np,
+                                                      unsigned *__restrict__ key, int *__restrict__ idx,
+                                                      int *__restrict__ bad)
 {
-    const int p = blockIdx.x * kBlock + threadIdx.x;
-    const bool checker = p == 0;
-    double q = 0.0;
-    int oob = 0;
-    for (int j = 0; j < n; ++j) {
-        const int mj = map[j];
-        oob |= (mj < 0 || mj >= np) ? 1 : 0;
-        if (mj == p) q = fma(sigma[j], drec[(size_t)j * R_STRIDE + R_AREA], q);
-    }
-    if (checker && oob) *bad = 1;
-    if (p < np) sbar[p] = q / prec[(size_t)p * R_STRIDE + R_AREA];
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    const int mj = map[j];
+    const bool ok = mj >= 0 && mj < np;
+    if (!ok) bad[0] = 1;
+    key[j] = ok ? (unsigned)mj : (unsigned)np;
+    idx[j] = j;
 }
 
-void launch_prim_density(const double *drec, const double *sigma, const int32_t *map, int64_t n,
-                         const double *prec, int64_t np, double *sbar, int *bad, hipStream_t s)
+__device__ __forceinline__ int lower_bound_u(const unsigned *__restrict__ a, int n, unsigned v)
 {
-    if (np <= 0) return;
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_prim_density(const double *__restrict__ drec,
+                                                         const double *__restrict__ sigma,
+                                                         const unsigned *__restrict__ key,
+                                                         const int *__restrict__ idx, int n,
+                                                         const double *__restrict__ prec, int np,
+                                                         double *__restrict__ sbar)
+{
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= np) return;
+    const int s0 = lower_bound_u(key, n, (unsigned)p), s1 = lower_bound_u(key, n, (unsigned)p + 1u);
+    double q = 0.0;
+    for (int s = s0; s < s1; ++s) {
+        const int j = idx[s];
+        q = fma(sigma[j], drec[(size_t)j * R_STRIDE + R_AREA], q);
+    }
+    sbar[p] = q / prec[(size_t)p * R_STRIDE + R_AREA];
+}
+
+size_t prim_density_workspace(int64_t n)
+{
+    size_t sort_b = 0;
+    if (rocprim::radix_sort_pairs(nullptr, sort_b, (unsigned *)nullptr, (unsigned *)nullptr, (int *)nullptr,
+                                  (int *)nullptr, (int)n, 0u, 32u) != hipSuccess)
+        return 0;
+    const size_t a = ((size_t)(n > 0 ? n : 1) * 4 + 255) & ~(size_t)255;
+    return 4 * a + sort_b;
+}
+
+hipError_t launch_prim_density(const double *drec, const double *sigma, const int32_t *map, int64_t n,
+                               const double *prec, int64_t np, double *sbar, int *bad, void *ws, size_t ws_bytes,
+                               hipStream_t s)
+{
+    if (np <= 0 || n <= 0) return hipSuccess;
+    const size_t need = prim_density_workspace(n);
+    if (!need || !ws || ws_bytes < need) return hipErrorInvalidValue;
+    const size_t a = ((size_t)n * 4 + 255) & ~(size_t)255;
+    char *w = static_cast<char *>(ws);
+    unsigned *kin = reinterpret_cast<unsigned *>(w), *kout = reinterpret_cast<unsigned *>(w + a);
+    int *iin = reinterpret_cast<int *>(w + 2 * a), *iout = reinterpret_cast<int *>(w + 3 * a);
+    const unsigned gn = (unsigned)((n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_prim_keys, dim3(gn), dim3(kBlock), 0, s, map, (int)n, (int)np, kin, iin, bad);
+    size_t sort_b = need - 4 * a;
+    hipError_t e = rocprim::radix_sort_pairs(w + 4 * a, sort_b, kin, kout, iin, iout, (int)n, 0u, 32u, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_prim_density, dim3((unsigned)((np + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, drec, sigma,
-                       map, (int)n, prec, (int)np, sbar, bad);
+                       kout, iout, (int)n, prec, (int)np, sbar);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------- several sigma columns

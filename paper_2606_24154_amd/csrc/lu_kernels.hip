@@ -456,6 +456,10 @@ __global__ __launch_bounds__(256) void k_gemm_update(T *__restrict__ A, int n, i
     const int li = lane & 15, lk = lane >> 4;
     // The accumulators start from C itself (loads issued before the operand
     // staging so that the two overlap); the MFMA chain then adds (-L21) U12.
+    // Every global load is unconditional, from an index clamped into the
+    // matrix, and out-of-range entries are replaced when they reach LDS (or
+    // are never stored, for C): a load under a branch would have to complete
+    // inside that branch, one memory latency per load.
     V4 acc[2][2];
 #pragma unroll
     for (int tc = 0; tc < 2; ++tc)
@@ -465,16 +469,15 @@ __global__ __launch_bounds__(256) void k_gemm_update(T *__restrict__ A, int n, i
             for (int v = 0; v < 4; ++v) {
                 const int gc = col0 + wc + 16 * tc + Acc<T>::row(lk, v);
                 const int gr = row0 + wr + 16 * tr + li;
-                acc[tc][tr][v] = (gc < c1 && gr < r1) ? A[(size_t)gc * n + gr] : T(0);
+                acc[tc][tr][v] = A[(size_t)min(gc, c1 - 1) * n + min(gr, r1 - 1)];
             }
     // K in chunks of kKC; entries past kb are staged as zeros, so every chunk
     // has the same compile-time shape (index arithmetic by shifts, the MFMA
     // loop fully unrolled).  FP32: the next chunk's global loads are issued
     // into registers before the current chunk's MFMAs and stored to LDS
-    // after them, so their latency hides behind the matrix-core work (-23 %
-    // at N = 41 600).  FP64: the same prefetch needs 172 VGPRs, halving the
-    // resident workgroups, and ran 26 % slower; it stages each chunk when
-    // it is needed.
+    // after them, so their latency hides behind the matrix-core work.  FP64:
+    // the chunk's loads are issued together when it is needed (the prefetch
+    // registers would halve the resident workgroups).
     constexpr bool kPrefetch = sizeof(T) == 4;
     constexpr int kPer = kKC * kGT / 256;  // staged entries per thread and operand
     T pl[kPer], pu[kPer];
@@ -483,37 +486,26 @@ __global__ __launch_bounds__(256) void k_gemm_update(T *__restrict__ A, int n, i
         for (int u = 0; u < kPer; ++u) {
             const int e = tid + 256 * u;
             const int rr = e % kGT, kl = e / kGT;
-            const int gr = row0 + rr, gkl = k0 + kl;
-            pl[u] = (gr < r1 && gkl < kb) ? -A[(size_t)(k + gkl) * n + gr] : T(0);
+            pl[u] = A[(size_t)(k + min(k0 + kl, kb - 1)) * n + min(row0 + rr, r1 - 1)];
             const int ku = e % kKC, cc = e / kKC;
-            const int gc = col0 + cc, gku = k0 + ku;
-            pu[u] = (gc < c1 && gku < kb) ? A[(size_t)gc * n + k + gku] : T(0);
+            pu[u] = A[(size_t)min(col0 + cc, c1 - 1) * n + k + min(k0 + ku, kb - 1)];
+        }
+    };
+    auto stage = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + 256 * u;
+            const int rr = e % kGT, kl = e / kGT;
+            sL[kl][rr] = (row0 + rr < r1 && k0 + kl < kb) ? -pl[u] : T(0);
+            const int ku = e % kKC, cc = e / kKC;
+            sU[cc][ku] = (col0 + cc < c1 && k0 + ku < kb) ? pu[u] : T(0);
         }
     };
     if constexpr (kPrefetch) fetch(0);
     for (int k0 = 0; k0 < kb; k0 += kKC) {
         if (k0) __syncthreads();  // every wave is done reading the previous chunk
-        if constexpr (kPrefetch) {
-#pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                const int e = tid + 256 * u;
-                sL[e / kGT][e % kGT] = pl[u];
-                sU[e / kKC][e % kKC] = pu[u];
-            }
-        } else {
-#pragma unroll
-            for (int e = tid; e < kKC * kGT; e += 256) {
-                const int rr = e % kGT, kk = e / kGT;
-                const int gr = row0 + rr, gk = k0 + kk;
-                sL[kk][rr] = (gr < r1 && gk < kb) ? -A[(size_t)(k + gk) * n + gr] : T(0);
-            }
-#pragma unroll
-            for (int e = tid; e < kKC * kGT; e += 256) {
-                const int kk = e % kKC, cc = e / kKC;
-                const int gc = col0 + cc, gk = k0 + kk;
-                sU[cc][kk] = (gc < c1 && gk < kb) ? A[(size_t)gc * n + k + gk] : T(0);
-            }
-        }
+        if constexpr (!kPrefetch) fetch(k0);
+        stage(k0);
         __syncthreads();
         if constexpr (kPrefetch) {
             if (k0 + kKC < kb) fetch(k0 + kKC);
@@ -542,10 +534,127 @@ __global__ __launch_bounds__(256) void k_gemm_update(T *__restrict__ A, int n, i
             }
 }
 
+// The same update with 128 x 128 workgroup tiles for large trailing
+// matrices: four waves of 64 x 64 (4 x 4 MFMA tiles, 16 accumulators in the
+// matrix-core registers), K in chunks of kBK staged through two LDS buffers,
+// the next chunk's global loads held in registers while the current chunk's
+// MFMAs run, one workgroup barrier per chunk.  Per output element the MFMA
+// sequence (accumulator from C, K in steps of 4 in increasing order) is that
+// of k_gemm_update, so both give bit-identical results; the larger tile
+// halves the operand bytes staged per FLOP.
+constexpr int kBT = 128;  // large-update workgroup tile (rows and columns)
+constexpr int kBK = 16;   // its K chunk
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_gemm_update_big(T *__restrict__ A, int n, int k, int kb, int r0, int r1,
+                                                            int c0, int c1, int per_xcd)
+{
+    typedef typename Acc<T>::type V4;
+    // strides as in k_gemm_update: consecutive k of sL, and the 16 columns a
+    // half-wave reads from sU, fall on distinct LDS banks
+    __shared__ T sL[2][kBK][kBT + 16];  // sL[buf][kk][row] = -L21
+    __shared__ T sU[2][kBT][kBK + 2];   // sU[buf][col][kk] =  U12
+    const int nt_r = (r1 - r0 + kBT - 1) / kBT, nt_c = (c1 - c0 + kBT - 1) / kBT;
+    const int lin = (int)(blockIdx.x % kXCD) * per_xcd + (int)(blockIdx.x / kXCD);
+    if (lin >= nt_r * nt_c) return;  // whole workgroup: padding of the last die's range
+    const int gsz = kGroupR * nt_c;
+    const int first = (lin / gsz) * kGroupR;
+    const int rows_in = min(kGroupR, nt_r - first);
+    const int within = lin % gsz;
+    const int row0 = r0 + (first + within % rows_in) * kBT;
+    const int col0 = c0 + (within / rows_in) * kBT;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wr = (wave & 1) * 64, wc = (wave >> 1) * 64;  // wave's 64 x 64 sub-tile
+    const int li = lane & 15, lk = lane >> 4;
+    // Every global load is unconditional, from an index clamped into the
+    // matrix, and out-of-range entries are replaced when they reach LDS or
+    // the accumulators: a load under a branch would have to complete inside
+    // that branch, one memory latency per load.
+    V4 acc[4][4];
+#pragma unroll
+    for (int tc = 0; tc < 4; ++tc)
+#pragma unroll
+        for (int tr = 0; tr < 4; ++tr)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gc = col0 + wc + 16 * tc + Acc<T>::row(lk, v);
+                const int gr = row0 + wr + 16 * tr + li;
+                acc[tc][tr][v] = A[(size_t)min(gc, c1 - 1) * n + min(gr, r1 - 1)];
+            }
+    constexpr int kPer = kBK * kBT / 256;  // staged entries per thread and operand
+    T pl[kPer], pu[kPer];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + 256 * u;
+            const int rr = e % kBT, kl = e / kBT;
+            pl[u] = A[(size_t)(k + min(k0 + kl, kb - 1)) * n + min(row0 + rr, r1 - 1)];
+            const int ku = e % kBK, cc = e / kBK;
+            pu[u] = A[(size_t)min(col0 + cc, c1 - 1) * n + k + min(k0 + ku, kb - 1)];
+        }
+    };
+    auto stage = [&](int b, int k0) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + 256 * u;
+            const int rr = e % kBT, kl = e / kBT;
+            sL[b][kl][rr] = (row0 + rr < r1 && k0 + kl < kb) ? -pl[u] : T(0);
+            const int ku = e % kBK, cc = e / kBK;
+            sU[b][cc][ku] = (col0 + cc < c1 && k0 + ku < kb) ? pu[u] : T(0);
+        }
+    };
+    const int nch = (kb + kBK - 1) / kBK;
+    fetch(0);
+    stage(0, 0);
+    if (nch > 1) fetch(kBK);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int b = c & 1;
+#pragma unroll
+        for (int kk = 0; kk < kBK; kk += 4) {
+            T u[4], l[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                u[t] = sU[b][wc + 16 * t + li][kk + lk];
+                l[t] = sL[b][kk + lk][wr + 16 * t + li];
+            }
+#pragma unroll
+            for (int tc = 0; tc < 4; ++tc)
+#pragma unroll
+                for (int tr = 0; tr < 4; ++tr) acc[tc][tr] = mfma16(u[tc], l[tr], acc[tc][tr]);
+        }
+        // the other buffer was last read in chunk c - 1, which every wave
+        // finished before the previous barrier
+        if (c + 1 < nch) {
+            stage(b ^ 1, (c + 1) * kBK);
+            if (c + 2 < nch) fetch((c + 2) * kBK);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int tc = 0; tc < 4; ++tc)
+#pragma unroll
+        for (int tr = 0; tr < 4; ++tr)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gc = col0 + wc + 16 * tc + Acc<T>::row(lk, v);
+                const int gr = row0 + wr + 16 * tr + li;
+                if (gc < c1 && gr < r1) A[(size_t)gc * n + gr] = acc[tc][tr][v];
+            }
+}
+
 template <typename T>
 static void gemm_update(T *A, int n, int k, int kb, int r0, int r1, int c0, int c1, hipStream_t s)
 {
     if (r1 <= r0 || c1 <= c0 || kb <= 0) return;
+    if (r1 - r0 >= 2 * kBT && c1 - c0 >= 2 * kBT) {
+        const int tiles = ((r1 - r0 + kBT - 1) / kBT) * ((c1 - c0 + kBT - 1) / kBT);
+        const int per_xcd = (tiles + kXCD - 1) / kXCD;
+        hipLaunchKernelGGL(k_gemm_update_big<T>, dim3((unsigned)(per_xcd * kXCD)), dim3(256), 0, s, A, n, k, kb, r0,
+                           r1, c0, c1, per_xcd);
+        return;
+    }
     const int tiles = ((r1 - r0 + kGT - 1) / kGT) * ((c1 - c0 + kGT - 1) / kGT);
     const int per_xcd = (tiles + kXCD - 1) / kXCD;
     hipLaunchKernelGGL(k_gemm_update<T>, dim3((unsigned)(per_xcd * kXCD)), dim3(256), 0, s, A, n, k, kb, r0, r1, c0,

@@ -136,10 +136,13 @@ void launch_line_rhs(const double *drec, int64_t n, const double *lines, int64_t
 
 // o_c[i] += add[c m + i] for each non-null o_c
 void launch_add4(const double *add, int64_t m, double *o0, double *o1, double *o2, double *o3, hipStream_t s);
-// sbar[p] = sum_{map[j] == p} sigma_j A_j / A_p (records drec, prec); *bad
-// (device int, cleared by the caller) set if a map entry is outside [0, np)
-void launch_prim_density(const double *drec, const double *sigma, const int32_t *map, int64_t n,
-                         const double *prec, int64_t np, double *sbar, int *bad, hipStream_t s);
+// sbar[p] = sum_{map[j] == p} sigma_j A_j / A_p (records drec, prec), in
+// element order; *bad (device int, cleared by the caller) set if a map entry
+// is outside [0, np); ws of prim_density_workspace(n) bytes (0 on error)
+size_t prim_density_workspace(int64_t n);
+hipError_t launch_prim_density(const double *drec, const double *sigma, const int32_t *map, int64_t n,
+                               const double *prec, int64_t np, double *sbar, int *bad, void *ws, size_t ws_bytes,
+                               hipStream_t s);
 
 // Output columns of a several-column evaluation: component c (phi, ex, ey,
 // ez) of column k at c[c] + k * stride; a null c[c] is not stored.

@@ -201,7 +201,7 @@ void launch_unorder4(const double *src, const int *perm, int64_t m, double *d0, 
 
 // ------------------------------------------------------- evaluation driver
 namespace {
-constexpr size_t kPartBudget = size_t(256) << 20;  // preferred bytes of segment partial sums per chunk
+constexpr size_t kPartBudget = size_t(512) << 20;  // preferred bytes of segment partial sums per chunk
 
 struct EvalShape {
     SegPlan sp;
@@ -337,6 +337,13 @@ hipError_t run_eval(const double *drec, const double *sigma, int64_t n, int ncol
         c = std::max<int64_t>(256, (c / 2) & ~(int64_t)255);
     }
     if (L.total > 0 && !ws) return hipErrorInvalidValue;
+    // as many chunks as needed, of equal size (a short last chunk would be a
+    // launch too small to fill the device)
+    {
+        const int64_t nch = (m + c - 1) / c;
+        const int64_t even = ((m + nch - 1) / nch + 255) & ~(int64_t)255;
+        if (even < c) c = even;
+    }
     char *w = static_cast<char *>(ws);
     double *part = sh.part_pp ? reinterpret_cast<double *>(w + L.part) : nullptr;
     for (int64_t p0 = 0; p0 < m; p0 += c) {

@@ -10,12 +10,14 @@ import time
 import numpy as np
 
 
-def replay(server, requests, make_points):
+def replay(server, requests, make_points, progress=None):
     """requests: list of (arrival_s, geometry, n_points, seed) sorted by
     arrival; make_points(geometry, n, seed) -> (n, 3) float64.  Returns a dict
-    with per-request latencies (s), points/s and the span of the run."""
+    with per-request latencies (s), points/s and the span of the run.
+    progress(k, n), if given, is called after each completed request."""
     pts = [make_points(g, n, sd) for (_, g, n, sd) in requests]
     tickets = [None] * len(requests)
+    submitted = [threading.Event() for _ in requests]
     errors = []
 
     def submitter():
@@ -28,21 +30,27 @@ def replay(server, requests, make_points):
                 tickets[k] = server.submit(g, pts[k], want=("phi", "ex", "ey", "ez"))
             except Exception as e:  # recorded, the run continues
                 errors.append((k, repr(e)))
+            submitted[k].set()
 
     th = threading.Thread(target=submitter)
     th.start()
-    th.join()
     lat, t_first, t_last, npts = [], None, None, 0
     results = [None] * len(requests)
-    for k, t in enumerate(tickets):
+    # collect results in submission order while later requests still arrive
+    for k in range(len(requests)):
+        submitted[k].wait()
+        t = tickets[k]
         if t is None:
             continue
         out, st = server.wait(t)
         results[k] = out
+        if progress is not None:
+            progress(k + 1, len(requests))
         lat.append(st.t_done - st.t_submit)
         t_first = st.t_submit if t_first is None else min(t_first, st.t_submit)
         t_last = st.t_done if t_last is None else max(t_last, st.t_done)
         npts += int(st.points)
+    th.join()
     lat = np.array(lat)
     span = (t_last - t_first) if lat.size else 0.0
     return {

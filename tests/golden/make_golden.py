@@ -15,7 +15,9 @@ traj: the reduced space-charge trajectory: the same cell with copies +-1,
       charges, Algorithm 2's sum; re-solve at steps 0 and 10, dt = 1 ps,
       mobility 1e-4 m^2/Vs): for 1024 sampled charges, positions and the
       field at the charges after steps 0, 9, 10 and 19 (around each
-      re-solve and at the end), and sigma after each re-solve.
+      re-solve and at the end), at every step the field's magnitude and the
+      sum of the magnitudes of the charge-charge terms (the scale of the
+      FP32 pair terms' error), and sigma after each re-solve.
 """
 import os
 import sys
@@ -68,11 +70,15 @@ def make_traj():
     centre = [0.5 * (g.images.a1[0] + g.images.a2[0]), 0.5 * g.images.a2[1], 0.0]
     xyz, q = charge_cloud(centre, 20e-6, TRAJ_CHARGES, seed=3)
     params = oracle.SpaceChargeParams(dt=1e-12, mobility=1e-4, resolve_every=10)
-    pos, E, sig = [], [], []
+    pos, E, sig, pair_abs = [], [], [], []
     sigma = None
     x = xyz.copy()
+    sample = np.sort(np.random.default_rng(17).choice(TRAJ_CHARGES, TRAJ_SAMPLE, replace=False))
     for k in range(TRAJ_STEPS):
         t0 = time.time()
+        # the charge-charge terms' magnitudes at the start-of-step positions
+        _, ab = oracle.coulomb(x[sample], x, q, sample, with_abs=True)
+        pair_abs.append(ab)
         x, sigma, e = oracle.spacecharge_step(g, A, b0, sigma, x, q, k, params)
         pos.append(x)
         E.append(e)
@@ -80,9 +86,9 @@ def make_traj():
             sig.append(sigma)
         log(f"traj: step {k} in {time.time() - t0:.0f} s")
     keep = np.array(TRAJ_KEEP_STEPS)
-    sample = np.sort(np.random.default_rng(17).choice(TRAJ_CHARGES, TRAJ_SAMPLE, replace=False))
     np.savez(os.path.join(HERE, "gem_cell_trajectory.npz"), steps=keep, sample=sample,
              positions=np.stack(pos)[keep][:, sample], fields=np.stack(E)[keep][:, sample], sigma=np.stack(sig),
+             field_norm=np.linalg.norm(np.stack(E)[:, sample], axis=2), pair_abs=np.stack(pair_abs),
              n_steps=TRAJ_STEPS, n_charges=TRAJ_CHARGES, dt=params.dt, mobility=params.mobility,
              resolve_every=params.resolve_every)
 

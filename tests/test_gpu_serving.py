@@ -75,6 +75,7 @@ def test_mix_equals_alone_and_admission(nb, precision):
     c = srv.counters()
     assert c.points_done == sum(r[2] for r in reqs) and c.launches >= 2
     checked = 0
+    sigmas = [x.sigma().cpu().numpy() for x in ses]
     # the same requests one at a time through the same server, and through
     # the request's session
     for k, (_, g, n, sd) in enumerate(reqs):
@@ -85,19 +86,17 @@ def test_mix_equals_alone_and_admission(nb, precision):
         for name, r in zip(("phi", "ex", "ey", "ez"), ref):
             assert np.array_equal(out[name], alone[name]), (k, name)
             assert np.array_equal(out[name], r), (k, name, "session")
-        # served values against the oracle with the session's sigma, on a
-        # sample of the points (FP64 bar / mixed bar)
-        if g > 0 and checked < 4:
-            checked += 1
-            pts = run["points_in"][k]
-            idx = np.random.default_rng(k).choice(len(pts), min(16, len(pts)), replace=False)
-            sigma = ses[g].sigma().cpu().numpy()
-            want = oracle.eval_points(geoms[g], sigma, pts[idx])
-            got = np.column_stack([out[name][idx] for name in ("phi", "ex", "ey", "ez")])
-            ephi, eE = _rel_errors(got, want)
-            tol = 1e-10 if precision == 0 else 1e-6
-            assert ephi < tol and eE < tol, (k, ephi, eE)
-    assert checked == 4
+        # every request's served values against the oracle with the
+        # session's sigma, on 8 sampled points (FP64 bar / mixed bar)
+        checked += 1
+        pts = run["points_in"][k]
+        idx = np.random.default_rng(k).choice(len(pts), min(8, len(pts)), replace=False)
+        want = oracle.eval_points(geoms[g], sigmas[g], pts[idx])
+        got = np.column_stack([out[name][idx] for name in ("phi", "ex", "ey", "ez")])
+        ephi, eE = _rel_errors(got, want)
+        tol = 1e-10 if precision == 0 else 1e-6
+        assert ephi < tol and eE < tol, (k, g, ephi, eE)
+    assert checked == len(reqs)
     assert run["p99_s"] >= run["p50_s"] > 0
     srv.close()
     for x in ses:
