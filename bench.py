@@ -48,8 +48,8 @@ ALG_FLOPS_TRI = 100.0
 # hash to source_sha16 (otherwise the counter figures are not reported).
 COUNTER_CALIBRATION = {
     # profiles/eval_fp64_thgem_200k.md: one 2e5-point launch, 1.00672e12 interactions
-    "thgem": {"flops_per_interaction": 122.21, "valu_per_interaction": 88.60, "traffic_bytes": 537092096,
-              "points_per_launch": 200000, "source_sha16": "74d163b174faf977"},
+    "thgem": {"flops_per_interaction": 101.04, "valu_per_interaction": 73.09, "traffic_bytes": 537299200,
+              "points_per_launch": 200000, "source_sha16": "0757a6e2d6bdd71d"},
 }
 EVAL_SOURCES = ("field_kernels.hip", "panel_fp64.hpp", "fastmath_fp64.hpp", "poly_coeffs.hpp", "farfield_mixed.hpp",
                 "order_kernels.hip", "nebem_internal.hpp")
@@ -232,16 +232,14 @@ def serve_matrix(args):
         if k % 50 == 0 or k == n:
             log(f"  {k}/{n} requests done")
 
-    def stats(run, reqs, skip, sat):
+    def stats(run, reqs, skip):
         lat = run["latency_s"][skip:]
-        # slowdown: latency over the request's own time on an otherwise idle
-        # device at the saturation rate (its interactions / that rate)
-        own = np.array([n * geoms[g].n * geoms[g].images.count for (_, g, n, _) in reqs[skip:]]) / sat
-        sd = lat / own
-        return {"p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
-                "max_ms": 1e3 * float(lat.max()), "mean_ms": 1e3 * float(lat.mean()), "measured": int(lat.size),
-                "slowdown_p50": float(np.percentile(sd, 50)), "slowdown_p99": float(np.percentile(sd, 99)),
-                "own_time_p99_ms": 1e3 * float(np.percentile(own, 99))}
+        geo = np.array([g for (_, g, _, _) in reqs[skip:]])
+        pct = lambda a, f: 1e3 * float(np.percentile(a, f)) if a.size else None
+        return {"p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "max_ms": 1e3 * float(lat.max()),
+                "mean_ms": 1e3 * float(lat.mean()), "measured": int(lat.size),
+                "per_geometry": {geoms[k].name: {"requests": int((geo == k).sum()), "p50_ms": pct(lat[geo == k], 50),
+                                                 "p99_ms": pct(lat[geo == k], 99)} for k in range(len(geoms))}}
 
     out = {"requests": n_req, "warmup_requests": n_warm, "geometries": [g.name for g in geoms]}
     sat = args.serve_sat
@@ -277,12 +275,11 @@ def serve_matrix(args):
             run = replay(srv, reqs, make_points, progress)
             c = srv.counters()
             srv.close()
-            st = stats(run, reqs, n_warm, out["saturation_interactions_per_s"])
+            st = stats(run, reqs, n_warm)
             res[str(load)] = {"arrival_rate_hz": rate, **st, "points_per_s": run["points_per_s"],
                               "interactions_per_s": c.interactions / run["span_s"], "launches": int(c.launches),
                               "errors": len(run["errors"])}
-            log(f"{name} load {load}: p50 {st['p50_ms']:.0f} ms, p99 {st['p99_ms']:.0f} ms, slowdown p50 "
-                f"{st['slowdown_p50']:.2f} p99 {st['slowdown_p99']:.1f} ({st['measured']} requests)")
+            log(f"{name} load {load}: p50 {st['p50_ms']:.0f} ms, p99 {st['p99_ms']:.0f} ms ({st['measured']} requests)")
             # each (precision, load) row as soon as it is measured
             print(json.dumps({"serve_matrix_row": {"precision": name, "load": load, **res[str(load)]}}), flush=True)
         for x in ses:

@@ -104,11 +104,46 @@ __global__ __launch_bounds__(kBlock) void k_prep(nebem_panels p, double *__restr
     r[R_BC] = (double)bc;
 }
 
+// Triangle pairs: two consecutive right triangles with the same right-angle
+// corner, one leg shared (same direction and length) and the other legs
+// opposite -- the two halves of a triangle cut at the foot of its altitude,
+// as a mesher emits them -- all to 1e-12 relative.  Element i is marked
+// kind 2 when its second leg is the shared one (the pair's first triangle
+// is i), kind 3 when its first leg is (the first triangle is i + 1).  The
+// field kernels then evaluate the two together (rtri_pair_far), taking the
+// second triangle's legs as c e2 and -b e1 in the first one's frame: a
+// change of its geometry of at most 1e-12 relative, below the far forms'
+// own rounding error (~R/D ulps).  Only i's kind is written, so launches
+// over any ranges of elements agree.
+__device__ __forceinline__ double dist3(const double *a, const double *b, double sb)
+{
+    const double x = a[0] - sb * b[0], y = a[1] - sb * b[1], z = a[2] - sb * b[2];
+    return sqrt(x * x + y * y + z * z);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pair_flags(nebem_panels p, double *__restrict__ drec)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i + 1 >= p.n) return;
+    if (p.kind[i] != 1 || p.kind[i + 1] != 1) return;
+    double *r = drec + i * R_STRIDE;
+    const double *q = r + R_STRIDE;
+    constexpr double tol = 1e-12;
+    if (!(dist3(r + R_OX, q + R_OX, 1.0) <= tol * fmax(r[R_DIAM], q[R_DIAM]))) return;
+    if (dist3(r + R_E2X, q + R_E1X, 1.0) <= tol && dist3(r + R_E1X, q + R_E2X, -1.0) <= tol &&
+        fabs(r[R_LZ] - q[R_LX]) <= tol * r[R_LZ])
+        r[R_KIND] = 2.0;
+    else if (dist3(q + R_E2X, r + R_E1X, 1.0) <= tol && dist3(q + R_E1X, r + R_E2X, -1.0) <= tol &&
+             fabs(q[R_LZ] - r[R_LX]) <= tol * q[R_LZ])
+        r[R_KIND] = 3.0;
+}
+
 void launch_prep(const nebem_panels *p, double *drec, int *bad, hipStream_t s)
 {
     if (p->n <= 0) return;
     const unsigned g = (unsigned)((p->n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_prep, dim3(g), dim3(kBlock), 0, s, *p, drec, bad);
+    hipLaunchKernelGGL(k_pair_flags, dim3(g), dim3(kBlock), 0, s, *p, drec);
 }
 
 // ------------------------------------------------------------- one element
@@ -143,6 +178,22 @@ __device__ __forceinline__ Elem load_elem(const double *d)
     e.area = uni(d[R_AREA]);
     e.kind = uni((int)d[R_KIND]);
     return e;
+}
+
+// The second triangle of a pair (element records of kind 2 or 3: see
+// k_pair_flags): what the pair form needs from its record.
+struct PairB {
+    double lz, hyp, ihyp, diam;
+};
+
+__device__ __forceinline__ PairB load_pair_b(const double *d)
+{
+    PairB f;
+    f.lz = uni(d[R_LZ]);
+    f.hyp = uni(d[R_HYP]);
+    f.ihyp = uni(d[R_IHYP]);
+    f.diam = uni(d[R_DIAM]);
+    return f;
 }
 
 // Sum over lattice translations of one element, local frame; (X0,Z0,H0) is
@@ -297,6 +348,113 @@ __device__ __forceinline__ void element_copies(const Elem &e, const ImgArgs &img
     }
 }
 
+// Sum over lattice translations of a triangle pair (FP64 evaluation only),
+// in the first triangle's frame: the second triangle's legs are c = e.lz
+// along e2 and b = f.lz along -e1 (the geometry the pair flag was tested
+// for, within 1e-12 of its own record), so its frame is (e2, -e1, e3) and
+// its sums come back in that frame.  Tiers as in sum_translations, by the
+// distance from the shared corner in units of the larger diameter; below
+// the far regime each triangle takes the general form.
+template <bool HOLE>
+__device__ __forceinline__ void sum_translations_pair(const Elem &e, const PairB &f, int n1, int n2, int hole,
+                                                      double X0, double Z0, double H0, double aX, double aZ,
+                                                      double aH, double bX, double bZ, double bH, double (&s1)[4],
+                                                      double (&s2)[4])
+{
+    const double a = e.lx, c = e.lz, b = f.lz;
+    const double dp = fmax(e.diam, f.diam);
+    const double far2 = (kFarDiam * kFarDiam) * (dp * dp);
+    const double vfar2 = (kVeryFarDiam * kVeryFarDiam) * (dp * dp);
+#pragma unroll 1
+    for (int i1 = -n1; i1 <= n1; ++i1) {
+        const double f1 = -(double)i1;
+        const double X1 = fma(f1, aX, X0), Z1 = fma(f1, aZ, Z0), H1 = fma(f1, aH, H0);
+        const bool cut = HOLE && abs(i1) <= hole;
+#pragma unroll 1
+        for (int seg = 0; seg <= (int)cut; ++seg) {
+            const int i2a = seg == 0 ? -n2 : hole + 1;
+            const int i2b = (cut && seg == 0) ? -hole - 1 : n2;
+#pragma unroll 1
+            for (int i2 = i2a; i2 <= i2b; ++i2) {
+                const double f2 = -(double)i2;
+                const double X = fma(f2, bX, X1), Z = fma(f2, bZ, Z1);
+                const double H = fma(f2, bH, H1);
+                const double r0sq = fma(X, X, fma(Z, Z, H * H));
+                Kern k1, k2;
+                if (r0sq >= vfar2) {  // far forms return the potentials added to the sums
+                    rtri_pair_far<true>(X, H, Z, a, b, c, e.hyp, f.hyp, r0sq, s1[0], s2[0], k1, k2);
+                } else if (r0sq >= far2) {
+                    rtri_pair_far<false>(X, H, Z, a, b, c, e.hyp, f.hyp, r0sq, s1[0], s2[0], k1, k2);
+                } else {
+                    k1 = rtri_fp64(X, H, Z, a, c, e.hyp, e.ihyp, r0sq);
+                    k2 = rtri_fp64(Z, H, -X, c, b, f.hyp, f.ihyp, r0sq);
+                    k1.phi += s1[0];
+                    k2.phi += s2[0];
+                }
+                s1[0] = k1.phi;
+                s1[1] += k1.ex;
+                s1[2] += k1.ez;
+                s1[3] += k1.en;
+                s2[0] = k2.phi;
+                s2[1] += k2.ex;
+                s2[2] += k2.ez;
+                s2[3] += k2.en;
+            }
+        }
+    }
+}
+
+// phi', E' (global frame) of both triangles of a pair with all their copies
+// at P: o1 for the first, o2 for the second.
+template <bool HOLE>
+__device__ __forceinline__ void element_pair_copies(const Elem &e, const PairB &f, const ImgArgs &img, double Px,
+                                                    double Py, double Pz, double (&o1)[4], double (&o2)[4])
+{
+#pragma unroll
+    for (int c = 0; c < 4; ++c) o1[c] = o2[c] = 0.0;
+    for (int r = 0; r < img.nref; ++r) {
+        const int ax = img.axes[r];
+        const double Qx = (ax & 1) ? 2.0 * img.mpos[0] - Px : Px;
+        const double Qy = (ax & 2) ? 2.0 * img.mpos[1] - Py : Py;
+        const double Qz = (ax & 4) ? 2.0 * img.mpos[2] - Pz : Pz;
+        const double rx = Qx - e.ox, ry = Qy - e.oy, rz = Qz - e.oz;
+        const double X0 = rx * e.e1x + ry * e.e1y + rz * e.e1z;
+        const double Z0 = rx * e.e2x + ry * e.e2y + rz * e.e2z;
+        const double H0 = rx * e.e3x + ry * e.e3y + rz * e.e3z;
+        const double *a = img.a1[r], *b = img.a2[r];
+        const double aX = a[0] * e.e1x + a[1] * e.e1y + a[2] * e.e1z;
+        const double aZ = a[0] * e.e2x + a[1] * e.e2y + a[2] * e.e2z;
+        const double aH = a[0] * e.e3x + a[1] * e.e3y + a[2] * e.e3z;
+        const double bX = b[0] * e.e1x + b[1] * e.e1y + b[2] * e.e1z;
+        const double bZ = b[0] * e.e2x + b[1] * e.e2y + b[2] * e.e2z;
+        const double bH = b[0] * e.e3x + b[1] * e.e3y + b[2] * e.e3z;
+        double s1[4] = {0.0, 0.0, 0.0, 0.0}, s2[4] = {0.0, 0.0, 0.0, 0.0};
+        sum_translations_pair<HOLE>(e, f, img.n1, img.n2, img.hole, X0, Z0, H0, aX, aZ, aH, bX, bZ, bH, s1, s2);
+        // first triangle: frame (e1, e2, e3); second: (e2, -e1, e3)
+        double g1x = s1[1] * e.e1x + s1[2] * e.e2x + s1[3] * e.e3x;
+        double g1y = s1[1] * e.e1y + s1[2] * e.e2y + s1[3] * e.e3y;
+        double g1z = s1[1] * e.e1z + s1[2] * e.e2z + s1[3] * e.e3z;
+        double g2x = s2[1] * e.e2x - s2[2] * e.e1x + s2[3] * e.e3x;
+        double g2y = s2[1] * e.e2y - s2[2] * e.e1y + s2[3] * e.e3y;
+        double g2z = s2[1] * e.e2z - s2[2] * e.e1z + s2[3] * e.e3z;
+        g1x = (ax & 1) ? -g1x : g1x;
+        g1y = (ax & 2) ? -g1y : g1y;
+        g1z = (ax & 4) ? -g1z : g1z;
+        g2x = (ax & 1) ? -g2x : g2x;
+        g2y = (ax & 2) ? -g2y : g2y;
+        g2z = (ax & 4) ? -g2z : g2z;
+        const double par = img.parity[r];
+        o1[0] += par * s1[0];
+        o1[1] += par * g1x;
+        o1[2] += par * g1y;
+        o1[3] += par * g1z;
+        o2[0] += par * s2[0];
+        o2[1] += par * g2x;
+        o2[2] += par * g2y;
+        o2[3] += par * g2z;
+    }
+}
+
 // -------------------------------------------------------------- evaluation
 // One workgroup's share of an evaluation: points [base, base + BS) of the
 // m points, all n elements (records drec, densities sigma) and their copies,
@@ -325,6 +483,22 @@ __device__ __forceinline__ void eval_block(const double *__restrict__ drec, cons
         __syncthreads();
         for (int p = 0; p < cnt; ++p) {
             const Elem e = load_elem(t_rec + p * R_STRIDE);
+            if (!MIXED && e.kind >= 2 && p + 1 < cnt) {
+                // a triangle pair inside this tile: both in one pass (c1 for
+                // element p, c2 for p + 1, whichever is the pair's first)
+                const int q1 = e.kind == 2 ? p : p + 1, q2 = e.kind == 2 ? p + 1 : p;
+                double c[2][4];
+                element_pair_copies<HOLE>(load_elem(t_rec + q1 * R_STRIDE), load_pair_b(t_rec + q2 * R_STRIDE), img,
+                                          Px, Py, Pz, c[q1 - p], c[q2 - p]);
+                const double(&c1)[4] = c[0], (&c2)[4] = c[1];
+                const double s1 = uni(t_sig[p]), s2 = uni(t_sig[p + 1]);
+                aphi = fma(s2, c2[0], fma(s1, c1[0], aphi));
+                aex = fma(s2, c2[1], fma(s1, c1[1], aex));
+                aey = fma(s2, c2[2], fma(s1, c1[2], aey));
+                aez = fma(s2, c2[3], fma(s1, c1[3], aez));
+                ++p;
+                continue;
+            }
             double cp, cx, cy, cz;
             element_copies<MIXED, HOLE>(e, img, Px, Py, Pz, false, near_factor, cp, cx, cy, cz);
             const double sg = uni(t_sig[p]);
@@ -565,6 +739,24 @@ __device__ __forceinline__ void eval_block_multi(const double *__restrict__ drec
         __syncthreads();
         for (int p = 0; p < cnt; ++p) {
             const Elem e = load_elem(t_rec + p * R_STRIDE);
+            if (!MIXED && e.kind >= 2 && p + 1 < cnt) {
+                // a triangle pair inside this tile, as in eval_block
+                const int q1 = e.kind == 2 ? p : p + 1, q2 = e.kind == 2 ? p + 1 : p;
+                double c[2][4];
+                element_pair_copies<false>(load_elem(t_rec + q1 * R_STRIDE), load_pair_b(t_rec + q2 * R_STRIDE), img,
+                                           Px, Py, Pz, c[q1 - p], c[q2 - p]);
+                const double(&c1)[4] = c[0], (&c2)[4] = c[1];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const double s1 = uni(t_sig[p * K + k]), s2 = uni(t_sig[(p + 1) * K + k]);
+                    aphi[k] = fma(s2, c2[0], fma(s1, c1[0], aphi[k]));
+                    aex[k] = fma(s2, c2[1], fma(s1, c1[1], aex[k]));
+                    aey[k] = fma(s2, c2[2], fma(s1, c1[2], aey[k]));
+                    aez[k] = fma(s2, c2[3], fma(s1, c1[3], aez[k]));
+                }
+                ++p;
+                continue;
+            }
             double cp, cx, cy, cz;
             element_copies<MIXED>(e, img, Px, Py, Pz, false, near_factor, cp, cx, cy, cz);
 #pragma unroll

@@ -26,7 +26,7 @@ enum DRec : int {
     R_CX, R_CY, R_CZ,          // centroid
     R_DIAM,                    // diameter (rect diagonal / triangle hypotenuse)
     R_AREA,                    // area
-    R_KIND,                    // 0 rectangle, 1 right triangle (as double)
+    R_KIND,                    // 0 rectangle, 1 right triangle, 2 / 3 right triangle paired with the next one (as double)
     R_JUMP,                    // dielectric diagonal term (eps+ + eps-)/(2 eps0 (eps+ - eps-)), else 0
     R_BC,                      // 0 conductor, 1 dielectric (as double)
     R_STRIDE = 24

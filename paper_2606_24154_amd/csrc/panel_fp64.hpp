@@ -261,4 +261,58 @@ __device__ __forceinline__ Kern rtri_far(double X, double H, double Z, double lx
     return k;
 }
 
+// Two right triangles that share their right-angle corner o and one leg:
+// triangle 1 with legs a along e1 and c along e2 (vertices o, A = o + a e1,
+// C = o + c e2) and triangle 2 with legs c along e2 and b along -e1
+// (vertices o, C, B = o - b e1), both with normal e3 -- the two halves of a
+// triangle cut at the foot of its altitude.  Triangle 2 in its own frame
+// (e2, -e1, e3) sees the point at (Z, H, -X), and its closed form is
+// rtri_far's with lx = c, lz = b; evaluated together, the two share the
+// distances to o and C, the edge o-C with its logarithm, and one reciprocal
+// for all seven divisions (its error scales every quotient of both by the
+// same factor).  Four square roots and five edge logarithms per pair instead
+// of six and six.  k2 is in triangle 2's frame; the potentials are returned
+// added to acc1, acc2.
+template <bool VF>
+__device__ __forceinline__ void rtri_pair_far(double X, double H, double Z, double a, double b, double c,
+                                              double hyp1, double hyp2, double r0sq, double acc1, double acc2,
+                                              Kern &k1, Kern &k2)
+{
+    const double d0A = fma(-X, a, r0sq);  // (P - o).(P - A)
+    const double d0C = fma(-Z, c, r0sq);  // (P - o).(P - C)
+    const double dAC = fma(-Z, c, d0A);   // (P - A).(P - C)
+    const double d0B = fma(X, b, r0sq);   // (P - o).(P - B)
+    const double dCB = fma(X, b, d0C);    // (P - C).(P - B)
+    const double r0 = sqrt64_far(r0sq);
+    const double rA = sqrt64_far(fma(-X, a, d0A + a * a));
+    const double rC = sqrt64_far(fma(-Z, c, d0C + c * c));
+    const double rB = sqrt64_far(fma(X, b, d0B + b * b));
+    const double s0A = r0 + rA, sAC = rA + rC, sC0 = rC + r0, sCB = rC + rB, sB0 = rB + r0;
+    const double D1 = fma(fma(r0, rA, d0A), rC, fma(d0C, rA, dAC * r0));
+    const double D2 = fma(fma(r0, rC, d0C), rB, fma(d0B, rC, dCB * r0));
+    // one reciprocal for 1/s (five edges) and 1/D1, 1/D2
+    const double a1 = s0A * sAC, b1 = a1 * sC0, P1 = b1 * D1;
+    const double a2 = sCB * sB0, P2 = a2 * D2;
+    const double inv = rcp64_common(P1 * P2);
+    const double i1 = P2 * inv, i2 = P1 * inv;  // 1/P1, 1/P2
+    const double iD1 = b1 * i1, ib1 = D1 * i1, ia1 = ib1 * sC0;
+    const double iD2 = a2 * i2, ia2 = D2 * i2;
+    const double L0A = two_atanh_poly(a * (ia1 * sAC), FarPoly<VF>::log);
+    const double LACh = two_atanh_over(ia1 * s0A, hyp1, FarPoly<VF>::log);  // Lam_AC / hyp1
+    const double LC0 = two_atanh_poly(c * (ib1 * a1), FarPoly<VF>::log);     // the shared edge
+    const double LCBh = two_atanh_over(ia2 * sB0, hyp2, FarPoly<VF>::log);  // Lam_CB / hyp2
+    const double LB0 = two_atanh_poly(b * (ia2 * sCB), FarPoly<VF>::log);
+    const double om1 = two_atan_half(H * (2.0 * a * c) * iD1, FarPoly<VF>::atan);
+    const double om2 = two_atan_half(H * (2.0 * c * b) * iD2, FarPoly<VF>::atan);
+    k1.ex = fma(c, LACh, -LC0);
+    k1.ez = fma(a, LACh, -L0A);
+    k1.phi = fma(-Z, k1.ez, fma(-X, k1.ex, fma(a * c, LACh, fma(-H, om1, acc1))));
+    k1.en = om1;
+    // triangle 2: frame coordinates (Z, -X), legs c (along its e1) and b
+    k2.ex = fma(b, LCBh, -LB0);
+    k2.ez = fma(c, LCBh, -LC0);
+    k2.phi = fma(X, k2.ez, fma(-Z, k2.ex, fma(c * b, LCBh, fma(-H, om2, acc2))));
+    k2.en = om2;
+}
+
 }  // namespace nebem

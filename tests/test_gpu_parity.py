@@ -139,6 +139,70 @@ def test_far_regime_switch_and_element_plane(nb, kind):
         assert en.max() < 1e-10, en.max()
 
 
+def _pair_geometry(rng, n_tri, copies=0):
+    """n_tri general triangles with random orientation, each cut by the
+    builder into its two right triangles (consecutive elements sharing the
+    right-angle corner and a leg), lattice copies +-copies"""
+    b = GeometryBuilder()
+    for _ in range(n_tri):
+        Q = _rot(rng)
+        c0 = rng.uniform(-100e-6, 100e-6, 3)
+        p3 = [c0 + rng.uniform(5e-6, 30e-6) * (np.cos(t) * Q[:, 0] + np.sin(t) * Q[:, 1])
+              for t in np.sort(rng.uniform(0, 2 * np.pi, 3))]
+        b.triangle(*p3)
+    img = Images(a1=np.array([400e-6, 0, 0]), a2=np.array([0, 400e-6, 0]), n1=copies, n2=copies)
+    return b.build("pairs", img, np.full(3, -1e-3), np.full(3, 1e-3))
+
+
+def test_triangle_pairs_against_oracle_and_singles(nb):
+    """Right-triangle pairs (a triangle cut at its altitude's foot) are
+    evaluated together; against the oracle at the FP64 bar at 1e-3 .. 1e3
+    diameters and near the plane, and against the same triangles in the
+    opposite order (which is never paired) to 1e-11."""
+    rng = np.random.default_rng(77)
+    g = _pair_geometry(rng, 24, copies=2)
+    assert g.n == 48 and np.all(g.kind == 1)
+    sigma = rng.uniform(0.5, 1.5, g.n) * rng.choice([-1, 1], g.n)
+    m = 3000
+    d = rng.standard_normal((m, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    pts = rng.uniform(-100e-6, 100e-6, 3) + (30e-6 * 10 ** rng.uniform(-2, 2.3, m))[:, None] * d
+    got = gpu_eval(nb, g, sigma, pts)
+    ref = oracle.eval_points(g, sigma, pts)
+    ephi, eE = rel_errors(got, ref)
+    assert ephi < 1e-10 and eE < 1e-10, (ephi, eE)
+    # the same elements with each pair's two triangles swapped: no pairs
+    perm = np.arange(g.n).reshape(-1, 2)[:, ::-1].ravel()
+    gs = g.subset(perm)
+    got_s = gpu_eval(nb, gs, sigma[perm], pts)
+    ephi, eE = rel_errors(got, got_s)
+    assert ephi < 1e-11 and eE < 1e-11, (ephi, eE)
+    assert not np.array_equal(got, got_s)  # the pair path did run
+
+
+def test_triangle_pair_at_tile_edge(nb):
+    """A pair whose second triangle falls into the next tile of 64 elements
+    is evaluated as two single triangles; every element still counted once."""
+    rng = np.random.default_rng(78)
+    b = GeometryBuilder()
+    for k in range(63):  # 63 rectangles, then the pair at positions 63, 64
+        b.rect(rng.uniform(-1e-4, 1e-4, 3), (10e-6, 0, 0), (0, 10e-6, 0))
+    pg = _pair_geometry(rng, 2)
+    g0 = b.build("edge", Images(), np.full(3, -1e-3), np.full(3, 1e-3))
+    idx = np.arange(pg.n)
+    g = type(g0)("edge", np.concatenate([g0.kind, pg.kind]), np.vstack([g0.o, pg.o]), np.vstack([g0.u, pg.u]),
+                 np.vstack([g0.w, pg.w]), np.concatenate([g0.bc, pg.bc]), np.concatenate([g0.value, pg.value]),
+                 np.concatenate([g0.eps_pos, pg.eps_pos]), np.concatenate([g0.eps_neg, pg.eps_neg]), Images(),
+                 g0.box_lo, g0.box_hi)
+    assert g.n == 63 + len(idx)
+    sigma = rng.uniform(0.5, 1.5, g.n)
+    pts = uniform_points(np.full(3, -3e-4), np.full(3, 3e-4), 512, 5)
+    got = gpu_eval(nb, g, sigma, pts)
+    ref = oracle.eval_points(g, sigma, pts)
+    ephi, eE = rel_errors(got, ref)
+    assert ephi < 1e-10 and eE < 1e-10, (ephi, eE)
+
+
 # -------------------------------------------------------- parallel plates
 
 @pytest.fixture(scope="module")
