@@ -428,7 +428,7 @@ nebem_status nebem_spacecharge_step_lines(nebem_session *s, double *qx, double *
 typedef struct nebem_server nebem_server;
 typedef struct nebem_server_options {
     int64_t hbm_budget;         /* bytes of device staging for admitted requests (2 GiB) */
-    double batch_interactions;  /* work per launch, interactions (5e10) */
+    double batch_interactions;  /* work per launch, interactions (1e10) */
     int32_t max_items;          /* work items per launch (65536) */
 } nebem_server_options;
 typedef struct nebem_request_stats {

@@ -589,6 +589,13 @@ def _np_ptr(a):
     return None if a is None else ctypes.c_void_p(a.ctypes.data)
 
 
+def server_default_options() -> ServerOptions:
+    """The library's default server options (nebem_server_default_options)."""
+    o = ServerOptions()
+    lib.nebem_server_default_options(ctypes.byref(o))
+    return o
+
+
 class Server:
     """Continuous-batching evaluation service over resident sessions (host
     numpy arrays in and out; the arrays must stay alive until `wait`)."""

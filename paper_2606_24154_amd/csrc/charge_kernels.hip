@@ -12,25 +12,25 @@
 // run-to-run identical results.
 //
 // Pair sums at the charges (k_coulomb_sorted): the charges are first put in
-// Morton order of their bounding box, so that the 256 targets of a
-// workgroup and the 256 sources of an LDS tile each sit in a small box (the
-// boxes of all 256-charge tiles are computed once per step).  A source tile
-// whose box is farther from the workgroup's box than twice the larger box's
-// diagonal is far: its sources are staged as FP32 offsets in micrometres from
-// the workgroup's first target, as are the targets (one FP64 subtraction
-// and rounding per staged value, not per pair), and a pair costs 3 FP32
+// Morton order of their bounding box, so that every 64 consecutive charges
+// -- a wave of targets, a run of sources -- sit in a small box (the boxes of
+// all 64-charge runs are computed once per step).  Each source is staged as
+// its FP32 offset in micrometres from the centre of its run's box (and as
+// its FP64 position).  For a wave and a run whose boxes are at least the
+// run's diagonal apart (far), every target first takes its own FP32 offset
+// from that centre (once per run, not per pair), and a pair costs 3 FP32
 // subtractions, 3 FMAs for r^2 (seeded with 1e-24 um^2, far below any
 // resolvable distance, which keeps 1/r^3 finite), one reciprocal square
-// root, 3 multiplications and 3 FMAs: 13 VALU instructions.  An offset's
-// rounding is relative to its size, at most about the pair distance plus
-// three box diagonals, so in a far tile the difference keeps ~1.5e-7 of the
-// pair distance.  The few near tiles (the workgroup's own and its spatial
-// neighbours: under 1 % of the pairs for a 10^6-charge cloud) take the
-// difference in FP64 and round it once, so close pairs -- whose terms can
-// dominate a charge's field -- keep the FP32 pair term's own accuracy.
-// Runs of 64 sources are summed in FP32 (eight interleaved sums of 8 in the
-// far tiles, where Morton-adjacent terms add coherently) and then added to
-// FP64 accumulators.
+// root, 2 multiplications and 3 FMAs: 12 VALU instructions.  The source
+// offset is at most half a diagonal and the target offset at most the pair
+// distance d plus half a diagonal, so their rounding leaves the difference
+// within ~1.2e-7 d.  Nearer runs (the wave's own and its spatial
+// neighbours: ~4 % of the pairs for a 10^6-charge cloud, against 57 % when
+// the test was made per 256 charges) take the difference in FP64 and round
+// it once, so close pairs -- whose terms can dominate a charge's field --
+// keep the FP32 pair term's own accuracy.  Runs of 64 sources are summed in
+// FP32 (eight interleaved sums of 8 in the far runs, where Morton-adjacent
+// terms add coherently) and then added to FP64 accumulators.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,29 +41,30 @@
 namespace nebem {
 
 constexpr int kCB = 256;   // lanes per workgroup = sources per LDS tile
-constexpr int kRun = 64;   // sources per FP32 partial sum
+constexpr int kRun = 64;   // charges per box: a wave of targets, a run of sources
 
 static inline unsigned blocks(int64_t n) { return (unsigned)((n + kCB - 1) / kCB); }
+static inline unsigned runs(int64_t n) { return (unsigned)((n + kRun - 1) / kRun); }
 
 constexpr double kUm = 1e6;          // metres -> micrometres for the FP32 offsets
 constexpr float kSeedR2 = 1e-24f;    // um^2, keeps 1/r^3 finite at r = 0
 
 // box[6 t .. 6 t + 5] = (min x, y, z, max x, y, z) of sorted charges
-// [256 t, 256 t + 256)
-__global__ __launch_bounds__(kCB) void k_tile_boxes(const double *__restrict__ sx, const double *__restrict__ sy,
-                                                    const double *__restrict__ sz, int nq, double *__restrict__ box)
+// [64 t, 64 t + 64); one 64-lane workgroup per box
+__global__ __launch_bounds__(kRun) void k_tile_boxes(const double *__restrict__ sx, const double *__restrict__ sy,
+                                                     const double *__restrict__ sz, int nq, double *__restrict__ box)
 {
-    __shared__ double red[6][kCB];
-    const int i = blockIdx.x * kCB + threadIdx.x;
+    __shared__ double red[6][kRun];
+    const int i = blockIdx.x * kRun + threadIdx.x;
+    const int i0 = blockIdx.x * kRun;
     const bool act = i < nq;
-    const double v[3] = {act ? sx[i] : sx[blockIdx.x * kCB], act ? sy[i] : sy[blockIdx.x * kCB],
-                         act ? sz[i] : sz[blockIdx.x * kCB]};
+    const double v[3] = {act ? sx[i] : sx[i0], act ? sy[i] : sy[i0], act ? sz[i] : sz[i0]};
     for (int k = 0; k < 3; ++k) {
         red[k][threadIdx.x] = v[k];
         red[3 + k][threadIdx.x] = v[k];
     }
     __syncthreads();
-    for (int h = kCB / 2; h > 0; h >>= 1) {
+    for (int h = kRun / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h)
             for (int k = 0; k < 6; ++k)
                 red[k][threadIdx.x] = k < 3 ? fmin(red[k][threadIdx.x], red[k][threadIdx.x + h])
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(kCB) void k_tile_boxes(const double *__restrict__ s
 }
 
 // E at every charge from all other charges, over charges in Morton order
-// (positions sx/sy/sz, charges sq, all sorted; tile boxes from
+// (positions sx/sy/sz, charges sq, all sorted; 64-charge boxes from
 // k_tile_boxes); written to the sorted outputs ox/oy/oz, scaled by k_e.
 __global__ __launch_bounds__(kCB) void k_coulomb_sorted(const double *__restrict__ sx, const double *__restrict__ sy,
                                                         const double *__restrict__ sz, const double *__restrict__ sq,
@@ -82,45 +83,50 @@ __global__ __launch_bounds__(kCB) void k_coulomb_sorted(const double *__restrict
                                                         double *__restrict__ ox, double *__restrict__ oy,
                                                         double *__restrict__ oz)
 {
-    __shared__ float4 src[kCB];
-    __shared__ double nx[kCB], ny[kCB], nz[kCB];
+    __shared__ float4 src[kCB];                   // offset from the run's box centre (um), charge
+    __shared__ double nx[kCB], ny[kCB], nz[kCB];  // FP64 positions, for the near runs
+    const int nbox = (nq + kRun - 1) / kRun;
     const int b0 = blockIdx.x * kCB;
-    const double cx = sx[b0], cy = sy[b0], cz = sz[b0];  // the block's origin
-    const double *mb = box + 6 * (size_t)blockIdx.x;
-    const double m0 = mb[0], m1 = mb[1], m2 = mb[2], m3 = mb[3], m4 = mb[4], m5 = mb[5];
-    const double mdiag2 = (m3 - m0) * (m3 - m0) + (m4 - m1) * (m4 - m1) + (m5 - m2) * (m5 - m2);
     const int i = b0 + threadIdx.x;
     const bool act = i < nq;
-    const double xi = act ? sx[i] : cx, yi = act ? sy[i] : cy, zi = act ? sz[i] : cz;
-    const float tx = (float)((xi - cx) * kUm);
-    const float ty = (float)((yi - cy) * kUm);
-    const float tz = (float)((zi - cz) * kUm);
+    // lanes past the last charge stand at the block's first charge
+    const double xi = act ? sx[i] : sx[b0], yi = act ? sy[i] : sy[b0], zi = act ? sz[i] : sz[b0];
+    // the wave's box (wave-uniform, so the near / far choice is a scalar branch)
+    const int tbox =
+        __builtin_amdgcn_readfirstlane(min((int)(blockIdx.x * (kCB / kRun)) + (int)(threadIdx.x / kRun), nbox - 1));
+    const double *mb = box + 6 * (size_t)tbox;
+    const double m0 = mb[0], m1 = mb[1], m2 = mb[2], m3 = mb[3], m4 = mb[4], m5 = mb[5];
     double ax = 0.0, ay = 0.0, az = 0.0;
     for (int base = 0; base < nq; base += kCB) {
-        const double *tb = box + 6 * (size_t)(base / kCB);
-        const double gx = fmax(0.0, fmax(tb[0] - m3, m0 - tb[3]));
-        const double gy = fmax(0.0, fmax(tb[1] - m4, m1 - tb[4]));
-        const double gz = fmax(0.0, fmax(tb[2] - m5, m2 - tb[5]));
-        const double tdiag2 = (tb[3] - tb[0]) * (tb[3] - tb[0]) + (tb[4] - tb[1]) * (tb[4] - tb[1]) +
-                              (tb[5] - tb[2]) * (tb[5] - tb[2]);
-        const bool near = gx * gx + gy * gy + gz * gz < 4.0 * fmax(mdiag2, tdiag2);  // uniform
         __syncthreads();
         const int j = base + threadIdx.x;
-        if (near) {
-            // padding: a zero charge at the target block's origin
-            nx[threadIdx.x] = j < nq ? sx[j] : cx;
-            ny[threadIdx.x] = j < nq ? sy[j] : cy;
-            nz[threadIdx.x] = j < nq ? sz[j] : cz;
-            src[threadIdx.x] = make_float4(0.0f, 0.0f, 0.0f, j < nq ? (float)sq[j] : 0.0f);
-        } else {
-            src[threadIdx.x] = j < nq ? make_float4((float)((sx[j] - cx) * kUm), (float)((sy[j] - cy) * kUm),
-                                                    (float)((sz[j] - cz) * kUm), (float)sq[j])
-                                      : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (j < nq) {
+            const double *jb = box + 6 * (size_t)(j / kRun);
+            const double ocx = 0.5 * (jb[0] + jb[3]), ocy = 0.5 * (jb[1] + jb[4]), ocz = 0.5 * (jb[2] + jb[5]);
+            src[threadIdx.x] = make_float4((float)((sx[j] - ocx) * kUm), (float)((sy[j] - ocy) * kUm),
+                                           (float)((sz[j] - ocz) * kUm), (float)sq[j]);
+            nx[threadIdx.x] = sx[j];
+            ny[threadIdx.x] = sy[j];
+            nz[threadIdx.x] = sz[j];
+        } else {  // padding: a zero charge at the box centre / the block's first charge
+            src[threadIdx.x] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            nx[threadIdx.x] = sx[b0];
+            ny[threadIdx.x] = sy[b0];
+            nz[threadIdx.x] = sz[b0];
         }
         __syncthreads();
-        if (near) {
 #pragma unroll 1
-            for (int r0 = 0; r0 < kCB; r0 += kRun) {
+        for (int r0 = 0; r0 < kCB; r0 += kRun) {
+            const int sb = (base + r0) / kRun;  // uniform
+            if (sb >= nbox) break;
+            const double *tb = box + 6 * (size_t)sb;
+            const double gx = fmax(0.0, fmax(tb[0] - m3, m0 - tb[3]));
+            const double gy = fmax(0.0, fmax(tb[1] - m4, m1 - tb[4]));
+            const double gz = fmax(0.0, fmax(tb[2] - m5, m2 - tb[5]));
+            const double g2 = gx * gx + gy * gy + gz * gz;
+            const double sd2 = (tb[3] - tb[0]) * (tb[3] - tb[0]) + (tb[4] - tb[1]) * (tb[4] - tb[1]) +
+                               (tb[5] - tb[2]) * (tb[5] - tb[2]);
+            if (g2 == 0.0 || g2 < sd2) {  // near (uniform per wave)
                 float fx = 0.0f, fy = 0.0f, fz = 0.0f;
 #pragma unroll 8
                 for (int k = r0; k < r0 + kRun; ++k) {
@@ -138,11 +144,12 @@ __global__ __launch_bounds__(kCB) void k_coulomb_sorted(const double *__restrict
                 ax += (double)fx;
                 ay += (double)fy;
                 az += (double)fz;
+                continue;
             }
-            continue;
-        }
-#pragma unroll 1
-        for (int r0 = 0; r0 < kCB; r0 += kRun) {
+            // far: the target's offset from this run's box centre
+            const float tx = (float)((xi - 0.5 * (tb[0] + tb[3])) * kUm);
+            const float ty = (float)((yi - 0.5 * (tb[1] + tb[4])) * kUm);
+            const float tz = (float)((zi - 0.5 * (tb[2] + tb[5])) * kUm);
             float fx[8], fy[8], fz[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) fx[u] = fy[u] = fz[u] = 0.0f;
@@ -363,7 +370,7 @@ size_t coulomb_workspace(int64_t nq)
     if (!w) return 0;
     const size_t n = (size_t)nq;
     return w + align256c(4 * n) + align256c(24 * n) + align256c(8 * n) + align256c(24 * n) +
-           align256c(48 * (size_t)blocks(nq));
+           align256c(48 * (size_t)runs(nq));
 }
 
 hipError_t launch_coulomb(const double *qx, const double *qy, const double *qz, const double *q, int64_t nq,
@@ -383,7 +390,7 @@ hipError_t launch_coulomb(const double *qx, const double *qy, const double *qz, 
     hipError_t e = launch_order_points(qx, qy, qz, nq, sp, sp + n, sp + 2 * n, perm, ws, w0, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gather1, dim3(blocks(nq)), dim3(kCB), 0, s, q, perm, (int)nq, sq);
-    hipLaunchKernelGGL(k_tile_boxes, dim3(blocks(nq)), dim3(kCB), 0, s, sp, sp + n, sp + 2 * n, (int)nq, bx);
+    hipLaunchKernelGGL(k_tile_boxes, dim3(runs(nq)), dim3(kRun), 0, s, sp, sp + n, sp + 2 * n, (int)nq, bx);
     hipLaunchKernelGGL(k_coulomb_sorted, dim3(blocks(nq)), dim3(kCB), 0, s, sp, sp + n, sp + 2 * n, sq, bx, (int)nq,
                        se, se + n, se + 2 * n);
     hipLaunchKernelGGL(k_scatter_add3, dim3(blocks(nq)), dim3(kCB), 0, s, se, perm, (int)nq, ex, ey, ez);

@@ -327,7 +327,7 @@ void nebem_server_default_options(nebem_server_options *o)
 {
     if (!o) return;
     o->hbm_budget = (int64_t)2 << 30;
-    o->batch_interactions = 5e10;
+    o->batch_interactions = 1e10;
     o->max_items = 65536;
 }
 
