@@ -346,7 +346,7 @@ def fastvol_bench(args):
     a regular 5 um grid, and a graded grid (x, y: uniform 2 um -- the cell's
     box holds parts of the neighbouring holes, so no band of one axis is
     away from every hole; z: 1 um at the foil and at the drift plane,
-    growing by 5 % per node up to 40 um in between) --
+    growing by 5 % per node up to 10 um in between) --
     each built by one FP64 evaluation at its nodes.  Trilinear lookups at
     10^6 drift-gap points (HIP events); interpolation error against direct
     evaluation at 2*10^4 of them and at 2*10^4 points in the 100 um above
@@ -402,7 +402,7 @@ def fastvol_bench(args):
     step = tuple((hi[a] - lo[a]) / (shape[a] - 1) for a in range(3))
     hxy = 2e-6
     axes = tuple(np.linspace(lo[a], hi[a], int(np.ceil((hi[a] - lo[a]) / hxy)) + 1) for a in range(2)) + \
-        (graded_axis(lo[2], hi[2], 1e-6, 1.05, 40e-6),)
+        (graded_axis(lo[2], hi[2], 1e-6, 1.05, 10e-6),)
     axd = [torch.from_numpy(a).to(dev) for a in axes]
     rows = {}
     for name in ("regular", "graded"):
@@ -417,7 +417,7 @@ def fastvol_bench(args):
             look = lambda p: nb.fastvol_interp_axes(vals, *axd, *p)
             nodes = int(np.prod([len(a) for a in axes]))
             desc = (f"{len(axes[0])}x{len(axes[1])}x{len(axes[2])}; x, y uniform {hxy * 1e6:.0f} um; z 1 um at "
-                    f"the foil and at the drift plane, growing 5 %/node to 40 um in between")
+                    f"the foil and at the drift plane, growing 5 %/node to 10 um in between")
         ev[1].record(stream)
         out = look(pt)  # warm-up
         reps = 20

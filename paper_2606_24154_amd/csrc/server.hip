@@ -23,6 +23,13 @@
 //      submission order if sorted), its results copied back to the
 //      caller's host arrays, its arena space freed and its waiter woken; new
 //      requests are admitted on the next iteration.
+// Launches alternate between two streams, and the worker builds and issues
+// launch L before it waits for launch L - 1: the device always holds the
+// next launch, so the host's work between launches (completions, copies,
+// admission, the next list) is hidden, and launch L's workgroups fill the
+// slots that launch L - 1's last, uneven round leaves idle.  Admission
+// work (point copies and sorts) runs on a third stream that each launch
+// waits for.
 // Each point's partial sums and their reduction have a fixed order that does
 // not depend on the other requests, so a request's results are identical
 // whether it runs alone or in a mix.
@@ -62,7 +69,7 @@ struct Request {
     int nseg = 1;               // element segments of its geometry
     int64_t nitems = 0;         // 64-point chunks x segments
     int64_t next = 0;           // first item not yet scheduled
-    int64_t inflight = 0;       // items scheduled in the current launch
+    int64_t infl[2] = {0, 0};   // items in the launch on stream 0 / 1 not yet retired
     int64_t done_items = 0;
     int status = NEBEM_OK;
     bool ordered = false;       // points sorted into Morton order on admission
@@ -122,12 +129,14 @@ struct nebem_server {
     std::vector<int> geom_segsz;  // elements per segment (last may be shorter)
     int mixed = 0;
     double near_factor = 4.0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;            // admission: point copies and sorts
+    hipStream_t lst[2] = {nullptr, nullptr};  // item launches, alternating
+    hipEvent_t ev_adm = nullptr, ev_launch[2] = {nullptr, nullptr};
     void *arena_dev = nullptr;
     nebem::Arena arena;
     nebem::ImgArgs *imgs_dev = nullptr;
-    nebem::WorkItem *items_dev = nullptr;
-    nebem::WorkItem *items_host = nullptr;  // pinned
+    nebem::WorkItem *items_dev = nullptr;   // 2 x items_cap: one list per launch stream
+    nebem::WorkItem *items_host = nullptr;  // pinned, 2 x items_cap
     void *sort_ws = nullptr;                // scratch of the point sort (grown on demand)
     size_t sort_ws_bytes = 0;
     int items_cap = 0;
@@ -178,17 +187,23 @@ static void worker_main(nebem_server *s)
 {
     (void)hipSetDevice(s->device);
     std::vector<Request *> fresh;
+    int64_t nlaunch = 0;     // launches issued
+    int pend = -1;           // stream of the launch in flight, -1 if none
+    bool adm_event = false;  // ev_adm recorded at least once
+    double t_busy = 0.0;     // start of the current stretch with a launch in flight
     for (;;) {
         std::vector<Request *> act;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->active.empty(); });
-            if (s->stop && s->queue.empty() && s->active.empty()) return;
+            if (pend < 0)
+                s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->active.empty(); });
+            if (s->stop && s->queue.empty() && s->active.empty() && pend < 0) return;
             const size_t before = s->active.size();
             admit_locked(s);
             fresh.assign(s->active.begin() + before, s->active.end());
             act = s->active;
         }
+        const int cur = (int)(nlaunch & 1);
         // copy the new requests' points in; large ones land in the result
         // columns and are sorted into the point columns
         for (Request *r : fresh) {
@@ -219,10 +234,14 @@ static void worker_main(nebem_server *s)
                 r->status = NEBEM_EDEVICE;
             }
         }
+        if (!fresh.empty() && hipEventRecord(s->ev_adm, s->stream) == hipSuccess) adm_event = true;
         // build the work list: round-robin, one item per request per round,
         // until the iteration's budget is used and the list fills whole
         // rounds of the device's work-item slots (an item is one wave, and a
-        // launch whose last round is part-filled leaves CUs idle at its end)
+        // launch whose last round is part-filled leaves CUs idle at its end).
+        // This stream's previous list (launch nlaunch - 2) has completed.
+        WorkItem *items_host = s->items_host + (size_t)cur * s->items_cap;
+        WorkItem *items_dev = s->items_dev + (size_t)cur * s->items_cap;
         int nitems = 0;
         double budget = s->opt.batch_interactions;
         bool progress = true;
@@ -238,7 +257,7 @@ static void worker_main(nebem_server *s)
                 const int cnt = (int)std::min<int64_t>(64, r->m - p0);
                 const int e0 = seg * s->geom_segsz[r->geom];
                 const int ne = (int)std::min<int64_t>(s->geom_segsz[r->geom], g->n - e0);
-                WorkItem &w = s->items_host[nitems++];
+                WorkItem &w = items_host[nitems++];
                 w.drec = g->drec.as<double>() + (size_t)e0 * R_STRIDE;
                 w.sigma = g->sigma.as<double>() + e0;
                 w.n = ne;
@@ -253,7 +272,7 @@ static void worker_main(nebem_server *s)
                 w.ey = stage(s, r, 10 + 4 * seg) + p0;
                 w.ez = stage(s, r, 11 + 4 * seg) + p0;
                 r->next += 1;
-                r->inflight += 1;
+                r->infl[cur] += 1;
                 const double work = (double)ne * g->img_count * cnt;
                 budget -= work;
                 s->interactions_done += work;
@@ -261,40 +280,55 @@ static void worker_main(nebem_server *s)
                 if (!more()) break;
             }
         }
-        const double t0 = now_s();
+        bool launched = false;
         if (nitems > 0) {
-            hipError_t e = hipMemcpyAsync(s->items_dev, s->items_host, (size_t)nitems * sizeof(WorkItem),
-                                          hipMemcpyHostToDevice, s->stream);
+            hipError_t e = adm_event ? hipStreamWaitEvent(s->lst[cur], s->ev_adm, 0) : hipSuccess;
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(items_dev, items_host, (size_t)nitems * sizeof(WorkItem), hipMemcpyHostToDevice,
+                                   s->lst[cur]);
             if (e == hipSuccess) {
-                launch_eval_items(s->items_dev, nitems, s->imgs_dev, s->mixed, s->near_factor, s->stream);
+                launch_eval_items(items_dev, nitems, s->imgs_dev, s->mixed, s->near_factor, s->lst[cur]);
                 e = hipGetLastError();
             }
+            if (e == hipSuccess) e = hipEventRecord(s->ev_launch[cur], s->lst[cur]);
             if (e != hipSuccess) {
                 std::lock_guard<std::mutex> lk(s->mu);
                 s->worker_error = hipGetErrorString(e);
                 for (Request *r : act) r->status = NEBEM_EDEVICE;
             }
+            if (pend < 0) t_busy = now_s();
+            launched = true;
+            ++nlaunch;
             ++s->launches;
         }
-        // retire finished requests: reduce their segments, copy results back
+        // retire the previous launch: its requests whose items are all done
+        // (or that failed and have nothing in flight) get their segments
+        // reduced, results copied back, arena space freed
         std::vector<Request *> done;
-        for (Request *r : act) {
-            r->done_items += r->inflight;
-            r->inflight = 0;
-            if (r->status != NEBEM_OK || r->done_items >= r->nitems) done.push_back(r);
+        if (pend >= 0) {
+            (void)hipEventSynchronize(s->ev_launch[pend]);
+            for (Request *r : act) {
+                r->done_items += r->infl[pend];
+                r->infl[pend] = 0;
+            }
         }
+        for (Request *r : act)
+            if (r->done_items >= r->nitems || (r->status != NEBEM_OK && r->infl[0] == 0 && r->infl[1] == 0))
+                done.push_back(r);
         // results of sorted requests end in the first partial-sum columns, in
         // submission order
+        const int rs = pend >= 0 ? pend : cur;  // a stream with nothing of these requests ahead
         for (Request *r : done)
             if (r->status == NEBEM_OK) {
                 const OutCols out = {{stage(s, r, 3), stage(s, r, 4), stage(s, r, 5), stage(s, r, 6)}, r->m};
-                launch_reduce_segments(stage(s, r, 8), r->nseg, 1, r->m, 4 * r->m, out, s->stream);
+                launch_reduce_segments(stage(s, r, 8), r->nseg, 1, r->m, 4 * r->m, out, s->lst[rs]);
                 if (r->ordered)
                     launch_unorder4(stage(s, r, 3), reinterpret_cast<const int *>(stage(s, r, 7)), r->m,
-                                    stage(s, r, 8), stage(s, r, 9), stage(s, r, 10), stage(s, r, 11), s->stream);
+                                    stage(s, r, 8), stage(s, r, 9), stage(s, r, 10), stage(s, r, 11), s->lst[rs]);
             }
-        (void)hipStreamSynchronize(s->stream);
-        s->busy_s += now_s() - t0;
+        if (!done.empty()) (void)hipStreamSynchronize(s->lst[rs]);
+        if (!launched && pend >= 0) s->busy_s += now_s() - t_busy;
+        pend = launched ? cur : -1;
         for (Request *r : done) {
             if (r->status == NEBEM_OK) {
                 const size_t b = (size_t)r->m * sizeof(double);
@@ -374,6 +408,14 @@ nebem_status nebem_server_create(nebem_session *const *sessions, int32_t nsessio
     if ((e = hipGetDevice(&s->device)) != hipSuccess) return bail(e, "hipGetDevice");
     if ((e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) != hipSuccess)
         return bail(e, "hipStreamCreate");
+    for (int k = 0; k < 2; ++k) {
+        if ((e = hipStreamCreateWithFlags(&s->lst[k], hipStreamNonBlocking)) != hipSuccess)
+            return bail(e, "hipStreamCreate");
+        if ((e = hipEventCreateWithFlags(&s->ev_launch[k], hipEventDisableTiming)) != hipSuccess)
+            return bail(e, "hipEventCreate");
+    }
+    if ((e = hipEventCreateWithFlags(&s->ev_adm, hipEventDisableTiming)) != hipSuccess)
+        return bail(e, "hipEventCreate");
     if ((e = hipMalloc(&s->arena_dev, (size_t)o.hbm_budget)) != hipSuccess) return bail(e, "hipMalloc(arena)");
     s->arena.init((size_t)o.hbm_budget);
     std::vector<ImgArgs> imgs(nsessions);
@@ -385,9 +427,9 @@ nebem_status nebem_server_create(nebem_session *const *sessions, int32_t nsessio
     s->items_cap = o.max_items;
     s->round_items = eval_items_slots(mixed);
     if (s->round_items < 1 || s->round_items > s->items_cap) s->round_items = 1;
-    if ((e = hipMalloc((void **)&s->items_dev, sizeof(WorkItem) * s->items_cap)) != hipSuccess)
+    if ((e = hipMalloc((void **)&s->items_dev, 2 * sizeof(WorkItem) * s->items_cap)) != hipSuccess)
         return bail(e, "hipMalloc(work list)");
-    if ((e = hipHostMalloc((void **)&s->items_host, sizeof(WorkItem) * s->items_cap, hipHostMallocDefault)) !=
+    if ((e = hipHostMalloc((void **)&s->items_host, 2 * sizeof(WorkItem) * s->items_cap, hipHostMallocDefault)) !=
         hipSuccess)
         return bail(e, "hipHostMalloc(work list)");
     s->worker = std::thread(worker_main, s);
@@ -488,6 +530,11 @@ void nebem_server_destroy(nebem_server *s)
     if (s->sort_ws) (void)hipFree(s->sort_ws);
     if (s->imgs_dev) (void)hipFree(s->imgs_dev);
     if (s->arena_dev) (void)hipFree(s->arena_dev);
+    for (int k = 0; k < 2; ++k) {
+        if (s->ev_launch[k]) (void)hipEventDestroy(s->ev_launch[k]);
+        if (s->lst[k]) (void)hipStreamDestroy(s->lst[k]);
+    }
+    if (s->ev_adm) (void)hipEventDestroy(s->ev_adm);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
