@@ -183,7 +183,7 @@ __device__ __forceinline__ Elem load_elem(const double *d)
 // The second triangle of a pair (element records of kind 2 or 3: see
 // k_pair_flags): what the pair form needs from its record.
 struct PairB {
-    double lz, hyp, ihyp, diam;
+    double lz, hyp, ihyp, diam, area;
 };
 
 __device__ __forceinline__ PairB load_pair_b(const double *d)
@@ -193,6 +193,7 @@ __device__ __forceinline__ PairB load_pair_b(const double *d)
     f.hyp = uni(d[R_HYP]);
     f.ihyp = uni(d[R_IHYP]);
     f.diam = uni(d[R_DIAM]);
+    f.area = uni(d[R_AREA]);
     return f;
 }
 
@@ -455,6 +456,238 @@ __device__ __forceinline__ void element_pair_copies(const Elem &e, const PairB &
     }
 }
 
+// ----------------------------------------------------- mixed-path pairs
+// In the mixed path a triangle pair far enough away is taken as one charge
+// distribution: the sigma-weighted monopole (FP64), dipole and second
+// moments (FP32) of both triangles about the centroid c0 of the whole
+// triangle they came from.  In the first triangle's frame the pair has
+// vertices o, A = o + a e1, C = o + c e2, B = o - b e1; its triangles'
+// centroids lie (b/3, 0) and (-a/3, 0) from c0 = o + ((a - b)/3, c/3), so
+// with charges w1 = sigma1 A1, w2 = sigma2 A2 the dipole is
+// ((w1 b - w2 a)/3, 0) and the second moments are the triangles' central
+// ones (right triangle per unit area: lx^2/18, lz^2/18, -lx lz/36 in its
+// own frame; the second triangle's frame is (e2, -e1)) moved to c0.  The
+// expansion is the multipole series of the single-triangle quadrupole tier
+// (farfield_mixed.hpp) with the dipole term added; it is used from 96
+// diameters of the whole triangle (a + b, which bounds every vertex's
+// distance from c0 by (a + b) 2/3), where the truncation error relative to
+// |w1| + |w2| is at most the single triangle's at 96 of its own diameters.
+// Nearer copies take each triangle's own mixed tiers.  One such copy costs
+// about what one triangle's quadrupole copy costs.
+// The FP32 moments are carried in units of sc = |w1| + |w2| (so that their
+// range does not depend on the densities' scale), and the FP32 corrections
+// are multiplied by sc once, in FP64, after the copies.
+template <int K>
+struct PairMoments {
+    double q[K], sc[K];                   // w1 + w2; |w1| + |w2|
+    float dx[K], mxx[K], mzz[K], mxz[K];  // dipole (along e1), second moments, in units of sc
+};
+
+template <int K>
+__device__ __forceinline__ PairMoments<K> pair_moments(double a, double b, double c, double area1, double area2,
+                                                       const double (&sg1)[K], const double (&sg2)[K])
+{
+    PairMoments<K> m;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double v1 = sg1[k] * area1, v2 = sg2[k] * area2;
+        m.q[k] = v1 + v2;
+        const double sc = fabs(v1) + fabs(v2);
+        m.sc[k] = sc > 0.0 ? sc : 1.0;
+        const double w1 = v1 / m.sc[k], w2 = v2 / m.sc[k];
+        m.dx[k] = (float)((w1 * b - w2 * a) * (1.0 / 3.0));
+        m.mxx[k] = (float)(w1 * (a * a * (1.0 / 18.0) + b * b * (1.0 / 9.0)) +
+                           w2 * (b * b * (1.0 / 18.0) + a * a * (1.0 / 9.0)));
+        m.mzz[k] = (float)((w1 + w2) * (c * c * (1.0 / 18.0)));
+        m.mxz[k] = (float)((w2 * b - w1 * a) * (c * (1.0 / 36.0)));
+    }
+    return m;
+}
+
+// One copy of the pair as one distribution at p = P - c0 (FP64, the first
+// triangle's frame), rc2 = |p|^2: sigma-weighted monopole into s[k] (FP64),
+// dipole + quadrupole corrections, in units of m.sc[k], into fc[k] (FP32).
+template <int K>
+__device__ __forceinline__ void pair_far_moments(double px, double pz, double ph, double rc2,
+                                                 const PairMoments<K> &m, double (&s)[K][4], FarCorr (&fc)[K])
+{
+    const float fx = (float)px, fz = (float)pz, fh = (float)ph;
+    const float frc2 = (float)rc2;
+    const float fic = __builtin_amdgcn_rsqf(frc2);
+    const float fic2 = fic * fic;
+    const float fic3 = fic2 * fic;
+    const float fic5 = fic3 * fic2;
+    double ir = (double)fic;
+    ir = ir * (1.5 - 0.5 * rc2 * ir * ir);
+    const double ir2 = ir * ir;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double air = m.q[k] * ir;
+        const double air3 = air * ir2;
+        s[k][0] += air;
+        s[k][1] = fma(air3, px, s[k][1]);
+        s[k][2] = fma(air3, pz, s[k][2]);
+        s[k][3] = fma(air3, ph, s[k][3]);
+        const float mpx = fmaf(m.mxx[k], fx, m.mxz[k] * fz);
+        const float mpz = fmaf(m.mxz[k], fx, m.mzz[k] * fz);
+        const float t = m.mxx[k] + m.mzz[k];
+        const float u = fmaf(3.0f, fmaf(fx, mpx, fz * mpz), -frc2 * t);  // 3q - R^2 t
+        const float dpx = m.dx[k] * fx;                                   // d.p
+        const float G = fmaf(3.0f, dpx, fmaf(2.5f * u, fic2, t));  // p coefficient (x fic5): quadrupole g + dipole 3 d.p
+        fc[k].p += fmaf(0.5f * u, fic5, dpx * fic3);
+        fc[k].x += fmaf(fic5, fmaf(G, fx, -3.0f * mpx), -m.dx[k] * fic3);
+        fc[k].z = fmaf(fic5, fmaf(G, fz, -3.0f * mpz), fc[k].z);
+        fc[k].n = fmaf(fic5, G * fh, fc[k].n);
+    }
+}
+
+// One copy of one right triangle in the mixed path, unit density, at
+// centroid-relative (Xc, Zc, H) in its own frame: the tiers of
+// sum_translations<1, true>.
+__device__ __forceinline__ void tri_copy_mixed(double Xc, double Zc, double H, double lx, double lz, double hyp,
+                                               double ihyp, double area, const MixParams &mp, double far2,
+                                               double vfar2, double (&s)[4], FarCorr &fc)
+{
+    const double rc2 = fma(Xc, Xc, fma(Zc, Zc, H * H));
+    if (rc2 >= mp.quad2) {
+        far_quadrupole<1>(Xc, Zc, H, rc2, lx, lz, area, s[0], s[1], s[2], s[3], fc);
+        return;
+    }
+    if (rc2 >= mp.low2) {
+        far_mixed<1>(Xc, Zc, H, rc2, lx, lz, area, s[0], s[1], s[2], s[3], fc);
+        return;
+    }
+    const double X = Xc + lx * (1.0 / 3.0), Z = Zc + lz * (1.0 / 3.0);
+    const double r0sq = fma(X, X, fma(Z, Z, H * H));
+    Kern k;
+    if (r0sq >= vfar2) {
+        k = rtri_far<true>(X, H, Z, lx, lz, hyp, r0sq, s[0]);
+    } else if (r0sq >= far2) {
+        k = rtri_far<false>(X, H, Z, lx, lz, hyp, r0sq, s[0]);
+    } else {
+        k = rtri_fp64(X, H, Z, lx, lz, hyp, ihyp, r0sq);
+        k.phi += s[0];
+    }
+    s[0] = k.phi;
+    s[1] += k.ex;
+    s[2] += k.ez;
+    s[3] += k.en;
+}
+
+__device__ __forceinline__ MixParams mix_params(double near_factor, double diam, double low_d, double quad_d)
+{
+    MixParams mp;
+    const double nd = near_factor * diam;
+    const double ld = fmax(nd, low_d * diam), qd = fmax(nd, quad_d * diam);
+    mp.low2 = ld * ld;
+    mp.quad2 = qd * qd;
+    return mp;
+}
+
+// phi', E' (global frame) of a triangle pair with all its copies at P in the
+// mixed path, weighted by each column's densities (sg1, sg2): out[k].
+template <int K, bool HOLE>
+__device__ __forceinline__ void element_pair_copies_mixed(const Elem &e, const PairB &f, const double (&sg1)[K],
+                                                          const double (&sg2)[K], const ImgArgs &img,
+                                                          double near_factor, double Px, double Py, double Pz,
+                                                          double (&out)[K][4])
+{
+    const double a = e.lx, c = e.lz, b = f.lz;
+    const PairMoments<K> pm = pair_moments<K>(a, b, c, e.area, f.area, sg1, sg2);
+    const MixParams mp1 = mix_params(near_factor, e.diam, 48.0, 96.0);
+    const MixParams mp2 = mix_params(near_factor, f.diam, 48.0, 96.0);
+    const MixParams mpp = mix_params(near_factor, a + b, 48.0, 96.0);
+    const double far1 = (kFarDiam * kFarDiam) * (e.diam * e.diam), vfar1 = (kVeryFarDiam * kVeryFarDiam) * (e.diam * e.diam);
+    const double far2 = (kFarDiam * kFarDiam) * (f.diam * f.diam), vfar2 = (kVeryFarDiam * kVeryFarDiam) * (f.diam * f.diam);
+    const double c0x = (a - b) * (1.0 / 3.0), c0z = c * (1.0 / 3.0);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[k][q] = 0.0;
+    for (int r = 0; r < img.nref; ++r) {
+        const int ax = img.axes[r];
+        const double Qx = (ax & 1) ? 2.0 * img.mpos[0] - Px : Px;
+        const double Qy = (ax & 2) ? 2.0 * img.mpos[1] - Py : Py;
+        const double Qz = (ax & 4) ? 2.0 * img.mpos[2] - Pz : Pz;
+        const double rx = Qx - e.ox, ry = Qy - e.oy, rz = Qz - e.oz;
+        // coordinates relative to c0
+        const double X0 = rx * e.e1x + ry * e.e1y + rz * e.e1z - c0x;
+        const double Z0 = rx * e.e2x + ry * e.e2y + rz * e.e2z - c0z;
+        const double H0 = rx * e.e3x + ry * e.e3y + rz * e.e3z;
+        const double *av = img.a1[r], *bv = img.a2[r];
+        const double aX = av[0] * e.e1x + av[1] * e.e1y + av[2] * e.e1z;
+        const double aZ = av[0] * e.e2x + av[1] * e.e2y + av[2] * e.e2z;
+        const double aH = av[0] * e.e3x + av[1] * e.e3y + av[2] * e.e3z;
+        const double bX = bv[0] * e.e1x + bv[1] * e.e1y + bv[2] * e.e1z;
+        const double bZ = bv[0] * e.e2x + bv[1] * e.e2y + bv[2] * e.e2z;
+        const double bH = bv[0] * e.e3x + bv[1] * e.e3y + bv[2] * e.e3z;
+        double sp[K][4];  // sigma-weighted, first triangle's frame
+        FarCorr fp[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            sp[k][0] = sp[k][1] = sp[k][2] = sp[k][3] = 0.0;
+            fp[k] = {0.0f, 0.0f, 0.0f, 0.0f};
+        }
+        double s1[4] = {0.0, 0.0, 0.0, 0.0}, s2[4] = {0.0, 0.0, 0.0, 0.0};  // unit density, own frames
+        FarCorr f1 = {0.0f, 0.0f, 0.0f, 0.0f}, f2 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+        for (int i1 = -img.n1; i1 <= img.n1; ++i1) {
+            const double g1 = -(double)i1;
+            const double X1 = fma(g1, aX, X0), Z1 = fma(g1, aZ, Z0), H1 = fma(g1, aH, H0);
+            const bool cut = HOLE && abs(i1) <= img.hole;
+#pragma unroll 1
+            for (int seg = 0; seg <= (int)cut; ++seg) {
+                const int i2a = seg == 0 ? -img.n2 : img.hole + 1;
+                const int i2b = (cut && seg == 0) ? -img.hole - 1 : img.n2;
+#pragma unroll 1
+                for (int i2 = i2a; i2 <= i2b; ++i2) {
+                    const double g2 = -(double)i2;
+                    const double X = fma(g2, bX, X1), Z = fma(g2, bZ, Z1), H = fma(g2, bH, H1);
+                    const double rc2 = fma(X, X, fma(Z, Z, H * H));
+                    if (rc2 >= mpp.quad2) {
+                        pair_far_moments<K>(X, Z, H, rc2, pm, sp, fp);
+                        continue;
+                    }
+                    // each triangle on its own: corner-relative (X + c0x, Z + c0z);
+                    // the second one's frame (e2, -e1): (Z + c0z, -(X + c0x))
+                    const double Xo = X + c0x, Zo = Z + c0z;
+                    tri_copy_mixed(Xo - a * (1.0 / 3.0), Zo - c * (1.0 / 3.0), H, a, c, e.hyp, e.ihyp, e.area, mp1,
+                                   far1, vfar1, s1, f1);
+                    tri_copy_mixed(Zo - c * (1.0 / 3.0), -Xo - b * (1.0 / 3.0), H, c, b, f.hyp, f.ihyp, f.area, mp2,
+                                   far2, vfar2, s2, f2);
+                }
+            }
+        }
+        // unit-density sums with their FP32 corrections, the second
+        // triangle's turned into the first one's frame (e1 = -e2', e2 = e1')
+        const double u1[4] = {fma(e.area, (double)f1.p, s1[0]), fma(e.area, (double)f1.x, s1[1]),
+                              fma(e.area, (double)f1.z, s1[2]), fma(e.area, (double)f1.n, s1[3])};
+        const double u2[4] = {fma(f.area, (double)f2.p, s2[0]), -fma(f.area, (double)f2.z, s2[2]),
+                              fma(f.area, (double)f2.x, s2[1]), fma(f.area, (double)f2.n, s2[3])};
+        const double par = img.parity[r];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double l[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) l[q] = fma(sg2[k], u2[q], fma(sg1[k], u1[q], sp[k][q]));
+            l[0] = fma(pm.sc[k], (double)fp[k].p, l[0]);
+            l[1] = fma(pm.sc[k], (double)fp[k].x, l[1]);
+            l[2] = fma(pm.sc[k], (double)fp[k].z, l[2]);
+            l[3] = fma(pm.sc[k], (double)fp[k].n, l[3]);
+            double gx = l[1] * e.e1x + l[2] * e.e2x + l[3] * e.e3x;
+            double gy = l[1] * e.e1y + l[2] * e.e2y + l[3] * e.e3y;
+            double gz = l[1] * e.e1z + l[2] * e.e2z + l[3] * e.e3z;
+            gx = (ax & 1) ? -gx : gx;
+            gy = (ax & 2) ? -gy : gy;
+            gz = (ax & 4) ? -gz : gz;
+            out[k][0] += par * l[0];
+            out[k][1] += par * gx;
+            out[k][2] += par * gy;
+            out[k][3] += par * gz;
+        }
+    }
+}
+
 // -------------------------------------------------------------- evaluation
 // One workgroup's share of an evaluation: points [base, base + BS) of the
 // m points, all n elements (records drec, densities sigma) and their copies,
@@ -483,6 +716,20 @@ __device__ __forceinline__ void eval_block(const double *__restrict__ drec, cons
         __syncthreads();
         for (int p = 0; p < cnt; ++p) {
             const Elem e = load_elem(t_rec + p * R_STRIDE);
+            if (MIXED && e.kind >= 2 && p + 1 < cnt) {
+                // a triangle pair inside this tile, sigma-weighted in one pass
+                const int q1 = e.kind == 2 ? p : p + 1, q2 = e.kind == 2 ? p + 1 : p;
+                const double sg1[1] = {uni(t_sig[q1])}, sg2[1] = {uni(t_sig[q2])};
+                double c[1][4];
+                element_pair_copies_mixed<1, HOLE>(load_elem(t_rec + q1 * R_STRIDE), load_pair_b(t_rec + q2 * R_STRIDE),
+                                                   sg1, sg2, img, near_factor, Px, Py, Pz, c);
+                aphi += c[0][0];
+                aex += c[0][1];
+                aey += c[0][2];
+                aez += c[0][3];
+                ++p;
+                continue;
+            }
             if (!MIXED && e.kind >= 2 && p + 1 < cnt) {
                 // a triangle pair inside this tile: both in one pass (c1 for
                 // element p, c2 for p + 1, whichever is the pair's first)
@@ -571,10 +818,11 @@ __global__ __launch_bounds__(kBlock) void k_eval_fp64(
                                     ex ? ex + so : nullptr, ey ? ey + so : nullptr, ez ? ez + so : nullptr);
 }
 
-// Mixed: three waves per SIMD (13 % faster than two): the allocator spills a
-// few values of the per-element setup, outside the per-copy loop.
+// Mixed: two waves per SIMD (the triangle-pair path holds two triangles'
+// unit-density sums and the pair's weighted ones at once; at three waves it
+// spilled inside the copy loop).
 template <bool HOLE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_eval_mixed(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_eval_mixed(
     const double *__restrict__ drec, const double *__restrict__ sigma, int n, int segsz, ImgArgs img,
     double near_factor, const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz,
     int m, double scale, double *__restrict__ phi, double *__restrict__ ex, double *__restrict__ ey,
@@ -739,6 +987,28 @@ __device__ __forceinline__ void eval_block_multi(const double *__restrict__ drec
         __syncthreads();
         for (int p = 0; p < cnt; ++p) {
             const Elem e = load_elem(t_rec + p * R_STRIDE);
+            if (MIXED && e.kind >= 2 && p + 1 < cnt) {
+                // a triangle pair inside this tile, as in eval_block
+                const int q1 = e.kind == 2 ? p : p + 1, q2 = e.kind == 2 ? p + 1 : p;
+                double sg1[K], sg2[K], c[K][4];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    sg1[k] = uni(t_sig[q1 * K + k]);
+                    sg2[k] = uni(t_sig[q2 * K + k]);
+                }
+                element_pair_copies_mixed<K, false>(load_elem(t_rec + q1 * R_STRIDE),
+                                                    load_pair_b(t_rec + q2 * R_STRIDE), sg1, sg2, img, near_factor, Px,
+                                                    Py, Pz, c);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    aphi[k] += c[k][0];
+                    aex[k] += c[k][1];
+                    aey[k] += c[k][2];
+                    aez[k] += c[k][3];
+                }
+                ++p;
+                continue;
+            }
             if (!MIXED && e.kind >= 2 && p + 1 < cnt) {
                 // a triangle pair inside this tile, as in eval_block
                 const int q1 = e.kind == 2 ? p : p + 1, q2 = e.kind == 2 ? p + 1 : p;
@@ -875,7 +1145,7 @@ __global__ __launch_bounds__(64) void k_eval_items_fp64(const WorkItem *__restri
 }
 
 // three waves per SIMD, as k_eval_mixed
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_eval_items_mixed(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_eval_items_mixed(
     const WorkItem *__restrict__ items, const ImgArgs *__restrict__ imgs, double near_factor)
 {
     const WorkItem &w = items[blockIdx.x];
