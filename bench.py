@@ -49,19 +49,30 @@ ALG_FLOPS_TRI = 100.0
 COUNTER_CALIBRATION = {
     # profiles/eval_fp64_thgem_200k.md: one 2e5-point launch, 1.00672e12 interactions
     "thgem": {"flops_per_interaction": 101.04, "valu_per_interaction": 73.09, "traffic_bytes": 537282944,
-              "points_per_launch": 200000, "source_sha16": "b51a094ce0c8d484"},
+              "points_per_launch": 200000, "source_sha16": "1b886789b31f0e81"},
 }
 EVAL_SOURCES = ("field_kernels.hip", "panel_fp64.hpp", "fastmath_fp64.hpp", "poly_coeffs.hpp", "farfield_mixed.hpp",
                 "order_kernels.hip", "nebem_internal.hpp")
 
 
+def _code_only(text):
+    """C++ source without comments and with runs of whitespace collapsed
+    (the sources hold no comment markers inside string literals)"""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def eval_source_sha16():
-    """sha256 (first 16 hex digits) of the evaluation kernel's sources"""
+    """sha256 (first 16 hex digits) of the evaluation kernel's sources,
+    comments and layout left out (so a comment edit does not retire the
+    counter figures)"""
     import hashlib
     h = hashlib.sha256()
     for name in EVAL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2606_24154_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2606_24154_amd", "csrc", name)) as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 FP64_VALU_PEAK = 78.6e12      # MI355X, FLOP/s
 HBM_PEAK = 8.0e12             # B/s

@@ -1144,7 +1144,7 @@ __global__ __launch_bounds__(64) void k_eval_items_fp64(const WorkItem *__restri
                           w.ex, w.ey, w.ez);
 }
 
-// three waves per SIMD, as k_eval_mixed
+// two waves per SIMD, as k_eval_mixed
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_eval_items_mixed(
     const WorkItem *__restrict__ items, const ImgArgs *__restrict__ imgs, double near_factor)
 {
