@@ -157,8 +157,9 @@ def _pair_geometry(rng, n_tri, copies=0):
 def test_triangle_pairs_against_oracle_and_singles(nb):
     """Right-triangle pairs (a triangle cut at its altitude's foot) are
     evaluated together; against the oracle at the FP64 bar at 1e-3 .. 1e3
-    diameters and near the plane, and against the same triangles in the
-    opposite order (which is never paired) to 1e-11."""
+    diameters and near the plane, and against the same triangles with every
+    pair's halves apart in the element order (first halves, then second
+    halves: never paired) to 1e-11."""
     rng = np.random.default_rng(77)
     g = _pair_geometry(rng, 24, copies=2)
     assert g.n == 48 and np.all(g.kind == 1)
@@ -171,13 +172,37 @@ def test_triangle_pairs_against_oracle_and_singles(nb):
     ref = oracle.eval_points(g, sigma, pts)
     ephi, eE = rel_errors(got, ref)
     assert ephi < 1e-10 and eE < 1e-10, (ephi, eE)
-    # the same elements with each pair's two triangles swapped: no pairs
-    perm = np.arange(g.n).reshape(-1, 2)[:, ::-1].ravel()
+    # the same elements with each pair's halves apart: no pairs
+    perm = np.concatenate([np.arange(0, g.n, 2), np.arange(1, g.n, 2)])
     gs = g.subset(perm)
     got_s = gpu_eval(nb, gs, sigma[perm], pts)
     ephi, eE = rel_errors(got, got_s)
     assert ephi < 1e-11 and eE < 1e-11, (ephi, eE)
     assert not np.array_equal(got, got_s)  # the pair path did run
+
+
+def test_triangle_pairs_mixed_against_oracle_and_singles(nb):
+    """The mixed path's triangle pairs (one multipole expansion per far pair
+    copy, each triangle's own tiers nearer): against the oracle at the mixed
+    bar, at distances reaching past 96 diameters of the whole triangles, and
+    against the same triangles with every pair's halves apart (single-element
+    tiers) at the same bar."""
+    rng = np.random.default_rng(79)
+    g = _pair_geometry(rng, 24, copies=3)
+    sigma = rng.uniform(0.5, 1.5, g.n) * rng.choice([-1, 1], g.n)
+    m = 4000
+    d = rng.standard_normal((m, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    pts = (30e-6 * 10 ** rng.uniform(0, 2.5, m))[:, None] * d
+    got = gpu_eval(nb, g, sigma, pts, precision=nb.MIXED)
+    ref = oracle.eval_points(g, sigma, pts)
+    ephi, eE = rel_errors(got, ref)
+    assert ephi < 1e-6 and eE < 1e-6, (ephi, eE)
+    perm = np.concatenate([np.arange(0, g.n, 2), np.arange(1, g.n, 2)])
+    got_s = gpu_eval(nb, g.subset(perm), sigma[perm], pts, precision=nb.MIXED)
+    ephi, eE = rel_errors(got, got_s)
+    assert ephi < 1e-6 and eE < 1e-6, (ephi, eE)
+    assert not np.array_equal(got, got_s)
 
 
 def test_triangle_pair_at_tile_edge(nb):
