@@ -210,7 +210,7 @@ def serve_replay(nb, geoms, sessions, n_req, load, eval_rate, seed=4):
     return {"requests": n_req, "arrival_rate_hz": load * mu_req, "load": load,
             "p50_ms": 1e3 * run["p50_s"], "p99_ms": 1e3 * run["p99_s"],
             "points_per_s": run["points_per_s"], "interactions_per_s": c.interactions / run["span_s"],
-            "launches": int(c.launches), "errors": len(run["errors"])}
+            "launches": int(c.launches), "backfilled": int(c.backfilled), "errors": len(run["errors"])}
 
 
 def serve_matrix(args):
@@ -292,7 +292,7 @@ def serve_matrix(args):
             st = stats(run, reqs, n_warm)
             res[str(load)] = {"arrival_rate_hz": rate, **st, "points_per_s": run["points_per_s"],
                               "interactions_per_s": c.interactions / run["span_s"], "launches": int(c.launches),
-                              "errors": len(run["errors"])}
+                              "backfilled": int(c.backfilled), "errors": len(run["errors"])}
             log(f"{name} load {load}: p50 {st['p50_ms']:.0f} ms, p99 {st['p99_ms']:.0f} ms ({st['measured']} requests)")
             # each (precision, load) row as soon as it is measured
             print(json.dumps({"serve_matrix_row": {"precision": name, "load": load, **res[str(load)]}}), flush=True)

@@ -416,15 +416,17 @@ nebem_status nebem_spacecharge_step_lines(nebem_session *s, double *qx, double *
  * submit batches of points (host arrays) naming one of the server's
  * sessions; a worker thread admits requests in arrival order while their
  * staging (8 + 4 x nseg doubles per point, nseg = element segments of the
- * geometry, about N x copies / 1.2e5, at most 64) fits the device budget,
- * sorts the points of requests of >= 4096 points into Morton order, cuts the
+ * geometry, about N x copies / 1.2e5, at most 64) fits the device budget
+ * (behind a head of the line that does not fit, up to 64 requests of at
+ * most 1/64 of the budget that do fit are admitted past it), sorts the
+ * points of requests of >= 4096 points into Morton order, cuts the
  * admitted requests into work items of 64 points x one element segment, and
  * evaluates work items of several requests and geometries in each kernel
  * launch (round-robin, up to batch_interactions element-copy x point pairs
  * per launch).  Requests that arrive while others are on the GPU join at the
  * next launch.  A point's result is bit-identical whatever else shares its
- * launches, and equal to nebem_session_eval's to rounding (the segment sums
- * are added in a fixed order of their own). */
+ * launches, and bit-identical to nebem_session_eval's (the same element
+ * segments, added in the same order). */
 typedef struct nebem_server nebem_server;
 typedef struct nebem_server_options {
     int64_t hbm_budget;         /* bytes of device staging for admitted requests (2 GiB) */
@@ -440,6 +442,7 @@ typedef struct nebem_server_counters {
     double interactions; /* evaluated so far */
     double busy_s;       /* worker time spent in launches */
     int64_t queued, active;
+    int64_t backfilled; /* requests admitted past a head of the line that did not fit */
 } nebem_server_counters;
 
 void nebem_server_default_options(nebem_server_options *opt);

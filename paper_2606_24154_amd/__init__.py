@@ -94,7 +94,8 @@ class RequestStats(ctypes.Structure):
 class ServerCounters(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("points_done", ctypes.c_int64),
                 ("interactions", ctypes.c_double), ("busy_s", ctypes.c_double),
-                ("queued", ctypes.c_int64), ("active", ctypes.c_int64)]
+                ("queued", ctypes.c_int64), ("active", ctypes.c_int64),
+                ("backfilled", ctypes.c_int64)]
 
 
 def _load():

@@ -7,10 +7,15 @@
 //   1. admission: queued requests enter, in arrival order, while their
 //      staging (points, results, permutation and per-segment partial sums:
 //      8 + 4 nseg doubles per point) fits into the device arena of
-//      hbm_budget bytes; their points are copied in and, for requests of
-//      4096 points or more, sorted into Morton order on the device (so that
-//      the lanes of a work item share the near/far branches; each lane's
-//      arithmetic is unchanged);
+//      hbm_budget bytes.  A request that does not fit blocks the head of
+//      the line; behind it, small requests (at most 1/64 of the arena) that
+//      fit are admitted past it, placed at the arena's top end so that the
+//      space freed below stays in one piece, at most kMaxBypass of them per
+//      blocked head (so the head waits for a bounded number of them).
+//      Admitted points are copied in and, for requests of 4096 points or
+//      more, sorted into Morton order on the device (so that the lanes of a
+//      work item share the near/far branches; each lane's arithmetic is
+//      unchanged);
 //   2. batching: the active requests are cut into work items of 64 points x
 //      one segment of the geometry's elements (each geometry's element range
 //      is split into a fixed number of segments of about kSegWork
@@ -76,7 +81,11 @@ struct Request {
     bool finished = false;
 };
 
-// first-fit allocator over [0, size) with 256-byte granules
+constexpr int kBackfillFrac = 64;  // requests of at most size / 64 may pass a blocked head
+constexpr int kMaxBypass = 64;     // ... and at most this many per blocked head
+
+// first-fit allocator over [0, size) with 256-byte granules; alloc_top takes
+// the top end of the highest free block that fits
 struct Arena {
     size_t size = 0;
     std::map<size_t, size_t> free_;  // offset -> length
@@ -95,6 +104,19 @@ struct Arena {
                 const size_t rest = it->second - bytes;
                 free_.erase(it);
                 if (rest) free_[off + bytes] = rest;
+                return true;
+            }
+        return false;
+    }
+    bool alloc_top(size_t bytes, size_t &off)
+    {
+        bytes = (bytes + 255) & ~size_t(255);
+        for (auto it = free_.rbegin(); it != free_.rend(); ++it)
+            if (it->second >= bytes) {
+                const size_t start = it->first, rest = it->second - bytes;
+                off = start + rest;
+                free_.erase(std::next(it).base());
+                if (rest) free_[start] = rest;
                 return true;
             }
         return false;
@@ -145,12 +167,14 @@ struct nebem_server {
     std::condition_variable cv_work, cv_done;
     std::deque<nebem::Request *> queue;
     std::vector<nebem::Request *> active;
+    int64_t blocked_id = 0;  // id of the head of the line that did not fit (0: none)
+    int bypassed = 0;        // requests admitted past it
     std::map<int64_t, nebem::Request *> all;
     int64_t next_id = 1;
     bool stop = false;
     std::thread worker;
     // statistics
-    int64_t launches = 0, points_done = 0;
+    int64_t launches = 0, points_done = 0, backfilled = 0;
     double interactions_done = 0, busy_s = 0;
     std::string worker_error;
 };
@@ -162,16 +186,36 @@ namespace nebem {
 static bool admit_locked(nebem_server *s)
 {
     bool any = false;
-    while (!s->queue.empty()) {
-        Request *r = s->queue.front();
+    const Request *head = nullptr;  // first queued request that does not fit
+    for (auto it = s->queue.begin(); it != s->queue.end();) {
+        Request *r = *it;
         size_t off;
-        if (!s->arena.alloc(r->bytes, off)) break;  // head of line waits for space
+        if (!head) {
+            if (!s->arena.alloc(r->bytes, off)) {
+                head = r;
+                if (s->blocked_id != r->id) {
+                    s->blocked_id = r->id;
+                    s->bypassed = 0;
+                }
+                ++it;
+                continue;
+            }
+        } else {
+            if (s->bypassed >= kMaxBypass) break;
+            if (r->bytes > s->arena.size / kBackfillFrac || !s->arena.alloc_top(r->bytes, off)) {
+                ++it;
+                continue;
+            }
+            ++s->bypassed;
+            ++s->backfilled;
+        }
         r->off = off;
         r->t_admit = now_s();
-        s->queue.pop_front();
+        it = s->queue.erase(it);
         s->active.push_back(r);
         any = true;
     }
+    if (!head) s->blocked_id = 0;
     return any;
 }
 
@@ -510,6 +554,7 @@ nebem_status nebem_server_stats(nebem_server *s, nebem_server_counters *out)
     out->points_done = s->points_done;
     out->interactions = s->interactions_done;
     out->busy_s = s->busy_s;
+    out->backfilled = s->backfilled;
     out->queued = (int64_t)s->queue.size();
     out->active = (int64_t)s->active.size();
     return NEBEM_OK;

@@ -116,3 +116,34 @@ def test_oversized_request_refused(nb):
     srv.close()
     for x in ses:
         x.close()
+
+
+def test_small_request_passes_blocked_head(nb):
+    """A large request that does not fit beside an active one blocks the head
+    of the line; a small request submitted after it is admitted past it and
+    finishes first, with results still bit-equal to the session's."""
+    geoms = _geometries()
+    ses = _sessions(nb, 0, [geoms[0], geoms[2]])
+    per_pt = (8 + 4 * 3) * 8  # the three-segment geometry's staging per point
+    # one launch = one round of work items, so the first request (12 288
+    # items) stays active over several launches
+    srv = nb.Server(ses, hbm_budget=per_pt * 300000, batch_interactions=1.0)
+    big = uniform_points(geoms[2].box_lo, geoms[2].box_hi, 262144, 31)
+    blocked = uniform_points(geoms[2].box_lo, geoms[2].box_hi, 65536, 32)
+    small = uniform_points(geoms[0].box_lo, geoms[0].box_hi, 200, 33)
+    ta = srv.submit(1, big)
+    tb = srv.submit(1, blocked)
+    tc = srv.submit(0, small)
+    out_c, st_c = srv.wait(tc)
+    out_b, st_b = srv.wait(tb)
+    out_a, st_a = srv.wait(ta)
+    assert srv.counters().backfilled >= 1
+    assert st_c.t_admit < st_b.t_admit and st_c.t_done < st_b.t_admit
+    assert st_b.t_admit >= st_a.t_done - 1e-3
+    for out, g, pts in ((out_c, 0, small), (out_b, 1, blocked)):
+        ref = _alone(nb, ses[g], pts)
+        for name, r in zip(("phi", "ex", "ey", "ez"), ref):
+            assert np.array_equal(out[name], r), (g, name)
+    srv.close()
+    for x in ses:
+        x.close()
