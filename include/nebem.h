@@ -453,7 +453,8 @@ nebem_status nebem_server_create(nebem_session *const *sessions, int32_t nsessio
 /* Queues m points (HOST arrays px/py/pz, read until the request completes)
  * on session `geometry`; results go to the HOST arrays phi/ex/ey/ez (any may
  * be NULL).  Returns a ticket.  NEBEM_EBUSY if the request alone exceeds the
- * budget or the server is shutting down. */
+ * budget (its staging rounded up, the budget down, to 256 bytes) or the
+ * server is shutting down. */
 nebem_status nebem_server_submit(nebem_server *s, int32_t geometry, const double *px, const double *py,
                                  const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
                                  int64_t *ticket);

@@ -53,6 +53,7 @@
 
 #include "host_util.hpp"
 #include "nebem_internal.hpp"
+#include "server_admission.hpp"
 #include "session_internal.hpp"
 
 namespace nebem {
@@ -79,65 +80,6 @@ struct Request {
     int status = NEBEM_OK;
     bool ordered = false;       // points sorted into Morton order on admission
     bool finished = false;
-};
-
-constexpr int kBackfillFrac = 64;  // requests of at most size / 64 may pass a blocked head
-constexpr int kMaxBypass = 64;     // ... and at most this many per blocked head
-
-// first-fit allocator over [0, size) with 256-byte granules; alloc_top takes
-// the top end of the highest free block that fits
-struct Arena {
-    size_t size = 0;
-    std::map<size_t, size_t> free_;  // offset -> length
-    void init(size_t s)
-    {
-        size = s;
-        free_.clear();
-        if (s) free_[0] = s;
-    }
-    bool alloc(size_t bytes, size_t &off)
-    {
-        bytes = (bytes + 255) & ~size_t(255);
-        for (auto it = free_.begin(); it != free_.end(); ++it)
-            if (it->second >= bytes) {
-                off = it->first;
-                const size_t rest = it->second - bytes;
-                free_.erase(it);
-                if (rest) free_[off + bytes] = rest;
-                return true;
-            }
-        return false;
-    }
-    bool alloc_top(size_t bytes, size_t &off)
-    {
-        bytes = (bytes + 255) & ~size_t(255);
-        for (auto it = free_.rbegin(); it != free_.rend(); ++it)
-            if (it->second >= bytes) {
-                const size_t start = it->first, rest = it->second - bytes;
-                off = start + rest;
-                free_.erase(std::next(it).base());
-                if (rest) free_[start] = rest;
-                return true;
-            }
-        return false;
-    }
-    void release(size_t off, size_t bytes)
-    {
-        bytes = (bytes + 255) & ~size_t(255);
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
 };
 
 }  // namespace nebem
@@ -167,14 +109,13 @@ struct nebem_server {
     std::condition_variable cv_work, cv_done;
     std::deque<nebem::Request *> queue;
     std::vector<nebem::Request *> active;
-    int64_t blocked_id = 0;  // id of the head of the line that did not fit (0: none)
-    int bypassed = 0;        // requests admitted past it
+    nebem::AdmitState adm;
     std::map<int64_t, nebem::Request *> all;
     int64_t next_id = 1;
     bool stop = false;
     std::thread worker;
     // statistics
-    int64_t launches = 0, points_done = 0, backfilled = 0;
+    int64_t launches = 0, points_done = 0;
     double interactions_done = 0, busy_s = 0;
     std::string worker_error;
 };
@@ -183,40 +124,12 @@ using namespace nebem;
 
 namespace nebem {
 
-static bool admit_locked(nebem_server *s)
+static void admit_locked(nebem_server *s)
 {
-    bool any = false;
-    const Request *head = nullptr;  // first queued request that does not fit
-    for (auto it = s->queue.begin(); it != s->queue.end();) {
-        Request *r = *it;
-        size_t off;
-        if (!head) {
-            if (!s->arena.alloc(r->bytes, off)) {
-                head = r;
-                if (s->blocked_id != r->id) {
-                    s->blocked_id = r->id;
-                    s->bypassed = 0;
-                }
-                ++it;
-                continue;
-            }
-        } else {
-            if (s->bypassed >= kMaxBypass) break;
-            if (r->bytes > s->arena.size / kBackfillFrac || !s->arena.alloc_top(r->bytes, off)) {
-                ++it;
-                continue;
-            }
-            ++s->bypassed;
-            ++s->backfilled;
-        }
-        r->off = off;
+    admit(s->queue, s->arena, s->adm, [&](Request *r) {
         r->t_admit = now_s();
-        it = s->queue.erase(it);
         s->active.push_back(r);
-        any = true;
-    }
-    if (!head) s->blocked_id = 0;
-    return any;
+    });
 }
 
 // device addresses of a request's staging: columns 0-2 points (sorted if
@@ -235,6 +148,9 @@ static void worker_main(nebem_server *s)
     int pend = -1;           // stream of the launch in flight, -1 if none
     bool adm_event = false;  // ev_adm recorded at least once
     double t_busy = 0.0;     // start of the current stretch with a launch in flight
+    // statistics gathered outside the lock, added to the server's under it
+    double d_inter = 0.0, d_busy = 0.0;
+    int64_t d_launches = 0;
     for (;;) {
         std::vector<Request *> act;
         {
@@ -319,7 +235,7 @@ static void worker_main(nebem_server *s)
                 r->infl[cur] += 1;
                 const double work = (double)ne * g->img_count * cnt;
                 budget -= work;
-                s->interactions_done += work;
+                d_inter += work;
                 progress = true;
                 if (!more()) break;
             }
@@ -343,7 +259,7 @@ static void worker_main(nebem_server *s)
             if (pend < 0) t_busy = now_s();
             launched = true;
             ++nlaunch;
-            ++s->launches;
+            ++d_launches;
         }
         // retire the previous launch: its requests whose items are all done
         // (or that failed and have nothing in flight) get their segments
@@ -371,7 +287,7 @@ static void worker_main(nebem_server *s)
                                     stage(s, r, 8), stage(s, r, 9), stage(s, r, 10), stage(s, r, 11), s->lst[rs]);
             }
         if (!done.empty()) (void)hipStreamSynchronize(s->lst[rs]);
-        if (!launched && pend >= 0) s->busy_s += now_s() - t_busy;
+        if (!launched && pend >= 0) d_busy += now_s() - t_busy;
         pend = launched ? cur : -1;
         for (Request *r : done) {
             if (r->status == NEBEM_OK) {
@@ -386,6 +302,11 @@ static void worker_main(nebem_server *s)
         }
         {
             std::lock_guard<std::mutex> lk(s->mu);
+            s->interactions_done += d_inter;
+            s->busy_s += d_busy;
+            s->launches += d_launches;
+            d_inter = d_busy = 0.0;
+            d_launches = 0;
             for (Request *r : done) {
                 s->arena.release(r->off, r->bytes);
                 s->active.erase(std::find(s->active.begin(), s->active.end(), r));
@@ -504,7 +425,7 @@ nebem_status nebem_server_submit(nebem_server *s, int32_t geometry, const double
     r->nitems = ((m + 63) / 64) * r->nseg;
     r->ordered = eval_ordering_pays(m);
     r->bytes = (size_t)m * (8 + 4 * (size_t)r->nseg) * sizeof(double);
-    if (r->bytes > (size_t)s->opt.hbm_budget) {
+    if (arena_bytes(r->bytes) > s->arena.size) {
         delete r;
         return fail(NEBEM_EBUSY, "server_submit: request larger than the server's HBM budget");
     }
@@ -554,7 +475,7 @@ nebem_status nebem_server_stats(nebem_server *s, nebem_server_counters *out)
     out->points_done = s->points_done;
     out->interactions = s->interactions_done;
     out->busy_s = s->busy_s;
-    out->backfilled = s->backfilled;
+    out->backfilled = s->adm.backfilled;
     out->queued = (int64_t)s->queue.size();
     out->active = (int64_t)s->active.size();
     return NEBEM_OK;
