@@ -113,6 +113,9 @@ def parse():
     p.add_argument("--serve-loads", default="0.5,0.8,0.95", help="serving study: loads to run (of 0.5, 0.8, 0.95)")
     p.add_argument("--serve-batch", type=float, default=None,
                    help="serving study: interactions per server launch (default: the library's)")
+    p.add_argument("--serve-max-large", type=int, default=None,
+                   help="serving study: large requests (1e11 interactions or more) active at once, 0: no limit "
+                        "(default: the library's, one)")
     p.add_argument("--serve-sat", type=float, default=None,
                    help="serving study: FP64 saturation rate (interactions/s) instead of measuring it")
     p.add_argument("--weighting", action="store_true",
@@ -255,7 +258,9 @@ def serve_matrix(args):
                                                  "p99_ms": pct(lat[geo == k], 99)} for k in range(len(geoms))}}
 
     out = {"requests": n_req, "warmup_requests": n_warm, "geometries": [g.name for g in geoms],
-           "batch_interactions": args.serve_batch or nb.server_default_options().batch_interactions}
+           "batch_interactions": args.serve_batch or nb.server_default_options().batch_interactions,
+           "max_large": (args.serve_max_large if args.serve_max_large is not None
+                         else nb.server_default_options().max_large)}
     sat = args.serve_sat
     for name in modes:
         pr = nb.FP64 if name == "fp64" else nb.MIXED
@@ -266,7 +271,7 @@ def serve_matrix(args):
         if sat is None:
             burst = [(0.0, g, n, sd) for (_, g, n, sd) in serve_requests(n_req, 1.0, 3, seed=4)]
             work = sum(n * geoms[g].n * geoms[g].images.count for (_, g, n, _) in burst)
-            srv = nb.Server(ses, batch_interactions=args.serve_batch)
+            srv = nb.Server(ses, batch_interactions=args.serve_batch, max_large=args.serve_max_large)
             run = replay(srv, burst, make_points, progress)
             srv.close()
             sat = work / run["span_s"]
@@ -285,7 +290,7 @@ def serve_matrix(args):
                 continue
             rate = load * out["saturation_requests_per_s"]
             reqs = serve_requests(n_warm + n_req, rate, 3, seed=4 + ri)
-            srv = nb.Server(ses, batch_interactions=args.serve_batch)
+            srv = nb.Server(ses, batch_interactions=args.serve_batch, max_large=args.serve_max_large)
             run = replay(srv, reqs, make_points, progress)
             c = srv.counters()
             srv.close()

@@ -418,7 +418,10 @@ nebem_status nebem_spacecharge_step_lines(nebem_session *s, double *qx, double *
  * staging (8 + 4 x nseg doubles per point, nseg = element segments of the
  * geometry, about N x copies / 1.2e5, at most 64) fits the device budget
  * (behind a head of the line that does not fit, up to 64 requests of at
- * most 1/64 of the budget that do fit are admitted past it), sorts the
+ * most 1/64 of the budget that do fit are admitted past it; with max_large
+ * > 0 at most that many large requests are active at once -- first come
+ * first served among them -- and a large one beyond it waits at the head
+ * like one that does not fit), sorts the
  * points of requests of >= 4096 points into Morton order, cuts the
  * admitted requests into work items of 64 points x one element segment, and
  * evaluates work items of several requests and geometries in each kernel
@@ -432,6 +435,8 @@ typedef struct nebem_server_options {
     int64_t hbm_budget;         /* bytes of device staging for admitted requests (2 GiB) */
     double batch_interactions;  /* work per launch, interactions (1e10) */
     int32_t max_items;          /* work items per launch (65536) */
+    double large_interactions;  /* a request of at least this much work (interactions) is large (1e11) */
+    int32_t max_large;          /* large requests active at once; 0: no limit (1) */
 } nebem_server_options;
 typedef struct nebem_request_stats {
     double t_submit, t_admit, t_done; /* host steady-clock seconds */

@@ -83,7 +83,8 @@ class SolveInfo(ctypes.Structure):
 
 class ServerOptions(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_int64), ("batch_interactions", ctypes.c_double),
-                ("max_items", ctypes.c_int32)]
+                ("max_items", ctypes.c_int32), ("large_interactions", ctypes.c_double),
+                ("max_large", ctypes.c_int32)]
 
 
 class RequestStats(ctypes.Structure):
@@ -601,9 +602,14 @@ class Server:
     """Continuous-batching evaluation service over resident sessions (host
     numpy arrays in and out; the arrays must stay alive until `wait`)."""
 
-    def __init__(self, sessions, hbm_budget=None, batch_interactions=None, max_items=None):
+    def __init__(self, sessions, hbm_budget=None, batch_interactions=None, max_items=None,
+                 large_interactions=None, max_large=None):
         o = ServerOptions()
         lib.nebem_server_default_options(ctypes.byref(o))
+        if large_interactions is not None:
+            o.large_interactions = float(large_interactions)
+        if max_large is not None:
+            o.max_large = int(max_large)
         if hbm_budget is not None:
             o.hbm_budget = int(hbm_budget)
         if batch_interactions is not None:

@@ -12,6 +12,10 @@
 //      fit are admitted past it, placed at the arena's top end so that the
 //      space freed below stays in one piece, at most kMaxBypass of them per
 //      blocked head (so the head waits for a bounded number of them).
+//      At most max_large requests of large_interactions or more are active
+//      at once (by default one: first come first served among them, the
+//      smaller ones sharing the device with them), so that the largest
+//      requests do not all slow each other down.
 //      Admitted points are copied in and, for requests of 4096 points or
 //      more, sorted into Morton order on the device (so that the lanes of a
 //      work item share the near/far branches; each lane's arithmetic is
@@ -79,6 +83,7 @@ struct Request {
     int64_t done_items = 0;
     int status = NEBEM_OK;
     bool ordered = false;       // points sorted into Morton order on admission
+    bool large = false;         // at least large_interactions of work
     bool finished = false;
 };
 
@@ -126,7 +131,7 @@ namespace nebem {
 
 static void admit_locked(nebem_server *s)
 {
-    admit(s->queue, s->arena, s->adm, [&](Request *r) {
+    admit(s->queue, s->arena, s->adm, s->opt.max_large, [&](Request *r) {
         r->t_admit = now_s();
         s->active.push_back(r);
     });
@@ -309,6 +314,7 @@ static void worker_main(nebem_server *s)
             d_launches = 0;
             for (Request *r : done) {
                 s->arena.release(r->off, r->bytes);
+                if (r->large) --s->adm.active_large;
                 s->active.erase(std::find(s->active.begin(), s->active.end(), r));
                 s->points_done += r->m;
                 r->finished = true;
@@ -328,6 +334,8 @@ void nebem_server_default_options(nebem_server_options *o)
     o->hbm_budget = (int64_t)2 << 30;
     o->batch_interactions = 1e10;
     o->max_items = 65536;
+    o->large_interactions = 1e11;
+    o->max_large = 1;
 }
 
 nebem_status nebem_server_create(nebem_session *const *sessions, int32_t nsessions, const nebem_server_options *opt,
@@ -341,7 +349,8 @@ nebem_status nebem_server_create(nebem_session *const *sessions, int32_t nsessio
         o = *opt;
     else
         nebem_server_default_options(&o);
-    if (o.hbm_budget < 4096 || !(o.batch_interactions > 0) || o.max_items < 1 || o.max_items > (1 << 20))
+    if (o.hbm_budget < 4096 || !(o.batch_interactions > 0) || o.max_items < 1 || o.max_items > (1 << 20) ||
+        !(o.large_interactions > 0) || o.max_large < 0)
         return fail(NEBEM_EINVAL, "server_create: bad options");
     for (int k = 0; k < nsessions; ++k)
         if (!sessions[k]) return fail(NEBEM_EINVAL, "server_create: NULL session");
@@ -424,6 +433,7 @@ nebem_status nebem_server_submit(nebem_server *s, int32_t geometry, const double
     r->nseg = s->geom_nseg[geometry];
     r->nitems = ((m + 63) / 64) * r->nseg;
     r->ordered = eval_ordering_pays(m);
+    r->large = (double)m * (double)s->geom_n[geometry] * s->geoms[geometry]->img_count >= s->opt.large_interactions;
     r->bytes = (size_t)m * (8 + 4 * (size_t)r->nseg) * sizeof(double);
     if (arena_bytes(r->bytes) > s->arena.size) {
         delete r;

@@ -12,7 +12,10 @@
 // admitted past it (backfill) at the arena's top end, so that the space
 // freed below stays in one piece for the head, and at most kMaxBypass of
 // them per blocked head: the head then waits only for the requests already
-// admitted to finish.
+// admitted to finish.  Optionally (max_large > 0) at most max_large "large"
+// requests (the caller's flag) are active at once: a large request beyond
+// the cap blocks the head of the line like one that does not fit, and a
+// small one behind the head is passed over while the cap is reached.
 #pragma once
 
 #include <cstddef>
@@ -86,21 +89,24 @@ struct AdmitState {
     int64_t blocked_id = 0;  // id of the blocked head of the line (0: none)
     int bypassed = 0;        // requests admitted past it
     int64_t backfilled = 0;  // requests admitted past any blocked head, in total
+    int active_large = 0;    // large requests admitted and not yet finished
 };
 
-// R: a request with members id (> 0), bytes and off.  Admitted requests
-// leave the queue with off set and are passed to on_admit in admission
-// order.  Returns whether any was admitted.
+// R: a request with members id (> 0), bytes, off and large.  Admitted
+// requests leave the queue with off set and are passed to on_admit in
+// admission order; the caller decrements st.active_large when a large one
+// finishes.  max_large <= 0: no cap.  Returns whether any was admitted.
 template <class R, class OnAdmit>
-bool admit(std::deque<R *> &queue, Arena &arena, AdmitState &st, OnAdmit &&on_admit)
+bool admit(std::deque<R *> &queue, Arena &arena, AdmitState &st, int max_large, OnAdmit &&on_admit)
 {
     bool any = false;
     const R *head = nullptr;
     for (auto it = queue.begin(); it != queue.end();) {
         R *r = *it;
         size_t off;
+        const bool capped = r->large && max_large > 0 && st.active_large >= max_large;
         if (!head) {
-            if (!arena.alloc(r->bytes, off)) {
+            if (capped || !arena.alloc(r->bytes, off)) {
                 head = r;
                 if (st.blocked_id != r->id) {
                     st.blocked_id = r->id;
@@ -111,7 +117,7 @@ bool admit(std::deque<R *> &queue, Arena &arena, AdmitState &st, OnAdmit &&on_ad
             }
         } else {
             if (st.bypassed >= kMaxBypass) break;
-            if (r->bytes > arena.size / kBackfillFrac || !arena.alloc_top(r->bytes, off)) {
+            if (capped || r->bytes > arena.size / kBackfillFrac || !arena.alloc_top(r->bytes, off)) {
                 ++it;
                 continue;
             }
@@ -119,6 +125,7 @@ bool admit(std::deque<R *> &queue, Arena &arena, AdmitState &st, OnAdmit &&on_ad
             ++st.backfilled;
         }
         r->off = off;
+        if (r->large) ++st.active_large;
         it = queue.erase(it);
         on_admit(r);
         any = true;

@@ -25,6 +25,7 @@ static int failures = 0;
 struct Req {
     int64_t id = 0;
     size_t bytes = 0, off = 0;
+    bool large = false;
     bool live = false;
 };
 
@@ -83,7 +84,7 @@ static void fcfs_and_backfill()
         r->live = true;
         order.push_back(r->id);
     };
-    CHECK(nebem::admit(q, a, st, on));
+    CHECK(nebem::admit(q, a, st, 0, on));
     CHECK((order == std::vector<int64_t>{1, 3, 5, 6}));
     CHECK(q.size() == 2 && q[0]->id == 2 && q[1]->id == 4);
     CHECK(st.blocked_id == 2 && st.bypassed == 3 && st.backfilled == 3);
@@ -94,7 +95,7 @@ static void fcfs_and_backfill()
     a.release(rs[0].off, rs[0].bytes);
     rs[0].live = false;
     order.clear();
-    CHECK(nebem::admit(q, a, st, on));
+    CHECK(nebem::admit(q, a, st, 0, on));
     CHECK((order == std::vector<int64_t>{2, 4}));
     CHECK(q.empty() && st.blocked_id == 0);
     CHECK(disjoint(rs, a.size));
@@ -119,7 +120,7 @@ static void bypass_cap()
         r->live = true;
         ++admitted;
     };
-    nebem::admit(q, a, st, on);
+    nebem::admit(q, a, st, 0, on);
     CHECK(admitted == 2);  // the big one and one small one in the last granule
     // the small ones keep finishing; the head stays blocked while the big
     // one runs, and after kMaxBypass of them no more pass it
@@ -129,7 +130,7 @@ static void bypass_cap()
                 a.release(r.off, r.bytes);
                 r.live = false;
             }
-        nebem::admit(q, a, st, on);
+        nebem::admit(q, a, st, 0, on);
         CHECK(disjoint(rs, a.size));
     }
     CHECK(st.bypassed == nebem::kMaxBypass && st.blocked_id == 2);
@@ -142,7 +143,7 @@ static void bypass_cap()
             r.live = false;
         }
     std::vector<int64_t> order;
-    nebem::admit(q, a, st, [&](Req *r) {
+    nebem::admit(q, a, st, 0, [&](Req *r) {
         r->live = true;
         order.push_back(r->id);
     });
@@ -150,7 +151,52 @@ static void bypass_cap()
     CHECK(q.empty() && st.blocked_id == 0);
 }
 
-static void random_traffic()
+static void large_cap()
+{
+    // room for everything; at most one large request at a time
+    Arena a;
+    a.init(64 * 256);
+    AdmitState st;
+    std::vector<Req> rs(5);
+    for (int k = 0; k < 5; ++k) {
+        rs[k].id = k + 1;
+        rs[k].bytes = 256;
+    }
+    rs[0].large = rs[1].large = rs[3].large = true;
+    std::deque<Req *> q;
+    for (auto &r : rs) q.push_back(&r);
+    std::vector<int64_t> order;
+    auto on = [&](Req *r) {
+        r->live = true;
+        order.push_back(r->id);
+    };
+    nebem::admit(q, a, st, 1, on);
+    CHECK((order == std::vector<int64_t>{1, 3, 5}));  // 2 waits at the head, 3 and 5 pass, 4 is large
+    CHECK(st.active_large == 1 && st.blocked_id == 2 && st.backfilled == 2);
+    // the large one finishes (the caller's part: release and decrement)
+    a.release(rs[0].off, rs[0].bytes);
+    rs[0].live = false;
+    --st.active_large;
+    order.clear();
+    nebem::admit(q, a, st, 1, on);
+    CHECK((order == std::vector<int64_t>{2}));
+    CHECK(st.active_large == 1 && q.size() == 1 && q[0]->id == 4);
+    // without a cap all of them enter at once
+    Arena b;
+    b.init(64 * 256);
+    AdmitState st2;
+    std::vector<Req> rs2 = rs;
+    std::deque<Req *> q2;
+    for (auto &r : rs2) {
+        r.live = false;
+        q2.push_back(&r);
+    }
+    int n = 0;
+    nebem::admit(q2, b, st2, 0, [&](Req *) { ++n; });
+    CHECK(n == 5 && st2.active_large == 3 && st2.backfilled == 0);
+}
+
+static void random_traffic(int max_large)
 {
     std::mt19937_64 g(7);
     Arena a;
@@ -169,6 +215,7 @@ static void random_traffic()
             if (r.live) {
                 a.release(r.off, r.bytes);
                 r.live = false;
+                if (r.large) --st.active_large;
             }
     };
     for (int step = 0; step < 20000; ++step) {
@@ -178,6 +225,7 @@ static void random_traffic()
             // log-uniform sizes from 1 byte to half the arena
             const double u = std::uniform_real_distribution<double>(0.0, 1.0)(g);
             r.bytes = (size_t)std::exp(u * std::log((double)(1 << 20) / 2.0)) + 1;
+            r.large = r.bytes > (1u << 14);
             q.push_back(&r);
             ++next;
         }
@@ -185,21 +233,23 @@ static void random_traffic()
             if (rs[k].live && g() % 16 == 0) {
                 a.release(rs[k].off, rs[k].bytes);
                 rs[k].live = false;
+                if (rs[k].large) --st.active_large;
             }
-        nebem::admit(q, a, st, on);
+        nebem::admit(q, a, st, max_large, on);
         if (step % 97 == 0) CHECK(disjoint(rs, a.size));
         CHECK(st.bypassed <= nebem::kMaxBypass);
+        CHECK(max_large <= 0 || st.active_large <= max_large);
     }
     CHECK(disjoint(rs, a.size));
     // drain: whatever is queued enters once the arena empties
     for (int k = 0; k < 4000 && !q.empty(); ++k) {
         release_all();
-        nebem::admit(q, a, st, on);
+        nebem::admit(q, a, st, max_large, on);
     }
     CHECK(q.empty() && admitted == (int64_t)next && next == rs.size());
     CHECK(st.backfilled > 0);
     release_all();
-    CHECK(a.free_.size() == 1 && a.free_.begin()->second == a.size);
+    CHECK(a.free_.size() == 1 && a.free_.begin()->second == a.size && st.active_large == 0);
 }
 
 int main()
@@ -207,7 +257,9 @@ int main()
     arena_basics();
     fcfs_and_backfill();
     bypass_cap();
-    random_traffic();
+    large_cap();
+    random_traffic(0);
+    random_traffic(2);
     if (failures) return 1;
     std::printf("checks passed\n");
     return 0;

@@ -147,3 +147,32 @@ def test_small_request_passes_blocked_head(nb):
     srv.close()
     for x in ses:
         x.close()
+
+
+def test_large_request_cap(nb):
+    """With at most one large request active, a second large one waits at
+    the head of the line until the first finishes while a small one passes
+    it; results bit-equal to the session's."""
+    geoms = _geometries()
+    ses = _sessions(nb, 0, [geoms[0], geoms[2]])
+    srv = nb.Server(ses, batch_interactions=1.0, large_interactions=1e9, max_large=1)
+    big = uniform_points(geoms[2].box_lo, geoms[2].box_hi, 262144, 41)
+    big2 = uniform_points(geoms[2].box_lo, geoms[2].box_hi, 20000, 42)
+    small = uniform_points(geoms[0].box_lo, geoms[0].box_hi, 300, 43)
+    # 688 x 441 interactions per point: both GEM requests are large, the
+    # plates one (512 per point) is not
+    ta = srv.submit(1, big)
+    tb = srv.submit(1, big2)
+    tc = srv.submit(0, small)
+    out_c, st_c = srv.wait(tc)
+    out_b, st_b = srv.wait(tb)
+    out_a, st_a = srv.wait(ta)
+    assert st_b.t_admit >= st_a.t_done - 1e-3
+    assert st_c.t_done < st_a.t_done
+    for out, g, pts in ((out_a, 1, big), (out_b, 1, big2), (out_c, 0, small)):
+        ref = _alone(nb, ses[g], pts)
+        for name, r in zip(("phi", "ex", "ey", "ez"), ref):
+            assert np.array_equal(out[name], r), (g, name)
+    srv.close()
+    for x in ses:
+        x.close()

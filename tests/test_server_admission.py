@@ -3,7 +3,8 @@ policy (`csrc/server_admission.hpp`): aligned, disjoint placements inside
 the arena and full coalescing on release; arrival order while requests
 fit; small requests admitted past a blocked head of the line at the
 arena's top end, at most kMaxBypass per head, and the head first once
-space frees; randomized traffic that drains completely.  Compiled with the
+space frees; the optional cap on large requests active at once;
+randomized traffic (with and without the cap) that drains completely.  Compiled with the
 host C++ compiler (no GPU, no HIP runtime)."""
 import os
 import shutil
