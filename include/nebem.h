@@ -464,7 +464,9 @@ nebem_status nebem_server_submit(nebem_server *s, int32_t geometry, const double
                                  const double *pz, int64_t m, double *phi, double *ex, double *ey, double *ez,
                                  int64_t *ticket);
 /* Blocks until the ticket's request has completed and its results are in the
- * host arrays; fills `stats` (may be NULL).  Each ticket is waited once. */
+ * host arrays; fills `stats` (may be NULL).  Each ticket is waited once:
+ * NEBEM_EINVAL for an unknown ticket, one already waited for, or one that
+ * another thread is waiting for. */
 nebem_status nebem_server_wait(nebem_server *s, int64_t ticket, nebem_request_stats *stats);
 nebem_status nebem_server_stats(nebem_server *s, nebem_server_counters *out);
 /* Finishes every submitted request, stops the worker and frees the server. */

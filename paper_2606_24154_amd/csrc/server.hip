@@ -84,6 +84,7 @@ struct Request {
     int status = NEBEM_OK;
     bool ordered = false;       // points sorted into Morton order on admission
     bool large = false;         // at least large_interactions of work
+    bool waited = false;        // a nebem_server_wait call holds its ticket
     bool finished = false;
 };
 
@@ -463,6 +464,8 @@ nebem_status nebem_server_wait(nebem_server *s, int64_t ticket, nebem_request_st
     auto it = s->all.find(ticket);
     if (it == s->all.end()) return fail(NEBEM_EINVAL, "server_wait: unknown ticket");
     r = it->second;
+    if (r->waited) return fail(NEBEM_EINVAL, "server_wait: ticket already being waited for");
+    r->waited = true;
     s->cv_done.wait(lk, [&] { return r->finished; });
     if (st) {
         st->t_submit = r->t_submit;
