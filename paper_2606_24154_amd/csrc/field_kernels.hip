@@ -797,7 +797,7 @@ SegPlan seg_plan(int64_t n, const ImgArgs &img)
     return p;
 }
 
-// FP64: the default allocation (about 200 VGPRs, two waves per SIMD) keeps every
+// FP64: the default allocation (about 250 VGPRs, two waves per SIMD) keeps every
 // value in registers; a three-wave target made the allocator spill part of
 // the per-element setup to scratch (10.6 GB of HBM writes per 10^6-point
 // launch) for no measurable gain.  HOLE: img.hole is honoured (a separate
