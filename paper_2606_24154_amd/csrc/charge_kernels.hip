@@ -25,7 +25,7 @@
 // offset is at most half a diagonal and the target offset at most the pair
 // distance d plus half a diagonal, so their rounding leaves the difference
 // within ~1.2e-7 d.  Nearer runs (the wave's own and its spatial
-// neighbours: ~4 % of the pairs for a 10^6-charge cloud, against 57 % when
+// neighbours: ~8 % of the pairs for a 10^6-charge cloud, against 57 % when
 // the test was made per 256 charges) take the difference in FP64 and round
 // it once, so close pairs -- whose terms can dominate a charge's field --
 // keep the FP32 pair term's own accuracy.  Runs of 64 sources are summed in
