@@ -2,7 +2,8 @@
 algorithmic operation count per interaction over the benchmark geometries'
 element mix, the source hash that ties the stored counter figures to the
 evaluation kernel's code (a comment edit keeps it, a code edit changes it),
-and the pointwise relative difference reported for the mixed path."""
+the pointwise relative difference reported for the mixed path, and the
+paper's own figures carried on the line as context."""
 import json
 import os
 import shutil
@@ -57,3 +58,10 @@ def test_rel_diff():
     # the third point lies below 1e-3 of the largest magnitude and is not counted
     assert abs(ephi - 3e-7) < 1e-15
     assert abs(eE - 2e-7) < 1e-15
+
+
+def test_paper_context_serialises():
+    ctx = json.loads(json.dumps(bench.PAPER_CONTEXT))
+    assert "T1000" in ctx["hardware"] and "Xeon" in ctx["hardware"]
+    t = ctx["total_solve_min"]
+    assert abs(t["cpu_1_thread"] / t["hybrid_16_threads_gpu"] - t["speedup_vs_serial"]) < 0.01
