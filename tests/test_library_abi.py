@@ -85,3 +85,26 @@ def test_line_charge_entry_points_validate_without_gpu(lib):
                                          ctypes.byref(out), None) == nb.NEBEM_EINVAL
     assert nb.lib.nebem_charge_field_lines(None, None, None, None, 0, ctypes.byref(g), 5, None, None, None,
                                            ctypes.byref(nl), None) == nb.NEBEM_EINVAL
+
+
+def test_server_options_layout_and_validation(lib):
+    """The binding's server-option structure matches the library's (the
+    defaults read back through it), and bad options or a NULL output are
+    refused before anything touches a device."""
+    import paper_2606_24154_amd as nb
+    o = nb.server_default_options()
+    assert o.hbm_budget == 2 << 30 and o.batch_interactions == 1e10 and o.max_items == 65536
+    assert o.large_interactions == 1e11 and o.max_large == 1
+    assert ctypes.sizeof(nb.ServerOptions) == 40
+    h = ctypes.c_void_p()
+    assert nb.lib.nebem_server_create(None, 0, ctypes.byref(o), ctypes.byref(h)) == nb.NEBEM_EINVAL
+    assert nb.lib.nebem_server_create(None, 1, ctypes.byref(o), None) == nb.NEBEM_EINVAL
+    arr = (ctypes.c_void_p * 1)(None)
+    for field, bad in (("max_large", -1), ("large_interactions", 0.0), ("hbm_budget", 100)):
+        b = nb.server_default_options()
+        setattr(b, field, bad)
+        assert nb.lib.nebem_server_create(arr, 1, ctypes.byref(b), ctypes.byref(h)) == nb.NEBEM_EINVAL, field
+        assert b"bad options" in nb.lib.nebem_last_error(), field
+    assert nb.lib.nebem_server_create(arr, 1, ctypes.byref(o), ctypes.byref(h)) == nb.NEBEM_EINVAL
+    assert b"NULL session" in nb.lib.nebem_last_error()
+    assert nb.lib.nebem_server_wait(None, 1, None) == nb.NEBEM_EINVAL
