@@ -65,3 +65,18 @@ def test_paper_context_serialises():
     assert "T1000" in ctx["hardware"] and "Xeon" in ctx["hardware"]
     t = ctx["total_solve_min"]
     assert abs(t["cpu_1_thread"] / t["hybrid_16_threads_gpu"] - t["speedup_vs_serial"]) < 0.01
+
+
+def test_point_charge_reference_matches_oracle():
+    """The host point-charge sum that serves as the line-charge benchmark's
+    accuracy reference agrees with the oracle's Coulomb sum (self pairs and
+    coincident charges skipped in both)."""
+    import oracle
+    from synth import charge_cloud
+    xyz, q = charge_cloud([0.0, 0.0, 0.0], 20e-6, 3000, seed=8)
+    xyz[7] = xyz[3]  # a coincident pair
+    idx = np.array([0, 3, 7, 11, 2999])
+    got = bench.point_charge_field(xyz, q, idx, chunk=2)
+    want = oracle.coulomb(xyz[idx], xyz, q, idx)[:, 1:]
+    scale = np.linalg.norm(want, axis=1)
+    assert np.all(np.linalg.norm(got - want, axis=1) <= 1e-12 * scale)
